@@ -1,0 +1,86 @@
+/*
+ * vd_oracle.h -- CPU oracle for clipped / restricted Voronoi diagrams.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may include, link
+ * or call this code; only the tests, the smoke check and the CPU-baseline
+ * leg of the benchmark use it.  It shares no code with the GPU library.
+ *
+ * What it computes is the plain definition of the paper (Sec. 3.1, Eq. 1):
+ * for every domain simplex T_a and site v_i the piece
+ *     P_{a,i} = T_a  intersected with  { x : |x - v_i| <= |x - v_j|, all j != i },
+ * with face labels as in Sec. 3.2 (Fig. 2): a face on the bisector of v_i and
+ * v_j carries label j >= 0, a face shared with simplex T_b carries -(b+1),
+ * and a face on the domain boundary carries INT32_MIN + f (f = local face).
+ *
+ * Two modes:
+ *   brute  : every site of every simplex is clipped by all n-1 bisectors in
+ *            index order -- Eq. 1 written out.
+ *   pruned : candidate (simplex, site) pairs are filtered with a Lipschitz
+ *            bound on the nearest-site distance, and bisectors are applied in
+ *            grid shells around v_i until the security radius of the related
+ *            work (Sec. 2.2) proves every remaining half-space contains the
+ *            piece.  Every skipped clip is provably a no-op, and vertices are
+ *            always recomputed from their three defining planes, so both modes
+ *            take the same sign decisions in general position.
+ *
+ * Status codes: 0 ok, 1 invalid argument, 2 out of memory, 3 degenerate
+ * geometry (a vertex not defined by exactly three planes, or a capacity of
+ * the fixed-size polytope exceeded).
+ */
+#ifndef VD_ORACLE_H
+#define VD_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Result of an oracle run.  All arrays are malloc'd by the oracle and
+ * released with vdo_free_result.  Pieces are sorted by (site, simplex). */
+typedef struct {
+  int64_t n_pieces;
+  int32_t *piece_site;     /* [n_pieces] */
+  int32_t *piece_simplex;  /* [n_pieces] */
+  double *piece_mass;      /* [n_pieces] volume (tets) or area (triangles) */
+  double *piece_moment;    /* [n_pieces*3] first moment, absolute coords */
+  double *piece_energy;    /* [n_pieces] integral of |x - v_i|^2 */
+  int64_t *piece_face_off; /* [n_pieces+1] */
+  int32_t *face_label;     /* [n_faces] face/edge labels of each piece */
+  double *face_measure;    /* [n_faces] area (tets) or length (triangles) */
+  int64_t *face_vert_off;  /* [n_faces+1] */
+  int32_t *face_vert;      /* [n_face_verts] piece-local vertex indices; loops are
+                              counter-clockwise seen from outside the piece */
+  int64_t n_faces, n_face_verts;
+  int64_t *piece_vert_off; /* [n_pieces+1] */
+  double *vert_xyz;        /* [n_verts*3] absolute coords */
+  int32_t *vert_label;     /* [n_verts*3] labels of the defining planes, ascending
+                              (for triangles: 2 labels + the slot holds INT32_MAX) */
+  int64_t n_verts;
+  double min_margin;       /* smallest |signed distance| / scale seen in a cut */
+} vdo_result;
+
+/* Clipped VD (simplex_dim 3, k = 4) or restricted VD (simplex_dim 2, k = 3).
+ * sites [n*3], verts [nv*3], simp [m*k], adj [m*k] (-1 = boundary).
+ * only_sites: NULL -> all sites; else n_only site indices whose pieces are
+ * computed (pruned mode only).  threads <= 0 -> OpenMP default. */
+int vdo_compute(const double *sites, int64_t n, const double *verts, int64_t nv,
+                const int32_t *simp, const int32_t *adj, int64_t m, int simplex_dim,
+                int brute, const int32_t *only_sites, int64_t n_only, int threads,
+                vdo_result *out);
+
+void vdo_free_result(vdo_result *r);
+
+/* Adjoint of L = sum_k g_m[k] m_k + g_c[k].c_k + g_E[k] E_k with respect to the
+ * sites, at fixed combinatorics, from a result that covers ALL sites.
+ * mass/cent are the per-site masses and centroids (from the same result).
+ * g_* may be NULL (treated as zero).  g_sites [n*3] is overwritten. */
+int vdo_moments_backward(const vdo_result *r, const double *sites, int64_t n,
+                         const double *mass, const double *cent,
+                         const double *g_m, const double *g_c, const double *g_E,
+                         const double *verts, const int32_t *simp, int simplex_dim,
+                         double *g_sites);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
