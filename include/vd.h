@@ -1,0 +1,204 @@
+/*
+ * vd.h -- clipped and restricted Voronoi diagrams on one MI355X (gfx950).
+ *
+ * Method: Xiao, Cao & Chen, "Efficient Computation of Voronoi Diagrams Using
+ * Point-in-Cell Tests".  Given sites V = {v_i} and a domain M = {T_a} made of
+ * simplices (tetrahedra, or triangles in R^3), the library computes every
+ * domain-cell intersection P_{a,i} = T_a intersected with the Voronoi cell
+ * Omega_i (Sec. 3.1, Eq. 1), with the face flags of Sec. 3.2, and per site the
+ * mass, centroid and CVT energy integrand (Sec. 7.4, Eq. 3, density 1).
+ * Each piece is carved by point-in-cell tests (Sec. 4.1, Eq. 2) and the
+ * edge-based bisector search (Sec. 4.2, improved as in Sec. 6.1) on straddling
+ * or virtual edges (Alg. 1 and Alg. 3), the clip removing only the connected
+ * outside component R_p (Sec. 6.3).  Nearest-site queries use a uniform grid
+ * built by counting sort (Sec. 6.2).
+ *
+ * Conventions shared by every entry point
+ *  - C linkage; only plain types cross the boundary.  Pointers named *_host
+ *    are host memory; every other array pointer is DEVICE memory (HIP).
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    work is enqueued on it; calls return once the work is enqueued unless
+ *    stated otherwise.
+ *  - Coordinates are float64, row-major (x, y, z) per point; topology is int32.
+ *  - Indices are 0-based.  Face/edge labels (Sec. 3.2): a face on the bisector
+ *    of v_i and v_j carries j >= 0; a face shared with simplex T_b carries
+ *    -(b+1); a face on the domain boundary carries VD_BOUNDARY_BASE + f, where
+ *    f is the local face (tet: opposite vertex f; triangle: opposite vertex f).
+ *  - Every call returns a vd_status and never aborts.  vd_last_error() gives a
+ *    thread-local message for the last failure.  Handles are not thread-safe;
+ *    use one per stream.
+ *  - Handles own their device memory and keep it between calls: passing an
+ *    existing handle back in (*out != NULL) reuses its buffers when they are
+ *    large enough, so a steady-state loop performs no allocation.
+ */
+#ifndef VD_H
+#define VD_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VD_BOUNDARY_BASE (-2147483647 - 1)
+
+typedef enum {
+  VD_OK = 0,
+  VD_ERR_INVALID_ARG = 1,   /* bad sizes, NULL pointers, a site outside the domain */
+  VD_ERR_OUT_OF_MEMORY = 2, /* a device allocation failed */
+  VD_ERR_HIP = 3,           /* a HIP runtime call failed (message has details) */
+  VD_ERR_CAPACITY = 4,      /* a per-wave LDS capacity was exceeded (see vd_options) */
+  VD_ERR_DEGENERATE = 5     /* a search did not converge (inputs not in general position) */
+} vd_status;
+
+typedef struct vd_grid_s *vd_grid;
+typedef struct vd_domain_s *vd_domain;
+typedef struct vd_cells_s *vd_cells;
+
+/* Tuning and behaviour knobs; vd_options_default() fills the defaults. */
+typedef struct {
+  double sites_per_cell;   /* grid density; <= 0 -> 3.5 (3D, Sec. 6.2) */
+  int32_t improved_search; /* 1: shorten search edges by lambda*delta steps (Sec. 6.1) */
+  int32_t use_straddle_edges; /* 1: prefer edges with one inside end (Alg. 1);
+                                 0: virtual edges from the site only (Alg. 3) */
+  int32_t max_search_iters;   /* cap of the bisector search and of the lambda loop */
+  int32_t emit_polytopes;     /* 1: write per-piece faces and vertices */
+  int32_t want_grad;          /* 1: also store the face integrals the adjoint needs */
+} vd_options;
+
+void vd_options_default(vd_options *opt);
+
+const char *vd_last_error(void);
+const char *vd_status_string(vd_status s);
+
+/* ---------------------------------------------------------------------
+ * vd_build_grid -- uniform grid over the sites for nearest-site queries
+ * (Sec. 6.2), built by counting sort: per-site cell ids and a histogram,
+ * an exclusive scan into cell offsets, a scatter of the coordinates into
+ * cell order (sites of one cell ordered by index), and for every site
+ * delta_i = |N_i - v_i| / 2, half the distance to its nearest other site
+ * (Sec. 6.1).
+ *   sites      [n*3] device, caller-owned; read during the call's stream work only.
+ *   n          >= 1.
+ *   bbox_host  [6] host (xmin,ymin,zmin,xmax,ymax,zmax) or NULL; the grid box
+ *              is the union of this box and the sites' bounding box.
+ *   sites_per_cell  mean sites per grid cell (<= 0 -> 3.5).
+ *   surface_area    > 0 for sites spread over a surface of this area: the
+ *              cell size then targets sites_per_cell per non-empty cell.
+ *   out        *out == NULL -> a new handle; else the handle is rebuilt in place.
+ * Errors: VD_ERR_INVALID_ARG (n < 1, NULL), VD_ERR_OUT_OF_MEMORY, VD_ERR_HIP.
+ * --------------------------------------------------------------------- */
+vd_status vd_build_grid(const double *sites, int64_t n, const double *bbox_host,
+                        double sites_per_cell, double surface_area, void *stream, vd_grid *out);
+void vd_grid_free(vd_grid g);
+
+/* ---------------------------------------------------------------------
+ * vd_domain_create -- stages a simplex domain M = {T_a} (Sec. 3.1) on the
+ * device: copies verts/simplices/adjacency and, for tetrahedra, builds the
+ * point-location grid that finds the simplex containing each site (the seed of
+ * the per-site propagation over negative face flags, Alg. 5).
+ *   verts [nv*3], simplices [m*(dim+1)], adjacency [m*(dim+1)] (-1 = boundary):
+ *   device pointers, caller-owned, copied during the call.
+ *   simplex_dim 3: tetrahedra, positively oriented, local face f opposite
+ *   vertex f.  simplex_dim 2: triangles in R^3, local edge f opposite vertex f.
+ * Synchronises `stream` once (validation result).
+ * Errors: VD_ERR_INVALID_ARG (indices out of range, non-positive tet volume),
+ * VD_ERR_OUT_OF_MEMORY, VD_ERR_HIP.
+ * --------------------------------------------------------------------- */
+vd_status vd_domain_create(const double *verts, int64_t nv, const int32_t *simplices,
+                           const int32_t *adjacency, int64_t m, int32_t simplex_dim,
+                           void *stream, vd_domain *out);
+void vd_domain_free(vd_domain d);
+
+/* ---------------------------------------------------------------------
+ * vd_clip_cells -- all domain-cell intersections P_{a,i} (Sec. 3.1).
+ * 3D (tetrahedra): one wavefront per site; the site's tetrahedra are visited
+ * through negative face flags starting from the tetrahedron that contains the
+ * site (Alg. 5, propagation part), and each piece is carved by Alg. 1/Alg. 3.
+ * Surface (triangles): one wavefront per triangle; the triangle's sites are
+ * found by propagation over positive edge flags from the site nearest to the
+ * triangle's centroid (Alg. 4), each piece carved by Alg. 3.
+ *   g, d    handles from vd_build_grid / vd_domain_create.
+ *   opt     NULL -> defaults.
+ *   out     *out == NULL -> a new handle; else reused.
+ * Synchronises `stream` once to read the output sizes (and re-runs with
+ * larger arenas if an output arena overflowed).
+ * Errors: VD_ERR_INVALID_ARG (3D: a site outside every tetrahedron),
+ * VD_ERR_CAPACITY, VD_ERR_DEGENERATE, VD_ERR_OUT_OF_MEMORY, VD_ERR_HIP.
+ * --------------------------------------------------------------------- */
+vd_status vd_clip_cells(vd_grid g, vd_domain d, const vd_options *opt, void *stream,
+                        vd_cells *out);
+void vd_cells_free(vd_cells c);
+
+typedef struct {
+  int64_t n_sites, n_pieces, n_faces, n_verts, n_nbrs;
+  int64_t nn_queries;  /* point-in-cell tests (nearest-site queries) performed */
+  int64_t clips;       /* clips applied */
+  int64_t candidates;  /* sites examined by the nearest-site queries */
+  int32_t first_bad_site; /* -1, or a site whose carve hit a capacity/degeneracy */
+  int32_t status;         /* vd_status of the last clip */
+} vd_cells_info_t;
+
+/* Host struct of sizes and counters (synchronises `stream` of the last call). */
+vd_status vd_cells_info(vd_cells c, vd_cells_info_t *info_host);
+
+/* Device pointers into library memory, valid until the next vd_clip_cells on
+ * the same handle or vd_cells_free.  Sites and simplices use the caller's
+ * indices.  Pieces of site i are piece_id[cell_piece_off[i] .. cell_piece_off[i+1]),
+ * in the order they were carved; per piece p (an index into the piece arrays):
+ *   piece_site[p], piece_simplex[p], piece_mass[p], piece_moment[3p..] (first
+ *   moment, absolute coordinates), piece_energy[p],
+ *   faces face_label[piece_face_start[p] + k], k < piece_nface[p],
+ *   vertices vert_xyz[3(piece_vert_start[p] + k)..], vert_label[3(..)..]
+ *   (the labels of the vertex's three planes, counter-clockwise seen from
+ *   outside; for triangles the vertex lies on two edges and the third label
+ *   is INT32_MAX), k < piece_nvert[p].
+ * Neighbours of site i: nbr[nbr_off[i] .. nbr_off[i+1]), ascending. */
+typedef struct {
+  int64_t n_sites, n_pieces;
+  const int64_t *cell_piece_off; /* [n+1] */
+  const int32_t *piece_id;       /* [n_pieces] */
+  const int32_t *piece_site, *piece_simplex, *piece_nface, *piece_nvert;
+  const int64_t *piece_face_start, *piece_vert_start;
+  const double *piece_mass, *piece_moment, *piece_energy;
+  const int32_t *face_label;
+  const double *vert_xyz;
+  const int32_t *vert_label;
+  const int64_t *nbr_off; /* [n+1] */
+  const int32_t *nbr;
+} vd_cells_view_t;
+
+vd_status vd_cells_view(vd_cells c, vd_cells_view_t *view_host);
+
+/* ---------------------------------------------------------------------
+ * vd_cell_moments -- per-site mass (volume, or area for surfaces), centroid
+ * and energy E_i = integral over Omega_i cap M of |x - v_i|^2 (Eq. 3 with
+ * density 1).  A site whose cell misses the domain gets mass 0, centroid
+ * v_i, energy 0.  Per-site sums run over the site's pieces in a fixed order
+ * (no floating-point atomics), so results are bitwise reproducible.
+ *   mass [n], centroid [n*3], energy [n] (nullable): caller-owned device memory.
+ * --------------------------------------------------------------------- */
+vd_status vd_cell_moments(vd_cells c, double *mass, double *centroid, double *energy,
+                          void *stream);
+
+/* ---------------------------------------------------------------------
+ * vd_cell_moments_backward -- adjoint of the moments at fixed combinatorics.
+ * For L = sum_k g_mass[k] m_k + g_centroid[k].c_k + g_energy[k] E_k it writes
+ * dL/dv_i = 2 gE_i m_i (v_i - c_i)
+ *         + sum over faces F_ik of cell i of  integral over F_ik of
+ *           [(a_i - a_k) + (b_i - b_k).x + (gE_i - gE_k)|x - v_i|^2] (x - v_i)/|v_k - v_i| dA
+ * with a_k = g_mass[k] - g_centroid[k].c_k/m_k, b_k = g_centroid[k]/m_k: a face
+ * on the bisector of v_i and v_k moves with normal speed (x - v_i).dv_i/|v_k - v_i|
+ * (Reynolds transport applied to Eq. 1 and Eq. 3; the paper has no gradient).
+ * For surfaces the face is a segment and the speed is divided by the sine
+ * between the bisector and the triangle plane.  Requires want_grad = 1 in the
+ * options of the vd_clip_cells call.  Deterministic, no atomics.
+ *   g_mass [n], g_centroid [n*3], g_energy [n]: device, each nullable (zero).
+ *   g_sites [n*3]: device, overwritten.
+ * --------------------------------------------------------------------- */
+vd_status vd_cell_moments_backward(vd_cells c, const double *g_mass, const double *g_centroid,
+                                   const double *g_energy, double *g_sites, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,76 @@
+// cells.hip -- output compaction and per-site moments.
+//
+// The clip kernels reserve per-site lists with one atomic per wave, so lists
+// sit anywhere in their arenas.  Finalize turns them into CSR: an exclusive scan
+// of the per-site counts and a gather (one thread per site).  Moments convert
+// the per-site mass / first moment / energy sums (accumulated in a fixed order
+// inside each wave) into mass, centroid and energy.
+#include "vd_internal.h"
+#include "vd_scan.h"
+
+namespace {
+
+constexpr int kB = 256;
+inline unsigned blocks(long long n) { return (unsigned)((n + kB - 1) / kB > 0 ? (n + kB - 1) / kB : 1); }
+
+__global__ void __launch_bounds__(kB) gather_lists(long long n, const int *__restrict__ count,
+                                                   const long long *__restrict__ start,
+                                                   const int *__restrict__ arena,
+                                                   const long long *__restrict__ off,
+                                                   int *__restrict__ out) {
+  const long long i = (long long)blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+  const long long o = off[i], s = start[i];
+  const int c = count[i];
+  for (int k = 0; k < c; k++) out[o + k] = arena[s + k];
+}
+
+__global__ void __launch_bounds__(kB) moments_kernel(long long n, const int *__restrict__ rank,
+                                                     const double *__restrict__ sx, const double *__restrict__ sy,
+                                                     const double *__restrict__ sz, const double *__restrict__ mass,
+                                                     const double *__restrict__ mom, const double *__restrict__ en,
+                                                     double *__restrict__ out_m, double *__restrict__ out_c,
+                                                     double *__restrict__ out_e) {
+  const long long i = (long long)blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+  const double m = mass[i];
+  if (out_m) out_m[i] = m;
+  if (out_c) {
+    if (m > 0.0) {
+      const double im = 1.0 / m;
+      out_c[3 * i + 0] = mom[3 * i + 0] * im;
+      out_c[3 * i + 1] = mom[3 * i + 1] * im;
+      out_c[3 * i + 2] = mom[3 * i + 2] * im;
+    } else {
+      const int p = rank[i];
+      out_c[3 * i + 0] = sx[p];
+      out_c[3 * i + 1] = sy[p];
+      out_c[3 * i + 2] = sz[p];
+    }
+  }
+  if (out_e) out_e[i] = m > 0.0 ? en[i] : 0.0;
+}
+
+}  // namespace
+
+void vd_launch_finalize(vd_cells c, hipStream_t st) {
+  const long long n = c->n;
+  const CellsDev &d = c->d;
+  vdscan::exclusive_scan<int, long long>(d.pcount, n, c->piece_off, c->scan_tmp, st);
+  hipLaunchKernelGGL(gather_lists, dim3(blocks(n)), dim3(kB), 0, st, n, (const int *)d.pcount,
+                     (const long long *)d.pstart, (const int *)d.plist, (const long long *)c->piece_off,
+                     c->piece_id);
+  vdscan::exclusive_scan<int, long long>(d.ncount, n, c->nbr_off, c->scan_tmp, st);
+  hipLaunchKernelGGL(gather_lists, dim3(blocks(n)), dim3(kB), 0, st, n, (const int *)d.ncount,
+                     (const long long *)d.nstart, (const int *)d.nbr_arena, (const long long *)c->nbr_off,
+                     c->nbr);
+}
+
+void vd_launch_moments(const vd_cells_s *c, const GridView &G, double *mass, double *cent, double *energy,
+                       hipStream_t st) {
+  const long long n = c->n;
+  vd_grid g = c->grid;
+  hipLaunchKernelGGL(moments_kernel, dim3(blocks(n)), dim3(kB), 0, st, n, (const int *)g->rank,
+                     G.sx, G.sy, G.sz, (const double *)c->d.mass, (const double *)c->d.mom,
+                     (const double *)c->d.energy, mass, cent, energy);
+}

@@ -1,0 +1,157 @@
+// grid.hip -- uniform grid over the sites for nearest-site queries (Sec. 6.2).
+//
+// Counting sort in five HBM-bound launches: bounding box, per-site cell id +
+// histogram, exclusive scan, scatter into cell order, and an in-cell sort by
+// the caller's index so the layout is deterministic.  A sixth launch computes
+// delta_i = half the distance to the nearest other site (Sec. 6.1).
+#include "vd_internal.h"
+#include "vd_scan.h"
+
+namespace {
+
+constexpr int kB = 256;
+
+__global__ void __launch_bounds__(kB) bbox_partial(const double *__restrict__ s, long long n,
+                                                   double *__restrict__ part) {
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (long long i = (long long)blockIdx.x * kB + threadIdx.x; i < n; i += (long long)gridDim.x * kB) {
+    for (int k = 0; k < 3; k++) {
+      const double x = s[3 * i + k];
+      lo[k] = fmin(lo[k], x);
+      hi[k] = fmax(hi[k], x);
+    }
+  }
+  __shared__ double red[6][kB];
+  for (int k = 0; k < 3; k++) { red[k][threadIdx.x] = lo[k]; red[3 + k][threadIdx.x] = hi[k]; }
+  __syncthreads();
+  for (int d = kB / 2; d > 0; d >>= 1) {
+    if (threadIdx.x < (unsigned)d)
+      for (int k = 0; k < 3; k++) {
+        red[k][threadIdx.x] = fmin(red[k][threadIdx.x], red[k][threadIdx.x + d]);
+        red[3 + k][threadIdx.x] = fmax(red[3 + k][threadIdx.x], red[3 + k][threadIdx.x + d]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) part[6 * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
+}
+
+struct Box6 { double v[6]; };
+
+__global__ void bbox_final(const double *__restrict__ part, int nb, Box6 user, int has_user, int gx,
+                           int gy, int gz, double *__restrict__ geom) {
+  if (threadIdx.x != 0) return;
+  double lo[3], hi[3];
+  for (int k = 0; k < 3; k++) {
+    lo[k] = has_user ? user.v[k] : 1e300;
+    hi[k] = has_user ? user.v[3 + k] : -1e300;
+  }
+  for (int b = 0; b < nb; b++)
+    for (int k = 0; k < 3; k++) {
+      lo[k] = fmin(lo[k], part[6 * b + k]);
+      hi[k] = fmax(hi[k], part[6 * b + 3 + k]);
+    }
+  const int g[3] = {gx, gy, gz};
+  double ext = 0;
+  for (int k = 0; k < 3; k++) ext = fmax(ext, hi[k] - lo[k]);
+  if (!(ext > 0)) ext = 1.0;
+  for (int k = 0; k < 3; k++) {
+    // pad so that points on the upper face fall inside the last cell
+    double e = hi[k] - lo[k];
+    if (!(e > 1e-12 * ext)) e = 1e-12 * ext;
+    const double pad = 1e-9 * e;
+    const double l = lo[k] - pad;
+    const double h = (e + 2 * pad) / g[k];
+    geom[k] = l;
+    geom[3 + k] = h;
+    geom[6 + k] = 1.0 / h;
+  }
+}
+
+__global__ void __launch_bounds__(kB) grid_hist(const double *__restrict__ s, long long n,
+                                                const double *__restrict__ geom, int gx, int gy, int gz,
+                                                int *__restrict__ cellid, int *__restrict__ count) {
+  const long long i = (long long)blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+  const int cx = cell_coord(s[3 * i + 0], geom[0], geom[6], gx);
+  const int cy = cell_coord(s[3 * i + 1], geom[1], geom[7], gy);
+  const int cz = cell_coord(s[3 * i + 2], geom[2], geom[8], gz);
+  const int c = cx + gx * (cy + gy * cz);
+  cellid[i] = c;
+  atomicAdd(&count[c], 1);
+}
+
+__global__ void __launch_bounds__(kB) grid_scatter(const double *__restrict__ s, long long n,
+                                                   const int *__restrict__ cellid,
+                                                   const int *__restrict__ cstart, int *__restrict__ fill,
+                                                   double *__restrict__ sx, double *__restrict__ sy,
+                                                   double *__restrict__ sz, int *__restrict__ perm) {
+  const long long i = (long long)blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+  const int c = cellid[i];
+  const int p = cstart[c] + atomicAdd(&fill[c], 1);
+  sx[p] = s[3 * i + 0];
+  sy[p] = s[3 * i + 1];
+  sz[p] = s[3 * i + 2];
+  perm[p] = (int)i;
+}
+
+// Order the sites of each cell by the caller's index (insertion sort; cells
+// hold a handful of sites at the target density).
+__global__ void __launch_bounds__(kB) grid_sort_cells(long long ncell, const int *__restrict__ cstart,
+                                                      double *__restrict__ sx, double *__restrict__ sy,
+                                                      double *__restrict__ sz, int *__restrict__ perm) {
+  const long long c = (long long)blockIdx.x * kB + threadIdx.x;
+  if (c >= ncell) return;
+  const int a = cstart[c], b = cstart[c + 1];
+  for (int i = a + 1; i < b; i++) {
+    const int key = perm[i];
+    const double x = sx[i], y = sy[i], z = sz[i];
+    int j = i - 1;
+    while (j >= a && perm[j] > key) {
+      perm[j + 1] = perm[j]; sx[j + 1] = sx[j]; sy[j + 1] = sy[j]; sz[j + 1] = sz[j];
+      j--;
+    }
+    perm[j + 1] = key; sx[j + 1] = x; sy[j + 1] = y; sz[j + 1] = z;
+  }
+}
+
+__global__ void __launch_bounds__(kB) grid_rank(long long n, const int *__restrict__ perm,
+                                                int *__restrict__ rank) {
+  const long long p = (long long)blockIdx.x * kB + threadIdx.x;
+  if (p < n) rank[perm[p]] = (int)p;
+}
+
+__global__ void __launch_bounds__(kB) grid_delta(GridView G, double *__restrict__ delta) {
+  const long long p = (long long)blockIdx.x * kB + threadIdx.x;
+  if (p >= G.n) return;
+  double d2;
+  const int k = nn_thread(G, G.sx[p], G.sy[p], G.sz[p], (int)p, d2);
+  delta[p] = k >= 0 ? 0.5 * sqrt(d2) : 1e300;
+}
+
+inline unsigned blocks(long long n) { return (unsigned)((n + kB - 1) / kB > 0 ? (n + kB - 1) / kB : 1); }
+
+}  // namespace
+
+void vd_launch_fill_int(int *p, long long n, int v, hipStream_t st);
+
+void vd_launch_grid_build(vd_grid g, const double *sites, const double *bbox_host, hipStream_t st) {
+  const long long n = g->n;
+  const int nb = 256;
+  hipLaunchKernelGGL(bbox_partial, dim3(nb), dim3(kB), 0, st, sites, n, g->bbox_part);
+  Box6 u;
+  for (int k = 0; k < 6; k++) u.v[k] = bbox_host ? bbox_host[k] : 0.0;
+  hipLaunchKernelGGL(bbox_final, dim3(1), dim3(64), 0, st, (const double *)g->bbox_part, nb, u,
+                     bbox_host ? 1 : 0, g->g[0], g->g[1], g->g[2], g->geom);
+  vd_launch_fill_int(g->ccount, g->ncell, 0, st);
+  vd_launch_fill_int(g->fill, g->ncell, 0, st);
+  hipLaunchKernelGGL(grid_hist, dim3(blocks(n)), dim3(kB), 0, st, sites, n, (const double *)g->geom,
+                     g->g[0], g->g[1], g->g[2], g->cellid, g->ccount);
+  vdscan::exclusive_scan<int, int>(g->ccount, g->ncell, g->cstart, g->scan_tmp, st);
+  hipLaunchKernelGGL(grid_scatter, dim3(blocks(n)), dim3(kB), 0, st, sites, n, (const int *)g->cellid,
+                     (const int *)g->cstart, g->fill, g->sx, g->sy, g->sz, g->perm);
+  hipLaunchKernelGGL(grid_sort_cells, dim3(blocks(g->ncell)), dim3(kB), 0, st, (long long)g->ncell,
+                     (const int *)g->cstart, g->sx, g->sy, g->sz, g->perm);
+  hipLaunchKernelGGL(grid_rank, dim3(blocks(n)), dim3(kB), 0, st, n, (const int *)g->perm, g->rank);
+  hipLaunchKernelGGL(grid_delta, dim3(blocks(n)), dim3(kB), 0, st, g->view(), g->delta);
+}

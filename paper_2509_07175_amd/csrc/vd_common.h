@@ -1,0 +1,204 @@
+// vd_common.h -- device-side building blocks shared by the kernels.
+//
+// gfx950 (CDNA4), wave64.  Geometry is float64 throughout (FP64 vector ALU is
+// full rate on this chip); nothing here is a dense contraction, so no MFMA.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define VD_WAVE 64
+#define VD_BND_BASE (-2147483647 - 1)
+
+// Device view of the nearest-site grid (Sec. 6.2).  Sites are stored in cell
+// order; "sorted position" indexes sx/sy/sz/delta, perm maps it back to the
+// caller's index.  geom = {lo[3], h[3], ih[3]} lives in device memory because
+// the bounding box is reduced on the device.
+struct GridView {
+  int n;
+  int g[3];
+  const double *geom;
+  const double *sx, *sy, *sz;
+  const int *cstart;  // [g0*g1*g2 + 1]
+  const int *perm;    // sorted position -> caller index
+  const double *delta;  // half nearest-other-site distance, by sorted position
+};
+
+__device__ __forceinline__ int vd_lane() {
+  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+__device__ __forceinline__ bool bit128(uint64_t lo, uint64_t hi, int s) {
+  return s < 64 ? ((lo >> s) & 1ull) : ((hi >> (s - 64)) & 1ull);
+}
+
+__device__ __forceinline__ int wave_incl_scan(int v) {
+  const int l = vd_lane();
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    int o = __shfl_up(v, d, 64);
+    if (l >= d) v += o;
+  }
+  return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+__device__ __forceinline__ uint64_t wave_or64(uint64_t v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    unsigned lo = (unsigned)v, hi = (unsigned)(v >> 32);
+    lo |= (unsigned)__shfl_xor((int)lo, m, 64);
+    hi |= (unsigned)__shfl_xor((int)hi, m, 64);
+    v = ((uint64_t)hi << 32) | lo;
+  }
+  return v;
+}
+
+// Lexicographic (distance^2, sorted position) minimum over the wave; every
+// lane ends with the result.
+__device__ __forceinline__ void wave_argmin(double &d, int &k) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    double od = __shfl_xor(d, m, 64);
+    int ok = __shfl_xor(k, m, 64);
+    if (od < d || (od == d && ok < k)) { d = od; k = ok; }
+  }
+}
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+__device__ __forceinline__ int cell_coord(double x, double lo, double ih, int g) {
+  double t = floor((x - lo) * ih);
+  if (!(t > 0.0)) return 0;  // also catches NaN
+  if (t >= (double)(g - 1)) return g - 1;
+  return (int)t;
+}
+
+// Scans every site whose grid cell lies in the box [b0, b1] (inclusive, per
+// axis) and folds it into the per-lane best (bd, bk).  The box is split into
+// x-rows; a row of consecutive cells is one contiguous range of sorted sites,
+// so the wave flattens all rows into one candidate list and lane t takes
+// candidates t, t+64, ...  (coalesced SoA loads).
+__device__ __forceinline__ void nn_scan_box(const GridView &G, int x0, int x1, int y0, int y1,
+                                            int z0, int z1, double qx, double qy, double qz,
+                                            double &bd, int &bk, long long &ncand) {
+  const int l = vd_lane();
+  const int nx = x1 - x0 + 1, ny = y1 - y0 + 1, nz = z1 - z0 + 1;
+  const int R = ny * nz;
+  for (int r0 = 0; r0 < R; r0 += 64) {
+    const int r = r0 + l;
+    int st = 0, cnt = 0;
+    if (r < R) {
+      const int yy = y0 + r % ny, zz = z0 + r / ny;
+      const int c0 = x0 + G.g[0] * (yy + G.g[1] * zz);
+      st = G.cstart[c0];
+      cnt = G.cstart[c0 + nx] - st;
+    }
+    const int inc = wave_incl_scan(cnt);
+    const int excl = inc - cnt;
+    const int total = __shfl(inc, 63, 64);
+    const int nrows = (R - r0) < 64 ? (R - r0) : 64;
+    ncand += total;
+    for (int base = 0; base < total; base += 64) {
+      const int t = base + l;
+      // largest row rr with excl[rr] <= t (rows are ordered by offset)
+      int rr = 0;
+#pragma unroll
+      for (int step = 32; step >= 1; step >>= 1) {
+        const int cand = rr + step;
+        const int v = __shfl(excl, cand & 63, 64);
+        if (cand < nrows && v <= t) rr = cand;
+      }
+      const int rst = __shfl(st, rr, 64);
+      const int rex = __shfl(excl, rr, 64);
+      if (t < total) {
+        const int p = rst + (t - rex);
+        const double dx = qx - G.sx[p], dy = qy - G.sy[p], dz = qz - G.sz[p];
+        const double d = dx * dx + dy * dy + dz * dz;
+        if (d < bd || (d == bd && p < bk)) { bd = d; bk = p; }
+      }
+    }
+  }
+}
+
+// Nearest site of q (absolute coordinates), wave-cooperative: every lane calls
+// it with the same q and gets the same answer.  (r2, k0) is a known candidate
+// (distance^2 and sorted position), e.g. the site whose cell is being carved.
+// Ties break towards the lower sorted position.  Returns the sorted position.
+__device__ __forceinline__ int nn_query(const GridView &G, double qx, double qy, double qz,
+                                        double r2, int k0, double &out_d2, long long &ncand) {
+  const double lox = G.geom[0], loy = G.geom[1], loz = G.geom[2];
+  const double ihx = G.geom[6], ihy = G.geom[7], ihz = G.geom[8];
+  const int gx = G.g[0], gy = G.g[1], gz = G.g[2];
+  double bd = r2;
+  int bk = k0;
+  const int cx = cell_coord(qx, lox, ihx, gx), cy = cell_coord(qy, loy, ihy, gy),
+            cz = cell_coord(qz, loz, ihz, gz);
+  double r = sqrt(r2);
+  // phase 1: the 3x3x3 block around q's cell, trimmed to the ball of radius r
+  int x0 = max(cx - 1, cell_coord(qx - r, lox, ihx, gx)), x1 = min(cx + 1, cell_coord(qx + r, lox, ihx, gx));
+  int y0 = max(cy - 1, cell_coord(qy - r, loy, ihy, gy)), y1 = min(cy + 1, cell_coord(qy + r, loy, ihy, gy));
+  int z0 = max(cz - 1, cell_coord(qz - r, loz, ihz, gz)), z1 = min(cz + 1, cell_coord(qz + r, loz, ihz, gz));
+  nn_scan_box(G, x0, x1, y0, y1, z0, z1, qx, qy, qz, bd, bk, ncand);
+  wave_argmin(bd, bk);
+  // phase 2: if the ball of the best radius leaves the scanned box, scan the
+  // whole box of that ball (the best radius only shrinks, so once suffices)
+  r = sqrt(bd);
+  const int X0 = cell_coord(qx - r, lox, ihx, gx), X1 = cell_coord(qx + r, lox, ihx, gx);
+  const int Y0 = cell_coord(qy - r, loy, ihy, gy), Y1 = cell_coord(qy + r, loy, ihy, gy);
+  const int Z0 = cell_coord(qz - r, loz, ihz, gz), Z1 = cell_coord(qz + r, loz, ihz, gz);
+  if (X0 < x0 || X1 > x1 || Y0 < y0 || Y1 > y1 || Z0 < z0 || Z1 > z1) {
+    nn_scan_box(G, X0, X1, Y0, Y1, Z0, Z1, qx, qy, qz, bd, bk, ncand);
+    wave_argmin(bd, bk);
+  }
+  out_d2 = bd;
+  return bk;
+}
+
+// Single-lane nearest site of q, excluding sorted position `excl` (-1: none).
+// Rings of cells around q's cell until the ring distance exceeds the best.
+__device__ __forceinline__ int nn_thread(const GridView &G, double qx, double qy, double qz, int excl,
+                                         double &out_d2) {
+  const double lox = G.geom[0], loy = G.geom[1], loz = G.geom[2];
+  const double hx = G.geom[3], hy = G.geom[4], hz = G.geom[5];
+  const double ihx = G.geom[6], ihy = G.geom[7], ihz = G.geom[8];
+  const int gx = G.g[0], gy = G.g[1], gz = G.g[2];
+  const int cx = cell_coord(qx, lox, ihx, gx), cy = cell_coord(qy, loy, ihy, gy),
+            cz = cell_coord(qz, loz, ihz, gz);
+  double bd = 1e300;
+  int bk = -1;
+  const double hmin = fmin(hx, fmin(hy, hz));
+  const int smax = gx + gy + gz;
+  for (int s = 0; s <= smax; s++) {
+    bool any = false;
+    for (int z = cz - s; z <= cz + s; z++) {
+      if (z < 0 || z >= gz) continue;
+      for (int y = cy - s; y <= cy + s; y++) {
+        if (y < 0 || y >= gy) continue;
+        // rows strictly inside the ring only touch it at x = cx - s and cx + s
+        const bool edge = (z == cz - s || z == cz + s || y == cy - s || y == cy + s);
+        const int step = edge ? 1 : 2 * s;
+        for (int x = cx - s; x <= cx + s; x += step) {
+          if (x < 0 || x >= gx) continue;
+          any = true;
+          const int c = x + gx * (y + gy * z);
+          for (int p = G.cstart[c]; p < G.cstart[c + 1]; p++) {
+            if (p == excl) continue;
+            const double dx = qx - G.sx[p], dy = qy - G.sy[p], dz = qz - G.sz[p];
+            const double d = dx * dx + dy * dy + dz * dz;
+            if (d < bd || (d == bd && p < bk)) { bd = d; bk = p; }
+          }
+        }
+      }
+    }
+    // sites in rings > s lie at least s*hmin away
+    if (bk >= 0 && sqrt(bd) <= s * hmin) break;
+    if (!any && s > 0 && bk >= 0) break;
+  }
+  out_d2 = bd;
+  return bk;
+}

@@ -1,0 +1,128 @@
+// vd_internal.h -- host-side handle layouts and kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/vd.h"
+#include "vd_common.h"
+
+// ---------------------------------------------------------------------------
+// per-wave LDS capacities of the 3D carve (one wavefront per site)
+// ---------------------------------------------------------------------------
+#define VD_P_MAX 64    // planes of one intermediate polytope
+#define VD_C_MAX 128   // corners (two slots per lane)
+#define VD_Q_MAX 64    // tetrahedra visited for one site
+#define VD_NB_MAX 96   // distinct neighbours of one site
+
+// device counters written by the clip kernels (one atomic per wave per field)
+enum {
+  CNT_PIECES = 0, CNT_FACES, CNT_VERTS, CNT_NBRS, CNT_PLIST, CNT_FINT,
+  CNT_QUERIES, CNT_CLIPS, CNT_CANDS, CNT_ERR_CAP, CNT_ERR_DEG, CNT_ERR_LOC, CNT_BAD_SITE,
+  CNT_N
+};
+
+struct vd_grid_s {
+  int64_t n = 0, cap_n = 0;
+  int g[3] = {1, 1, 1};
+  int64_t ncell = 0, cap_cell = 0;
+  double *geom = nullptr;     // lo[3], h[3], ih[3]
+  double *bbox_part = nullptr;  // per-block partial boxes
+  double *sx = nullptr, *sy = nullptr, *sz = nullptr, *delta = nullptr;
+  int *perm = nullptr, *rank = nullptr, *cellid = nullptr, *fill = nullptr;
+  int *cstart = nullptr, *ccount = nullptr, *scan_tmp = nullptr;
+  GridView view() const {
+    GridView v;
+    v.n = (int)n; v.g[0] = g[0]; v.g[1] = g[1]; v.g[2] = g[2];
+    v.geom = geom; v.sx = sx; v.sy = sy; v.sz = sz; v.cstart = cstart; v.perm = perm; v.delta = delta;
+    return v;
+  }
+};
+
+struct DomainView {
+  int m, nv, dim;
+  const double *verts;
+  const int *simp, *adj;
+  // point location grid over the simplices (tetrahedra only)
+  int lg[3];
+  const double *lgeom;  // lo[3], h[3], ih[3]
+  const int *lstart, *litems;
+};
+
+struct vd_domain_s {
+  int64_t m = 0, nv = 0;
+  int dim = 3;
+  double *verts = nullptr;
+  int *simp = nullptr, *adj = nullptr;
+  int lg[3] = {1, 1, 1};
+  double *lgeom = nullptr;
+  int *lstart = nullptr, *litems = nullptr, *lcount = nullptr, *lfill = nullptr, *scan_tmp = nullptr;
+  int64_t nitems = 0;
+  double area = 0.0;  // surface area (triangles) or volume (tets)
+  DomainView view() const {
+    DomainView d;
+    d.m = (int)m; d.nv = (int)nv; d.dim = dim; d.verts = verts; d.simp = simp; d.adj = adj;
+    d.lg[0] = lg[0]; d.lg[1] = lg[1]; d.lg[2] = lg[2];
+    d.lgeom = lgeom; d.lstart = lstart; d.litems = litems;
+    return d;
+  }
+};
+
+// Output arenas of a clip (device).  Per-piece records live in arena order;
+// per-site lists are reserved by atomics and compacted into CSR afterwards.
+struct CellsDev {
+  int n;           // sites
+  int emit;        // write faces / vertices
+  int want_grad;   // write face integrals
+  int improved;    // Sec. 6.1 search
+  int straddle;    // Alg. 1 edges when available
+  int max_iters;
+  unsigned long long *cnt;  // CNT_N counters
+  // per site (caller index)
+  double *mass, *mom, *energy;
+  int *pcount, *ncount;
+  long long *pstart, *nstart;
+  // arenas + capacities
+  int *plist; long long cap_plist;
+  int *nbr_arena; long long cap_nbr;
+  int *piece_site, *piece_simplex, *piece_nface, *piece_nvert;
+  long long *piece_fstart, *piece_vstart;
+  double *piece_mass, *piece_mom, *piece_energy;
+  long long cap_piece;
+  int *face_label; long long cap_face;
+  double *vert_xyz; int *vert_label; long long cap_vert;
+  // face integrals for the adjoint: per (site, neighbour) pair, 16 doubles
+  // {k, A[3], B[9], C[3]} summed over the site's pieces; stored by neighbour slot
+  double *fint; long long cap_fint;
+  int *seed;  // 3D: tetrahedron containing each site (sorted position order)
+};
+
+struct vd_cells_s {
+  int64_t n = 0;
+  int dim = 3;
+  vd_options opt;
+  CellsDev d{};
+  unsigned long long host_cnt[CNT_N] = {0};
+  // capacities (host copy) and allocations
+  int64_t cap_n = 0;
+  long long *piece_off = nullptr, *nbr_off = nullptr;  // CSR [n+1]
+  int *piece_id = nullptr, *nbr = nullptr;             // CSR payloads
+  long long *scan_tmp = nullptr;
+  int64_t cap_pid = 0, cap_nbr_csr = 0;
+  const double *sites_sorted_x = nullptr;  // borrowed from the grid for moments
+  vd_grid grid = nullptr;
+  int status = 0;
+  int first_bad = -1;
+};
+
+// launchers (defined in the .hip files)
+void vd_launch_grid_build(vd_grid g, const double *sites, const double *bbox_host, hipStream_t st);
+void vd_launch_domain_locator(vd_domain d, hipStream_t st);
+void vd_launch_locate_sites(const GridView &G, const DomainView &D, int *seed, unsigned long long *cnt,
+                            hipStream_t st);
+void vd_launch_clip3d(const GridView &G, const DomainView &D, const CellsDev &C, hipStream_t st);
+void vd_launch_surface(const GridView &G, const DomainView &D, const CellsDev &C, hipStream_t st);
+void vd_launch_finalize(vd_cells c, hipStream_t st);
+void vd_launch_moments(const vd_cells_s *c, const GridView &G, double *mass, double *cent,
+                       double *energy, hipStream_t st);
+void vd_launch_backward(const vd_cells_s *c, const GridView &G, const double *gm, const double *gc,
+                        const double *ge, double *gs, double *work, hipStream_t st);

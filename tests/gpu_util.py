@@ -1,0 +1,78 @@
+"""Helpers for the GPU parity tests: run the library, compare with the oracle."""
+import sys
+
+import numpy as np
+
+from canon import canon_pieces
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(sites, dom, bbox=(0, 0, 0, 1, 1, 1), surface_area=0.0, **opts):
+    import torch
+    import paper_2509_07175_amd as vd
+    s = torch.as_tensor(np.ascontiguousarray(sites), dtype=torch.float64, device="cuda")
+    d = vd.Domain.from_vdgen(dom)
+    g = vd.build_grid(s, bbox=bbox, surface_area=surface_area)
+    c = vd.clip_cells(g, d, vd.Options.default(**opts))
+    m, ce, e = c.moments()
+    torch.cuda.synchronize()
+    view = c.view()
+    res = vd.pieces_as_result(view)
+    out = {
+        "mass": m.cpu().numpy(), "centroid": ce.cpu().numpy(), "energy": e.cpu().numpy(),
+        "info": c.info(), "res": res,
+        "nbr_off": view["nbr_off"].cpu().numpy(), "nbr": view["nbr"].cpu().numpy(),
+        "cell_piece_off": view["cell_piece_off"].cpu().numpy(), "piece_id": view["piece_id"].cpu().numpy(),
+        "raw_piece_site": view["piece_site"].cpu().numpy(),
+        "cells": c, "grid": g, "domain": d, "sites_t": s,
+    }
+    return out
+
+
+def gpu_neighbors(out, n):
+    off, nb = out["nbr_off"], out["nbr"]
+    return [nb[off[i]:off[i + 1]] for i in range(n)]
+
+
+def assert_parity(gpu, ref_res, ref_mom, n, sites_subset=None, xyz_tol=1e-10, rel=1e-9):
+    """Bit-exact combinatorics (piece set, face labels, vertex label triples)
+    and moments within `rel` relative."""
+    subset = None if sites_subset is None else set(int(i) for i in sites_subset)
+    a = canon_pieces(gpu["res"])
+    b = canon_pieces(ref_res)
+    if subset is not None:
+        a = {k: v for k, v in a.items() if k[0] in subset}
+        b = {k: v for k, v in b.items() if k[0] in subset}
+    missing = sorted(set(b) - set(a))[:5]
+    extra = sorted(set(a) - set(b))[:5]
+    assert not missing and not extra, f"piece sets differ: missing {missing} extra {extra}"
+    nbad = 0
+    md = 0.0
+    for k in b:
+        if a[k][0] != b[k][0] or a[k][1] != b[k][1]:
+            nbad += 1
+            if nbad < 4:
+                log(f"combinatorics differ at {k}: gpu faces {a[k][0]} ref {b[k][0]}")
+            continue
+        if len(b[k][2]):
+            md = max(md, float(np.abs(a[k][2] - b[k][2]).max()))
+    assert nbad == 0, f"{nbad} pieces with different combinatorics"
+    assert md <= xyz_tol, f"vertex coordinates differ by {md}"
+    idx = np.arange(n) if subset is None else np.array(sorted(subset))
+    m_g, m_r = gpu["mass"][idx], ref_mom["mass"][idx]
+    nz = m_r > 0
+    assert np.all(np.abs(m_g - m_r) <= rel * np.maximum(m_r, 1e-300)), \
+        f"mass max rel err {np.max(np.abs(m_g - m_r)[nz] / m_r[nz])}"
+    c_g, c_r = gpu["centroid"][idx], ref_mom["centroid"][idx]
+    cerr = np.linalg.norm(c_g - c_r, axis=1) / np.maximum(np.linalg.norm(c_r, axis=1), 1e-300)
+    assert np.all(cerr[nz] <= rel), f"centroid max rel err {cerr[nz].max()}"
+    e_g, e_r = gpu["energy"][idx], ref_mom["energy"][idx]
+    assert np.all(np.abs(e_g - e_r)[nz] <= rel * e_r[nz]), \
+        f"energy max rel err {np.max(np.abs(e_g - e_r)[nz] / e_r[nz])}"
+    nb = gpu_neighbors(gpu, len(gpu["mass"]))
+    for i in idx:
+        assert list(nb[i]) == list(ref_mom["neighbors"][i]), f"neighbours of site {i} differ"
