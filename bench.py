@@ -1,0 +1,145 @@
+"""Throughput of the clipped-Voronoi hot path on one MI355X.
+
+One step = vd_build_grid + vd_clip_cells + vd_cell_moments on inputs resident
+in HBM (sites and the staged tetrahedral domain), i.e. cells plus centroids
+from device-resident inputs, excluding allocation and host transfers.
+Default workload: 1,000,000 clustered sites (8 Gaussians + 10% uniform) in a
+50^3-cube grid of 750,000 tetrahedra, float64.
+
+Prints one JSON line with the metric, the carve kernel's roofline figures
+(measured with hipEvents on the stream the kernel runs on) and the CPU
+oracle's throughput on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X dense FP64 vector
+FLOPS_PER_CANDIDATE = 8          # |q - s|^2: 3 sub + 3 mul/fma (fma = 2) + compare
+
+
+def workload(name):
+    import vdgen
+    if name == "c1":
+        s, d = vdgen.config_c1()
+        return s, d, "C1: 1,000 uniform sites, unit cube as 6 tetrahedra", 3.5
+    if name == "c2":
+        s, d = vdgen.config_c2()
+        return s, d, "C2: 100,000 uniform sites, 20^3 cubes x 6 = 48,000 tetrahedra", 3.5
+    s, d = vdgen.config_c3()
+    return (s, d, "C3: 1,000,000 clustered sites (8 Gaussians sigma 0.05 + 10% uniform), "
+                  "50^3 cubes x 6 = 750,000 tetrahedra", 0.25)
+
+
+def cpu_baseline(sites, dom, target_s=15.0):
+    """The oracle (plain CPU definition, pruned mode) on a bounded sample of sites."""
+    import numpy as np
+    import oracle
+    oracle.build(force=False)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+    rng = np.random.default_rng(5)
+    k = 64
+    elapsed = 0.0
+    while True:
+        sample = np.sort(rng.choice(len(sites), size=k, replace=False)).astype(np.int32)
+        t0 = time.perf_counter()
+        oracle.compute(sites, dom, only_sites=sample, threads=threads)
+        elapsed = time.perf_counter() - t0
+        if elapsed >= target_s / 4 or k >= len(sites):
+            break
+        k = min(len(sites), int(k * max(2.0, min(8.0, (target_s / 2) / max(elapsed, 1e-3)))))
+    return {"value": k / elapsed, "unit": "cells/s", "cores": threads, "kind": "oracle",
+            "sample": f"{k} sites drawn uniformly from the workload, all their pieces, "
+                      f"{elapsed:.2f} s wall on {threads} threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3"])
+    ap.add_argument("--rho", type=float, default=None, help="grid sites per cell")
+    ap.add_argument("--no-emit", action="store_true", help="skip writing per-piece polytopes")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on exactly one GPU (asked for {args.gpus}); "
+              "the multi-GPU design is described in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2509_07175_amd as vd
+
+    vd.load()
+    sites, dom, desc, rho_default = workload(args.workload)
+    rho = args.rho if args.rho is not None else rho_default
+    n = len(sites)
+    dev = torch.device("cuda:0")
+    s = torch.as_tensor(sites, dtype=torch.float64, device=dev).contiguous()
+    d = vd.Domain.from_vdgen(dom)
+    opts = vd.Options.default(time_kernels=1, emit_polytopes=0 if args.no_emit else 1)
+    grid, cells = vd.Grid(), vd.Cells()
+    mass = torch.empty(n, dtype=torch.float64, device=dev)
+    cent = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    en = torch.empty(n, dtype=torch.float64, device=dev)
+    bbox = (0.0, 0.0, 0.0, 1.0, 1.0, 1.0)
+
+    def step():
+        vd.build_grid(s, bbox=bbox, sites_per_cell=rho, grid=grid)
+        vd.clip_cells(grid, d, opts, cells=cells)
+        cells.moments(mass, cent, en)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    carve = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+        carve.append(cells.info()["carve_ms"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    info = cells.info()
+    ms = 1e3 * wall / args.steps
+    carve_ms = float(np.mean(carve))
+    flops = FLOPS_PER_CANDIDATE * info["candidates"]
+    achieved = flops / (carve_ms * 1e-3) / 1e12
+    total_mass = float(mass.sum().item())
+
+    out = {
+        "metric": "clipped Voronoi cells/s at 1M 3D sites; batched & backward vs plain on same GPU",
+        "value": n / (ms * 1e-3),
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "sites": n, "tetrahedra": int(dom.m), "grid_sites_per_cell": rho,
+                   "emit_polytopes": not args.no_emit},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "clip3d_kernel", "kernel_ms": carve_ms},
+        "counters": {"pieces": info["n_pieces"], "nn_queries": info["nn_queries"], "clips": info["clips"],
+                     "candidates": info["candidates"], "queries_per_cell": info["nn_queries"] / n,
+                     "mass_sum": total_mass},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sites, dom)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -63,6 +63,8 @@ typedef struct {
   int32_t max_search_iters;   /* cap of the bisector search and of the lambda loop */
   int32_t emit_polytopes;     /* 1: write per-piece faces and vertices */
   int32_t want_grad;          /* 1: also store the face integrals the adjoint needs */
+  int32_t time_kernels;       /* 1: record hipEvents around the carve kernel (see
+                                 vd_cells_info_t.carve_ms) */
 } vd_options;
 
 void vd_options_default(vd_options *opt);
@@ -136,6 +138,9 @@ typedef struct {
   int64_t candidates;  /* sites examined by the nearest-site queries */
   int32_t first_bad_site; /* -1, or a site whose carve hit a capacity/degeneracy */
   int32_t status;         /* vd_status of the last clip */
+  double carve_ms;        /* duration of the carve kernel of the last clip, measured
+                             with hipEvents on the caller's stream (time_kernels = 1),
+                             else -1 */
 } vd_cells_info_t;
 
 /* Host struct of sizes and counters (synchronises `stream` of the last call). */

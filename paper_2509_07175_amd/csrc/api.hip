@@ -96,6 +96,7 @@ void vd_options_default(vd_options *opt) {
   opt->max_search_iters = 64;
   opt->emit_polytopes = 1;
   opt->want_grad = 0;
+  opt->time_kernels = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -399,15 +400,24 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
     hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, st, d.cnt);
     GridView G = g->view();
     DomainView D = dom->view();
-    if (dom->dim == 3) {
-      vd_launch_locate_sites(G, D, d.seed, d.cnt, st);
-      vd_launch_clip3d(G, D, d, st);
-    } else {
-      vd_launch_surface(G, D, d, st);
+    if (opt.time_kernels && !c->ev0) {
+      HIP_TRY(hipEventCreate(&c->ev0));
+      HIP_TRY(hipEventCreate(&c->ev1));
     }
+    if (dom->dim == 3) vd_launch_locate_sites(G, D, d.seed, d.cnt, st);
+    if (opt.time_kernels) HIP_TRY(hipEventRecord(c->ev0, st));
+    if (dom->dim == 3) vd_launch_clip3d(G, D, d, st);
+    else vd_launch_surface(G, D, d, st);
+    if (opt.time_kernels) HIP_TRY(hipEventRecord(c->ev1, st));
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(c->host_cnt, d.cnt, sizeof(unsigned long long) * CNT_N, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    c->carve_ms = -1.0;
+    if (opt.time_kernels) {
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+      c->carve_ms = ms;
+    }
     const unsigned long long *hc = c->host_cnt;
     bool grow = false;
     Caps need = want;
@@ -458,6 +468,8 @@ void vd_cells_free(vd_cells c) {
   hipFree(d.piece_vstart); hipFree(d.piece_mass); hipFree(d.piece_mom); hipFree(d.piece_energy);
   hipFree(d.face_label); hipFree(d.vert_xyz); hipFree(d.vert_label); hipFree(d.fint); hipFree(d.seed);
   hipFree(c->piece_off); hipFree(c->nbr_off); hipFree(c->piece_id); hipFree(c->nbr); hipFree(c->scan_tmp);
+  if (c->ev0) hipEventDestroy(c->ev0);
+  if (c->ev1) hipEventDestroy(c->ev1);
   delete c;
 }
 
@@ -474,6 +486,7 @@ vd_status vd_cells_info(vd_cells c, vd_cells_info_t *info) {
   info->candidates = (int64_t)hc[CNT_CANDS];
   info->first_bad_site = c->first_bad;
   info->status = c->status;
+  info->carve_ms = c->carve_ms;
   return VD_OK;
 }
 

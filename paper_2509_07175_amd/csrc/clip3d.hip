@@ -362,6 +362,22 @@ __global__ void __launch_bounds__(64) clip3d_kernel(GridView G, DomainView D, Ce
       if (ps >= 0) { A[0] = S.cy[ps][0]; A[1] = S.cy[ps][1]; A[2] = S.cy[ps][2]; }
       double g[3] = {S.cy[pt][0], S.cy[pt][1], S.cy[pt][2]};
       int j = S.cnn[pt];
+      // Flags of a point on the edge p_s p_t: the two planes of the edge
+      // (Sec. 4.1 flag rule).  A search point whose nearest site is named by
+      // one of them lies on that face of Omega_i, i.e. inside.
+      int ef0 = -2, ef1 = -2;
+      if (ps >= 0) {
+        const int a0 = S.cpl[ps], b0 = S.cpl[pt];
+        int ne = 0;
+        for (int x = 0; x < 3; x++) {
+          const int px = p8(a0, x);
+          if (px == p8(b0, 0) || px == p8(b0, 1) || px == p8(b0, 2)) {
+            const int lab = S.plab[px];
+            if (ne == 0) ef0 = lab >= 0 ? lab : -2; else ef1 = lab >= 0 ? lab : -2;
+            ne++;
+          }
+        }
+      }
       // ---- improved search (Sec. 6.1): g = A + lambda*delta*u, lambda = 2, 3, ...
       if (C.improved) {
         const double d0 = g[0] - A[0], d1 = g[1] - A[1], d2 = g[2] - A[2];
@@ -376,7 +392,7 @@ __global__ void __launch_bounds__(64) clip3d_kernel(GridView G, DomainView D, Ce
             double dd;
             const int k = nn_query(G, qx, qy, qz, ex * ex + ey * ey + ez * ez, si, dd, st.cands);
             st.queries++;
-            if (k != si) { j = k; g[0] = gx; g[1] = gy; g[2] = gz; break; }
+            if (k != si && k != ef0 && k != ef1) { j = k; g[0] = gx; g[1] = gy; g[2] = gz; break; }
           }
         }
       }
@@ -397,7 +413,8 @@ __global__ void __launch_bounds__(64) clip3d_kernel(GridView G, DomainView D, Ce
         double dd;
         const int k = nn_query(G, qx, qy, qz, ex * ex + ey * ey + ez * ez, si, dd, st.cands);
         st.queries++;
-        if (k == si || k == j) break;  // q lies on the boundary of Omega_i: B_ij found
+        // q lies on the boundary of Omega_i: B_ij is a face of the cell
+        if (k == si || k == j || k == ef0 || k == ef1) break;
         j = k;
         g[0] = A[0] + t * e0; g[1] = A[1] + t * e1; g[2] = A[2] + t * e2;
       }
@@ -513,7 +530,8 @@ __global__ void __launch_bounds__(64) clip3d_kernel(GridView G, DomainView D, Ce
         }
       } else if (lab > VD_BND_BASE + 3) {
         const int b = -lab - 1;
-        const bool have = (l < nt && S.tq[l] == b);
+        bool have = false;
+        for (int e = l; e < nt; e += 64) have = have || (S.tq[e] == b);
         if (!__ballot(have)) {
           if (nt >= VD_Q_MAX) { err = 2; break; }
           __syncthreads();
@@ -545,7 +563,8 @@ __global__ void __launch_bounds__(64) clip3d_kernel(GridView G, DomainView D, Ce
   ps0 = __shfl(ps0, 0, 64);
   ns0 = __shfl(ns0, 0, 64);
   __syncthreads();
-  if (ps0 + npieces <= C.cap_plist && l < npieces) C.plist[ps0 + l] = S.pid[l];
+  if (ps0 + npieces <= C.cap_plist)
+    for (int e = l; e < npieces; e += 64) C.plist[ps0 + e] = S.pid[e];
   if (ns0 + nnb <= C.cap_nbr) {
     // neighbours in ascending caller index: rank sort
     for (int h = 0; h < 2; h++) {

@@ -11,7 +11,7 @@
 // ---------------------------------------------------------------------------
 #define VD_P_MAX 64    // planes of one intermediate polytope
 #define VD_C_MAX 128   // corners (two slots per lane)
-#define VD_Q_MAX 64    // tetrahedra visited for one site
+#define VD_Q_MAX 256   // tetrahedra visited for one site (4 per lane)
 #define VD_NB_MAX 96   // distinct neighbours of one site
 
 // device counters written by the clip kernels (one atomic per wave per field)
@@ -112,6 +112,8 @@ struct vd_cells_s {
   vd_grid grid = nullptr;
   int status = 0;
   int first_bad = -1;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;  // carve kernel timing (time_kernels)
+  double carve_ms = -1.0;
 };
 
 // launchers (defined in the .hip files)
