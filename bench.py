@@ -67,6 +67,9 @@ def main():
     ap.add_argument("--rho", type=float, default=None, help="grid sites per cell")
     ap.add_argument("--no-emit", action="store_true", help="skip writing per-piece polytopes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--carve-mode", type=int, default=1, choices=[0, 1])
+    ap.add_argument("--improved", type=int, default=1, choices=[0, 1])
+    ap.add_argument("--straddle", type=int, default=1, choices=[0, 1])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU (asked for {args.gpus}); "
@@ -85,7 +88,9 @@ def main():
     dev = torch.device("cuda:0")
     s = torch.as_tensor(sites, dtype=torch.float64, device=dev).contiguous()
     d = vd.Domain.from_vdgen(dom)
-    opts = vd.Options.default(time_kernels=1, emit_polytopes=0 if args.no_emit else 1)
+    opts = vd.Options.default(time_kernels=1, emit_polytopes=0 if args.no_emit else 1,
+                              carve_mode=args.carve_mode, improved_search=args.improved,
+                              use_straddle_edges=args.straddle)
     grid, cells = vd.Grid(), vd.Cells()
     mass = torch.empty(n, dtype=torch.float64, device=dev)
     cent = torch.empty((n, 3), dtype=torch.float64, device=dev)
@@ -100,18 +105,23 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    carve = []
+    carve, split = [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
-        carve.append(cells.info()["carve_ms"])
+        inf = cells.info()
+        carve.append(inf["carve_ms"])
+        split.append(inf["split_ms"])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     info = cells.info()
     ms = 1e3 * wall / args.steps
     carve_ms = float(np.mean(carve))
+    split_ms = float(np.mean(split))
+    # the dominant kernel: the cell carve (cell-first) or the per-piece kernel
+    dom_ms, dom_name = (carve_ms, "cell_kernel") if carve_ms >= split_ms else (split_ms, "piece_kernel")
     flops = FLOPS_PER_CANDIDATE * info["candidates"]
-    achieved = flops / (carve_ms * 1e-3) / 1e12
+    achieved = flops / (dom_ms * 1e-3) / 1e12
     total_mass = float(mass.sum().item())
 
     out = {
@@ -128,10 +138,12 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": desc, "sites": n, "tetrahedra": int(dom.m), "grid_sites_per_cell": rho,
-                   "emit_polytopes": not args.no_emit},
+                   "emit_polytopes": not args.no_emit, "carve_mode": args.carve_mode,
+                   "improved_search": args.improved, "straddle_edges": args.straddle},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "clip3d_kernel", "kernel_ms": carve_ms},
+                     "kernel": dom_name, "kernel_ms": dom_ms, "cell_kernel_ms": carve_ms,
+                     "piece_kernel_ms": split_ms},
         "counters": {"pieces": info["n_pieces"], "nn_queries": info["nn_queries"], "clips": info["clips"],
                      "candidates": info["candidates"], "queries_per_cell": info["nn_queries"] / n,
                      "mass_sum": total_mass},

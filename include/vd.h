@@ -56,7 +56,8 @@ typedef struct vd_cells_s *vd_cells;
 
 /* Tuning and behaviour knobs; vd_options_default() fills the defaults. */
 typedef struct {
-  double sites_per_cell;   /* grid density; <= 0 -> 3.5 (3D, Sec. 6.2) */
+  double sites_per_cell;   /* unused by vd_clip_cells (the grid density is an argument
+                              of vd_build_grid); kept for callers that store it here */
   int32_t improved_search; /* 1: shorten search edges by lambda*delta steps (Sec. 6.1) */
   int32_t use_straddle_edges; /* 1: prefer edges with one inside end (Alg. 1);
                                  0: virtual edges from the site only (Alg. 3) */
@@ -65,6 +66,12 @@ typedef struct {
   int32_t want_grad;          /* 1: also store the face integrals the adjoint needs */
   int32_t time_kernels;       /* 1: record hipEvents around the carve kernel (see
                                  vd_cells_info_t.carve_ms) */
+  int32_t carve_mode;         /* tetrahedral domains.  0: every piece T_a cap Omega_i is
+                                 carved by point-in-cell tests and the bisector search.
+                                 1 (default): the cell is carved once from the padded
+                                 bounding box of the domain (Sec. 5.2), then each piece is
+                                 T_a cut by the cell's certified bisector facets.  Both
+                                 give the same pieces. */
 } vd_options;
 
 void vd_options_default(vd_options *opt);
@@ -138,9 +145,10 @@ typedef struct {
   int64_t candidates;  /* sites examined by the nearest-site queries */
   int32_t first_bad_site; /* -1, or a site whose carve hit a capacity/degeneracy */
   int32_t status;         /* vd_status of the last clip */
-  double carve_ms;        /* duration of the carve kernel of the last clip, measured
-                             with hipEvents on the caller's stream (time_kernels = 1),
-                             else -1 */
+  double carve_ms;        /* durations of the last clip's kernels, measured with hipEvents
+                             on the caller's stream when time_kernels = 1 (else -1):
+                             the cell carve (cell-first mode; 0 otherwise) ... */
+  double split_ms;        /* ... and the piece kernel (tetrahedra) or surface kernel */
 } vd_cells_info_t;
 
 /* Host struct of sizes and counters (synchronises `stream` of the last call). */
@@ -149,7 +157,7 @@ vd_status vd_cells_info(vd_cells c, vd_cells_info_t *info_host);
 /* Device pointers into library memory, valid until the next vd_clip_cells on
  * the same handle or vd_cells_free.  Sites and simplices use the caller's
  * indices.  Pieces of site i are piece_id[cell_piece_off[i] .. cell_piece_off[i+1]),
- * in the order they were carved; per piece p (an index into the piece arrays):
+ * per piece p (an index into the piece arrays):
  *   piece_site[p], piece_simplex[p], piece_mass[p], piece_moment[3p..] (first
  *   moment, absolute coordinates), piece_energy[p],
  *   faces face_label[piece_face_start[p] + k], k < piece_nface[p],
@@ -157,6 +165,7 @@ vd_status vd_cells_info(vd_cells c, vd_cells_info_t *info_host);
  *   (the labels of the vertex's three planes, counter-clockwise seen from
  *   outside; for triangles the vertex lies on two edges and the third label
  *   is INT32_MAX), k < piece_nvert[p].
+ * Pieces of one site are listed by ascending simplex index.
  * Neighbours of site i: nbr[nbr_off[i] .. nbr_off[i+1]), ascending. */
 typedef struct {
   int64_t n_sites, n_pieces;

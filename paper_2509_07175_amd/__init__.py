@@ -38,7 +38,8 @@ class VDError(RuntimeError):
 class Options(C.Structure):
     _fields_ = [("sites_per_cell", C.c_double), ("improved_search", C.c_int32),
                 ("use_straddle_edges", C.c_int32), ("max_search_iters", C.c_int32),
-                ("emit_polytopes", C.c_int32), ("want_grad", C.c_int32), ("time_kernels", C.c_int32)]
+                ("emit_polytopes", C.c_int32), ("want_grad", C.c_int32), ("time_kernels", C.c_int32),
+                ("carve_mode", C.c_int32)]
 
     @classmethod
     def default(cls, **kw) -> "Options":
@@ -55,7 +56,8 @@ class _Info(C.Structure):
     _fields_ = [("n_sites", C.c_int64), ("n_pieces", C.c_int64), ("n_faces", C.c_int64),
                 ("n_verts", C.c_int64), ("n_nbrs", C.c_int64), ("nn_queries", C.c_int64),
                 ("clips", C.c_int64), ("candidates", C.c_int64), ("first_bad_site", C.c_int32),
-                ("status", C.c_int32), ("carve_ms", C.c_double)]
+                ("status", C.c_int32), ("carve_ms", C.c_double),
+                ("split_ms", C.c_double)]
 
 
 class _View(C.Structure):

@@ -97,6 +97,7 @@ void vd_options_default(vd_options *opt) {
   opt->emit_polytopes = 1;
   opt->want_grad = 0;
   opt->time_kernels = 0;
+  opt->carve_mode = 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -239,6 +240,7 @@ vd_status vd_domain_create(const double *verts, int64_t nv, const int32_t *simpl
   double tot = 0;
   for (double v : hmeas) tot += v;
   D->area = tot;
+  for (int a = 0; a < 6; a++) D->bbox[a] = hbox[a];
   if (simplex_dim == 3) {
     // location grid: about 2 tetrahedra per cell over the vertex bounding box
     double ext[3], vol = 1;
@@ -287,7 +289,7 @@ void vd_domain_free(vd_domain D) {
 namespace {
 
 struct Caps {
-  int64_t piece, face, vert, plist, nbr, fint;
+  int64_t piece, face, vert, nbr, fint;
 };
 
 hipError_t alloc_cells(vd_cells c, int64_t n, const Caps &want) {
@@ -306,6 +308,9 @@ hipError_t alloc_cells(vd_cells c, int64_t n, const Caps &want) {
     t = 0; if ((e = ensure(c->piece_off, t, n + 1)) != hipSuccess) return e;
     t = 0; if ((e = ensure(c->nbr_off, t, n + 1)) != hipSuccess) return e;
     t = 0; if ((e = ensure(c->scan_tmp, t, n / 1024 + 2)) != hipSuccess) return e;
+    t = 0; if ((e = ensure(c->fillc, t, n)) != hipSuccess) return e;
+    t = 0; if ((e = ensure(d.nfacet, t, n)) != hipSuccess) return e;
+    t = 0; if ((e = ensure(d.facet, t, (int64_t)VD_F_MAX * n)) != hipSuccess) return e;
     c->cap_n = n;
   }
   if ((e = ensure_fixed(d.cnt, CNT_N)) != hipSuccess) return e;
@@ -321,15 +326,9 @@ hipError_t alloc_cells(vd_cells c, int64_t n, const Caps &want) {
     t = 0; if ((e = ensure(d.piece_mass, t, want.piece)) != hipSuccess) return e;
     t = 0; if ((e = ensure(d.piece_mom, t, 3 * want.piece)) != hipSuccess) return e;
     t = 0; if ((e = ensure(d.piece_energy, t, want.piece)) != hipSuccess) return e;
+    t = 0; if ((e = ensure(c->piece_id, t, want.piece)) != hipSuccess) return e;
     d.cap_piece = want.piece;
-  }
-  if (d.cap_plist < want.plist) {
-    int64_t t = 0;
-    if ((e = ensure(d.plist, t, want.plist)) != hipSuccess) return e;
-    t = 0;
-    if ((e = ensure(c->piece_id, t, want.plist)) != hipSuccess) return e;
-    d.cap_plist = want.plist;
-    c->cap_pid = want.plist;
+    c->cap_pid = want.piece;
   }
   if (d.cap_nbr < want.nbr) {
     int64_t t = 0;
@@ -380,7 +379,6 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
   };
   Caps want;
   want.piece = std::max<int64_t>(std::max<int64_t>(c->d.cap_piece, 6 * n + 1024), dom->dim == 2 ? 2 * dom->m + 6 * n : 0);
-  want.plist = std::max<int64_t>(c->d.cap_plist, want.piece);
   want.nbr = std::max<int64_t>(c->d.cap_nbr, 20 * n + 1024);
   want.face = opt.emit_polytopes ? std::max<int64_t>(c->d.cap_face, 10 * want.piece) : 0;
   want.vert = opt.emit_polytopes ? std::max<int64_t>(c->d.cap_vert, 16 * want.piece) : 0;
@@ -397,38 +395,54 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
     d.improved = opt.improved_search ? 1 : 0;
     d.straddle = opt.use_straddle_edges ? 1 : 0;
     d.max_iters = opt.max_search_iters;
+    d.mode = (dom->dim == 3 && opt.carve_mode == 1) ? 1 : 0;
+    for (int a = 0; a < 3; a++) {
+      // the box strictly contains the domain so no box plane meets a simplex
+      const double ext = dom->bbox[3 + a] - dom->bbox[a];
+      const double pad = 1e-3 * std::max(ext, 1e-12) + 1e-9;
+      d.box_lo[a] = dom->bbox[a] - pad;
+      d.box_hi[a] = dom->bbox[3 + a] + pad;
+    }
     hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, st, d.cnt);
     GridView G = g->view();
     DomainView D = dom->view();
     if (opt.time_kernels && !c->ev0) {
       HIP_TRY(hipEventCreate(&c->ev0));
       HIP_TRY(hipEventCreate(&c->ev1));
+      HIP_TRY(hipEventCreate(&c->ev2));
+    }
+    if (!c->d_dev) HIP_TRY(hipMalloc((void **)&c->d_dev, sizeof(CellsDev)));
+    if (std::memcmp(&c->d_shadow, &d, sizeof(CellsDev)) != 0) {
+      c->d_shadow = d;
+      HIP_TRY(hipMemcpyAsync(c->d_dev, &c->d_shadow, sizeof(CellsDev), hipMemcpyHostToDevice, st));
     }
     if (dom->dim == 3) vd_launch_locate_sites(G, D, d.seed, d.cnt, st);
     if (opt.time_kernels) HIP_TRY(hipEventRecord(c->ev0, st));
-    if (dom->dim == 3) vd_launch_clip3d(G, D, d, st);
-    else vd_launch_surface(G, D, d, st);
+    if (dom->dim == 3 && d.mode == 1) vd_launch_cells3d(G, d, st);
     if (opt.time_kernels) HIP_TRY(hipEventRecord(c->ev1, st));
+    if (dom->dim == 3) vd_launch_pieces3d(G, D, c->d_dev, d.mode == 0, st);
+    else vd_launch_surface(G, D, d, st);
+    if (opt.time_kernels) HIP_TRY(hipEventRecord(c->ev2, st));
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(c->host_cnt, d.cnt, sizeof(unsigned long long) * CNT_N, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    c->carve_ms = -1.0;
+    c->carve_ms = c->split_ms = -1.0;
     if (opt.time_kernels) {
       float ms = 0.f;
       HIP_TRY(hipEventElapsedTime(&ms, c->ev0, c->ev1));
       c->carve_ms = ms;
+      HIP_TRY(hipEventElapsedTime(&ms, c->ev1, c->ev2));
+      c->split_ms = ms;
     }
     const unsigned long long *hc = c->host_cnt;
     bool grow = false;
     Caps need = want;
     auto up = [](int64_t used) { return used + used / 4 + 1024; };
     if ((int64_t)hc[CNT_PIECES] > d.cap_piece) { need.piece = up(hc[CNT_PIECES]); grow = true; }
-    if ((int64_t)hc[CNT_PLIST] > d.cap_plist) { need.plist = up(hc[CNT_PLIST]); grow = true; }
     if ((int64_t)hc[CNT_NBRS] > d.cap_nbr) { need.nbr = up(hc[CNT_NBRS]); grow = true; }
     if (opt.emit_polytopes && (int64_t)hc[CNT_FACES] > d.cap_face) { need.face = up(hc[CNT_FACES]); grow = true; }
     if (opt.emit_polytopes && (int64_t)hc[CNT_VERTS] > d.cap_vert) { need.vert = up(hc[CNT_VERTS]); grow = true; }
     if (opt.want_grad && (int64_t)hc[CNT_FINT] > d.cap_fint) { need.fint = up(hc[CNT_FINT]); grow = true; }
-    need.plist = std::max(need.plist, need.piece);
     if (grow) { want = need; continue; }
     int bad = (int)(hc[CNT_BAD_SITE] & 0xffffffffull);
     c->first_bad = bad == 0x7fffffff ? -1 : bad;
@@ -463,13 +477,15 @@ void vd_cells_free(vd_cells c) {
   if (!c) return;
   CellsDev &d = c->d;
   hipFree(d.cnt); hipFree(d.mass); hipFree(d.mom); hipFree(d.energy); hipFree(d.pcount); hipFree(d.ncount);
-  hipFree(d.pstart); hipFree(d.nstart); hipFree(d.plist); hipFree(d.nbr_arena); hipFree(d.piece_site);
+  hipFree(d.pstart); hipFree(d.nstart); hipFree(d.nbr_arena); hipFree(d.piece_site); hipFree(c->fillc);
   hipFree(d.piece_simplex); hipFree(d.piece_nface); hipFree(d.piece_nvert); hipFree(d.piece_fstart);
   hipFree(d.piece_vstart); hipFree(d.piece_mass); hipFree(d.piece_mom); hipFree(d.piece_energy);
   hipFree(d.face_label); hipFree(d.vert_xyz); hipFree(d.vert_label); hipFree(d.fint); hipFree(d.seed);
   hipFree(c->piece_off); hipFree(c->nbr_off); hipFree(c->piece_id); hipFree(c->nbr); hipFree(c->scan_tmp);
   if (c->ev0) hipEventDestroy(c->ev0);
   if (c->ev1) hipEventDestroy(c->ev1);
+  if (c->ev2) hipEventDestroy(c->ev2);
+  hipFree(c->d_dev); hipFree(d.facet); hipFree(d.nfacet);
   delete c;
 }
 
@@ -487,6 +503,7 @@ vd_status vd_cells_info(vd_cells c, vd_cells_info_t *info) {
   info->first_bad_site = c->first_bad;
   info->status = c->status;
   info->carve_ms = c->carve_ms;
+  info->split_ms = c->split_ms;
   return VD_OK;
 }
 

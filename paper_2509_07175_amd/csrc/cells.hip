@@ -25,6 +25,31 @@ __global__ void __launch_bounds__(kB) gather_lists(long long n, const int *__res
   for (int k = 0; k < c; k++) out[o + k] = arena[s + k];
 }
 
+__global__ void __launch_bounds__(kB) scatter_pieces(long long np, const int *__restrict__ site,
+                                                     const long long *__restrict__ off, int *__restrict__ fill,
+                                                     int *__restrict__ out) {
+  const long long p = (long long)blockIdx.x * kB + threadIdx.x;
+  if (p >= np) return;
+  const int s = site[p];
+  out[off[s] + atomicAdd(&fill[s], 1)] = (int)p;
+}
+
+// each site's pieces by ascending simplex index (insertion sort: a site has a
+// few dozen pieces at most)
+__global__ void __launch_bounds__(kB) sort_segments(long long n, const long long *__restrict__ off,
+                                                    const int *__restrict__ simplex, int *__restrict__ ids) {
+  const long long i = (long long)blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+  const long long a = off[i], b = off[i + 1];
+  for (long long x = a + 1; x < b; x++) {
+    const int id = ids[x];
+    const int key = simplex[id];
+    long long y = x - 1;
+    while (y >= a && simplex[ids[y]] > key) { ids[y + 1] = ids[y]; y--; }
+    ids[y + 1] = id;
+  }
+}
+
 __global__ void __launch_bounds__(kB) moments_kernel(long long n, const int *__restrict__ rank,
                                                      const double *__restrict__ sx, const double *__restrict__ sy,
                                                      const double *__restrict__ sz, const double *__restrict__ mass,
@@ -53,13 +78,19 @@ __global__ void __launch_bounds__(kB) moments_kernel(long long n, const int *__r
 
 }  // namespace
 
+void vd_launch_fill_int(int *p, long long n, int v, hipStream_t st);
+
 void vd_launch_finalize(vd_cells c, hipStream_t st) {
   const long long n = c->n;
   const CellsDev &d = c->d;
+  const long long npieces = (long long)c->host_cnt[CNT_PIECES];
+  // pieces: counting sort by site, then by simplex inside each site
   vdscan::exclusive_scan<int, long long>(d.pcount, n, c->piece_off, c->scan_tmp, st);
-  hipLaunchKernelGGL(gather_lists, dim3(blocks(n)), dim3(kB), 0, st, n, (const int *)d.pcount,
-                     (const long long *)d.pstart, (const int *)d.plist, (const long long *)c->piece_off,
-                     c->piece_id);
+  vd_launch_fill_int(c->fillc, n, 0, st);
+  hipLaunchKernelGGL(scatter_pieces, dim3(blocks(npieces)), dim3(kB), 0, st, npieces, (const int *)d.piece_site,
+                     (const long long *)c->piece_off, c->fillc, c->piece_id);
+  hipLaunchKernelGGL(sort_segments, dim3(blocks(n)), dim3(kB), 0, st, n, (const long long *)c->piece_off,
+                     (const int *)d.piece_simplex, c->piece_id);
   vdscan::exclusive_scan<int, long long>(d.ncount, n, c->nbr_off, c->scan_tmp, st);
   hipLaunchKernelGGL(gather_lists, dim3(blocks(n)), dim3(kB), 0, st, n, (const int *)d.ncount,
                      (const long long *)d.nstart, (const int *)d.nbr_arena, (const long long *)c->nbr_off,

@@ -1,28 +1,40 @@
 // clip3d.hip -- clipped Voronoi cells in a tetrahedral domain, one wavefront
 // per site.
 //
-// For site v_i the wave visits the tetrahedra of its cell breadth-first through
-// negative face flags, starting at the tetrahedron that contains v_i (the
-// propagation of Alg. 5).  Each piece P_{a,i} = T_a cap Omega_i is carved as in
-// Alg. 1 / Alg. 3:
-//   * every corner is classified by the point-in-cell test (Sec. 4.1, Eq. 2):
-//     inside iff its nearest site is v_i or one of the sites named by the flags
-//     of the faces through the corner;
-//   * while some corner is outside, a search edge is chosen: an edge from an
-//     inside corner to an outside one (Alg. 1), else the virtual edge from v_i
-//     to the lowest outside corner (Alg. 3);
-//   * the edge is shortened by lambda*delta steps (Sec. 6.1) and the bisector
-//     is found by the edge-based search (Sec. 4.2);
-//   * the clip removes only R_p, the connected outside component containing the
-//     chosen outside corner (Sec. 6.3).
+// Carving (shared by both modes) follows Alg. 1 / Alg. 3:
+//   * a corner is classified by the point-in-cell test (Sec. 4.1, Eq. 2): it is
+//     inside Omega_i iff its nearest site is v_i or a site named by the flag of
+//     one of the corner's planes.  Corners are tested lazily, up to four at a
+//     time (one 16-lane group per query): the loop only needs *some* outside
+//     corner, and corners that a later clip removes are never tested;
+//   * for an outside corner the search edge is an edge from a tested-inside
+//     neighbour (Alg. 1) or else the virtual edge from v_i (Alg. 3); it is
+//     optionally shortened by lambda*delta steps (Sec. 6.1), then the bisector
+//     is found by the edge-based search (Sec. 4.2), where a search point also
+//     counts as inside when its nearest site is named by the flag of a plane
+//     through the search edge;
+//   * the clip removes only R_p, the connected outside component that contains
+//     the chosen outside corner (Sec. 6.3).
+//
+// Modes (vd_options.carve_mode):
+//   0 per-simplex: the tetrahedra of the cell are visited breadth-first through
+//     negative face flags from the tetrahedron containing v_i (the propagation
+//     of Alg. 5) and each piece T_a cap Omega_i is carved as above.
+//   1 cell-first: the cell is carved once from the padded bounding box of the
+//     domain (the simple-domain kernel of Sec. 5.2, which Alg. 5 uses for its
+//     interior sites); every corner of the result is certified inside Omega_i,
+//     so its bisector facets F are exactly the half-spaces that bound the cell
+//     inside the box.  The same propagation then visits the tetrahedra and
+//     each piece is T_a cut by the half-spaces of F: T_a cap Omega_i =
+//     T_a cap cell, with no further point-in-cell test.
 //
 // Polytope layout in LDS (the dual triangle mesh of Sec. 6.3): planes (normal,
 // offset, flag) and corners; a corner stores its three planes in
 // counter-clockwise order seen from outside (det of the outward normals > 0),
 // the corner across each of its three dual edges, its coordinates relative to
-// v_i and its in/out flag.  Lane l owns corner slots l and l+64, so
-// classification, flood fill of R_p, the fan of the new face and compaction
-// are wave-parallel; inside/outside/removed sets are 128-bit ballot masks.
+// v_i and its test state.  Lane l owns corner slots l and l+64, so the flood
+// fill of R_p, the fan of the new face and compaction are wave-parallel;
+// tested/inside/removed sets are 128-bit ballot masks.
 //
 // Moments of a piece: a fan of tetrahedra (v_i, foot of the face plane,
 // corner, next corner around the face), three per corner, reduced across the
@@ -31,32 +43,123 @@
 
 namespace {
 
-constexpr int kMaxClips = 256;
+constexpr int kMaxIters = 4096;  // queries + clips of one polytope
+constexpr int kBoxBase = VD_BND_BASE + 16;  // flags of the bounding-box planes (never emitted)
 
 struct __align__(16) WaveLds {
   double pn[VD_P_MAX][4];    // plane: outward normal (relative coords), offset
   double cy[VD_C_MAX][3];    // corner coordinates relative to v_i
-  int plab[VD_P_MAX];        // plane flag: sorted site >= 0, -(b+1), or boundary code
+  double fpn[VD_F_MAX][4];   // cell-first: bisector facets of the cell
+  int plab[VD_P_MAX];        // plane flag: sorted site >= 0, -(b+1), boundary/box code
+  int flab[VD_F_MAX];
   int cpl[VD_C_MAX];         // corner planes a | b << 8 | c << 16 (CCW from outside)
   int cnb[VD_C_MAX];         // corner across a->b | across b->c << 8 | across c->a << 16
-  int cnn[VD_C_MAX];         // nearest site found by the corner's point-in-cell test
-  int cflg[VD_C_MAX];        // bit 0: inside
+  int cst[VD_C_MAX];         // bit 0 inside, bit 1 tested, bits 8.. nearest site + 1
   unsigned char byFirst[VD_P_MAX], bySecond[VD_P_MAX];
   int tq[VD_Q_MAX];          // tetrahedra of this site, breadth-first
-  int pid[VD_Q_MAX];         // arena index of each emitted piece
   int nbl[VD_NB_MAX];        // neighbours found so far (sorted positions)
 };
 
 __device__ __forceinline__ int p8(int packed, int e) { return (packed >> (8 * e)) & 0xff; }
 __device__ __forceinline__ int pack3(int a, int b, int c) { return a | (b << 8) | (c << 16); }
-
-__device__ __forceinline__ uint64_t low_mask(int k) {  // bits [0, k), k in [0, 64]
-  return k >= 64 ? ~0ull : ((1ull << k) - 1ull);
-}
+__device__ __forceinline__ uint64_t low_mask(int k) { return k >= 64 ? ~0ull : ((1ull << k) - 1ull); }
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 struct Stats {
   long long queries = 0, cands = 0, clips = 0;
 };
+
+struct SiteCtx {
+  double vx, vy, vz, delta;
+  int si;
+};
+
+// ---------------------------------------------------------------------------
+// nearest-site query by a group of gs lanes (gs = 64: the whole wave; gs = 16:
+// four independent queries per wave).  q and the known candidate (r2, k0) are
+// uniform within a group.  The candidate box is split into x-rows; a row of
+// consecutive cells is one contiguous range of sorted sites, so the group
+// flattens all rows into one candidate list (coalesced SoA loads).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void scan_box(const GridView &G, int gs, int x0, int x1, int y0, int y1, int z0,
+                                         int z1, double qx, double qy, double qz, double &bd, int &bk,
+                                         long long &ncand) {
+  const int gl = vd_lane() & (gs - 1);
+  const int nx = x1 - x0 + 1, ny = y1 - y0 + 1;
+  const int R = ny * (z1 - z0 + 1);
+  for (int r0 = 0; r0 < R; r0 += gs) {
+    const int r = r0 + gl;
+    int st = 0, cnt = 0;
+    if (r < R) {
+      const int yy = y0 + r % ny, zz = z0 + r / ny;
+      const int c0 = x0 + G.g[0] * (yy + G.g[1] * zz);
+      st = G.cstart[c0];
+      cnt = G.cstart[c0 + nx] - st;
+    }
+    int inc = cnt;
+    for (int d = 1; d < gs; d <<= 1) {
+      const int o = __shfl_up(inc, d, gs);
+      if (gl >= d) inc += o;
+    }
+    const int excl = inc - cnt;
+    const int total = __shfl(inc, gs - 1, gs);
+    const int nrows = (R - r0) < gs ? (R - r0) : gs;
+    ncand += total;
+    for (int base = 0; base < total; base += gs) {
+      const int t = base + gl;
+      int rr = 0;
+      for (int step = gs >> 1; step >= 1; step >>= 1) {
+        const int cand = rr + step;
+        const int v = __shfl(excl, cand & (gs - 1), gs);
+        if (cand < nrows && v <= t) rr = cand;
+      }
+      const int rst = __shfl(st, rr, gs);
+      const int rex = __shfl(excl, rr, gs);
+      if (t < total) {
+        const int p = rst + (t - rex);
+        const double dx = qx - G.sx[p], dy = qy - G.sy[p], dz = qz - G.sz[p];
+        const double d = dx * dx + dy * dy + dz * dz;
+        if (d < bd || (d == bd && p < bk)) { bd = d; bk = p; }
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void group_argmin(double &d, int &k, int gs) {
+  for (int m = gs >> 1; m >= 1; m >>= 1) {
+    const double od = __shfl_xor(d, m, 64);
+    const int ok = __shfl_xor(k, m, 64);
+    if (od < d || (od == d && ok < k)) { d = od; k = ok; }
+  }
+}
+
+__device__ __forceinline__ int nn_query(const GridView &G, int gs, double qx, double qy, double qz, double r2,
+                                        int k0, long long &ncand) {
+  const double lox = G.geom[0], loy = G.geom[1], loz = G.geom[2];
+  const double ihx = G.geom[6], ihy = G.geom[7], ihz = G.geom[8];
+  const int gx = G.g[0], gy = G.g[1], gz = G.g[2];
+  double bd = r2;
+  int bk = k0;
+  const int cx = cell_coord(qx, lox, ihx, gx), cy = cell_coord(qy, loy, ihy, gy), cz = cell_coord(qz, loz, ihz, gz);
+  double r = sqrt(r2);
+  // phase 1: the 3x3x3 block around q's cell, trimmed to the ball of radius r
+  const int x0 = max(cx - 1, cell_coord(qx - r, lox, ihx, gx)), x1 = min(cx + 1, cell_coord(qx + r, lox, ihx, gx));
+  const int y0 = max(cy - 1, cell_coord(qy - r, loy, ihy, gy)), y1 = min(cy + 1, cell_coord(qy + r, loy, ihy, gy));
+  const int z0 = max(cz - 1, cell_coord(qz - r, loz, ihz, gz)), z1 = min(cz + 1, cell_coord(qz + r, loz, ihz, gz));
+  scan_box(G, gs, x0, x1, y0, y1, z0, z1, qx, qy, qz, bd, bk, ncand);
+  group_argmin(bd, bk, gs);
+  // phase 2: the whole box of the best ball if it leaves the scanned block
+  // (the best radius only shrinks, so once suffices)
+  r = sqrt(bd);
+  const int X0 = cell_coord(qx - r, lox, ihx, gx), X1 = cell_coord(qx + r, lox, ihx, gx);
+  const int Y0 = cell_coord(qy - r, loy, ihy, gy), Y1 = cell_coord(qy + r, loy, ihy, gy);
+  const int Z0 = cell_coord(qz - r, loz, ihz, gz), Z1 = cell_coord(qz + r, loz, ihz, gz);
+  if (X0 < x0 || X1 > x1 || Y0 < y0 || Y1 > y1 || Z0 < z0 || Z1 > z1) {
+    scan_box(G, gs, X0, X1, Y0, Y1, Z0, Z1, qx, qy, qz, bd, bk, ncand);
+    group_argmin(bd, bk, gs);
+  }
+  return bk;
+}
 
 // Vertex of three planes by Cramer's rule, planes taken in ascending flag order
 // so a vertex does not depend on the order in which its planes were created.
@@ -77,24 +180,6 @@ __device__ __forceinline__ void solve3(const WaveLds &S, int a, int b, int c, do
   for (int k = 0; k < 3; k++) y[k] = (n0[3] * c12[k] + n1[3] * c20[k] + n2[3] * c01[k]) * id;
 }
 
-// Point-in-cell test of corner s (Sec. 4.1): nearest site of the corner, inside
-// iff it is the site itself or a site named by a flag of the corner's planes.
-__device__ __forceinline__ bool classify(WaveLds &S, const GridView &G, int s, int si, double vx,
-                                         double vy, double vz, Stats &st) {
-  const double y0 = S.cy[s][0], y1 = S.cy[s][1], y2 = S.cy[s][2];
-  const double qx = vx + y0, qy = vy + y1, qz = vz + y2;
-  const double dx = qx - vx, dy = qy - vy, dz = qz - vz;
-  double d2;
-  const int k = nn_query(G, qx, qy, qz, dx * dx + dy * dy + dz * dz, si, d2, st.cands);
-  st.queries++;
-  const int pl = S.cpl[s];
-  const bool in = (k == si) || (k == S.plab[p8(pl, 0)]) || (k == S.plab[p8(pl, 1)]) || (k == S.plab[p8(pl, 2)]);
-  __syncthreads();
-  if (vd_lane() == 0) { S.cnn[s] = k; S.cflg[s] = in ? 1 : 0; }
-  __syncthreads();
-  return in;
-}
-
 // Drop planes that no corner references (keeps slot order).  Returns the new
 // plane count.
 __device__ int compact_planes(WaveLds &S, int npl, int nc) {
@@ -106,7 +191,6 @@ __device__ int compact_planes(WaveLds &S, int npl, int nc) {
   }
   used = wave_or64(used);
   const int newnpl = __popcll(used);
-  // new index of plane x = number of used planes below x
   double pv[4] = {0, 0, 0, 0};
   int lab = 0;
   const bool mine = l < npl && ((used >> l) & 1ull);
@@ -125,10 +209,9 @@ __device__ int compact_planes(WaveLds &S, int npl, int nc) {
   for (int h = 0; h < 2; h++) {
     const int s = l + 64 * h;
     if (s < nc) {
-      int a = p8(cp[h], 0), b = p8(cp[h], 1), c = p8(cp[h], 2);
-      a = __popcll(used & low_mask(a));
-      b = __popcll(used & low_mask(b));
-      c = __popcll(used & low_mask(c));
+      const int a = __popcll(used & low_mask(p8(cp[h], 0)));
+      const int b = __popcll(used & low_mask(p8(cp[h], 1)));
+      const int c = __popcll(used & low_mask(p8(cp[h], 2)));
       S.cpl[s] = pack3(a, b, c);
     }
   }
@@ -137,27 +220,40 @@ __device__ int compact_planes(WaveLds &S, int npl, int nc) {
 }
 
 // Clip by plane slot P, removing R_p: the connected set of corners strictly
-// outside P that contains corner pt (Sec. 6.3).  New corners are created on
-// every dual edge leaving R_p and form the fan of the new face.
-// Returns 0 ok, 1 empty, 2 capacity, 3 degenerate.  On success nc and nsurv
-// (corners kept; new corners are slots [nsurv, nc)) are updated.
-__device__ int clip_poly(WaveLds &S, int P, int pt, int &nc, int &nsurv_out) {
+// outside P that contains corner pt (Sec. 6.3); pt < 0 picks the corner
+// farthest outside (geometric cut).  New corners are created on every dual edge
+// leaving R_p and form the fan of the new face.
+// Returns 0 (nothing outside: unchanged), 1 empty, 2 capacity, 3 degenerate,
+// 4 cut (nc updated).
+__device__ int clip_poly(WaveLds &S, int P, int pt, int &nc) {
   const int l = vd_lane();
   const double nx = S.pn[P][0], ny = S.pn[P][1], nz = S.pn[P][2], c = S.pn[P][3];
-  int pl[2] = {0, 0}, nb[2] = {0, 0}, fl[2] = {0, 0}, nn[2] = {0, 0};
+  int pl[2] = {0, 0}, nb[2] = {0, 0}, cs[2] = {0, 0};
   double y[2][3] = {{0, 0, 0}, {0, 0, 0}};
   bool v[2], o[2];
+  double sd[2] = {-1.0, -1.0};
   for (int h = 0; h < 2; h++) {
     const int s = l + 64 * h;
     v[h] = s < nc;
     if (v[h]) {
-      pl[h] = S.cpl[s]; nb[h] = S.cnb[s]; fl[h] = S.cflg[s]; nn[h] = S.cnn[s];
+      pl[h] = S.cpl[s]; nb[h] = S.cnb[s]; cs[h] = S.cst[s];
       y[h][0] = S.cy[s][0]; y[h][1] = S.cy[s][1]; y[h][2] = S.cy[s][2];
+      sd[h] = nx * y[h][0] + ny * y[h][1] + nz * y[h][2] - c;
     }
-    o[h] = v[h] && (nx * y[h][0] + ny * y[h][1] + nz * y[h][2] - c > 0.0);
+    o[h] = v[h] && sd[h] > 0.0;
   }
   const uint64_t olo = __ballot(o[0]), ohi = __ballot(o[1]);
-  if (!bit128(olo, ohi, pt)) return 3;
+  if (!(olo | ohi)) return pt < 0 ? 0 : 3;
+  if (pt < 0) {
+    // farthest outside corner (ties: lowest slot)
+    double best = -sd[0];
+    int bs = l;
+    if (-sd[1] < best) { best = -sd[1]; bs = l + 64; }
+    group_argmin(best, bs, 64);
+    pt = uni(bs);
+  } else if (!bit128(olo, ohi, pt)) {
+    return 3;
+  }
   uint64_t Rlo = pt < 64 ? (1ull << pt) : 0ull, Rhi = pt >= 64 ? (1ull << (pt - 64)) : 0ull;
   for (int it = 0; it < VD_C_MAX; it++) {
     bool j[2];
@@ -174,7 +270,7 @@ __device__ int clip_poly(WaveLds &S, int P, int pt, int &nc, int &nsurv_out) {
   const int nR = __popcll(Rlo) + __popcll(Rhi);
   if (nR >= nc) return 1;
   bool r[2];
-  int em[2] = {0, 0};  // boundary edges of removed corners
+  int em[2] = {0, 0};
   for (int h = 0; h < 2; h++) {
     const int s = l + 64 * h;
     r[h] = v[h] && bit128(Rlo, Rhi, s);
@@ -202,9 +298,8 @@ __device__ int clip_poly(WaveLds &S, int P, int pt, int &nc, int &nsurv_out) {
     for (int h = 0; h < 2; h++)
       for (int e = 0; e < 3; e++)
         if (em[h] & (1 << e)) {
-          const int u = p8(pl[h], e), w = p8(pl[h], (e + 1) % 3);
-          S.byFirst[u] = (unsigned char)(nsurv + t);
-          S.bySecond[w] = (unsigned char)(nsurv + t);
+          S.byFirst[p8(pl[h], e)] = (unsigned char)(nsurv + t);
+          S.bySecond[p8(pl[h], (e + 1) % 3)] = (unsigned char)(nsurv + t);
           t++;
         }
   }
@@ -215,8 +310,7 @@ __device__ int clip_poly(WaveLds &S, int P, int pt, int &nc, int &nsurv_out) {
     for (int h = 0; h < 2; h++)
       for (int e = 0; e < 3; e++)
         if (em[h] & (1 << e)) {
-          const int u = p8(pl[h], e), w = p8(pl[h], (e + 1) % 3);
-          if (S.byFirst[u] != nsurv + t || S.bySecond[w] != nsurv + t) bad = true;
+          if (S.byFirst[p8(pl[h], e)] != nsurv + t || S.bySecond[p8(pl[h], (e + 1) % 3)] != nsurv + t) bad = true;
           t++;
         }
   }
@@ -224,6 +318,7 @@ __device__ int clip_poly(WaveLds &S, int P, int pt, int &nc, int &nsurv_out) {
   // all old corner data sits in registers: write the new layout
   {
     int t = base;
+#pragma unroll 1
     for (int h = 0; h < 2; h++) {
       const int s = l + 64 * h;
       if (v[h] && !r[h]) {
@@ -235,20 +330,18 @@ __device__ int clip_poly(WaveLds &S, int P, int pt, int &nc, int &nsurv_out) {
         }
         S.cpl[ns] = pl[h];
         S.cnb[ns] = pack3(nbo[0], nbo[1], nbo[2]);
-        S.cflg[ns] = fl[h];
-        S.cnn[ns] = nn[h];
+        S.cst[ns] = cs[h];
         S.cy[ns][0] = y[h][0]; S.cy[ns][1] = y[h][1]; S.cy[ns][2] = y[h][2];
       }
       if (r[h])
+#pragma unroll 1
         for (int e = 0; e < 3; e++)
           if (em[h] & (1 << e)) {
             const int u = p8(pl[h], e), w = p8(pl[h], (e + 1) % 3);
             const int ns = nsurv + t;
-            const int m = p8(nb[h], e);
             S.cpl[ns] = pack3(u, w, P);
-            S.cnb[ns] = pack3(rank(m), S.byFirst[w], S.bySecond[u]);
-            S.cflg[ns] = 0;
-            S.cnn[ns] = -1;
+            S.cnb[ns] = pack3(rank(p8(nb[h], e)), S.byFirst[w], S.bySecond[u]);
+            S.cst[ns] = 0;
             double yy[3];
             solve3(S, u, w, P, yy);
             S.cy[ns][0] = yy[0]; S.cy[ns][1] = yy[1]; S.cy[ns][2] = yy[2];
@@ -258,198 +351,402 @@ __device__ int clip_poly(WaveLds &S, int P, int pt, int &nc, int &nsurv_out) {
   }
   __syncthreads();
   nc = nsurv + nnew;
-  nsurv_out = nsurv;
-  return 0;
+  return 4;
 }
 
-__device__ __forceinline__ void masks_inside(const WaveLds &S, int nc, uint64_t &ilo, uint64_t &ihi) {
+__device__ __forceinline__ void state_masks(const WaveLds &S, int nc, uint64_t &tlo, uint64_t &thi,
+                                            uint64_t &ilo, uint64_t &ihi) {
   const int l = vd_lane();
-  const bool a = l < nc && (S.cflg[l] & 1);
-  const bool b = l + 64 < nc && (S.cflg[l + 64] & 1);
-  ilo = __ballot(a);
-  ihi = __ballot(b);
+  const int a = l < nc ? S.cst[l] : 0;
+  const int b = l + 64 < nc ? S.cst[l + 64] : 0;
+  tlo = __ballot(a & 2); thi = __ballot(b & 2);
+  ilo = __ballot(a & 1); ihi = __ballot(b & 1);
 }
 
-__device__ __forceinline__ int convert_label(const GridView &G, int lab) {
-  return lab >= 0 ? G.perm[lab] : lab;
+// Alg. 1 / Alg. 3 on the polytope in LDS until every corner is certified inside
+// Omega_i.  Written as a loop with a single nearest-site query per iteration:
+//   TEST    up to four untested corners, one 16-lane group each (taken when no
+//           tested corner is known to be outside);
+//   LAMBDA  a point A + lambda*delta*u of the improved search (Sec. 6.1);
+//   SEARCH  the crossing of the search edge with B_ij (Sec. 4.2).
+// Returns 0 (done, non-empty), 1 (empty), 2 capacity, 3 degenerate.
+struct CarveParams {
+  int improved, straddle, max_iters;
+};
+
+__device__ int carve(WaveLds &S, const GridView &G, const CarveParams C, const SiteCtx &X, int &npl, int &nc,
+                     Stats &st) {
+  enum { PICK = 0, TEST, LAMBDA, SEARCH };
+  const int l = vd_lane();
+  const int grp = l >> 4;
+  int mode = PICK;
+  int pt = -1, j = -1, ef0 = -2, ef1 = -2, lam = 2, nstep = 0;
+  int tslot = -1, nbatch = 0;
+  double A0 = 0, A1 = 0, A2 = 0, g0 = 0, g1 = 0, g2 = 0, u0 = 0, u1 = 0, u2 = 0, L = 0;
+  double n0 = 0, n1 = 0, n2 = 0, nc3 = 0;
+  double q0 = 0, q1 = 0, q2 = 0;  // query point relative to v_i (per group for TEST)
+  // crossing of [A, g] with B_ij (j = current candidate)
+  auto bisector_point = [&]() {
+    n0 = G.sx[j] - X.vx; n1 = G.sy[j] - X.vy; n2 = G.sz[j] - X.vz;
+    nc3 = 0.5 * (n0 * n0 + n1 * n1 + n2 * n2);
+    const double e0 = g0 - A0, e1 = g1 - A1, e2 = g2 - A2;
+    const double den = n0 * e0 + n1 * e1 + n2 * e2;
+    const double num = nc3 - (n0 * A0 + n1 * A1 + n2 * A2);
+    double t = den > 0.0 ? num / den : 1.0;
+    t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+    q0 = A0 + t * e0; q1 = A1 + t * e1; q2 = A2 + t * e2;
+  };
+  for (int it = 0; it < kMaxIters; it++) {
+    if (mode == PICK) {
+      uint64_t tlo, thi, ilo, ihi;
+      state_masks(S, nc, tlo, thi, ilo, ihi);
+      const uint64_t olo = tlo & ~ilo, ohi = thi & ~ihi;
+      if (!(olo | ohi)) {
+        // no known outside corner: test the next untested ones
+        const uint64_t vlo = low_mask(nc < 64 ? nc : 64), vhi = low_mask(nc > 64 ? nc - 64 : 0);
+        const uint64_t ulo = vlo & ~tlo, uhi = vhi & ~thi;
+        if (!(ulo | uhi)) return 0;
+        tslot = -1;
+        nbatch = 0;
+        uint64_t m = ulo;
+        for (int h = 0; h < 2; h++) {
+          while (m && nbatch < 4) {
+            const int b = __ffsll((unsigned long long)m) - 1;
+            if (nbatch == grp) tslot = b + 64 * h;
+            nbatch++;
+            m &= m - 1;
+          }
+          m = uhi;
+        }
+        const int s = tslot >= 0 ? tslot : (ulo ? __ffsll((unsigned long long)ulo) - 1
+                                                : 64 + __ffsll((unsigned long long)uhi) - 1);
+        q0 = S.cy[s][0]; q1 = S.cy[s][1]; q2 = S.cy[s][2];
+        mode = TEST;
+      } else {
+        // ---- the search edge: from a tested-inside neighbour (Alg. 1) or v_i (Alg. 3)
+        pt = -1;
+        int ps = -1;
+        if (C.straddle) {
+          bool cand[2];
+          for (int h = 0; h < 2; h++) {
+            const int s = l + 64 * h;
+            cand[h] = false;
+            if (bit128(olo, ohi, s)) {
+              const int nbp = S.cnb[s];
+              cand[h] = bit128(ilo, ihi, p8(nbp, 0)) || bit128(ilo, ihi, p8(nbp, 1)) || bit128(ilo, ihi, p8(nbp, 2));
+            }
+          }
+          const uint64_t clo = __ballot(cand[0]), chi = __ballot(cand[1]);
+          if (clo | chi) {
+            pt = clo ? __ffsll((unsigned long long)clo) - 1 : 64 + __ffsll((unsigned long long)chi) - 1;
+            const int nbp = uni(S.cnb[pt]);
+            for (int e = 0; e < 3; e++)
+              if (bit128(ilo, ihi, p8(nbp, e))) { ps = p8(nbp, e); break; }
+          }
+        }
+        if (pt < 0) pt = olo ? __ffsll((unsigned long long)olo) - 1 : 64 + __ffsll((unsigned long long)ohi) - 1;
+        A0 = A1 = A2 = 0;
+        if (ps >= 0) { A0 = S.cy[ps][0]; A1 = S.cy[ps][1]; A2 = S.cy[ps][2]; }
+        g0 = S.cy[pt][0]; g1 = S.cy[pt][1]; g2 = S.cy[pt][2];
+        j = uni((S.cst[pt] >> 8) - 1);
+        if (j < 0 || j == X.si) return 3;
+        // flags of a point on the edge p_s p_t: the two planes through the edge
+        ef0 = ef1 = -2;
+        if (ps >= 0) {
+          const int a0 = uni(S.cpl[ps]), b0 = uni(S.cpl[pt]);
+          int ne = 0;
+          for (int x = 0; x < 3; x++) {
+            const int px = p8(a0, x);
+            if (px == p8(b0, 0) || px == p8(b0, 1) || px == p8(b0, 2)) {
+              const int lab = S.plab[px];
+              if (ne == 0) ef0 = lab >= 0 ? lab : -2; else ef1 = lab >= 0 ? lab : -2;
+              ne++;
+            }
+          }
+          ef0 = uni(ef0); ef1 = uni(ef1);
+        }
+        nstep = 0;
+        const double d0 = g0 - A0, d1 = g1 - A1, d2 = g2 - A2;
+        L = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        if (C.improved && L > 0 && 2.0 * X.delta < L) {
+          u0 = d0 / L; u1 = d1 / L; u2 = d2 / L;
+          lam = 2;
+          q0 = A0 + 2.0 * X.delta * u0; q1 = A1 + 2.0 * X.delta * u1; q2 = A2 + 2.0 * X.delta * u2;
+          mode = LAMBDA;
+        } else {
+          bisector_point();
+          mode = SEARCH;
+        }
+      }
+    }
+    // ---- the one nearest-site query of this iteration ----
+    const int gs = mode == TEST ? 16 : 64;
+    const double qx = X.vx + q0, qy = X.vy + q1, qz = X.vz + q2;
+    const double dx = qx - X.vx, dy = qy - X.vy, dz = qz - X.vz;
+    const int kq = nn_query(G, gs, qx, qy, qz, dx * dx + dy * dy + dz * dz, X.si, st.cands);
+    if (mode == TEST) {
+      st.queries += nbatch;
+      const int pl = tslot >= 0 ? S.cpl[tslot] : 0;
+      const bool in = (kq == X.si) || (kq == S.plab[p8(pl, 0)]) || (kq == S.plab[p8(pl, 1)]) ||
+                      (kq == S.plab[p8(pl, 2)]);
+      __syncthreads();
+      if (tslot >= 0 && (l & 15) == 0) S.cst[tslot] = (in ? 1 : 0) | 2 | ((kq + 1) << 8);
+      __syncthreads();
+      mode = PICK;
+      continue;
+    }
+    st.queries++;
+    const int k = uni(kq);
+    if (mode == LAMBDA) {
+      if (k != X.si && k != ef0 && k != ef1) {
+        j = k; g0 = q0; g1 = q1; g2 = q2;
+      } else {
+        lam++;
+        if (lam < 2 + C.max_iters && lam * X.delta < L) {
+          const double tt = lam * X.delta;
+          q0 = A0 + tt * u0; q1 = A1 + tt * u1; q2 = A2 + tt * u2;
+          continue;
+        }
+      }
+      bisector_point();
+      mode = SEARCH;
+      continue;
+    }
+    // SEARCH: q lies on the boundary of Omega_i -> B_ij is a face of the cell
+    if (!(k == X.si || k == j || k == ef0 || k == ef1)) {
+      if (++nstep >= C.max_iters) return 3;
+      j = k;
+      g0 = q0; g1 = q1; g2 = q2;
+      bisector_point();
+      continue;
+    }
+    // ---- clip by B_ij ----
+    if (npl >= VD_P_MAX) {
+      npl = compact_planes(S, npl, nc);
+      if (npl >= VD_P_MAX) return 2;
+    }
+    const int P = npl++;
+    __syncthreads();
+    if (l == 0) {
+      S.pn[P][0] = n0; S.pn[P][1] = n1; S.pn[P][2] = n2; S.pn[P][3] = nc3;
+      S.plab[P] = j;
+    }
+    __syncthreads();
+    const int rc = clip_poly(S, P, pt, nc);
+    st.clips++;
+    if (rc == 1) return 1;
+    if (rc != 4) return rc == 0 ? 3 : rc;
+    mode = PICK;
+  }
+  return 3;
 }
 
-__global__ void __launch_bounds__(64) clip3d_kernel(GridView G, DomainView D, CellsDev C) {
+// P <- T_a: 4 planes (face f opposite vertex f), 4 corners.  Lane l < 4
+// builds plane l and corner l; the fixed topology of a positively oriented
+// tetrahedron is packed in constants (no indexed local arrays).
+__device__ void init_tet(WaveLds &S, const DomainView &D, const SiteCtx &X, int a, int tested) {
+  const int l = vd_lane();
+  if (l < 4) {
+    const int *tv = &D.simp[(long long)a * 4];
+    // face loops {1,2,3},{0,3,2},{0,1,3},{0,2,1}: 2 bits per vertex, 6 bits per face
+    const unsigned loops = (1u | 2u << 2 | 3u << 4) | (0u | 3u << 2 | 2u << 4) << 6 |
+                           (0u | 1u << 2 | 3u << 4) << 12 | (0u | 2u << 2 | 1u << 4) << 18;
+    const unsigned lf = loops >> (6 * l);
+    const double *pA = &D.verts[3 * (long long)tv[lf & 3]];
+    const double *pB = &D.verts[3 * (long long)tv[(lf >> 2) & 3]];
+    const double *pC = &D.verts[3 * (long long)tv[(lf >> 4) & 3]];
+    const double A0 = pA[0] - X.vx, A1 = pA[1] - X.vy, A2 = pA[2] - X.vz;
+    const double ab0 = pB[0] - pA[0], ab1 = pB[1] - pA[1], ab2 = pB[2] - pA[2];
+    const double ac0 = pC[0] - pA[0], ac1 = pC[1] - pA[1], ac2 = pC[2] - pA[2];
+    const double n0 = ab1 * ac2 - ab2 * ac1, n1 = ab2 * ac0 - ab0 * ac2, n2 = ab0 * ac1 - ab1 * ac0;
+    S.pn[l][0] = n0; S.pn[l][1] = n1; S.pn[l][2] = n2;
+    S.pn[l][3] = n0 * A0 + n1 * A1 + n2 * A2;
+    const int b = D.adj[(long long)a * 4 + l];
+    S.plab[l] = b >= 0 ? -(b + 1) : VD_BND_BASE + l;
+    // corner l = vertex l: planes counter-clockwise from outside
+    // {1,3,2},{0,2,3},{0,3,1},{0,1,2}; neighbours {2,1,3},{3,0,2},{1,0,3},{2,0,1}
+    S.cpl[l] = l == 0 ? pack3(1, 3, 2) : (l == 1 ? pack3(0, 2, 3) : (l == 2 ? pack3(0, 3, 1) : pack3(0, 1, 2)));
+    S.cnb[l] = l == 0 ? pack3(2, 1, 3) : (l == 1 ? pack3(3, 0, 2) : (l == 2 ? pack3(1, 0, 3) : pack3(2, 0, 1)));
+    S.cst[l] = tested ? 3 : 0;
+    const double *p = &D.verts[3 * (long long)tv[l]];
+    S.cy[l][0] = p[0] - X.vx; S.cy[l][1] = p[1] - X.vy; S.cy[l][2] = p[2] - X.vz;
+  }
+  __syncthreads();
+}
+
+// P <- box [lo, hi] (planes x-,x+,y-,y+,z-,z+; corner (bx,by,bz) = 4bx+2by+bz)
+__device__ void init_box(WaveLds &S, const SiteCtx &X, const double *lo, const double *hi) {
+  const int l = vd_lane();
+  if (l < 6) {
+    const int ax = l >> 1, side = l & 1;
+    const double vc = ax == 0 ? X.vx : (ax == 1 ? X.vy : X.vz);
+    const double lov = ax == 0 ? lo[0] : (ax == 1 ? lo[1] : lo[2]);
+    const double hiv = ax == 0 ? hi[0] : (ax == 1 ? hi[1] : hi[2]);
+    S.pn[l][0] = ax == 0 ? (side ? 1.0 : -1.0) : 0.0;
+    S.pn[l][1] = ax == 1 ? (side ? 1.0 : -1.0) : 0.0;
+    S.pn[l][2] = ax == 2 ? (side ? 1.0 : -1.0) : 0.0;
+    S.pn[l][3] = side ? hiv - vc : vc - lov;
+    S.plab[l] = kBoxBase + l;
+  }
+  if (l < 8) {
+    // planes / neighbours of corner l, 4 bits per entry (12 bits per corner)
+    const unsigned long long CP = 0x240ull | 0x520ull << 12 | 0x430ull << 24 | 0x350ull << 36 | 0x421ull << 48;
+    const unsigned long long CP2 = 0x251ull | 0x341ull << 12 | 0x531ull << 24;
+    const unsigned long long CN = 0x142ull | 0x350ull << 12 | 0x063ull << 24 | 0x271ull << 36 | 0x605ull << 48;
+    const unsigned long long CN2 = 0x417ull | 0x724ull << 12 | 0x536ull << 24;
+    const unsigned cpl = l < 5 ? (unsigned)((CP >> (12 * l)) & 0xfff) : (unsigned)((CP2 >> (12 * (l - 5))) & 0xfff);
+    const unsigned cnb = l < 5 ? (unsigned)((CN >> (12 * l)) & 0xfff) : (unsigned)((CN2 >> (12 * (l - 5))) & 0xfff);
+    S.cpl[l] = pack3(cpl & 15, (cpl >> 4) & 15, (cpl >> 8) & 15);
+    S.cnb[l] = pack3(cnb & 15, (cnb >> 4) & 15, (cnb >> 8) & 15);
+    S.cst[l] = 0;
+    S.cy[l][0] = ((l >> 2) & 1 ? hi[0] : lo[0]) - X.vx;
+    S.cy[l][1] = ((l >> 1) & 1 ? hi[1] : lo[1]) - X.vy;
+    S.cy[l][2] = (l & 1 ? hi[2] : lo[2]) - X.vz;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ int convert_label(const GridView &G, int lab) { return lab >= 0 ? G.perm[lab] : lab; }
+
+// ---------------------------------------------------------------------------
+// Kernel A (cell-first): carve Omega_i cap box for every site and store the
+// labels of its bisector facets (sorted positions), VD_F_MAX slots per site.
+// ---------------------------------------------------------------------------
+struct CellArgs {
+  CarveParams P;
+  double box_lo[3], box_hi[3];
+  int *facet;         // [n * VD_F_MAX] by sorted position
+  int *nfacet;        // [n] by sorted position; -2 capacity, -3 degenerate
+  unsigned long long *cnt;
+};
+
+__global__ void __launch_bounds__(64) cell_kernel(GridView G, CellArgs A) {
   __shared__ WaveLds S;
   const int l = vd_lane();
   // consecutive sorted sites go to the same XCD (workgroup b runs on XCD b % 8)
   const int q8 = gridDim.x >> 3;
   const int si = (blockIdx.x & 7) * q8 + (blockIdx.x >> 3);
   if (si >= G.n) return;
-  const double vx = G.sx[si], vy = G.sy[si], vz = G.sz[si];
+  SiteCtx X;
+  X.vx = G.sx[si]; X.vy = G.sy[si]; X.vz = G.sz[si];
+  X.delta = G.delta[si];
+  X.si = si;
+  Stats st;
+  init_box(S, X, A.box_lo, A.box_hi);
+  int npl = 6, nc = 8;
+  int rc = carve(S, G, A.P, X, npl, nc, st);
+  int nf = 0;
+  if (rc == 0) {
+    uint64_t used = 0, bis = 0;
+    for (int s = l; s < nc; s += 64) {
+      const int pl = S.cpl[s];
+      used |= (1ull << p8(pl, 0)) | (1ull << p8(pl, 1)) | (1ull << p8(pl, 2));
+    }
+    for (int x = l; x < npl; x += 64)
+      if (S.plab[x] >= 0) bis |= 1ull << x;
+    used = wave_or64(used) & wave_or64(bis);
+    nf = __popcll(used);
+    if (nf > VD_F_MAX) rc = 2;
+    else if (l < npl && ((used >> l) & 1ull)) A.facet[(long long)si * VD_F_MAX + __popcll(used & low_mask(l))] = S.plab[l];
+  } else if (rc == 1) {
+    rc = 3;  // the site lies in the box, so its cell cannot be empty
+  }
+  if (l == 0) {
+    A.nfacet[si] = rc ? -rc : nf;
+    atomicAdd(&A.cnt[CNT_QUERIES], (unsigned long long)st.queries);
+    atomicAdd(&A.cnt[CNT_CLIPS], (unsigned long long)st.clips);
+    atomicAdd(&A.cnt[CNT_CANDS], (unsigned long long)st.cands);
+    if (rc) {
+      atomicAdd(&A.cnt[rc == 2 ? CNT_ERR_CAP : CNT_ERR_DEG], 1ull);
+      atomicMin((int *)&A.cnt[CNT_BAD_SITE], G.perm[si]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Kernel B: the pieces of every site.  The tetrahedra of the cell are visited
+// breadth-first through negative face flags from the tetrahedron containing
+// v_i (the propagation of Alg. 5).  CARVE = false (cell-first): T_a is cut by
+// the half-spaces of the cell's certified facets.  CARVE = true (per-simplex):
+// T_a is carved by point-in-cell tests and the bisector search.
+// ---------------------------------------------------------------------------
+template <bool CARVE>
+__global__ void __launch_bounds__(64) piece_kernel(GridView G, DomainView D, const CellsDev *__restrict__ Cp) {
+  __shared__ WaveLds S;
+  const int l = vd_lane();
+  const int q8 = gridDim.x >> 3;
+  const int si = (blockIdx.x & 7) * q8 + (blockIdx.x >> 3);
+  if (si >= G.n) return;
+  const CellsDev &C = *Cp;
+  SiteCtx X;
+  X.vx = G.sx[si]; X.vy = G.sy[si]; X.vz = G.sz[si];
+  X.delta = G.delta[si];
+  X.si = si;
   const int orig = G.perm[si];
-  const double delta = G.delta[si];
   const int seed = C.seed[si];
   Stats st;
   int err = 0;  // 2 capacity, 3 degenerate
-  int nt = 0, head = 0, nnb = 0, npieces = 0;
+  int nt = 0, head = 0, nnb = 0, npieces = 0, nf = 0;
   double Mv = 0, Mx = 0, My = 0, Mz = 0, Me = 0;
   if (seed >= 0 && seed < D.m) {
     if (l == 0) S.tq[0] = seed;
     nt = 1;
   }
+  if (!CARVE) {
+    nf = C.nfacet[si];
+    if (nf < 0) { nt = 0; nf = 0; }  // carve failure, already reported
+    // planes of the facets: B_ij with n = v_j - v_i, offset |n|^2 / 2
+    if (l < nf) {
+      const int j = C.facet[(long long)si * VD_F_MAX + l];
+      const double n0 = G.sx[j] - X.vx, n1 = G.sy[j] - X.vy, n2 = G.sz[j] - X.vz;
+      S.fpn[l][0] = n0; S.fpn[l][1] = n1; S.fpn[l][2] = n2;
+      S.fpn[l][3] = 0.5 * (n0 * n0 + n1 * n1 + n2 * n2);
+      S.flab[l] = j;
+    }
+  }
+  const CarveParams P = {C.improved, C.straddle, C.max_iters};
   __syncthreads();
   while (head < nt && !err) {
     const int a = S.tq[head++];
-    // ---- P <- T_a (4 planes, 4 corners) ----
-    {
-      const int *tv = &D.simp[(long long)a * 4];
-      double q[4][3];
-      for (int k = 0; k < 4; k++) {
-        const double *p = &D.verts[3 * (long long)tv[k]];
-        q[k][0] = p[0] - vx; q[k][1] = p[1] - vy; q[k][2] = p[2] - vz;
-      }
-      if (l < 4) {
-        // face f = l opposite vertex f, counter-clockwise from outside
-        const int L[4][3] = {{1, 2, 3}, {0, 3, 2}, {0, 1, 3}, {0, 2, 1}};
-        const double *A = q[L[l][0]], *B = q[L[l][1]], *Cc = q[L[l][2]];
-        const double ab[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
-        const double ac[3] = {Cc[0] - A[0], Cc[1] - A[1], Cc[2] - A[2]};
-        const double n[3] = {ab[1] * ac[2] - ab[2] * ac[1], ab[2] * ac[0] - ab[0] * ac[2], ab[0] * ac[1] - ab[1] * ac[0]};
-        S.pn[l][0] = n[0]; S.pn[l][1] = n[1]; S.pn[l][2] = n[2];
-        S.pn[l][3] = n[0] * A[0] + n[1] * A[1] + n[2] * A[2];
-        const int b = D.adj[(long long)a * 4 + l];
-        S.plab[l] = b >= 0 ? -(b + 1) : VD_BND_BASE + l;
-        // corner l = vertex l; planes CCW from outside and neighbours across
-        // the dual edges (fixed for positively oriented tetrahedra)
-        const int CP[4] = {pack3(1, 3, 2), pack3(0, 2, 3), pack3(0, 3, 1), pack3(0, 1, 2)};
-        const int CN[4] = {pack3(2, 1, 3), pack3(3, 0, 2), pack3(1, 0, 3), pack3(2, 0, 1)};
-        S.cpl[l] = CP[l];
-        S.cnb[l] = CN[l];
-        S.cflg[l] = 0;
-        S.cnn[l] = -1;
-        S.cy[l][0] = q[l][0]; S.cy[l][1] = q[l][1]; S.cy[l][2] = q[l][2];
-      }
-    }
-    __syncthreads();
     int npl = 4, nc = 4;
-    for (int s = 0; s < 4; s++) classify(S, G, s, si, vx, vy, vz, st);
     bool empty = false;
-    for (int it = 0;; it++) {
-      if (it >= kMaxClips) { err = 3; break; }
-      uint64_t ilo, ihi;
-      masks_inside(S, nc, ilo, ihi);
-      const uint64_t vlo = low_mask(nc < 64 ? nc : 64), vhi = low_mask(nc > 64 ? nc - 64 : 0);
-      const uint64_t olo = vlo & ~ilo, ohi = vhi & ~ihi;
-      if (!(olo | ohi)) break;
-      // ---- choose the search edge ----
-      int pt = -1, ps = -1;
-      if (C.straddle) {
-        bool cand[2];
-        for (int h = 0; h < 2; h++) {
-          const int s = l + 64 * h;
-          cand[h] = false;
-          if (bit128(olo, ohi, s)) {
-            const int nbp = S.cnb[s];
-            cand[h] = bit128(ilo, ihi, p8(nbp, 0)) || bit128(ilo, ihi, p8(nbp, 1)) || bit128(ilo, ihi, p8(nbp, 2));
-          }
+    if (!CARVE) {
+      init_tet(S, D, X, a, 1);
+      for (int f = 0; f < nf; f++) {
+        if (npl >= VD_P_MAX) {
+          npl = compact_planes(S, npl, nc);
+          if (npl >= VD_P_MAX) { err = 2; break; }
         }
-        const uint64_t clo = __ballot(cand[0]), chi = __ballot(cand[1]);
-        if (clo | chi) {
-          pt = clo ? __ffsll((unsigned long long)clo) - 1 : 64 + __ffsll((unsigned long long)chi) - 1;
-          const int nbp = S.cnb[pt];
-          for (int e = 0; e < 3; e++)
-            if (bit128(ilo, ihi, p8(nbp, e))) { ps = p8(nbp, e); break; }
-        }
+        const int Pl = npl;
+        __syncthreads();
+        if (l < 4) S.pn[Pl][l] = S.fpn[f][l];
+        if (l == 0) S.plab[Pl] = S.flab[f];
+        __syncthreads();
+        const int rc = clip_poly(S, Pl, -1, nc);
+        if (rc == 4) { npl++; st.clips++; }
+        else if (rc == 1) { empty = true; break; }
+        else if (rc != 0) { err = rc; break; }
       }
-      if (pt < 0) pt = olo ? __ffsll((unsigned long long)olo) - 1 : 64 + __ffsll((unsigned long long)ohi) - 1;
-      double A[3] = {0, 0, 0};
-      if (ps >= 0) { A[0] = S.cy[ps][0]; A[1] = S.cy[ps][1]; A[2] = S.cy[ps][2]; }
-      double g[3] = {S.cy[pt][0], S.cy[pt][1], S.cy[pt][2]};
-      int j = S.cnn[pt];
-      // Flags of a point on the edge p_s p_t: the two planes of the edge
-      // (Sec. 4.1 flag rule).  A search point whose nearest site is named by
-      // one of them lies on that face of Omega_i, i.e. inside.
-      int ef0 = -2, ef1 = -2;
-      if (ps >= 0) {
-        const int a0 = S.cpl[ps], b0 = S.cpl[pt];
-        int ne = 0;
-        for (int x = 0; x < 3; x++) {
-          const int px = p8(a0, x);
-          if (px == p8(b0, 0) || px == p8(b0, 1) || px == p8(b0, 2)) {
-            const int lab = S.plab[px];
-            if (ne == 0) ef0 = lab >= 0 ? lab : -2; else ef1 = lab >= 0 ? lab : -2;
-            ne++;
-          }
-        }
-      }
-      // ---- improved search (Sec. 6.1): g = A + lambda*delta*u, lambda = 2, 3, ...
-      if (C.improved) {
-        const double d0 = g[0] - A[0], d1 = g[1] - A[1], d2 = g[2] - A[2];
-        const double L = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-        if (L > 0) {
-          const double u0 = d0 / L, u1 = d1 / L, u2 = d2 / L;
-          for (int lam = 2; lam < 2 + C.max_iters && lam * delta < L; lam++) {
-            const double t = lam * delta;
-            const double gx = A[0] + t * u0, gy = A[1] + t * u1, gz = A[2] + t * u2;
-            const double qx = vx + gx, qy = vy + gy, qz = vz + gz;
-            const double ex = qx - vx, ey = qy - vy, ez = qz - vz;
-            double dd;
-            const int k = nn_query(G, qx, qy, qz, ex * ex + ey * ey + ez * ez, si, dd, st.cands);
-            st.queries++;
-            if (k != si && k != ef0 && k != ef1) { j = k; g[0] = gx; g[1] = gy; g[2] = gz; break; }
-          }
-        }
-      }
-      // ---- edge-based bisector search (Sec. 4.2) on [A, g] ----
-      if (j < 0 || j == si) { err = 3; break; }
-      double nj[4];
-      for (int stp = 0;; stp++) {
-        if (stp >= C.max_iters) { err = 3; break; }
-        nj[0] = G.sx[j] - vx; nj[1] = G.sy[j] - vy; nj[2] = G.sz[j] - vz;
-        nj[3] = 0.5 * (nj[0] * nj[0] + nj[1] * nj[1] + nj[2] * nj[2]);
-        const double e0 = g[0] - A[0], e1 = g[1] - A[1], e2 = g[2] - A[2];
-        const double den = nj[0] * e0 + nj[1] * e1 + nj[2] * e2;
-        const double num = nj[3] - (nj[0] * A[0] + nj[1] * A[1] + nj[2] * A[2]);
-        double t = den > 0.0 ? num / den : 1.0;
-        t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
-        const double qx = vx + (A[0] + t * e0), qy = vy + (A[1] + t * e1), qz = vz + (A[2] + t * e2);
-        const double ex = qx - vx, ey = qy - vy, ez = qz - vz;
-        double dd;
-        const int k = nn_query(G, qx, qy, qz, ex * ex + ey * ey + ez * ez, si, dd, st.cands);
-        st.queries++;
-        // q lies on the boundary of Omega_i: B_ij is a face of the cell
-        if (k == si || k == j || k == ef0 || k == ef1) break;
-        j = k;
-        g[0] = A[0] + t * e0; g[1] = A[1] + t * e1; g[2] = A[2] + t * e2;
-      }
-      if (err) break;
-      // ---- clip by B_ij ----
-      if (npl >= VD_P_MAX) {
-        npl = compact_planes(S, npl, nc);
-        if (npl >= VD_P_MAX) { err = 2; break; }
-      }
-      const int P = npl++;
-      __syncthreads();
-      if (l == 0) {
-        S.pn[P][0] = nj[0]; S.pn[P][1] = nj[1]; S.pn[P][2] = nj[2]; S.pn[P][3] = nj[3];
-        S.plab[P] = j;
-      }
-      __syncthreads();
-      int nsurv = nc;
-      const int rc = clip_poly(S, P, pt, nc, nsurv);
-      st.clips++;
-      if (rc == 1) { empty = true; break; }
-      if (rc) { err = rc; break; }
-      for (int s = nsurv; s < nc; s++) classify(S, G, s, si, vx, vy, vz, st);
+    } else {
+      init_tet(S, D, X, a, 0);
+      const int rc = carve(S, G, P, X, npl, nc, st);
+      if (rc == 1) empty = true;
+      else if (rc) err = rc;
     }
     if (err) break;
-    if (empty || nc == 0) continue;
+    if (empty) continue;
     // ---- moments of the piece ----
     double pv = 0, pmx = 0, pmy = 0, pmz = 0, pe = 0;
     uint64_t fmask = 0;
+#pragma unroll 1
     for (int h = 0; h < 2; h++) {
       const int s = l + 64 * h;
       if (s >= nc) continue;
       const int pl = S.cpl[s], nb = S.cnb[s];
       const double y0 = S.cy[s][0], y1 = S.cy[s][1], y2 = S.cy[s][2];
       fmask |= (1ull << p8(pl, 0)) | (1ull << p8(pl, 1)) | (1ull << p8(pl, 2));
-      // plane p8(pl,e) continues around the face to the corner across edge (e+2)%3
+      // plane p8(pl,e) continues around its face to the corner across edge (e+2)%3
+#pragma unroll 1
       for (int e = 0; e < 3; e++) {
         const int x = p8(pl, e);
         const int nx_ = p8(nb, (e + 2) % 3);
@@ -491,9 +788,9 @@ __global__ void __launch_bounds__(64) clip3d_kernel(GridView G, DomainView D, Ce
         C.piece_nface[pidx] = nface;
         C.piece_nvert[pidx] = nc;
         C.piece_mass[pidx] = pv;
-        C.piece_mom[3 * pidx + 0] = pmx + pv * vx;
-        C.piece_mom[3 * pidx + 1] = pmy + pv * vy;
-        C.piece_mom[3 * pidx + 2] = pmz + pv * vz;
+        C.piece_mom[3 * pidx + 0] = pmx + pv * X.vx;
+        C.piece_mom[3 * pidx + 1] = pmy + pv * X.vy;
+        C.piece_mom[3 * pidx + 2] = pmz + pv * X.vz;
         C.piece_energy[pidx] = pe;
         C.piece_fstart[pidx] = C.emit ? fo : -1;
         C.piece_vstart[pidx] = C.emit ? vo : -1;
@@ -505,22 +802,22 @@ __global__ void __launch_bounds__(64) clip3d_kernel(GridView G, DomainView D, Ce
           const int s = l + 64 * h;
           if (s < nc) {
             const int pl = S.cpl[s];
-            C.vert_xyz[3 * (vo + s) + 0] = S.cy[s][0] + vx;
-            C.vert_xyz[3 * (vo + s) + 1] = S.cy[s][1] + vy;
-            C.vert_xyz[3 * (vo + s) + 2] = S.cy[s][2] + vz;
+            C.vert_xyz[3 * (vo + s) + 0] = S.cy[s][0] + X.vx;
+            C.vert_xyz[3 * (vo + s) + 1] = S.cy[s][1] + X.vy;
+            C.vert_xyz[3 * (vo + s) + 2] = S.cy[s][2] + X.vz;
             for (int e = 0; e < 3; e++) C.vert_label[3 * (vo + s) + e] = convert_label(G, S.plab[p8(pl, e)]);
           }
         }
       }
     }
-    if (l == 0) S.pid[npieces] = (int)pidx;
     npieces++;
     // ---- propagate: neighbours (positive flags), tetrahedra (negative flags) ----
     for (uint64_t m = fmask; m; m &= m - 1) {
       const int x = __ffsll((unsigned long long)m) - 1;
-      const int lab = S.plab[x];
+      const int lab = uni(S.plab[x]);
       if (lab >= 0) {
-        const bool have = (l < nnb && S.nbl[l] == lab) || (l + 64 < nnb && S.nbl[l + 64] == lab);
+        bool have = false;
+        for (int e = l; e < nnb; e += 64) have = have || (S.nbl[e] == lab);
         if (!__ballot(have)) {
           if (nnb >= VD_NB_MAX) { err = 2; break; }
           __syncthreads();
@@ -544,43 +841,35 @@ __global__ void __launch_bounds__(64) clip3d_kernel(GridView G, DomainView D, Ce
     __syncthreads();
   }
   // ---- per-site results ----
+  long long ns0 = 0;
   if (l == 0) {
     C.mass[orig] = Mv;
-    C.mom[3 * (long long)orig + 0] = Mx + Mv * vx;
-    C.mom[3 * (long long)orig + 1] = My + Mv * vy;
-    C.mom[3 * (long long)orig + 2] = Mz + Mv * vz;
+    C.mom[3 * (long long)orig + 0] = Mx + Mv * X.vx;
+    C.mom[3 * (long long)orig + 1] = My + Mv * X.vy;
+    C.mom[3 * (long long)orig + 2] = Mz + Mv * X.vz;
     C.energy[orig] = Me;
     C.pcount[orig] = npieces;
     C.ncount[orig] = nnb;
-  }
-  long long ps0 = 0, ns0 = 0;
-  if (l == 0) {
-    ps0 = (long long)atomicAdd(&C.cnt[CNT_PLIST], (unsigned long long)npieces);
     ns0 = (long long)atomicAdd(&C.cnt[CNT_NBRS], (unsigned long long)nnb);
-    C.pstart[orig] = ps0;
     C.nstart[orig] = ns0;
   }
-  ps0 = __shfl(ps0, 0, 64);
   ns0 = __shfl(ns0, 0, 64);
   __syncthreads();
-  if (ps0 + npieces <= C.cap_plist)
-    for (int e = l; e < npieces; e += 64) C.plist[ps0 + e] = S.pid[e];
   if (ns0 + nnb <= C.cap_nbr) {
     // neighbours in ascending caller index: rank sort
-    for (int h = 0; h < 2; h++) {
-      const int e = l + 64 * h;
-      if (e < nnb) {
-        const int me = G.perm[S.nbl[e]];
-        int rk = 0;
-        for (int o = 0; o < nnb; o++) rk += (G.perm[S.nbl[o]] < me) ? 1 : 0;
-        C.nbr_arena[ns0 + rk] = me;
-      }
+    for (int e = l; e < nnb; e += 64) {
+      const int me = G.perm[S.nbl[e]];
+      int rk = 0;
+      for (int o = 0; o < nnb; o++) rk += (G.perm[S.nbl[o]] < me) ? 1 : 0;
+      C.nbr_arena[ns0 + rk] = me;
     }
   }
   if (l == 0) {
-    atomicAdd(&C.cnt[CNT_QUERIES], (unsigned long long)st.queries);
+    if (CARVE) {
+      atomicAdd(&C.cnt[CNT_QUERIES], (unsigned long long)st.queries);
+      atomicAdd(&C.cnt[CNT_CANDS], (unsigned long long)st.cands);
+    }
     atomicAdd(&C.cnt[CNT_CLIPS], (unsigned long long)st.clips);
-    atomicAdd(&C.cnt[CNT_CANDS], (unsigned long long)st.cands);
     if (err) {
       atomicAdd(&C.cnt[err == 2 ? CNT_ERR_CAP : CNT_ERR_DEG], 1ull);
       atomicMin((int *)&C.cnt[CNT_BAD_SITE], orig);
@@ -590,7 +879,18 @@ __global__ void __launch_bounds__(64) clip3d_kernel(GridView G, DomainView D, Ce
 
 }  // namespace
 
-void vd_launch_clip3d(const GridView &G, const DomainView &D, const CellsDev &C, hipStream_t st) {
+void vd_launch_cells3d(const GridView &G, const CellsDev &C, hipStream_t st) {
   const unsigned q8 = (unsigned)((G.n + 7) / 8);
-  hipLaunchKernelGGL(clip3d_kernel, dim3(q8 * 8), dim3(64), 0, st, G, D, C);
+  CellArgs A;
+  A.P.improved = C.improved; A.P.straddle = C.straddle; A.P.max_iters = C.max_iters;
+  for (int k = 0; k < 3; k++) { A.box_lo[k] = C.box_lo[k]; A.box_hi[k] = C.box_hi[k]; }
+  A.facet = C.facet; A.nfacet = C.nfacet; A.cnt = C.cnt;
+  hipLaunchKernelGGL(cell_kernel, dim3(q8 * 8), dim3(64), 0, st, G, A);
+}
+
+void vd_launch_pieces3d(const GridView &G, const DomainView &D, const CellsDev *Cdev, int carve_each,
+                        hipStream_t st) {
+  const unsigned q8 = (unsigned)((G.n + 7) / 8);
+  if (carve_each) hipLaunchKernelGGL(piece_kernel<true>, dim3(q8 * 8), dim3(64), 0, st, G, D, Cdev);
+  else hipLaunchKernelGGL(piece_kernel<false>, dim3(q8 * 8), dim3(64), 0, st, G, D, Cdev);
 }

@@ -13,6 +13,7 @@
 #define VD_C_MAX 128   // corners (two slots per lane)
 #define VD_Q_MAX 256   // tetrahedra visited for one site (4 per lane)
 #define VD_NB_MAX 96   // distinct neighbours of one site
+#define VD_F_MAX 48    // bisector facets of one cell (cell-first mode)
 
 // device counters written by the clip kernels (one atomic per wave per field)
 enum {
@@ -58,6 +59,7 @@ struct vd_domain_s {
   int *lstart = nullptr, *litems = nullptr, *lcount = nullptr, *lfill = nullptr, *scan_tmp = nullptr;
   int64_t nitems = 0;
   double area = 0.0;  // surface area (triangles) or volume (tets)
+  double bbox[6] = {0, 0, 0, 0, 0, 0};  // vertex bounding box
   DomainView view() const {
     DomainView d;
     d.m = (int)m; d.nv = (int)nv; d.dim = dim; d.verts = verts; d.simp = simp; d.adj = adj;
@@ -76,13 +78,14 @@ struct CellsDev {
   int improved;    // Sec. 6.1 search
   int straddle;    // Alg. 1 edges when available
   int max_iters;
+  int mode;        // 0 per-simplex carve, 1 cell-first
+  double box_lo[3], box_hi[3];  // padded domain box (cell-first)
   unsigned long long *cnt;  // CNT_N counters
   // per site (caller index)
   double *mass, *mom, *energy;
   int *pcount, *ncount;
   long long *pstart, *nstart;
   // arenas + capacities
-  int *plist; long long cap_plist;
   int *nbr_arena; long long cap_nbr;
   int *piece_site, *piece_simplex, *piece_nface, *piece_nvert;
   long long *piece_fstart, *piece_vstart;
@@ -94,6 +97,7 @@ struct CellsDev {
   // {k, A[3], B[9], C[3]} summed over the site's pieces; stored by neighbour slot
   double *fint; long long cap_fint;
   int *seed;  // 3D: tetrahedron containing each site (sorted position order)
+  int *facet, *nfacet;  // cell-first: facet labels [n * VD_F_MAX], counts [n] (sorted order)
 };
 
 struct vd_cells_s {
@@ -106,14 +110,17 @@ struct vd_cells_s {
   int64_t cap_n = 0;
   long long *piece_off = nullptr, *nbr_off = nullptr;  // CSR [n+1]
   int *piece_id = nullptr, *nbr = nullptr;             // CSR payloads
+  int *fillc = nullptr;                                // per-site scatter counters
   long long *scan_tmp = nullptr;
   int64_t cap_pid = 0, cap_nbr_csr = 0;
   const double *sites_sorted_x = nullptr;  // borrowed from the grid for moments
   vd_grid grid = nullptr;
   int status = 0;
   int first_bad = -1;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;  // carve kernel timing (time_kernels)
-  double carve_ms = -1.0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;  // kernel timing (time_kernels)
+  double carve_ms = -1.0, split_ms = -1.0;
+  CellsDev *d_dev = nullptr;  // device copy of d (read by the piece kernel)
+  CellsDev d_shadow{};        // host copy last sent to d_dev
 };
 
 // launchers (defined in the .hip files)
@@ -121,7 +128,9 @@ void vd_launch_grid_build(vd_grid g, const double *sites, const double *bbox_hos
 void vd_launch_domain_locator(vd_domain d, hipStream_t st);
 void vd_launch_locate_sites(const GridView &G, const DomainView &D, int *seed, unsigned long long *cnt,
                             hipStream_t st);
-void vd_launch_clip3d(const GridView &G, const DomainView &D, const CellsDev &C, hipStream_t st);
+void vd_launch_cells3d(const GridView &G, const CellsDev &C, hipStream_t st);
+void vd_launch_pieces3d(const GridView &G, const DomainView &D, const CellsDev *Cdev, int carve_each,
+                        hipStream_t st);
 void vd_launch_surface(const GridView &G, const DomainView &D, const CellsDev &C, hipStream_t st);
 void vd_launch_finalize(vd_cells c, hipStream_t st);
 void vd_launch_moments(const vd_cells_s *c, const GridView &G, double *mass, double *cent,

@@ -52,10 +52,12 @@ def test_two_sites(oracle_mod):
     _check_case(oracle_mod, s, dom)
 
 
+@pytest.mark.parametrize("mode", [1, 0])
 @pytest.mark.parametrize("n,k,seed", [(300, 3, 5), (2000, 4, 6), (777, 5, 7)])
-def test_multi_tet_parity(oracle_mod, n, k, seed):
+def test_multi_tet_parity(oracle_mod, n, k, seed, mode):
+    """Both carve modes: cell-first (1) and per-simplex carving (0)."""
     sites, dom = vdgen.small_case(n, k, seed=seed)
-    _check_case(oracle_mod, sites, dom, brute=False)
+    _check_case(oracle_mod, sites, dom, brute=False, carve_mode=mode)
 
 
 def test_jittered_domain(oracle_mod):
@@ -63,18 +65,20 @@ def test_jittered_domain(oracle_mod):
     _check_case(oracle_mod, sites, dom, brute=False)
 
 
+@pytest.mark.parametrize("mode", [1, 0])
 @pytest.mark.parametrize("straddle,improved", [(0, 1), (1, 0), (0, 0)])
-def test_search_variants_same_result(oracle_mod, straddle, improved):
+def test_search_variants_same_result(oracle_mod, straddle, improved, mode):
     """Alg. 1 vs Alg. 3 edges and the improved search change the path, not the result."""
     sites, dom = vdgen.small_case(800, 3, seed=13)
     _check_case(oracle_mod, sites, dom, brute=False, use_straddle_edges=straddle,
-                improved_search=improved)
+                improved_search=improved, carve_mode=mode)
 
 
-def test_clustered_small(oracle_mod):
+@pytest.mark.parametrize("mode", [1, 0])
+def test_clustered_small(oracle_mod, mode):
     s = vdgen.gaussian_mixture_sites(400, 4, 200, 0.05, centre_seed=3, sample_seed=4, jitter=1e-7)
     dom = vdgen.kuhn_cube_grid(6)
-    _check_case(oracle_mod, s, dom, brute=False)
+    _check_case(oracle_mod, s, dom, brute=False, carve_mode=mode)
 
 
 def test_c2_full_size_sampled(oracle_mod):
