@@ -102,9 +102,12 @@ def main():
         vd.clip_cells(grid, d, opts, cells=cells)
         cells.moments(mass, cent, en)
 
-    for _ in range(args.warmup):
+    print(f"bench: {desc}; inputs on the device, warming up", file=sys.stderr, flush=True)
+    for w in range(args.warmup):
+        t1 = time.perf_counter()
         step()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        print(f"bench: warmup {w} {1e3 * (time.perf_counter() - t1):.1f} ms", file=sys.stderr, flush=True)
     carve, split = [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -112,6 +115,8 @@ def main():
         inf = cells.info()
         carve.append(inf["carve_ms"])
         split.append(inf["split_ms"])
+        print(f"bench: step {len(carve)} cell {inf['carve_ms']:.2f} ms piece {inf['split_ms']:.2f} ms",
+              file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     info = cells.info()

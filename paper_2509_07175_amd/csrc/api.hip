@@ -327,6 +327,8 @@ hipError_t alloc_cells(vd_cells c, int64_t n, const Caps &want) {
     t = 0; if ((e = ensure(d.piece_mom, t, 3 * want.piece)) != hipSuccess) return e;
     t = 0; if ((e = ensure(d.piece_energy, t, want.piece)) != hipSuccess) return e;
     t = 0; if ((e = ensure(c->piece_id, t, want.piece)) != hipSuccess) return e;
+    t = 0; if ((e = ensure(d.piece_fint_start, t, want.piece)) != hipSuccess) return e;
+    t = 0; if ((e = ensure(d.piece_nfint, t, want.piece)) != hipSuccess) return e;
     d.cap_piece = want.piece;
     c->cap_pid = want.piece;
   }
@@ -352,7 +354,9 @@ hipError_t alloc_cells(vd_cells c, int64_t n, const Caps &want) {
   }
   if (want.fint > 0 && d.cap_fint < want.fint) {
     int64_t t = 0;
-    if ((e = ensure(d.fint, t, 16 * want.fint)) != hipSuccess) return e;
+    if ((e = ensure(d.fint, t, 12 * want.fint)) != hipSuccess) return e;
+    t = 0;
+    if ((e = ensure(d.fint_lab, t, want.fint)) != hipSuccess) return e;
     d.cap_fint = want.fint;
   }
   return hipSuccess;
@@ -380,9 +384,11 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
   Caps want;
   want.piece = std::max<int64_t>(std::max<int64_t>(c->d.cap_piece, 6 * n + 1024), dom->dim == 2 ? 2 * dom->m + 6 * n : 0);
   want.nbr = std::max<int64_t>(c->d.cap_nbr, 20 * n + 1024);
-  want.face = opt.emit_polytopes ? std::max<int64_t>(c->d.cap_face, 10 * want.piece) : 0;
-  want.vert = opt.emit_polytopes ? std::max<int64_t>(c->d.cap_vert, 16 * want.piece) : 0;
-  want.fint = opt.want_grad ? std::max<int64_t>(c->d.cap_fint, want.nbr) : 0;
+  // surfaces always keep the edge flags of their pieces (the per-site pass reads them)
+  const bool keep_faces = opt.emit_polytopes || dom->dim == 2;
+  want.face = keep_faces ? std::max<int64_t>(c->d.cap_face, 10 * want.piece) : 0;
+  want.vert = keep_faces ? std::max<int64_t>(c->d.cap_vert, 16 * want.piece) : 0;
+  want.fint = opt.want_grad ? std::max<int64_t>(c->d.cap_fint, 4 * want.piece) : 0;
   for (int attempt = 0; attempt < 4; attempt++) {
     hipError_t e = alloc_cells(c, n, want);
     if (e != hipSuccess)
@@ -417,11 +423,12 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
       HIP_TRY(hipMemcpyAsync(c->d_dev, &c->d_shadow, sizeof(CellsDev), hipMemcpyHostToDevice, st));
     }
     if (dom->dim == 3) vd_launch_locate_sites(G, D, d.seed, d.cnt, st);
+    else vd_launch_fill_int(d.pcount, n, 0, st);
     if (opt.time_kernels) HIP_TRY(hipEventRecord(c->ev0, st));
     if (dom->dim == 3 && d.mode == 1) vd_launch_cells3d(G, d, st);
     if (opt.time_kernels) HIP_TRY(hipEventRecord(c->ev1, st));
     if (dom->dim == 3) vd_launch_pieces3d(G, D, c->d_dev, d.mode == 0, st);
-    else vd_launch_surface(G, D, d, st);
+    else vd_launch_surface(G, D, c->d_dev, st);
     if (opt.time_kernels) HIP_TRY(hipEventRecord(c->ev2, st));
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(c->host_cnt, d.cnt, sizeof(unsigned long long) * CNT_N, hipMemcpyDeviceToHost, st));
@@ -440,8 +447,8 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
     auto up = [](int64_t used) { return used + used / 4 + 1024; };
     if ((int64_t)hc[CNT_PIECES] > d.cap_piece) { need.piece = up(hc[CNT_PIECES]); grow = true; }
     if ((int64_t)hc[CNT_NBRS] > d.cap_nbr) { need.nbr = up(hc[CNT_NBRS]); grow = true; }
-    if (opt.emit_polytopes && (int64_t)hc[CNT_FACES] > d.cap_face) { need.face = up(hc[CNT_FACES]); grow = true; }
-    if (opt.emit_polytopes && (int64_t)hc[CNT_VERTS] > d.cap_vert) { need.vert = up(hc[CNT_VERTS]); grow = true; }
+    if (keep_faces && (int64_t)hc[CNT_FACES] > d.cap_face) { need.face = up(hc[CNT_FACES]); grow = true; }
+    if (keep_faces && (int64_t)hc[CNT_VERTS] > d.cap_vert) { need.vert = up(hc[CNT_VERTS]); grow = true; }
     if (opt.want_grad && (int64_t)hc[CNT_FINT] > d.cap_fint) { need.fint = up(hc[CNT_FINT]); grow = true; }
     if (grow) { want = need; continue; }
     int bad = (int)(hc[CNT_BAD_SITE] & 0xffffffffull);
@@ -486,6 +493,7 @@ void vd_cells_free(vd_cells c) {
   if (c->ev1) hipEventDestroy(c->ev1);
   if (c->ev2) hipEventDestroy(c->ev2);
   hipFree(c->d_dev); hipFree(d.facet); hipFree(d.nfacet);
+  hipFree(d.fint_lab); hipFree(d.piece_fint_start); hipFree(d.piece_nfint); hipFree(c->wbuf);
   delete c;
 }
 
@@ -545,7 +553,12 @@ vd_status vd_cell_moments_backward(vd_cells c, const double *g_mass, const doubl
   if (!c || !g_sites) return fail(VD_ERR_INVALID_ARG, "vd_cell_moments_backward: NULL argument");
   if (!c->opt.want_grad) return fail(VD_ERR_INVALID_ARG, "vd_cell_moments_backward: clip ran without want_grad");
   if (c->status != VD_OK) return fail(VD_ERR_INVALID_ARG, "vd_cell_moments_backward: the clip failed");
-  vd_launch_backward(c, c->grid->view(), g_mass, g_centroid, g_energy, g_sites, nullptr, as_stream(stream));
+  {
+    int64_t t = c->cap_w;
+    HIP_TRY(ensure(c->wbuf, t, 5 * c->n));
+    c->cap_w = t;
+  }
+  vd_launch_backward(c, c->grid->view(), g_mass, g_centroid, g_energy, g_sites, c->wbuf, as_stream(stream));
   HIP_TRY(hipGetLastError());
   return VD_OK;
 }

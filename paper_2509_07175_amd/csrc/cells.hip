@@ -91,6 +91,8 @@ void vd_launch_finalize(vd_cells c, hipStream_t st) {
                      (const long long *)c->piece_off, c->fillc, c->piece_id);
   hipLaunchKernelGGL(sort_segments, dim3(blocks(n)), dim3(kB), 0, st, n, (const long long *)c->piece_off,
                      (const int *)d.piece_simplex, c->piece_id);
+  // surfaces: per-site sums and neighbour lists from the pieces, in CSR order
+  if (c->dim == 2) vd_launch_site_reduce(n, c->piece_off, c->piece_id, c->d_dev, st);
   vdscan::exclusive_scan<int, long long>(d.ncount, n, c->nbr_off, c->scan_tmp, st);
   hipLaunchKernelGGL(gather_lists, dim3(blocks(n)), dim3(kB), 0, st, n, (const int *)d.ncount,
                      (const long long *)d.nstart, (const int *)d.nbr_arena, (const long long *)c->nbr_off,

@@ -58,6 +58,7 @@ struct __align__(16) WaveLds {
   unsigned char byFirst[VD_P_MAX], bySecond[VD_P_MAX];
   int tq[VD_Q_MAX];          // tetrahedra of this site, breadth-first
   int nbl[VD_NB_MAX];        // neighbours found so far (sorted positions)
+  int pfirst[VD_P_MAX];      // lowest corner slot on each plane (face walks)
 };
 
 __device__ __forceinline__ int p8(int packed, int e) { return (packed >> (8 * e)) & 0xff; }
@@ -73,93 +74,6 @@ struct SiteCtx {
   double vx, vy, vz, delta;
   int si;
 };
-
-// ---------------------------------------------------------------------------
-// nearest-site query by a group of gs lanes (gs = 64: the whole wave; gs = 16:
-// four independent queries per wave).  q and the known candidate (r2, k0) are
-// uniform within a group.  The candidate box is split into x-rows; a row of
-// consecutive cells is one contiguous range of sorted sites, so the group
-// flattens all rows into one candidate list (coalesced SoA loads).
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void scan_box(const GridView &G, int gs, int x0, int x1, int y0, int y1, int z0,
-                                         int z1, double qx, double qy, double qz, double &bd, int &bk,
-                                         long long &ncand) {
-  const int gl = vd_lane() & (gs - 1);
-  const int nx = x1 - x0 + 1, ny = y1 - y0 + 1;
-  const int R = ny * (z1 - z0 + 1);
-  for (int r0 = 0; r0 < R; r0 += gs) {
-    const int r = r0 + gl;
-    int st = 0, cnt = 0;
-    if (r < R) {
-      const int yy = y0 + r % ny, zz = z0 + r / ny;
-      const int c0 = x0 + G.g[0] * (yy + G.g[1] * zz);
-      st = G.cstart[c0];
-      cnt = G.cstart[c0 + nx] - st;
-    }
-    int inc = cnt;
-    for (int d = 1; d < gs; d <<= 1) {
-      const int o = __shfl_up(inc, d, gs);
-      if (gl >= d) inc += o;
-    }
-    const int excl = inc - cnt;
-    const int total = __shfl(inc, gs - 1, gs);
-    const int nrows = (R - r0) < gs ? (R - r0) : gs;
-    ncand += total;
-    for (int base = 0; base < total; base += gs) {
-      const int t = base + gl;
-      int rr = 0;
-      for (int step = gs >> 1; step >= 1; step >>= 1) {
-        const int cand = rr + step;
-        const int v = __shfl(excl, cand & (gs - 1), gs);
-        if (cand < nrows && v <= t) rr = cand;
-      }
-      const int rst = __shfl(st, rr, gs);
-      const int rex = __shfl(excl, rr, gs);
-      if (t < total) {
-        const int p = rst + (t - rex);
-        const double dx = qx - G.sx[p], dy = qy - G.sy[p], dz = qz - G.sz[p];
-        const double d = dx * dx + dy * dy + dz * dz;
-        if (d < bd || (d == bd && p < bk)) { bd = d; bk = p; }
-      }
-    }
-  }
-}
-
-__device__ __forceinline__ void group_argmin(double &d, int &k, int gs) {
-  for (int m = gs >> 1; m >= 1; m >>= 1) {
-    const double od = __shfl_xor(d, m, 64);
-    const int ok = __shfl_xor(k, m, 64);
-    if (od < d || (od == d && ok < k)) { d = od; k = ok; }
-  }
-}
-
-__device__ __forceinline__ int nn_query(const GridView &G, int gs, double qx, double qy, double qz, double r2,
-                                        int k0, long long &ncand) {
-  const double lox = G.geom[0], loy = G.geom[1], loz = G.geom[2];
-  const double ihx = G.geom[6], ihy = G.geom[7], ihz = G.geom[8];
-  const int gx = G.g[0], gy = G.g[1], gz = G.g[2];
-  double bd = r2;
-  int bk = k0;
-  const int cx = cell_coord(qx, lox, ihx, gx), cy = cell_coord(qy, loy, ihy, gy), cz = cell_coord(qz, loz, ihz, gz);
-  double r = sqrt(r2);
-  // phase 1: the 3x3x3 block around q's cell, trimmed to the ball of radius r
-  const int x0 = max(cx - 1, cell_coord(qx - r, lox, ihx, gx)), x1 = min(cx + 1, cell_coord(qx + r, lox, ihx, gx));
-  const int y0 = max(cy - 1, cell_coord(qy - r, loy, ihy, gy)), y1 = min(cy + 1, cell_coord(qy + r, loy, ihy, gy));
-  const int z0 = max(cz - 1, cell_coord(qz - r, loz, ihz, gz)), z1 = min(cz + 1, cell_coord(qz + r, loz, ihz, gz));
-  scan_box(G, gs, x0, x1, y0, y1, z0, z1, qx, qy, qz, bd, bk, ncand);
-  group_argmin(bd, bk, gs);
-  // phase 2: the whole box of the best ball if it leaves the scanned block
-  // (the best radius only shrinks, so once suffices)
-  r = sqrt(bd);
-  const int X0 = cell_coord(qx - r, lox, ihx, gx), X1 = cell_coord(qx + r, lox, ihx, gx);
-  const int Y0 = cell_coord(qy - r, loy, ihy, gy), Y1 = cell_coord(qy + r, loy, ihy, gy);
-  const int Z0 = cell_coord(qz - r, loz, ihz, gz), Z1 = cell_coord(qz + r, loz, ihz, gz);
-  if (X0 < x0 || X1 > x1 || Y0 < y0 || Y1 > y1 || Z0 < z0 || Z1 > z1) {
-    scan_box(G, gs, X0, X1, Y0, Y1, Z0, Z1, qx, qy, qz, bd, bk, ncand);
-    group_argmin(bd, bk, gs);
-  }
-  return bk;
-}
 
 // Vertex of three planes by Cramer's rule, planes taken in ascending flag order
 // so a vertex does not depend on the order in which its planes were created.
@@ -608,6 +522,86 @@ __device__ void init_box(WaveLds &S, const SiteCtx &X, const double *lo, const d
 
 __device__ __forceinline__ int convert_label(const GridView &G, int lab) { return lab >= 0 ? G.perm[lab] : lab; }
 
+// Face moments of the bisector faces of the piece in LDS, for the adjoint:
+// for face x on B_ik, I0 = int y dA/d, I1 = int y y^T dA/d, I2 = int |y|^2 y dA/d
+// with y = x - v_i and d = |v_k - v_i|.  Lane x walks around face x from its
+// lowest corner (a fixed order, so the sums are reproducible) and integrates
+// the fan of triangles (foot of the plane, corner, next corner): linear and
+// quadratic terms in closed form, the cubic term with the degree-3 rule of
+// Strang and Fix (centroid -27/48, points (3/5,1/5,1/5) 25/48).
+__device__ void face_moments(WaveLds &S, int nc, int npl, uint64_t fmask, const CellsDev &C, const GridView &G,
+                             long long pidx) {
+  const int l = vd_lane();
+  __syncthreads();
+  if (l < npl) S.pfirst[l] = 0x7fffffff;
+  __syncthreads();
+  for (int s = l; s < nc; s += 64) {
+    const int pl = S.cpl[s];
+    atomicMin(&S.pfirst[p8(pl, 0)], s);
+    atomicMin(&S.pfirst[p8(pl, 1)], s);
+    atomicMin(&S.pfirst[p8(pl, 2)], s);
+  }
+  __syncthreads();
+  const bool mine = l < npl && ((fmask >> l) & 1ull) && S.plab[l] >= 0;
+  const uint64_t pos = __ballot(mine);
+  const int npos = __popcll(pos);
+  long long base = 0;
+  if (l == 0) base = (long long)atomicAdd(&C.cnt[CNT_FINT], (unsigned long long)npos);
+  base = __shfl(base, 0, 64);
+  if (l == 0 && pidx < C.cap_piece) { C.piece_fint_start[pidx] = base; C.piece_nfint[pidx] = npos; }
+  if (!mine) return;
+  const int x = l;
+  const double n0 = S.pn[x][0], n1 = S.pn[x][1], n2 = S.pn[x][2], cc = S.pn[x][3];
+  const double nn = n0 * n0 + n1 * n1 + n2 * n2;
+  const double d = sqrt(nn), f = cc / nn;
+  const double h0 = n0 / d, h1 = n1 / d, h2 = n2 / d;
+  const double r0 = n0 * f, r1 = n1 * f, r2 = n2 * f;
+  double I[12];
+  for (int k = 0; k < 12; k++) I[k] = 0.0;
+  const int start = S.pfirst[x];
+  int T = start;
+  for (int step = 0; step < VD_C_MAX; step++) {
+    const int pl = S.cpl[T];
+    const int e = p8(pl, 0) == x ? 0 : (p8(pl, 1) == x ? 1 : 2);
+    const int nx = p8(S.cnb[T], (e + 2) % 3);
+    const double a0 = S.cy[T][0], a1 = S.cy[T][1], a2 = S.cy[T][2];
+    const double b0 = S.cy[nx][0], b1 = S.cy[nx][1], b2 = S.cy[nx][2];
+    const double u0 = a0 - r0, u1 = a1 - r1, u2 = a2 - r2, w0 = b0 - r0, w1 = b1 - r1, w2 = b2 - r2;
+    const double A = 0.5 * ((u1 * w2 - u2 * w1) * h0 + (u2 * w0 - u0 * w2) * h1 + (u0 * w1 - u1 * w0) * h2);
+    const double s0 = r0 + a0 + b0, s1 = r1 + a1 + b1, s2 = r2 + a2 + b2;
+    I[0] += A * s0 / 3.0; I[1] += A * s1 / 3.0; I[2] += A * s2 / 3.0;
+    const double q = A / 12.0;
+    I[3] += q * (r0 * r0 + a0 * a0 + b0 * b0 + s0 * s0);
+    I[4] += q * (r0 * r1 + a0 * a1 + b0 * b1 + s0 * s1);
+    I[5] += q * (r0 * r2 + a0 * a2 + b0 * b2 + s0 * s2);
+    I[6] += q * (r1 * r1 + a1 * a1 + b1 * b1 + s1 * s1);
+    I[7] += q * (r1 * r2 + a1 * a2 + b1 * b2 + s1 * s2);
+    I[8] += q * (r2 * r2 + a2 * a2 + b2 * b2 + s2 * s2);
+    // cubic |y|^2 y: degree-3 rule on (r, a, b)
+    const double c0 = s0 / 3.0, c1 = s1 / 3.0, c2 = s2 / 3.0;
+    double t0 = -27.0 / 48.0 * (c0 * c0 + c1 * c1 + c2 * c2);
+    double acc0 = t0 * c0, acc1 = t0 * c1, acc2 = t0 * c2;
+#pragma unroll
+    for (int v = 0; v < 3; v++) {
+      // point 3/5 at vertex v, 1/5 at the other two
+      const double p0 = 0.2 * s0 + 0.4 * (v == 0 ? r0 : (v == 1 ? a0 : b0));
+      const double p1 = 0.2 * s1 + 0.4 * (v == 0 ? r1 : (v == 1 ? a1 : b1));
+      const double p2 = 0.2 * s2 + 0.4 * (v == 0 ? r2 : (v == 1 ? a2 : b2));
+      const double w = 25.0 / 48.0 * (p0 * p0 + p1 * p1 + p2 * p2);
+      acc0 += w * p0; acc1 += w * p1; acc2 += w * p2;
+    }
+    I[9] += A * acc0; I[10] += A * acc1; I[11] += A * acc2;
+    T = nx;
+    if (T == start) break;
+  }
+  const long long r = base + __popcll(pos & low_mask(l));
+  if (r < C.cap_fint) {
+    const double id = 1.0 / d;
+    for (int k = 0; k < 12; k++) C.fint[12 * r + k] = I[k] * id;
+    C.fint_lab[r] = G.perm[S.plab[x]];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Kernel A (cell-first): carve Omega_i cap box for every site and store the
 // labels of its bisector facets (sorted positions), VD_F_MAX slots per site.
@@ -712,7 +706,15 @@ __global__ void __launch_bounds__(64) piece_kernel(GridView G, DomainView D, con
     bool empty = false;
     if (!CARVE) {
       init_tet(S, D, X, a, 1);
-      for (int f = 0; f < nf; f++) {
+      // facets whose plane leaves a vertex of T_a outside; the others contain T_a
+      bool cuts = false;
+      if (l < nf) {
+        const double n0 = S.fpn[l][0], n1 = S.fpn[l][1], n2 = S.fpn[l][2], cc = S.fpn[l][3];
+        for (int k = 0; k < 4; k++) cuts = cuts || (n0 * S.cy[k][0] + n1 * S.cy[k][1] + n2 * S.cy[k][2] > cc);
+      }
+      uint64_t fm = __ballot(cuts);
+      for (; fm; fm &= fm - 1) {
+        const int f = __ffsll((unsigned long long)fm) - 1;
         if (npl >= VD_P_MAX) {
           npl = compact_planes(S, npl, nc);
           if (npl >= VD_P_MAX) { err = 2; break; }
@@ -781,6 +783,7 @@ __global__ void __launch_bounds__(64) piece_kernel(GridView G, DomainView D, con
     pidx = __shfl(pidx, 0, 64);
     fo = __shfl(fo, 0, 64);
     vo = __shfl(vo, 0, 64);
+    if (C.want_grad) face_moments(S, nc, npl, fmask, C, G, pidx);
     if (pidx < C.cap_piece) {
       if (l == 0) {
         C.piece_site[pidx] = orig;

@@ -1,3 +1,540 @@
-// surface.hip -- placeholder launcher (restricted VD kernel not built yet).
+// surface.hip -- restricted Voronoi diagram on a triangle mesh (Alg. 4).
+//
+// One wavefront per triangle T_a.  The first site is the nearest site of the
+// triangle's centroid; further sites come from the positive edge flags of the
+// pieces already carved (the propagation of Alg. 4, kept inside the wave:
+// the triangle's site list lives in LDS, so no global pair lists or atomic
+// labels are needed).  Each piece T_a cap Omega_i is a convex polygon in the
+// plane of T_a, carved by point-in-cell tests (Sec. 4.1) and the edge-based
+// bisector search (Sec. 4.2) along straddling polygon edges (Alg. 1) or the
+// virtual edge from v_i (Alg. 3, v_i is generally off the plane), removing
+// only the run of outside vertices that contains the chosen one (the 2D
+// form of R_p, Sec. 6.3).
+//
+// Polygon layout in LDS: lane t owns vertex t (up to 64); vertex t lies on the
+// supporting plane and on the planes of the edges t-1 -> t and t -> t+1.
+// Per-site sums (mass, centroid, energy, neighbours) are formed afterwards
+// from the pieces in a fixed order (site_reduce), so results do not depend on
+// the order in which waves finish.
 #include "vd_internal.h"
-void vd_launch_surface(const GridView &, const DomainView &, const CellsDev &, hipStream_t) {}
+
+namespace {
+
+constexpr int kSP = 64;        // planes of one polygon
+constexpr int kSV = 64;        // vertices of one polygon (one per lane)
+constexpr int kSS = 128;       // sites of one triangle
+constexpr int kMaxIters = 4096;
+
+struct __align__(16) TriLds {
+  double pn[kSP][4];  // slot 0 supporting plane, 1..3 triangle edges, then bisectors
+  double vy[kSV][3];  // vertex coordinates relative to the current site
+  int plab[kSP];
+  int ve[kSV];        // plane slot of the edge from vertex t to vertex t+1
+  int vst[kSV];       // bit 0 inside, bit 1 tested, bits 8.. nearest site + 1
+  int sq[kSS];        // sites of this triangle (sorted positions), breadth-first
+};
+
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t lowm(int k) { return k >= 64 ? ~0ull : ((1ull << k) - 1ull); }
+
+struct SStats {
+  long long queries = 0, cands = 0, clips = 0;
+};
+
+// vertex of the supporting plane and two planes (Cramer, planes in flag order)
+__device__ __forceinline__ void solve_s(const TriLds &S, int a, int b, double *y) {
+  int q[3] = {0, a, b};
+  if (S.plab[q[2]] < S.plab[q[1]]) { int t = q[1]; q[1] = q[2]; q[2] = t; }
+  const double *n0 = S.pn[q[0]], *n1 = S.pn[q[1]], *n2 = S.pn[q[2]];
+  const double c12[3] = {n1[1] * n2[2] - n1[2] * n2[1], n1[2] * n2[0] - n1[0] * n2[2], n1[0] * n2[1] - n1[1] * n2[0]};
+  const double c20[3] = {n2[1] * n0[2] - n2[2] * n0[1], n2[2] * n0[0] - n2[0] * n0[2], n2[0] * n0[1] - n2[1] * n0[0]};
+  const double c01[3] = {n0[1] * n1[2] - n0[2] * n1[1], n0[2] * n1[0] - n0[0] * n1[2], n0[0] * n1[1] - n0[1] * n1[0]};
+  const double det = n0[0] * c12[0] + n0[1] * c12[1] + n0[2] * c12[2];
+  const double id = 1.0 / det;
+  for (int k = 0; k < 3; k++) y[k] = (n0[3] * c12[k] + n1[3] * c20[k] + n2[3] * c01[k]) * id;
+}
+
+// P <- T_a relative to site v (slot 0 = supporting plane)
+__device__ void init_tri(TriLds &S, const DomainView &D, int a, double vx, double vy, double vz) {
+  const int l = vd_lane();
+  const int *tv = &D.simp[(long long)a * 3];
+  const double *p0 = &D.verts[3 * (long long)tv[0]], *p1 = &D.verts[3 * (long long)tv[1]],
+               *p2 = &D.verts[3 * (long long)tv[2]];
+  const double e1[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
+  const double e2[3] = {p2[0] - p0[0], p2[1] - p0[1], p2[2] - p0[2]};
+  const double N[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+  if (l == 0) {
+    S.pn[0][0] = N[0]; S.pn[0][1] = N[1]; S.pn[0][2] = N[2];
+    S.pn[0][3] = N[0] * (p0[0] - vx) + N[1] * (p0[1] - vy) + N[2] * (p0[2] - vz);
+    S.plab[0] = 2147483647;
+  }
+  if (l >= 1 && l <= 3) {
+    const int e = l - 1;  // edge opposite vertex e: from q_{e+1} to q_{e+2}
+    const double *A = &D.verts[3 * (long long)tv[(e + 1) % 3]], *B = &D.verts[3 * (long long)tv[(e + 2) % 3]];
+    const double d[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+    const double n[3] = {d[1] * N[2] - d[2] * N[1], d[2] * N[0] - d[0] * N[2], d[0] * N[1] - d[1] * N[0]};
+    S.pn[l][0] = n[0]; S.pn[l][1] = n[1]; S.pn[l][2] = n[2];
+    S.pn[l][3] = n[0] * (A[0] - vx) + n[1] * (A[1] - vy) + n[2] * (A[2] - vz);
+    const int b = D.adj[(long long)a * 3 + e];
+    S.plab[l] = b >= 0 ? -(b + 1) : VD_BND_BASE + e;
+  }
+  if (l < 3) {
+    const double *p = &D.verts[3 * (long long)tv[l]];
+    S.vy[l][0] = p[0] - vx; S.vy[l][1] = p[1] - vy; S.vy[l][2] = p[2] - vz;
+    S.ve[l] = 1 + (l + 2) % 3;  // edge from q_l to q_{l+1} is opposite q_{l+2}
+    S.vst[l] = 0;
+  }
+  __syncthreads();
+}
+
+// Drop planes no edge references (slot 0 stays).  Returns the new count.
+__device__ int compact_s(TriLds &S, int npl, int nv) {
+  const int l = vd_lane();
+  uint64_t used = 1ull;
+  if (l < nv) used |= 1ull << S.ve[l];
+  used = wave_or64(used);
+  double pv[4] = {0, 0, 0, 0};
+  int lab = 0;
+  const bool mine = l < npl && ((used >> l) & 1ull);
+  if (mine) { for (int k = 0; k < 4; k++) pv[k] = S.pn[l][k]; lab = S.plab[l]; }
+  const int e = l < nv ? S.ve[l] : 0;
+  __syncthreads();
+  if (mine) {
+    const int ni = __popcll(used & lowm(l));
+    for (int k = 0; k < 4; k++) S.pn[ni][k] = pv[k];
+    S.plab[ni] = lab;
+  }
+  if (l < nv) S.ve[l] = __popcll(used & lowm(e));
+  __syncthreads();
+  return __popcll(used);
+}
+
+// Clip the polygon by plane slot P, removing the run of consecutive outside
+// vertices that contains vertex pt (pt < 0: the farthest outside vertex).
+// Returns 0 unchanged, 1 empty, 2 capacity, 3 degenerate, 4 cut.
+__device__ int clip_s(TriLds &S, int P, int pt, int &nv) {
+  const int l = vd_lane();
+  const double nx = S.pn[P][0], ny = S.pn[P][1], nz = S.pn[P][2], c = S.pn[P][3];
+  double y0 = 0, y1 = 0, y2 = 0, sd = -1.0;
+  int e = 0, st = 0;
+  const bool v = l < nv;
+  if (v) {
+    y0 = S.vy[l][0]; y1 = S.vy[l][1]; y2 = S.vy[l][2];
+    e = S.ve[l]; st = S.vst[l];
+    sd = nx * y0 + ny * y1 + nz * y2 - c;
+  }
+  const uint64_t O = __ballot(v && sd > 0.0);
+  if (!O) return pt < 0 ? 0 : 3;
+  if (pt < 0) {
+    double b = -sd;
+    int bi = l;
+    group_argmin(b, bi, 64);
+    pt = uni(bi);
+  } else if (!((O >> pt) & 1ull)) {
+    return 3;
+  }
+  // the run [a, b] of outside vertices around pt (cyclic)
+  int a = pt, b = pt, len = 1;
+  while (len < nv && ((O >> ((a + nv - 1) % nv)) & 1ull)) { a = (a + nv - 1) % nv; len++; }
+  while (len < nv && ((O >> ((b + 1) % nv)) & 1ull)) { b = (b + 1) % nv; len++; }
+  if (len >= nv) return 1;
+  const int keep = nv - len;
+  if (keep + 2 > kSV) return 2;
+  const int am1 = (a + nv - 1) % nv;
+  const int eA = uni(S.ve[am1]), eB = uni(S.ve[b]);
+  __syncthreads();
+  // kept vertex t moves to (t - b - 1) mod nv; new vertices at keep, keep+1
+  const int k = (l - b - 1 + 2 * nv) % nv;
+  const bool kept = v && k < keep;
+  if (kept) {
+    S.vy[k][0] = y0; S.vy[k][1] = y1; S.vy[k][2] = y2;
+    S.ve[k] = e;
+    S.vst[k] = st;
+  }
+  __syncthreads();
+  if (l == 0 || l == 1) {
+    double yy[3];
+    if (l == 0) solve_s(S, eA, P, yy); else solve_s(S, P, eB, yy);
+    const int t = keep + l;
+    S.vy[t][0] = yy[0]; S.vy[t][1] = yy[1]; S.vy[t][2] = yy[2];
+    S.ve[t] = l == 0 ? P : eB;
+    S.vst[t] = 0;
+  }
+  __syncthreads();
+  nv = keep + 2;
+  return 4;
+}
+
+struct SParams {
+  int improved, straddle, max_iters;
+};
+
+// Carve the polygon until every vertex is certified inside Omega_i (TEST /
+// LAMBDA / SEARCH queries as in the 3D kernel).  Returns 0, 1 empty, 2, 3.
+__device__ int carve_s(TriLds &S, const GridView &G, const SParams C, int si, double vx, double vy, double vz,
+                       double delta, int &npl, int &nv, SStats &ss) {
+  enum { PICK = 0, TEST, LAMBDA, SEARCH };
+  const int l = vd_lane();
+  const int grp = l >> 4;
+  int mode = PICK;
+  int pt = -1, j = -1, ef0 = -2, lam = 2, nstep = 0, tslot = -1, nbatch = 0;
+  double A0 = 0, A1 = 0, A2 = 0, g0 = 0, g1 = 0, g2 = 0, u0 = 0, u1 = 0, u2 = 0, L = 0;
+  double n0 = 0, n1 = 0, n2 = 0, nc3 = 0, q0 = 0, q1 = 0, q2 = 0;
+  auto bisector_point = [&]() {
+    n0 = G.sx[j] - vx; n1 = G.sy[j] - vy; n2 = G.sz[j] - vz;
+    nc3 = 0.5 * (n0 * n0 + n1 * n1 + n2 * n2);
+    const double e0 = g0 - A0, e1 = g1 - A1, e2 = g2 - A2;
+    const double den = n0 * e0 + n1 * e1 + n2 * e2;
+    const double num = nc3 - (n0 * A0 + n1 * A1 + n2 * A2);
+    double t = den > 0.0 ? num / den : 1.0;
+    t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+    q0 = A0 + t * e0; q1 = A1 + t * e1; q2 = A2 + t * e2;
+  };
+  for (int it = 0; it < kMaxIters; it++) {
+    if (mode == PICK) {
+      const int vs = l < nv ? S.vst[l] : 0;
+      const uint64_t T = __ballot(vs & 2), I = __ballot(vs & 1);
+      const uint64_t O = T & ~I;
+      if (!O) {
+        const uint64_t U = lowm(nv) & ~T;
+        if (!U) return 0;
+        tslot = -1;
+        nbatch = 0;
+        uint64_t m = U;
+        while (m && nbatch < 4) {
+          const int b = __ffsll((unsigned long long)m) - 1;
+          if (nbatch == grp) tslot = b;
+          nbatch++;
+          m &= m - 1;
+        }
+        const int s = tslot >= 0 ? tslot : __ffsll((unsigned long long)U) - 1;
+        q0 = S.vy[s][0]; q1 = S.vy[s][1]; q2 = S.vy[s][2];
+        mode = TEST;
+      } else {
+        pt = -1;
+        int ps = -1, edge = -1;
+        if (C.straddle) {
+          // outside vertex with an inside neighbour along the polygon
+          const bool out = (O >> l) & 1ull;
+          const int prv = (l + nv - 1) % (nv > 0 ? nv : 1), nxt = (l + 1) % (nv > 0 ? nv : 1);
+          const bool cand = out && (((I >> prv) & 1ull) || ((I >> nxt) & 1ull));
+          const uint64_t Cm = __ballot(cand);
+          if (Cm) {
+            pt = __ffsll((unsigned long long)Cm) - 1;
+            const int pp = (pt + nv - 1) % nv, pn_ = (pt + 1) % nv;
+            if ((I >> pp) & 1ull) { ps = pp; edge = pp; } else { ps = pn_; edge = pt; }
+          }
+        }
+        if (pt < 0) pt = __ffsll((unsigned long long)O) - 1;
+        A0 = A1 = A2 = 0;
+        if (ps >= 0) { A0 = S.vy[ps][0]; A1 = S.vy[ps][1]; A2 = S.vy[ps][2]; }
+        g0 = S.vy[pt][0]; g1 = S.vy[pt][1]; g2 = S.vy[pt][2];
+        j = uni((S.vst[pt] >> 8) - 1);
+        if (j < 0 || j == si) return 3;
+        ef0 = -2;
+        if (edge >= 0) {
+          const int lab = uni(S.plab[uni(S.ve[edge])]);
+          ef0 = lab >= 0 ? lab : -2;
+        }
+        nstep = 0;
+        const double d0 = g0 - A0, d1 = g1 - A1, d2 = g2 - A2;
+        L = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        if (C.improved && L > 0 && 2.0 * delta < L) {
+          u0 = d0 / L; u1 = d1 / L; u2 = d2 / L;
+          lam = 2;
+          q0 = A0 + 2.0 * delta * u0; q1 = A1 + 2.0 * delta * u1; q2 = A2 + 2.0 * delta * u2;
+          mode = LAMBDA;
+        } else {
+          bisector_point();
+          mode = SEARCH;
+        }
+      }
+    }
+    const int gs = mode == TEST ? 16 : 64;
+    const double qx = vx + q0, qy = vy + q1, qz = vz + q2;
+    const double dx = qx - vx, dy = qy - vy, dz = qz - vz;
+    const int kq = nn_query(G, gs, qx, qy, qz, dx * dx + dy * dy + dz * dz, si, ss.cands);
+    if (mode == TEST) {
+      ss.queries += nbatch;
+      bool in = false;
+      if (tslot >= 0) {
+        const int prv = (tslot + nv - 1) % nv;
+        in = (kq == si) || (kq == S.plab[S.ve[prv]]) || (kq == S.plab[S.ve[tslot]]);
+      }
+      __syncthreads();
+      if (tslot >= 0 && (l & 15) == 0) S.vst[tslot] = (in ? 1 : 0) | 2 | ((kq + 1) << 8);
+      __syncthreads();
+      mode = PICK;
+      continue;
+    }
+    ss.queries++;
+    const int k = uni(kq);
+    if (mode == LAMBDA) {
+      if (k != si && k != ef0) {
+        j = k; g0 = q0; g1 = q1; g2 = q2;
+      } else {
+        lam++;
+        if (lam < 2 + C.max_iters && lam * delta < L) {
+          const double tt = lam * delta;
+          q0 = A0 + tt * u0; q1 = A1 + tt * u1; q2 = A2 + tt * u2;
+          continue;
+        }
+      }
+      bisector_point();
+      mode = SEARCH;
+      continue;
+    }
+    if (!(k == si || k == j || k == ef0)) {
+      if (++nstep >= C.max_iters) return 3;
+      j = k;
+      g0 = q0; g1 = q1; g2 = q2;
+      bisector_point();
+      continue;
+    }
+    if (npl >= kSP) {
+      npl = compact_s(S, npl, nv);
+      if (npl >= kSP) return 2;
+    }
+    const int P = npl++;
+    __syncthreads();
+    if (l == 0) {
+      S.pn[P][0] = n0; S.pn[P][1] = n1; S.pn[P][2] = n2; S.pn[P][3] = nc3;
+      S.plab[P] = j;
+    }
+    __syncthreads();
+    const int rc = clip_s(S, P, pt, nv);
+    ss.clips++;
+    if (rc == 1) return 1;
+    if (rc != 4) return rc == 0 ? 3 : rc;
+    mode = PICK;
+  }
+  return 3;
+}
+
+__device__ __forceinline__ int conv(const GridView &G, int lab) { return lab >= 0 ? G.perm[lab] : lab; }
+
+__global__ void __launch_bounds__(64) surface_kernel(GridView G, DomainView D, const CellsDev *__restrict__ Cp) {
+  __shared__ TriLds S;
+  const int l = vd_lane();
+  const int a = blockIdx.x;
+  if (a >= D.m) return;
+  const CellsDev &C = *Cp;
+  const SParams P = {C.improved, C.straddle, C.max_iters};
+  SStats ss;
+  int err = 0;
+  // seed: nearest site of the centroid (Alg. 4)
+  int nsq = 0, head = 0;
+  {
+    const int *tv = &D.simp[(long long)a * 3];
+    const double *p0 = &D.verts[3 * (long long)tv[0]], *p1 = &D.verts[3 * (long long)tv[1]],
+                 *p2 = &D.verts[3 * (long long)tv[2]];
+    const double cx = (p0[0] + p1[0] + p2[0]) / 3.0, cy = (p0[1] + p1[1] + p2[1]) / 3.0,
+                 cz = (p0[2] + p1[2] + p2[2]) / 3.0;
+    const int k = uni(nn_query(G, 64, cx, cy, cz, 1e300, -1, ss.cands));
+    ss.queries++;
+    if (k >= 0) {
+      if (l == 0) S.sq[0] = k;
+      nsq = 1;
+    } else {
+      err = 3;
+    }
+  }
+  __syncthreads();
+  while (head < nsq && !err) {
+    const int si = S.sq[head++];
+    const double vx = G.sx[si], vy = G.sy[si], vz = G.sz[si], delta = G.delta[si];
+    init_tri(S, D, a, vx, vy, vz);
+    int npl = 4, nv = 3;
+    const int rc = carve_s(S, G, P, si, vx, vy, vz, delta, npl, nv, ss);
+    if (rc == 1) continue;
+    if (rc) { err = rc; break; }
+    // ---- moments: fan from the foot of v_i on the supporting plane ----
+    const double N0 = S.pn[0][0], N1 = S.pn[0][1], N2 = S.pn[0][2], Nc = S.pn[0][3];
+    const double nn2 = N0 * N0 + N1 * N1 + N2 * N2;
+    const double fN = Nc / nn2, inrm = 1.0 / sqrt(nn2);
+    const double r0 = N0 * fN, r1 = N1 * fN, r2 = N2 * fN;
+    double pa = 0, pmx = 0, pmy = 0, pmz = 0, pe = 0;
+    if (l < nv) {
+      const int t2 = (l + 1) % nv;
+      const double a0 = S.vy[l][0] - r0, a1 = S.vy[l][1] - r1, a2 = S.vy[l][2] - r2;
+      const double b0 = S.vy[t2][0] - r0, b1 = S.vy[t2][1] - r1, b2 = S.vy[t2][2] - r2;
+      const double cr0 = a1 * b2 - a2 * b1, cr1 = a2 * b0 - a0 * b2, cr2 = a0 * b1 - a1 * b0;
+      const double ar = 0.5 * (cr0 * N0 + cr1 * N1 + cr2 * N2) * inrm;
+      const double y0 = S.vy[l][0], y1 = S.vy[l][1], y2 = S.vy[l][2];
+      const double z0 = S.vy[t2][0], z1 = S.vy[t2][1], z2 = S.vy[t2][2];
+      const double s0 = r0 + y0 + z0, s1 = r1 + y1 + z1, s2 = r2 + y2 + z2;
+      pa = ar;
+      pmx = ar * s0 / 3.0; pmy = ar * s1 / 3.0; pmz = ar * s2 / 3.0;
+      pe = ar / 12.0 * (r0 * r0 + r1 * r1 + r2 * r2 + y0 * y0 + y1 * y1 + y2 * y2 + z0 * z0 + z1 * z1 + z2 * z2 +
+                        s0 * s0 + s1 * s1 + s2 * s2);
+    }
+    pa = wave_sum(pa); pmx = wave_sum(pmx); pmy = wave_sum(pmy); pmz = wave_sum(pmz); pe = wave_sum(pe);
+    if (!(pa > 0.0)) continue;
+    const int orig = G.perm[si];
+    long long pidx = 0, fo = 0, vo = 0;
+    if (l == 0) {
+      pidx = (long long)atomicAdd(&C.cnt[CNT_PIECES], 1ull);
+      fo = (long long)atomicAdd(&C.cnt[CNT_FACES], (unsigned long long)nv);
+      vo = (long long)atomicAdd(&C.cnt[CNT_VERTS], (unsigned long long)nv);
+      atomicAdd(&C.pcount[orig], 1);
+    }
+    pidx = __shfl(pidx, 0, 64);
+    fo = __shfl(fo, 0, 64);
+    vo = __shfl(vo, 0, 64);
+    if (C.want_grad) {
+      // segment moments of the bisector edges: a point of the edge moves in
+      // the plane of T_a with speed (x - v_i).dv / (d s), s = |n - (n.N)N|
+      // (n, N unit normals of the bisector and of T_a); 2-point Gauss-Legendre
+      // is exact for the cubic integrand
+      const int lab = l < nv ? S.plab[S.ve[l]] : -1;
+      const uint64_t pos = __ballot(lab >= 0);
+      const int npos = __popcll(pos);
+      long long base = 0;
+      if (l == 0) base = (long long)atomicAdd(&C.cnt[CNT_FINT], (unsigned long long)npos);
+      base = __shfl(base, 0, 64);
+      if (l == 0 && pidx < C.cap_piece) { C.piece_fint_start[pidx] = base; C.piece_nfint[pidx] = npos; }
+      const long long r = base + __popcll(pos & lowm(l));
+      if (lab >= 0 && r < C.cap_fint) {
+        const int t2 = (l + 1) % nv;
+        const double n0 = G.sx[lab] - vx, n1 = G.sy[lab] - vy, n2 = G.sz[lab] - vz;
+        const double d = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+        const double h0 = n0 / d, h1 = n1 / d, h2 = n2 / d;
+        const double M0 = N0 * inrm, M1 = N1 * inrm, M2 = N2 * inrm;
+        const double hn = h0 * M0 + h1 * M1 + h2 * M2;
+        const double e0 = h0 - hn * M0, e1 = h1 - hn * M1, e2 = h2 - hn * M2;
+        const double sfac = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+        const double a0 = S.vy[l][0], a1 = S.vy[l][1], a2 = S.vy[l][2];
+        const double b0 = S.vy[t2][0], b1 = S.vy[t2][1], b2 = S.vy[t2][2];
+        const double ln = sqrt((b0 - a0) * (b0 - a0) + (b1 - a1) * (b1 - a1) + (b2 - a2) * (b2 - a2));
+        double I[12];
+        for (int k = 0; k < 12; k++) I[k] = 0.0;
+        const double gq = 0.5 / sqrt(3.0);
+        for (int g = 0; g < 2; g++) {
+          const double xi = g == 0 ? 0.5 - gq : 0.5 + gq;
+          const double y0 = a0 + xi * (b0 - a0), y1 = a1 + xi * (b1 - a1), y2 = a2 + xi * (b2 - a2);
+          const double w = 0.5 * ln;
+          const double yy = y0 * y0 + y1 * y1 + y2 * y2;
+          I[0] += w * y0; I[1] += w * y1; I[2] += w * y2;
+          I[3] += w * y0 * y0; I[4] += w * y0 * y1; I[5] += w * y0 * y2;
+          I[6] += w * y1 * y1; I[7] += w * y1 * y2; I[8] += w * y2 * y2;
+          I[9] += w * yy * y0; I[10] += w * yy * y1; I[11] += w * yy * y2;
+        }
+        const double sc = 1.0 / (d * sfac);
+        for (int k = 0; k < 12; k++) C.fint[12 * r + k] = I[k] * sc;
+        C.fint_lab[r] = G.perm[lab];
+      }
+    }
+    if (pidx < C.cap_piece) {
+      if (l == 0) {
+        C.piece_site[pidx] = orig;
+        C.piece_simplex[pidx] = a;
+        C.piece_nface[pidx] = nv;
+        C.piece_nvert[pidx] = nv;
+        C.piece_mass[pidx] = pa;
+        C.piece_mom[3 * pidx + 0] = pmx + pa * vx;
+        C.piece_mom[3 * pidx + 1] = pmy + pa * vy;
+        C.piece_mom[3 * pidx + 2] = pmz + pa * vz;
+        C.piece_energy[pidx] = pe;
+        C.piece_fstart[pidx] = fo;
+        C.piece_vstart[pidx] = vo;
+      }
+      if (fo + nv <= C.cap_face && vo + nv <= C.cap_vert && l < nv) {
+        const int prv = (l + nv - 1) % nv;
+        C.face_label[fo + l] = conv(G, S.plab[S.ve[l]]);
+        C.vert_xyz[3 * (vo + l) + 0] = S.vy[l][0] + vx;
+        C.vert_xyz[3 * (vo + l) + 1] = S.vy[l][1] + vy;
+        C.vert_xyz[3 * (vo + l) + 2] = S.vy[l][2] + vz;
+        C.vert_label[3 * (vo + l) + 0] = conv(G, S.plab[S.ve[prv]]);
+        C.vert_label[3 * (vo + l) + 1] = conv(G, S.plab[S.ve[l]]);
+        C.vert_label[3 * (vo + l) + 2] = 2147483647;
+      }
+    }
+    // ---- propagate over positive edge flags (Alg. 4) ----
+    const int lab = l < nv ? S.plab[S.ve[l]] : -1;
+    uint64_t pos = __ballot(lab >= 0);
+    for (; pos; pos &= pos - 1) {
+      const int t = __ffsll((unsigned long long)pos) - 1;
+      const int j = uni(__shfl(lab, t, 64));
+      bool have = false;
+      for (int e = l; e < nsq; e += 64) have = have || (S.sq[e] == j);
+      if (!__ballot(have)) {
+        if (nsq >= kSS) { err = 2; break; }
+        __syncthreads();
+        if (l == 0) S.sq[nsq] = j;
+        nsq++;
+        __syncthreads();
+      }
+    }
+    __syncthreads();
+  }
+  if (l == 0) {
+    atomicAdd(&C.cnt[CNT_QUERIES], (unsigned long long)ss.queries);
+    atomicAdd(&C.cnt[CNT_CLIPS], (unsigned long long)ss.clips);
+    atomicAdd(&C.cnt[CNT_CANDS], (unsigned long long)ss.cands);
+    if (err) {
+      atomicAdd(&C.cnt[err == 2 ? CNT_ERR_CAP : CNT_ERR_DEG], 1ull);
+      atomicMin((int *)&C.cnt[CNT_BAD_SITE], a);
+    }
+  }
+}
+
+// Per-site sums over the site's pieces (CSR order: ascending simplex) and the
+// sorted, de-duplicated positive edge flags as neighbour list.
+constexpr int kB = 256;
+constexpr int kNbLocal = 96;
+
+__global__ void __launch_bounds__(kB) site_reduce(long long n, const long long *__restrict__ poff,
+                                                  const int *__restrict__ pid, const CellsDev *__restrict__ Cp) {
+  const long long i = (long long)blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+  const CellsDev &C = *Cp;
+  double m = 0, mx = 0, my = 0, mz = 0, e = 0;
+  int nb[kNbLocal];
+  int cnt = 0, overflow = 0;
+  for (long long q = poff[i]; q < poff[i + 1]; q++) {
+    const int p = pid[q];
+    m += C.piece_mass[p];
+    mx += C.piece_mom[3 * (long long)p + 0];
+    my += C.piece_mom[3 * (long long)p + 1];
+    mz += C.piece_mom[3 * (long long)p + 2];
+    e += C.piece_energy[p];
+    const long long f0 = C.piece_fstart[p];
+    for (int f = 0; f < C.piece_nface[p]; f++) {
+      const int lab = C.face_label[f0 + f];
+      if (lab < 0) continue;
+      int k = 0;
+      while (k < cnt && nb[k] < lab) k++;
+      if (k < cnt && nb[k] == lab) continue;
+      if (cnt >= kNbLocal) { overflow = 1; continue; }
+      for (int x = cnt; x > k; x--) nb[x] = nb[x - 1];
+      nb[k] = lab;
+      cnt++;
+    }
+  }
+  C.mass[i] = m;
+  C.mom[3 * i + 0] = mx;
+  C.mom[3 * i + 1] = my;
+  C.mom[3 * i + 2] = mz;
+  C.energy[i] = e;
+  const long long s0 = (long long)atomicAdd(&C.cnt[CNT_NBRS], (unsigned long long)cnt);
+  C.ncount[i] = cnt;
+  C.nstart[i] = s0;
+  if (s0 + cnt <= C.cap_nbr)
+    for (int k = 0; k < cnt; k++) C.nbr_arena[s0 + k] = nb[k];
+  if (overflow) {
+    atomicAdd(&C.cnt[CNT_ERR_CAP], 1ull);
+    atomicMin((int *)&C.cnt[CNT_BAD_SITE], (int)i);
+  }
+}
+
+}  // namespace
+
+void vd_launch_surface(const GridView &G, const DomainView &D, const CellsDev *Cdev, hipStream_t st) {
+  hipLaunchKernelGGL(surface_kernel, dim3((unsigned)D.m), dim3(64), 0, st, G, D, Cdev);
+}
+
+void vd_launch_site_reduce(long long n, const long long *poff, const int *pid, const CellsDev *Cdev,
+                           hipStream_t st) {
+  const unsigned nb = (unsigned)((n + kB - 1) / kB > 0 ? (n + kB - 1) / kB : 1);
+  hipLaunchKernelGGL(site_reduce, dim3(nb), dim3(kB), 0, st, n, poff, pid, Cdev);
+}

@@ -78,19 +78,21 @@ __device__ __forceinline__ int cell_coord(double x, double lo, double ih, int g)
   return (int)t;
 }
 
-// Scans every site whose grid cell lies in the box [b0, b1] (inclusive, per
-// axis) and folds it into the per-lane best (bd, bk).  The box is split into
-// x-rows; a row of consecutive cells is one contiguous range of sorted sites,
-// so the wave flattens all rows into one candidate list and lane t takes
-// candidates t, t+64, ...  (coalesced SoA loads).
-__device__ __forceinline__ void nn_scan_box(const GridView &G, int x0, int x1, int y0, int y1,
-                                            int z0, int z1, double qx, double qy, double qz,
-                                            double &bd, int &bk, long long &ncand) {
-  const int l = vd_lane();
-  const int nx = x1 - x0 + 1, ny = y1 - y0 + 1, nz = z1 - z0 + 1;
-  const int R = ny * nz;
-  for (int r0 = 0; r0 < R; r0 += 64) {
-    const int r = r0 + l;
+// ---------------------------------------------------------------------------
+// nearest-site query by a group of gs lanes (gs = 64: the whole wave; gs = 16:
+// four independent queries per wave).  q and the known candidate (r2, k0) are
+// uniform within a group.  The candidate box is split into x-rows; a row of
+// consecutive cells is one contiguous range of sorted sites, so the group
+// flattens all rows into one candidate list (coalesced SoA loads).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void scan_box(const GridView &G, int gs, int x0, int x1, int y0, int y1, int z0,
+                                         int z1, double qx, double qy, double qz, double &bd, int &bk,
+                                         long long &ncand) {
+  const int gl = vd_lane() & (gs - 1);
+  const int nx = x1 - x0 + 1, ny = y1 - y0 + 1;
+  const int R = ny * (z1 - z0 + 1);
+  for (int r0 = 0; r0 < R; r0 += gs) {
+    const int r = r0 + gl;
     int st = 0, cnt = 0;
     if (r < R) {
       const int yy = y0 + r % ny, zz = z0 + r / ny;
@@ -98,23 +100,25 @@ __device__ __forceinline__ void nn_scan_box(const GridView &G, int x0, int x1, i
       st = G.cstart[c0];
       cnt = G.cstart[c0 + nx] - st;
     }
-    const int inc = wave_incl_scan(cnt);
+    int inc = cnt;
+    for (int d = 1; d < gs; d <<= 1) {
+      const int o = __shfl_up(inc, d, gs);
+      if (gl >= d) inc += o;
+    }
     const int excl = inc - cnt;
-    const int total = __shfl(inc, 63, 64);
-    const int nrows = (R - r0) < 64 ? (R - r0) : 64;
+    const int total = __shfl(inc, gs - 1, gs);
+    const int nrows = (R - r0) < gs ? (R - r0) : gs;
     ncand += total;
-    for (int base = 0; base < total; base += 64) {
-      const int t = base + l;
-      // largest row rr with excl[rr] <= t (rows are ordered by offset)
+    for (int base = 0; base < total; base += gs) {
+      const int t = base + gl;
       int rr = 0;
-#pragma unroll
-      for (int step = 32; step >= 1; step >>= 1) {
+      for (int step = gs >> 1; step >= 1; step >>= 1) {
         const int cand = rr + step;
-        const int v = __shfl(excl, cand & 63, 64);
+        const int v = __shfl(excl, cand & (gs - 1), gs);
         if (cand < nrows && v <= t) rr = cand;
       }
-      const int rst = __shfl(st, rr, 64);
-      const int rex = __shfl(excl, rr, 64);
+      const int rst = __shfl(st, rr, gs);
+      const int rex = __shfl(excl, rr, gs);
       if (t < total) {
         const int p = rst + (t - rex);
         const double dx = qx - G.sx[p], dy = qy - G.sy[p], dz = qz - G.sz[p];
@@ -125,37 +129,44 @@ __device__ __forceinline__ void nn_scan_box(const GridView &G, int x0, int x1, i
   }
 }
 
-// Nearest site of q (absolute coordinates), wave-cooperative: every lane calls
-// it with the same q and gets the same answer.  (r2, k0) is a known candidate
-// (distance^2 and sorted position), e.g. the site whose cell is being carved.
-// Ties break towards the lower sorted position.  Returns the sorted position.
-__device__ __forceinline__ int nn_query(const GridView &G, double qx, double qy, double qz,
-                                        double r2, int k0, double &out_d2, long long &ncand) {
+__device__ __forceinline__ void group_argmin(double &d, int &k, int gs) {
+  for (int m = gs >> 1; m >= 1; m >>= 1) {
+    const double od = __shfl_xor(d, m, 64);
+    const int ok = __shfl_xor(k, m, 64);
+    if (od < d || (od == d && ok < k)) { d = od; k = ok; }
+  }
+}
+
+__device__ __forceinline__ int nn_query(const GridView &G, int gs, double qx, double qy, double qz, double r2,
+                                        int k0, long long &ncand) {
   const double lox = G.geom[0], loy = G.geom[1], loz = G.geom[2];
   const double ihx = G.geom[6], ihy = G.geom[7], ihz = G.geom[8];
   const int gx = G.g[0], gy = G.g[1], gz = G.g[2];
   double bd = r2;
   int bk = k0;
-  const int cx = cell_coord(qx, lox, ihx, gx), cy = cell_coord(qy, loy, ihy, gy),
-            cz = cell_coord(qz, loz, ihz, gz);
-  double r = sqrt(r2);
-  // phase 1: the 3x3x3 block around q's cell, trimmed to the ball of radius r
-  int x0 = max(cx - 1, cell_coord(qx - r, lox, ihx, gx)), x1 = min(cx + 1, cell_coord(qx + r, lox, ihx, gx));
-  int y0 = max(cy - 1, cell_coord(qy - r, loy, ihy, gy)), y1 = min(cy + 1, cell_coord(qy + r, loy, ihy, gy));
-  int z0 = max(cz - 1, cell_coord(qz - r, loz, ihz, gz)), z1 = min(cz + 1, cell_coord(qz + r, loz, ihz, gz));
-  nn_scan_box(G, x0, x1, y0, y1, z0, z1, qx, qy, qz, bd, bk, ncand);
-  wave_argmin(bd, bk);
-  // phase 2: if the ball of the best radius leaves the scanned box, scan the
-  // whole box of that ball (the best radius only shrinks, so once suffices)
-  r = sqrt(bd);
-  const int X0 = cell_coord(qx - r, lox, ihx, gx), X1 = cell_coord(qx + r, lox, ihx, gx);
-  const int Y0 = cell_coord(qy - r, loy, ihy, gy), Y1 = cell_coord(qy + r, loy, ihy, gy);
-  const int Z0 = cell_coord(qz - r, loz, ihz, gz), Z1 = cell_coord(qz + r, loz, ihz, gz);
-  if (X0 < x0 || X1 > x1 || Y0 < y0 || Y1 > y1 || Z0 < z0 || Z1 > z1) {
-    nn_scan_box(G, X0, X1, Y0, Y1, Z0, Z1, qx, qy, qz, bd, bk, ncand);
-    wave_argmin(bd, bk);
+  const int cx = cell_coord(qx, lox, ihx, gx), cy = cell_coord(qy, loy, ihy, gy), cz = cell_coord(qz, loz, ihz, gz);
+  // Boxes of growing half-width R (in cells) around q's cell, each trimmed to
+  // the ball of the best distance so far; stop once that ball lies inside the
+  // scanned box (every site closer than the best has then been seen).  R = 1
+  // is the usual 3x3x3 block; far query points double R.
+  int R = 1;
+  for (int round = 0; round < 32; round++) {
+    const double r = sqrt(bd);
+    const int X0 = cell_coord(qx - r, lox, ihx, gx), X1 = cell_coord(qx + r, lox, ihx, gx);
+    const int Y0 = cell_coord(qy - r, loy, ihy, gy), Y1 = cell_coord(qy + r, loy, ihy, gy);
+    const int Z0 = cell_coord(qz - r, loz, ihz, gz), Z1 = cell_coord(qz + r, loz, ihz, gz);
+    const int x0 = max(cx - R, X0), x1 = min(cx + R, X1);
+    const int y0 = max(cy - R, Y0), y1 = min(cy + R, Y1);
+    const int z0 = max(cz - R, Z0), z1 = min(cz + R, Z1);
+    scan_box(G, gs, x0, x1, y0, y1, z0, z1, qx, qy, qz, bd, bk, ncand);
+    group_argmin(bd, bk, gs);
+    const double rn = sqrt(bd);
+    const bool inside = cell_coord(qx - rn, lox, ihx, gx) >= x0 && cell_coord(qx + rn, lox, ihx, gx) <= x1 &&
+                        cell_coord(qy - rn, loy, ihy, gy) >= y0 && cell_coord(qy + rn, loy, ihy, gy) <= y1 &&
+                        cell_coord(qz - rn, loz, ihz, gz) >= z0 && cell_coord(qz + rn, loz, ihz, gz) <= z1;
+    if (inside) break;
+    R *= 2;
   }
-  out_d2 = bd;
   return bk;
 }
 

@@ -93,9 +93,12 @@ struct CellsDev {
   long long cap_piece;
   int *face_label; long long cap_face;
   double *vert_xyz; int *vert_label; long long cap_vert;
-  // face integrals for the adjoint: per (site, neighbour) pair, 16 doubles
-  // {k, A[3], B[9], C[3]} summed over the site's pieces; stored by neighbour slot
-  double *fint; long long cap_fint;
+  // face moments for the adjoint (want_grad): one record per bisector face of a
+  // piece: 12 doubles {I0[3], I1[6] (xx,xy,xz,yy,yz,zz), I2[3]} with
+  // I0 = int y/d, I1 = int y y^T/d, I2 = int |y|^2 y/d (y = x - v_i, d = |v_k - v_i|,
+  // divided by the in-plane sine for surface edges), and the neighbour k
+  double *fint; int *fint_lab; long long cap_fint;
+  long long *piece_fint_start; int *piece_nfint;
   int *seed;  // 3D: tetrahedron containing each site (sorted position order)
   int *facet, *nfacet;  // cell-first: facet labels [n * VD_F_MAX], counts [n] (sorted order)
 };
@@ -121,6 +124,8 @@ struct vd_cells_s {
   double carve_ms = -1.0, split_ms = -1.0;
   CellsDev *d_dev = nullptr;  // device copy of d (read by the piece kernel)
   CellsDev d_shadow{};        // host copy last sent to d_dev
+  double *wbuf = nullptr;     // adjoint weights [5n]
+  int64_t cap_w = 0;
 };
 
 // launchers (defined in the .hip files)
@@ -131,7 +136,9 @@ void vd_launch_locate_sites(const GridView &G, const DomainView &D, int *seed, u
 void vd_launch_cells3d(const GridView &G, const CellsDev &C, hipStream_t st);
 void vd_launch_pieces3d(const GridView &G, const DomainView &D, const CellsDev *Cdev, int carve_each,
                         hipStream_t st);
-void vd_launch_surface(const GridView &G, const DomainView &D, const CellsDev &C, hipStream_t st);
+void vd_launch_surface(const GridView &G, const DomainView &D, const CellsDev *Cdev, hipStream_t st);
+void vd_launch_site_reduce(long long n, const long long *poff, const int *pid, const CellsDev *Cdev,
+                           hipStream_t st);
 void vd_launch_finalize(vd_cells c, hipStream_t st);
 void vd_launch_moments(const vd_cells_s *c, const GridView &G, double *mass, double *cent,
                        double *energy, hipStream_t st);

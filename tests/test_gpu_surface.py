@@ -1,0 +1,79 @@
+"""GPU parity of the restricted (surface) Voronoi path against the CPU oracle.
+
+Triangle meshes in R^3 cut by 3D bisectors (Alg. 4 propagation inside each
+triangle).  Same bar as the 3D path: bit-exact combinatorics, moments within
+1e-9 relative.
+"""
+import numpy as np
+import pytest
+
+import vdgen
+from gpu_util import assert_parity, gpu_neighbors, log, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _area(dom):
+    q = dom.verts[dom.simplices]
+    return 0.5 * np.linalg.norm(np.cross(q[:, 1] - q[:, 0], q[:, 2] - q[:, 0]), axis=1)
+
+
+def _surface_case(oracle_mod, sites, dom, brute=True, **opts):
+    log(f"surface case n={len(sites)} m={dom.m} opts={opts}")
+    area = float(_area(dom).sum())
+    gpu = run_gpu(sites, dom, bbox=(-1.01, -1.01, -1.01, 1.01, 1.01, 1.01), surface_area=area, **opts)
+    ref = oracle_mod.compute(sites, dom, brute=brute)
+    mom = oracle_mod.site_moments(ref, sites)
+    assert_parity(gpu, ref, mom, len(sites))
+    assert abs(gpu["mass"].sum() - area) <= 1e-12 * area
+    return gpu
+
+
+@pytest.mark.parametrize("n,level,seed", [(40, 2, 3), (500, 3, 4), (3000, 4, 5)])
+def test_sphere_parity(oracle_mod, n, level, seed):
+    s = vdgen.sphere_sites(n, seed=seed)
+    _surface_case(oracle_mod, s, vdgen.icosphere(level), brute=(n <= 500))
+
+
+@pytest.mark.parametrize("straddle,improved", [(0, 0), (1, 1)])
+def test_sphere_search_variants(oracle_mod, straddle, improved):
+    s = vdgen.sphere_sites(800, seed=8)
+    _surface_case(oracle_mod, s, vdgen.icosphere(3), brute=False, use_straddle_edges=straddle,
+                  improved_search=improved)
+
+
+def test_sites_off_the_surface(oracle_mod):
+    """Sites at radius 0.8..1.2 around the sphere mesh (not on it)."""
+    rng = np.random.default_rng(21)
+    s = vdgen.sphere_sites(600, seed=22) * rng.uniform(0.8, 1.2, size=(600, 1))
+    _surface_case(oracle_mod, s, vdgen.icosphere(3), brute=False)
+
+
+def test_c5_full_size_sampled(oracle_mod):
+    """C5 at its full size: 200,000 sites on S^2, level-6 icosphere (81,920
+    triangles).  Sampled sites against the oracle; partition for all."""
+    s, dom = vdgen.config_c5()
+    area = float(_area(dom).sum())
+    gpu = run_gpu(s, dom, bbox=(-1.01, -1.01, -1.01, 1.01, 1.01, 1.01), surface_area=area)
+    log(f"C5 info {gpu['info']}")
+    n = len(s)
+    assert abs(gpu["mass"].sum() - area) <= 1e-11 * area
+    rng = np.random.default_rng(2025)
+    sample = np.sort(rng.choice(n, size=100, replace=False))
+    ref = oracle_mod.compute(s, dom, only_sites=sample)
+    mom = oracle_mod.site_moments(ref, s)
+    assert_parity(gpu, ref, mom, n, sites_subset=sample)
+    res = gpu["res"]
+    per = np.bincount(res["piece_simplex"], weights=res["piece_mass"], minlength=dom.m)
+    assert np.allclose(per, _area(dom), rtol=1e-10, atol=0)
+    nb = gpu_neighbors(gpu, n)
+    for i in rng.choice(n, size=2000, replace=False):
+        for j in nb[i]:
+            assert i in set(nb[j].tolist())
