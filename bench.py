@@ -70,6 +70,7 @@ def main():
     ap.add_argument("--carve-mode", type=int, default=1, choices=[0, 1])
     ap.add_argument("--improved", type=int, default=1, choices=[0, 1])
     ap.add_argument("--straddle", type=int, default=1, choices=[0, 1])
+    ap.add_argument("--site-cache", type=int, default=1, choices=[0, 1])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU (asked for {args.gpus}); "
@@ -90,7 +91,7 @@ def main():
     d = vd.Domain.from_vdgen(dom)
     opts = vd.Options.default(time_kernels=1, emit_polytopes=0 if args.no_emit else 1,
                               carve_mode=args.carve_mode, improved_search=args.improved,
-                              use_straddle_edges=args.straddle)
+                              use_straddle_edges=args.straddle, site_cache=args.site_cache)
     grid, cells = vd.Grid(), vd.Cells()
     mass = torch.empty(n, dtype=torch.float64, device=dev)
     cent = torch.empty((n, 3), dtype=torch.float64, device=dev)
@@ -108,23 +109,19 @@ def main():
         step()
         torch.cuda.synchronize()
         print(f"bench: warmup {w} {1e3 * (time.perf_counter() - t1):.1f} ms", file=sys.stderr, flush=True)
-    carve, split = [], []
+    kern = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
         inf = cells.info()
-        carve.append(inf["carve_ms"])
-        split.append(inf["split_ms"])
-        print(f"bench: step {len(carve)} cell {inf['carve_ms']:.2f} ms piece {inf['split_ms']:.2f} ms",
-              file=sys.stderr, flush=True)
+        kern.append(inf["carve_ms"])
+        print(f"bench: step {len(kern)} site kernel {inf['carve_ms']:.2f} ms", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     info = cells.info()
     ms = 1e3 * wall / args.steps
-    carve_ms = float(np.mean(carve))
-    split_ms = float(np.mean(split))
-    # the dominant kernel: the cell carve (cell-first) or the per-piece kernel
-    dom_ms, dom_name = (carve_ms, "cell_kernel") if carve_ms >= split_ms else (split_ms, "piece_kernel")
+    # the dominant kernel: the persistent per-site kernel (cell carve + pieces)
+    dom_ms, dom_name = float(np.mean(kern)), "site_kernel"
     flops = FLOPS_PER_CANDIDATE * info["candidates"]
     achieved = flops / (dom_ms * 1e-3) / 1e12
     total_mass = float(mass.sum().item())
@@ -144,11 +141,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "sites": n, "tetrahedra": int(dom.m), "grid_sites_per_cell": rho,
                    "emit_polytopes": not args.no_emit, "carve_mode": args.carve_mode,
-                   "improved_search": args.improved, "straddle_edges": args.straddle},
+                   "improved_search": args.improved, "straddle_edges": args.straddle,
+                   "site_cache": args.site_cache},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
-                     "kernel": dom_name, "kernel_ms": dom_ms, "cell_kernel_ms": carve_ms,
-                     "piece_kernel_ms": split_ms},
+                     "kernel": dom_name, "kernel_ms": dom_ms},
         "counters": {"pieces": info["n_pieces"], "nn_queries": info["nn_queries"], "clips": info["clips"],
                      "candidates": info["candidates"], "queries_per_cell": info["nn_queries"] / n,
                      "mass_sum": total_mass},

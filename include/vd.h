@@ -54,6 +54,16 @@ typedef struct vd_grid_s *vd_grid;
 typedef struct vd_domain_s *vd_domain;
 typedef struct vd_cells_s *vd_cells;
 
+/* Stages of the per-site work, as bits of vd_cells_info_t.failed_stages. */
+enum {
+  VD_STAGE_CELL = 1,        /* carving the cell from the domain box (cell-first) */
+  VD_STAGE_PIECE_CUT = 2,   /* cutting the saved cell by a tetrahedron's planes */
+  VD_STAGE_PIECE_CARVE = 3, /* carving a piece from its simplex */
+  VD_STAGE_NEIGHBOURS = 4,  /* more distinct neighbours than a wave holds */
+  VD_STAGE_SIMPLICES = 5,   /* more simplices in one cell than a wave holds */
+  VD_STAGE_TRIANGLE = 6     /* surface: carving the pieces of a triangle */
+};
+
 /* Tuning and behaviour knobs; vd_options_default() fills the defaults. */
 typedef struct {
   double sites_per_cell;   /* unused by vd_clip_cells (the grid density is an argument
@@ -72,6 +82,10 @@ typedef struct {
                                  bounding box of the domain (Sec. 5.2), then each piece is
                                  T_a cut by the cell's certified bisector facets.  Both
                                  give the same pieces. */
+  int32_t site_cache;         /* 1 (default): each wave keeps the sites of a block of grid
+                                 cells around its site in LDS and answers a nearest-site
+                                 query there when the query's ball lies inside the block
+                                 (same answer as the grid query); 0: grid queries only */
 } vd_options;
 
 void vd_options_default(vd_options *opt);
@@ -144,11 +158,13 @@ typedef struct {
   int64_t clips;       /* clips applied */
   int64_t candidates;  /* sites examined by the nearest-site queries */
   int32_t first_bad_site; /* -1, or a site whose carve hit a capacity/degeneracy */
+  int32_t failed_stages;  /* bit mask of the stages that failed (VD_STAGE_*), 0 if none */
   int32_t status;         /* vd_status of the last clip */
-  double carve_ms;        /* durations of the last clip's kernels, measured with hipEvents
-                             on the caller's stream when time_kernels = 1 (else -1):
-                             the cell carve (cell-first mode; 0 otherwise) ... */
-  double split_ms;        /* ... and the piece kernel (tetrahedra) or surface kernel */
+  double carve_ms;        /* duration of the last clip's main kernel (the persistent
+                             per-site kernel for tetrahedra, the per-triangle kernel for
+                             surfaces), measured with hipEvents on the caller's stream
+                             when time_kernels = 1 (else -1) */
+  double split_ms;        /* 0 when timed (no second kernel), else -1 */
 } vd_cells_info_t;
 
 /* Host struct of sizes and counters (synchronises `stream` of the last call). */
@@ -166,11 +182,15 @@ vd_status vd_cells_info(vd_cells c, vd_cells_info_t *info_host);
  *   outside; for triangles the vertex lies on two edges and the third label
  *   is INT32_MAX), k < piece_nvert[p].
  * Pieces of one site are listed by ascending simplex index.
- * Neighbours of site i: nbr[nbr_off[i] .. nbr_off[i+1]), ascending. */
+ * Neighbours of site i: nbr[nbr_off[i] .. nbr_off[i+1]), ascending.
+ * The piece, face and vertex arrays are arenas of n_piece_slots, n_face_slots
+ * and n_vert_slots records: waves fill them in chunks, so a piece slot with
+ * piece_site = -1 is unused, and faces / vertices are reached only through
+ * the piece offsets. */
 typedef struct {
-  int64_t n_sites, n_pieces;
+  int64_t n_sites, n_piece_slots, n_face_slots, n_vert_slots;
   const int64_t *cell_piece_off; /* [n+1] */
-  const int32_t *piece_id;       /* [n_pieces] */
+  const int32_t *piece_id;       /* [cell_piece_off[n]] */
   const int32_t *piece_site, *piece_simplex, *piece_nface, *piece_nvert;
   const int64_t *piece_face_start, *piece_vert_start;
   const double *piece_mass, *piece_moment, *piece_energy;

@@ -39,7 +39,7 @@ class Options(C.Structure):
     _fields_ = [("sites_per_cell", C.c_double), ("improved_search", C.c_int32),
                 ("use_straddle_edges", C.c_int32), ("max_search_iters", C.c_int32),
                 ("emit_polytopes", C.c_int32), ("want_grad", C.c_int32), ("time_kernels", C.c_int32),
-                ("carve_mode", C.c_int32)]
+                ("carve_mode", C.c_int32), ("site_cache", C.c_int32)]
 
     @classmethod
     def default(cls, **kw) -> "Options":
@@ -56,12 +56,13 @@ class _Info(C.Structure):
     _fields_ = [("n_sites", C.c_int64), ("n_pieces", C.c_int64), ("n_faces", C.c_int64),
                 ("n_verts", C.c_int64), ("n_nbrs", C.c_int64), ("nn_queries", C.c_int64),
                 ("clips", C.c_int64), ("candidates", C.c_int64), ("first_bad_site", C.c_int32),
-                ("status", C.c_int32), ("carve_ms", C.c_double),
+                ("failed_stages", C.c_int32), ("status", C.c_int32), ("carve_ms", C.c_double),
                 ("split_ms", C.c_double)]
 
 
 class _View(C.Structure):
-    _fields_ = [("n_sites", C.c_int64), ("n_pieces", C.c_int64)] + [
+    _fields_ = [("n_sites", C.c_int64), ("n_piece_slots", C.c_int64), ("n_face_slots", C.c_int64),
+                ("n_vert_slots", C.c_int64)] + [
         (name, C.c_void_p) for name in (
             "cell_piece_off", "piece_id", "piece_site", "piece_simplex", "piece_nface", "piece_nvert",
             "piece_face_start", "piece_vert_start", "piece_mass", "piece_moment", "piece_energy",
@@ -269,7 +270,7 @@ class Cells:
         v = _View()
         _check(load().vd_cells_view(self.h, C.byref(v)))
         info = self.info()
-        n, npc = v.n_sites, v.n_pieces
+        n, npc = v.n_sites, v.n_piece_slots
         out = {
             "cell_piece_off": _to_torch(v.cell_piece_off, n + 1, torch.int64),
             "nbr_off": _to_torch(v.nbr_off, n + 1, torch.int64),
@@ -287,10 +288,10 @@ class Cells:
         tot_n = int(out["nbr_off"][-1].item()) if n > 0 else 0
         out["piece_id"] = _to_torch(v.piece_id, tot_p, torch.int32)
         out["nbr"] = _to_torch(v.nbr, tot_n, torch.int32)
-        if info["n_faces"] > 0 and v.face_label:
-            out["face_label"] = _to_torch(v.face_label, info["n_faces"], torch.int32)
-            out["vert_xyz"] = _to_torch(v.vert_xyz, 3 * info["n_verts"], torch.float64).reshape(-1, 3)
-            out["vert_label"] = _to_torch(v.vert_label, 3 * info["n_verts"], torch.int32).reshape(-1, 3)
+        if v.n_face_slots > 0 and v.face_label:
+            out["face_label"] = _to_torch(v.face_label, v.n_face_slots, torch.int32)
+            out["vert_xyz"] = _to_torch(v.vert_xyz, 3 * v.n_vert_slots, torch.float64).reshape(-1, 3)
+            out["vert_label"] = _to_torch(v.vert_label, 3 * v.n_vert_slots, torch.int32).reshape(-1, 3)
         return out
 
     def __del__(self):
@@ -306,11 +307,13 @@ def clip_cells(grid: Grid, domain: Domain, options: Options | None = None, cells
 
 
 def pieces_as_result(view: dict) -> dict:
-    """Host (NumPy) copy of the pieces in the oracle's layout, sorted by (site, simplex)."""
-    npc = view["piece_site"].numel()
+    """Host (NumPy) copy of the pieces in the oracle's layout, sorted by (site, simplex)
+    (unused arena slots dropped)."""
     site = view["piece_site"].cpu().numpy()
     simp = view["piece_simplex"].cpu().numpy()
-    order = np.lexsort((simp, site))
+    used = np.nonzero(site >= 0)[0]
+    npc = len(used)
+    order = used[np.lexsort((simp[used], site[used]))]
     nface = view["piece_nface"].cpu().numpy()[order]
     nvert = view["piece_nvert"].cpu().numpy()[order]
     fst = view["piece_face_start"].cpu().numpy()[order]

@@ -98,6 +98,7 @@ void vd_options_default(vd_options *opt) {
   opt->want_grad = 0;
   opt->time_kernels = 0;
   opt->carve_mode = 1;
+  opt->site_cache = 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -309,11 +310,10 @@ hipError_t alloc_cells(vd_cells c, int64_t n, const Caps &want) {
     t = 0; if ((e = ensure(c->nbr_off, t, n + 1)) != hipSuccess) return e;
     t = 0; if ((e = ensure(c->scan_tmp, t, n / 1024 + 2)) != hipSuccess) return e;
     t = 0; if ((e = ensure(c->fillc, t, n)) != hipSuccess) return e;
-    t = 0; if ((e = ensure(d.nfacet, t, n)) != hipSuccess) return e;
-    t = 0; if ((e = ensure(d.facet, t, (int64_t)VD_F_MAX * n)) != hipSuccess) return e;
     c->cap_n = n;
   }
   if ((e = ensure_fixed(d.cnt, CNT_N)) != hipSuccess) return e;
+  if ((e = ensure_fixed(d.queue, VD_QUEUES * VD_QSTRIDE)) != hipSuccess) return e;
   int64_t cp = d.cap_piece;
   if (cp < want.piece) {
     int64_t t;
@@ -402,14 +402,27 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
     d.straddle = opt.use_straddle_edges ? 1 : 0;
     d.max_iters = opt.max_search_iters;
     d.mode = (dom->dim == 3 && opt.carve_mode == 1) ? 1 : 0;
+    d.cache = opt.site_cache ? 1 : 0;
     for (int a = 0; a < 3; a++) {
-      // the box strictly contains the domain so no box plane meets a simplex
-      const double ext = dom->bbox[3 + a] - dom->bbox[a];
-      const double pad = 1e-3 * std::max(ext, 1e-12) + 1e-9;
-      d.box_lo[a] = dom->bbox[a] - pad;
-      d.box_hi[a] = dom->bbox[3 + a] + pad;
+      // The box strictly contains the domain so no box plane meets a simplex.
+      // The six paddings differ so that no box edge lies on a plane of
+      // symmetry of the domain (e.g. the diagonal planes of cube grids split
+      // into tetrahedra), where a tetrahedron plane would contain the edge.
+      const double ext = std::max(dom->bbox[3 + a] - dom->bbox[a], 1e-12);
+      d.box_lo[a] = dom->bbox[a] - (1.01e-3 + 0.12e-3 * a) * ext - 1e-9;
+      d.box_hi[a] = dom->bbox[3 + a] + (1.07e-3 + 0.14e-3 * a) * ext + 1e-9;
+    }
+    // persistent 3D kernel: each wave reserves output chunks of about 1/8 of an
+    // arena's share per wave, so unused chunk tails stay within 1/8 of it
+    const int64_t items = dom->dim == 3 ? n : dom->m;  // sites, or triangles
+    const int wg = dom->dim == 3 ? vd_sites3d_workgroups(n) : vd_surface_workgroups(dom->m);
+    {
+      const int64_t caps[AR_N] = {d.cap_piece, d.cap_face, d.cap_vert, d.cap_nbr, d.cap_fint};
+      for (int r = 0; r < AR_N; r++)
+        d.chunk[r] = std::max<int64_t>(1, std::min<int64_t>(4096, caps[r] / (8 * (int64_t)wg)));
     }
     hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, st, d.cnt);
+    vd_launch_queue_init(d.queue, items, st);
     GridView G = g->view();
     DomainView D = dom->view();
     if (opt.time_kernels && !c->ev0) {
@@ -425,11 +438,9 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
     if (dom->dim == 3) vd_launch_locate_sites(G, D, d.seed, d.cnt, st);
     else vd_launch_fill_int(d.pcount, n, 0, st);
     if (opt.time_kernels) HIP_TRY(hipEventRecord(c->ev0, st));
-    if (dom->dim == 3 && d.mode == 1) vd_launch_cells3d(G, d, st);
+    if (dom->dim == 3) vd_launch_sites3d(G, D, c->d_dev, wg, st);
+    else vd_launch_surface(G, D, c->d_dev, wg, st);
     if (opt.time_kernels) HIP_TRY(hipEventRecord(c->ev1, st));
-    if (dom->dim == 3) vd_launch_pieces3d(G, D, c->d_dev, d.mode == 0, st);
-    else vd_launch_surface(G, D, c->d_dev, st);
-    if (opt.time_kernels) HIP_TRY(hipEventRecord(c->ev2, st));
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(c->host_cnt, d.cnt, sizeof(unsigned long long) * CNT_N, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -438,8 +449,7 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
       float ms = 0.f;
       HIP_TRY(hipEventElapsedTime(&ms, c->ev0, c->ev1));
       c->carve_ms = ms;
-      HIP_TRY(hipEventElapsedTime(&ms, c->ev1, c->ev2));
-      c->split_ms = ms;
+      c->split_ms = 0.0;
     }
     const unsigned long long *hc = c->host_cnt;
     bool grow = false;
@@ -462,14 +472,23 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
     if (hc[CNT_ERR_CAP]) {
       c->status = VD_ERR_CAPACITY;
       *out = c;
-      return fail(VD_ERR_CAPACITY, "vd_clip_cells: %llu site(s) exceeded a per-wave capacity (first: %d)",
-                  (unsigned long long)hc[CNT_ERR_CAP], c->first_bad);
+      return fail(VD_ERR_CAPACITY,
+                  "vd_clip_cells: %llu site(s) exceeded a per-wave capacity (first: %d, stages 0x%llx)",
+                  (unsigned long long)hc[CNT_ERR_CAP], c->first_bad, (unsigned long long)hc[CNT_STAGES]);
     }
     if (hc[CNT_ERR_DEG]) {
       c->status = VD_ERR_DEGENERATE;
       *out = c;
-      return fail(VD_ERR_DEGENERATE, "vd_clip_cells: %llu site(s) hit a non-converging search (first: %d)",
-                  (unsigned long long)hc[CNT_ERR_DEG], c->first_bad);
+      return fail(VD_ERR_DEGENERATE,
+                  "vd_clip_cells: %llu site(s) hit a non-converging search (first: %d, stages 0x%llx)",
+                  (unsigned long long)hc[CNT_ERR_DEG], c->first_bad, (unsigned long long)hc[CNT_STAGES]);
+    }
+    if (dom->dim == 2) {
+      // a site's neighbours are distinct flags of its pieces' edges: the
+      // edges written bound the neighbour lists' total
+      int64_t t = c->cap_nbr_csr;
+      HIP_TRY(ensure(c->nbr, t, std::max<int64_t>((int64_t)hc[CNT_REAL_FACES], 1)));
+      c->cap_nbr_csr = t;
     }
     vd_launch_finalize(c, st);
     HIP_TRY(hipGetLastError());
@@ -492,7 +511,7 @@ void vd_cells_free(vd_cells c) {
   if (c->ev0) hipEventDestroy(c->ev0);
   if (c->ev1) hipEventDestroy(c->ev1);
   if (c->ev2) hipEventDestroy(c->ev2);
-  hipFree(c->d_dev); hipFree(d.facet); hipFree(d.nfacet);
+  hipFree(c->d_dev); hipFree(d.queue);
   hipFree(d.fint_lab); hipFree(d.piece_fint_start); hipFree(d.piece_nfint); hipFree(c->wbuf);
   delete c;
 }
@@ -501,14 +520,20 @@ vd_status vd_cells_info(vd_cells c, vd_cells_info_t *info) {
   if (!c || !info) return fail(VD_ERR_INVALID_ARG, "vd_cells_info: NULL");
   const unsigned long long *hc = c->host_cnt;
   info->n_sites = c->n;
-  info->n_pieces = (int64_t)hc[CNT_PIECES];
-  info->n_faces = (int64_t)hc[CNT_FACES];
-  info->n_verts = (int64_t)hc[CNT_VERTS];
-  info->n_nbrs = (int64_t)hc[CNT_NBRS];
+  info->n_pieces = (int64_t)hc[CNT_REAL_PIECES];
+  info->n_faces = (int64_t)hc[CNT_REAL_FACES];
+  info->n_verts = (int64_t)hc[CNT_REAL_VERTS];
+  info->n_nbrs = (int64_t)hc[CNT_REAL_NBRS];
+  if (c->dim == 2 && c->n > 0 && c->status == VD_OK) {
+    long long tot = 0;
+    HIP_TRY(hipMemcpy(&tot, c->nbr_off + c->n, sizeof(long long), hipMemcpyDeviceToHost));
+    info->n_nbrs = tot;
+  }
   info->nn_queries = (int64_t)hc[CNT_QUERIES];
   info->clips = (int64_t)hc[CNT_CLIPS];
   info->candidates = (int64_t)hc[CNT_CANDS];
   info->first_bad_site = c->first_bad;
+  info->failed_stages = (int32_t)c->host_cnt[CNT_STAGES];
   info->status = c->status;
   info->carve_ms = c->carve_ms;
   info->split_ms = c->split_ms;
@@ -519,7 +544,9 @@ vd_status vd_cells_view(vd_cells c, vd_cells_view_t *v) {
   if (!c || !v) return fail(VD_ERR_INVALID_ARG, "vd_cells_view: NULL");
   const CellsDev &d = c->d;
   v->n_sites = c->n;
-  v->n_pieces = (int64_t)c->host_cnt[CNT_PIECES];
+  v->n_piece_slots = std::min<int64_t>((int64_t)c->host_cnt[CNT_PIECES], d.cap_piece);
+  v->n_face_slots = d.face_label ? std::min<int64_t>((int64_t)c->host_cnt[CNT_FACES], d.cap_face) : 0;
+  v->n_vert_slots = d.vert_xyz ? std::min<int64_t>((int64_t)c->host_cnt[CNT_VERTS], d.cap_vert) : 0;
   v->cell_piece_off = (const int64_t *)c->piece_off;
   v->piece_id = c->piece_id;
   v->piece_site = d.piece_site;

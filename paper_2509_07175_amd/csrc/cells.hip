@@ -1,7 +1,8 @@
 // cells.hip -- output compaction and per-site moments.
 //
-// The clip kernels reserve per-site lists with one atomic per wave, so lists
-// sit anywhere in their arenas.  Finalize turns them into CSR: an exclusive scan
+// The clip kernels write pieces and per-site lists into chunks of shared
+// arenas, so records sit anywhere in their arenas (unused piece slots carry
+// site -1).  Finalize turns them into CSR: an exclusive scan
 // of the per-site counts and a gather (one thread per site).  Moments convert
 // the per-site mass / first moment / energy sums (accumulated in a fixed order
 // inside each wave) into mass, centroid and energy.
@@ -31,6 +32,7 @@ __global__ void __launch_bounds__(kB) scatter_pieces(long long np, const int *__
   const long long p = (long long)blockIdx.x * kB + threadIdx.x;
   if (p >= np) return;
   const int s = site[p];
+  if (s < 0) return;  // unused slot of a wave's chunk
   out[off[s] + atomicAdd(&fill[s], 1)] = (int)p;
 }
 
@@ -92,7 +94,12 @@ void vd_launch_finalize(vd_cells c, hipStream_t st) {
   hipLaunchKernelGGL(sort_segments, dim3(blocks(n)), dim3(kB), 0, st, n, (const long long *)c->piece_off,
                      (const int *)d.piece_simplex, c->piece_id);
   // surfaces: per-site sums and neighbour lists from the pieces, in CSR order
-  if (c->dim == 2) vd_launch_site_reduce(n, c->piece_off, c->piece_id, c->d_dev, st);
+  if (c->dim == 2) {
+    vd_launch_site_reduce(n, c->piece_off, c->piece_id, c->d_dev, st);
+    vdscan::exclusive_scan<int, long long>(d.ncount, n, c->nbr_off, c->scan_tmp, st);
+    vd_launch_site_nbrs(n, c->piece_off, c->piece_id, c->nbr_off, c->nbr, c->d_dev, st);
+    return;
+  }
   vdscan::exclusive_scan<int, long long>(d.ncount, n, c->nbr_off, c->scan_tmp, st);
   hipLaunchKernelGGL(gather_lists, dim3(blocks(n)), dim3(kB), 0, st, n, (const int *)d.ncount,
                      (const long long *)d.nstart, (const int *)d.nbr_arena, (const long long *)c->nbr_off,

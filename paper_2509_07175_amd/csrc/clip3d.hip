@@ -39,7 +39,9 @@
 // Moments of a piece: a fan of tetrahedra (v_i, foot of the face plane,
 // corner, next corner around the face), three per corner, reduced across the
 // wave with butterfly shuffles (fixed order, no floating-point atomics).
-#include "vd_internal.h"
+#include <type_traits>
+
+#include "vd_arena.h"
 
 namespace {
 
@@ -49,9 +51,7 @@ constexpr int kBoxBase = VD_BND_BASE + 16;  // flags of the bounding-box planes 
 struct __align__(16) WaveLds {
   double pn[VD_P_MAX][4];    // plane: outward normal (relative coords), offset
   double cy[VD_C_MAX][3];    // corner coordinates relative to v_i
-  double fpn[VD_F_MAX][4];   // cell-first: bisector facets of the cell
   int plab[VD_P_MAX];        // plane flag: sorted site >= 0, -(b+1), boundary/box code
-  int flab[VD_F_MAX];
   int cpl[VD_C_MAX];         // corner planes a | b << 8 | c << 16 (CCW from outside)
   int cnb[VD_C_MAX];         // corner across a->b | across b->c << 8 | across c->a << 16
   int cst[VD_C_MAX];         // bit 0 inside, bit 1 tested, bits 8.. nearest site + 1
@@ -59,6 +59,13 @@ struct __align__(16) WaveLds {
   int tq[VD_Q_MAX];          // tetrahedra of this site, breadth-first
   int nbl[VD_NB_MAX];        // neighbours found so far (sorted positions)
   int pfirst[VD_P_MAX];      // lowest corner slot on each plane (face walks)
+  WaveArena ar;              // output chunks, queue position, statistics
+  SiteCache K;               // sites around v_i for the nearest-site queries
+  // cell-first: the carved cell, restored before each tetrahedron
+  double bpn[VD_F_MAX][4];
+  double bcy[VD_CB_MAX][3];
+  int bplab[VD_F_MAX];
+  int bcpl[VD_CB_MAX], bcnb[VD_CB_MAX];
 };
 
 __device__ __forceinline__ int p8(int packed, int e) { return (packed >> (8 * e)) & 0xff; }
@@ -230,9 +237,10 @@ __device__ int clip_poly(WaveLds &S, int P, int pt, int &nc) {
   }
   if (__ballot(bad)) return 3;
   // all old corner data sits in registers: write the new layout
+  bool nf = false;
   {
     int t = base;
-#pragma unroll 1
+#pragma unroll
     for (int h = 0; h < 2; h++) {
       const int s = l + 64 * h;
       if (v[h] && !r[h]) {
@@ -258,6 +266,7 @@ __device__ int clip_poly(WaveLds &S, int P, int pt, int &nc) {
             S.cst[ns] = 0;
             double yy[3];
             solve3(S, u, w, P, yy);
+            nf = nf || !isfinite(yy[0] + yy[1] + yy[2]);
             S.cy[ns][0] = yy[0]; S.cy[ns][1] = yy[1]; S.cy[ns][2] = yy[2];
             t++;
           }
@@ -265,6 +274,9 @@ __device__ int clip_poly(WaveLds &S, int P, int pt, int &nc) {
   }
   __syncthreads();
   nc = nsurv + nnew;
+  // three planes without a common point (e.g. all containing one direction)
+  // give a non-finite corner: report the cut as degenerate
+  if (__ballot(nf)) return 3;
   return 4;
 }
 
@@ -397,7 +409,7 @@ __device__ int carve(WaveLds &S, const GridView &G, const CarveParams C, const S
     const int gs = mode == TEST ? 16 : 64;
     const double qx = X.vx + q0, qy = X.vy + q1, qz = X.vz + q2;
     const double dx = qx - X.vx, dy = qy - X.vy, dz = qz - X.vz;
-    const int kq = nn_query(G, gs, qx, qy, qz, dx * dx + dy * dy + dz * dz, X.si, st.cands);
+    const int kq = nn_cached(S.K, G, gs, qx, qy, qz, dx * dx + dy * dy + dz * dz, X.si, st.cands);
     if (mode == TEST) {
       st.queries += nbatch;
       const int pl = tslot >= 0 ? S.cpl[tslot] : 0;
@@ -455,35 +467,84 @@ __device__ int carve(WaveLds &S, const GridView &G, const CarveParams C, const S
   return 3;
 }
 
+// Plane of face f of T_a (opposite vertex f), outward, relative to v_i, and
+// its flag.  Face loops {1,2,3},{0,3,2},{0,1,3},{0,2,1} are packed 2 bits per
+// vertex, 6 bits per face (no indexed local arrays).
+__device__ __forceinline__ void tet_plane(const DomainView &D, const SiteCtx &X, int a, int f, double *pl,
+                                          int &lab) {
+  const int *tv = &D.simp[(long long)a * 4];
+  const unsigned loops = (1u | 2u << 2 | 3u << 4) | (0u | 3u << 2 | 2u << 4) << 6 |
+                         (0u | 1u << 2 | 3u << 4) << 12 | (0u | 2u << 2 | 1u << 4) << 18;
+  const unsigned lf = loops >> (6 * f);
+  const double *pA = &D.verts[3 * (long long)tv[lf & 3]];
+  const double *pB = &D.verts[3 * (long long)tv[(lf >> 2) & 3]];
+  const double *pC = &D.verts[3 * (long long)tv[(lf >> 4) & 3]];
+  const double A0 = pA[0] - X.vx, A1 = pA[1] - X.vy, A2 = pA[2] - X.vz;
+  const double ab0 = pB[0] - pA[0], ab1 = pB[1] - pA[1], ab2 = pB[2] - pA[2];
+  const double ac0 = pC[0] - pA[0], ac1 = pC[1] - pA[1], ac2 = pC[2] - pA[2];
+  const double n0 = ab1 * ac2 - ab2 * ac1, n1 = ab2 * ac0 - ab0 * ac2, n2 = ab0 * ac1 - ab1 * ac0;
+  pl[0] = n0; pl[1] = n1; pl[2] = n2;
+  pl[3] = n0 * A0 + n1 * A1 + n2 * A2;
+  const int b = D.adj[(long long)a * 4 + f];
+  lab = b >= 0 ? -(b + 1) : VD_BND_BASE + f;
+}
+
 // P <- T_a: 4 planes (face f opposite vertex f), 4 corners.  Lane l < 4
 // builds plane l and corner l; the fixed topology of a positively oriented
-// tetrahedron is packed in constants (no indexed local arrays).
+// tetrahedron is packed in constants.
 __device__ void init_tet(WaveLds &S, const DomainView &D, const SiteCtx &X, int a, int tested) {
   const int l = vd_lane();
   if (l < 4) {
-    const int *tv = &D.simp[(long long)a * 4];
-    // face loops {1,2,3},{0,3,2},{0,1,3},{0,2,1}: 2 bits per vertex, 6 bits per face
-    const unsigned loops = (1u | 2u << 2 | 3u << 4) | (0u | 3u << 2 | 2u << 4) << 6 |
-                           (0u | 1u << 2 | 3u << 4) << 12 | (0u | 2u << 2 | 1u << 4) << 18;
-    const unsigned lf = loops >> (6 * l);
-    const double *pA = &D.verts[3 * (long long)tv[lf & 3]];
-    const double *pB = &D.verts[3 * (long long)tv[(lf >> 2) & 3]];
-    const double *pC = &D.verts[3 * (long long)tv[(lf >> 4) & 3]];
-    const double A0 = pA[0] - X.vx, A1 = pA[1] - X.vy, A2 = pA[2] - X.vz;
-    const double ab0 = pB[0] - pA[0], ab1 = pB[1] - pA[1], ab2 = pB[2] - pA[2];
-    const double ac0 = pC[0] - pA[0], ac1 = pC[1] - pA[1], ac2 = pC[2] - pA[2];
-    const double n0 = ab1 * ac2 - ab2 * ac1, n1 = ab2 * ac0 - ab0 * ac2, n2 = ab0 * ac1 - ab1 * ac0;
-    S.pn[l][0] = n0; S.pn[l][1] = n1; S.pn[l][2] = n2;
-    S.pn[l][3] = n0 * A0 + n1 * A1 + n2 * A2;
-    const int b = D.adj[(long long)a * 4 + l];
-    S.plab[l] = b >= 0 ? -(b + 1) : VD_BND_BASE + l;
+    double pl[4];
+    int lab;
+    tet_plane(D, X, a, l, pl, lab);
+    S.pn[l][0] = pl[0]; S.pn[l][1] = pl[1]; S.pn[l][2] = pl[2]; S.pn[l][3] = pl[3];
+    S.plab[l] = lab;
     // corner l = vertex l: planes counter-clockwise from outside
     // {1,3,2},{0,2,3},{0,3,1},{0,1,2}; neighbours {2,1,3},{3,0,2},{1,0,3},{2,0,1}
     S.cpl[l] = l == 0 ? pack3(1, 3, 2) : (l == 1 ? pack3(0, 2, 3) : (l == 2 ? pack3(0, 3, 1) : pack3(0, 1, 2)));
     S.cnb[l] = l == 0 ? pack3(2, 1, 3) : (l == 1 ? pack3(3, 0, 2) : (l == 2 ? pack3(1, 0, 3) : pack3(2, 0, 1)));
     S.cst[l] = tested ? 3 : 0;
-    const double *p = &D.verts[3 * (long long)tv[l]];
+    const double *p = &D.verts[3 * (long long)D.simp[(long long)a * 4 + l]];
     S.cy[l][0] = p[0] - X.vx; S.cy[l][1] = p[1] - X.vy; S.cy[l][2] = p[2] - X.vz;
+  }
+  __syncthreads();
+}
+
+// cell-first: keep the carved cell (npl planes, nc corners) ...
+__device__ void save_cell(WaveLds &S, int npl, int nc) {
+  const int l = vd_lane();
+  if (l < npl) {
+    for (int k = 0; k < 4; k++) S.bpn[l][k] = S.pn[l][k];
+    S.bplab[l] = S.plab[l];
+  }
+  for (int s = l; s < nc; s += 64) {
+    S.bcpl[s] = S.cpl[s];
+    S.bcnb[s] = S.cnb[s];
+    for (int k = 0; k < 3; k++) S.bcy[s][k] = S.cy[s][k];
+  }
+  __syncthreads();
+}
+
+// ... and start a piece from it: the cell plus the four planes of T_a in
+// slots npl .. npl+3 (not yet cut)
+__device__ void restore_cell(WaveLds &S, int npl, int nc, const DomainView &D, const SiteCtx &X, int a) {
+  const int l = vd_lane();
+  if (l < npl) {
+    for (int k = 0; k < 4; k++) S.pn[l][k] = S.bpn[l][k];
+    S.plab[l] = S.bplab[l];
+  } else if (l < npl + 4) {
+    double pl[4];
+    int lab;
+    tet_plane(D, X, a, l - npl, pl, lab);
+    for (int k = 0; k < 4; k++) S.pn[l][k] = pl[k];
+    S.plab[l] = lab;
+  }
+  for (int s = l; s < nc; s += 64) {
+    S.cpl[s] = S.bcpl[s];
+    S.cnb[s] = S.bcnb[s];
+    S.cst[s] = 3;
+    for (int k = 0; k < 3; k++) S.cy[s][k] = S.bcy[s][k];
   }
   __syncthreads();
 }
@@ -545,9 +606,7 @@ __device__ void face_moments(WaveLds &S, int nc, int npl, uint64_t fmask, const 
   const bool mine = l < npl && ((fmask >> l) & 1ull) && S.plab[l] >= 0;
   const uint64_t pos = __ballot(mine);
   const int npos = __popcll(pos);
-  long long base = 0;
-  if (l == 0) base = (long long)atomicAdd(&C.cnt[CNT_FINT], (unsigned long long)npos);
-  base = __shfl(base, 0, 64);
+  const long long base = arena_take(S.ar, C, AR_FINT, npos);
   if (l == 0 && pidx < C.cap_piece) { C.piece_fint_start[pidx] = base; C.piece_nfint[pidx] = npos; }
   if (!mine) return;
   const int x = l;
@@ -603,137 +662,92 @@ __device__ void face_moments(WaveLds &S, int nc, int npl, uint64_t fmask, const 
 }
 
 // ---------------------------------------------------------------------------
-// Kernel A (cell-first): carve Omega_i cap box for every site and store the
-// labels of its bisector facets (sorted positions), VD_F_MAX slots per site.
+// One site: its pieces, per-site sums and neighbour list.  The tetrahedra of
+// the cell are visited breadth-first through negative face flags from the
+// tetrahedron containing v_i (the propagation of Alg. 5).
+//   cell-first (C.mode = 1): Omega_i cap box is carved once (Sec. 5.2); every
+//     corner of the result is certified by a point-in-cell test, so
+//     T_a cap Omega_i = T_a cap cell: the saved cell cut by the (at most four)
+//     planes of T_a.  A cell too large to save falls back to the other mode.
+//   per-simplex (C.mode = 0): each piece is carved from T_a by point-in-cell
+//     tests and the bisector search.
+// The carve has one call site: the first job of a cell-first site is the cell.
 // ---------------------------------------------------------------------------
-struct CellArgs {
-  CarveParams P;
-  double box_lo[3], box_hi[3];
-  int *facet;         // [n * VD_F_MAX] by sorted position
-  int *nfacet;        // [n] by sorted position; -2 capacity, -3 degenerate
-  unsigned long long *cnt;
-};
-
-__global__ void __launch_bounds__(64) cell_kernel(GridView G, CellArgs A) {
-  __shared__ WaveLds S;
+__device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, const CellsDev &C, int si) {
   const int l = vd_lane();
-  // consecutive sorted sites go to the same XCD (workgroup b runs on XCD b % 8)
-  const int q8 = gridDim.x >> 3;
-  const int si = (blockIdx.x & 7) * q8 + (blockIdx.x >> 3);
-  if (si >= G.n) return;
-  SiteCtx X;
-  X.vx = G.sx[si]; X.vy = G.sy[si]; X.vz = G.sz[si];
-  X.delta = G.delta[si];
-  X.si = si;
-  Stats st;
-  init_box(S, X, A.box_lo, A.box_hi);
-  int npl = 6, nc = 8;
-  int rc = carve(S, G, A.P, X, npl, nc, st);
-  int nf = 0;
-  if (rc == 0) {
-    uint64_t used = 0, bis = 0;
-    for (int s = l; s < nc; s += 64) {
-      const int pl = S.cpl[s];
-      used |= (1ull << p8(pl, 0)) | (1ull << p8(pl, 1)) | (1ull << p8(pl, 2));
-    }
-    for (int x = l; x < npl; x += 64)
-      if (S.plab[x] >= 0) bis |= 1ull << x;
-    used = wave_or64(used) & wave_or64(bis);
-    nf = __popcll(used);
-    if (nf > VD_F_MAX) rc = 2;
-    else if (l < npl && ((used >> l) & 1ull)) A.facet[(long long)si * VD_F_MAX + __popcll(used & low_mask(l))] = S.plab[l];
-  } else if (rc == 1) {
-    rc = 3;  // the site lies in the box, so its cell cannot be empty
-  }
-  if (l == 0) {
-    A.nfacet[si] = rc ? -rc : nf;
-    atomicAdd(&A.cnt[CNT_QUERIES], (unsigned long long)st.queries);
-    atomicAdd(&A.cnt[CNT_CLIPS], (unsigned long long)st.clips);
-    atomicAdd(&A.cnt[CNT_CANDS], (unsigned long long)st.cands);
-    if (rc) {
-      atomicAdd(&A.cnt[rc == 2 ? CNT_ERR_CAP : CNT_ERR_DEG], 1ull);
-      atomicMin((int *)&A.cnt[CNT_BAD_SITE], G.perm[si]);
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Kernel B: the pieces of every site.  The tetrahedra of the cell are visited
-// breadth-first through negative face flags from the tetrahedron containing
-// v_i (the propagation of Alg. 5).  CARVE = false (cell-first): T_a is cut by
-// the half-spaces of the cell's certified facets.  CARVE = true (per-simplex):
-// T_a is carved by point-in-cell tests and the bisector search.
-// ---------------------------------------------------------------------------
-template <bool CARVE>
-__global__ void __launch_bounds__(64) piece_kernel(GridView G, DomainView D, const CellsDev *__restrict__ Cp) {
-  __shared__ WaveLds S;
-  const int l = vd_lane();
-  const int q8 = gridDim.x >> 3;
-  const int si = (blockIdx.x & 7) * q8 + (blockIdx.x >> 3);
-  if (si >= G.n) return;
-  const CellsDev &C = *Cp;
   SiteCtx X;
   X.vx = G.sx[si]; X.vy = G.sy[si]; X.vz = G.sz[si];
   X.delta = G.delta[si];
   X.si = si;
   const int orig = G.perm[si];
   const int seed = C.seed[si];
+  const CarveParams P = {C.improved, C.straddle, C.max_iters};
   Stats st;
   int err = 0;  // 2 capacity, 3 degenerate
-  int nt = 0, head = 0, nnb = 0, npieces = 0, nf = 0;
+  int where = 0;  // failing stage (VD_STAGE_*)
+  int nt = 0, head = 0, nnb = 0, npieces = 0, npl0 = 0, nc0 = 0;
+  bool cell_job = C.mode == 1, saved = false;
   double Mv = 0, Mx = 0, My = 0, Mz = 0, Me = 0;
+  if (C.cache) {
+    cache_fill(S.K, G, X.vx, X.vy, X.vz);
+  } else {
+    if (l == 0) S.K.cnt = -1;
+  }
   if (seed >= 0 && seed < D.m) {
     if (l == 0) S.tq[0] = seed;
     nt = 1;
   }
-  if (!CARVE) {
-    nf = C.nfacet[si];
-    if (nf < 0) { nt = 0; nf = 0; }  // carve failure, already reported
-    // planes of the facets: B_ij with n = v_j - v_i, offset |n|^2 / 2
-    if (l < nf) {
-      const int j = C.facet[(long long)si * VD_F_MAX + l];
-      const double n0 = G.sx[j] - X.vx, n1 = G.sy[j] - X.vy, n2 = G.sz[j] - X.vz;
-      S.fpn[l][0] = n0; S.fpn[l][1] = n1; S.fpn[l][2] = n2;
-      S.fpn[l][3] = 0.5 * (n0 * n0 + n1 * n1 + n2 * n2);
-      S.flab[l] = j;
-    }
-  }
-  const CarveParams P = {C.improved, C.straddle, C.max_iters};
   __syncthreads();
-  while (head < nt && !err) {
-    const int a = S.tq[head++];
-    int npl = 4, nc = 4;
-    bool empty = false;
-    if (!CARVE) {
-      init_tet(S, D, X, a, 1);
-      // facets whose plane leaves a vertex of T_a outside; the others contain T_a
-      bool cuts = false;
-      if (l < nf) {
-        const double n0 = S.fpn[l][0], n1 = S.fpn[l][1], n2 = S.fpn[l][2], cc = S.fpn[l][3];
-        for (int k = 0; k < 4; k++) cuts = cuts || (n0 * S.cy[k][0] + n1 * S.cy[k][1] + n2 * S.cy[k][2] > cc);
-      }
-      uint64_t fm = __ballot(cuts);
-      for (; fm; fm &= fm - 1) {
-        const int f = __ffsll((unsigned long long)fm) - 1;
-        if (npl >= VD_P_MAX) {
-          npl = compact_planes(S, npl, nc);
-          if (npl >= VD_P_MAX) { err = 2; break; }
-        }
-        const int Pl = npl;
-        __syncthreads();
-        if (l < 4) S.pn[Pl][l] = S.fpn[f][l];
-        if (l == 0) S.plab[Pl] = S.flab[f];
-        __syncthreads();
-        const int rc = clip_poly(S, Pl, -1, nc);
-        if (rc == 4) { npl++; st.clips++; }
-        else if (rc == 1) { empty = true; break; }
-        else if (rc != 0) { err = rc; break; }
-      }
+  if (!nt) cell_job = false;
+  for (;;) {
+    int a = -1, npl = 4, nc = 4;
+    bool empty = false, need_carve = true;
+    if (cell_job) {
+      init_box(S, X, C.box_lo, C.box_hi);
+      npl = 6;
+      nc = 8;
     } else {
-      init_tet(S, D, X, a, 0);
+      if (head >= nt || err) break;
+      a = S.tq[head++];
+      if (saved) {
+        restore_cell(S, npl0, nc0, D, X, a);
+        npl = npl0 + 4;
+        nc = nc0;
+        need_carve = false;
+#pragma unroll 1
+        for (int f = 0; f < 4; f++) {
+          const int rc = clip_poly(S, npl0 + f, -1, nc);
+          if (rc == 4) st.clips++;
+          else if (rc == 1) { empty = true; break; }
+          else if (rc == 2) { err = rc; where = VD_STAGE_PIECE_CUT; break; }
+          else if (rc == 3) { need_carve = true; break; }  // degenerate cut: carve this piece from T_a
+        }
+        if (need_carve && !err) {
+          init_tet(S, D, X, a, 0);
+          npl = 4;
+          nc = 4;
+        }
+      } else {
+        init_tet(S, D, X, a, 0);
+      }
+    }
+    if (need_carve) {
       const int rc = carve(S, G, P, X, npl, nc, st);
+      if (cell_job) {
+        cell_job = false;
+        if (rc == 1 || rc == 3) { err = 3; where = VD_STAGE_CELL; continue; }  // the site lies in the box
+        if (rc == 2) continue;                           // too large: carve per simplex
+        npl = compact_planes(S, npl, nc);
+        if (npl <= VD_F_MAX && npl + 4 <= VD_P_MAX && nc <= VD_CB_MAX) {
+          save_cell(S, npl, nc);
+          npl0 = npl;
+          nc0 = nc;
+          saved = true;
+        }
+        continue;
+      }
       if (rc == 1) empty = true;
-      else if (rc) err = rc;
+      else if (rc) { err = rc; where = VD_STAGE_PIECE_CARVE; }
     }
     if (err) break;
     if (empty) continue;
@@ -772,17 +786,12 @@ __global__ void __launch_bounds__(64) piece_kernel(GridView G, DomainView D, con
     Mv += pv; Mx += pmx; My += pmy; Mz += pmz; Me += pe;
     // ---- emit the piece ----
     const int nface = __popcll(fmask);
-    long long pidx = 0, fo = 0, vo = 0;
-    if (l == 0) {
-      pidx = (long long)atomicAdd(&C.cnt[CNT_PIECES], 1ull);
-      if (C.emit) {
-        fo = (long long)atomicAdd(&C.cnt[CNT_FACES], (unsigned long long)nface);
-        vo = (long long)atomicAdd(&C.cnt[CNT_VERTS], (unsigned long long)nc);
-      }
+    const long long pidx = arena_take(S.ar, C, AR_PIECE, 1);
+    long long fo = 0, vo = 0;
+    if (C.emit) {
+      fo = arena_take(S.ar, C, AR_FACE, nface);
+      vo = arena_take(S.ar, C, AR_VERT, nc);
     }
-    pidx = __shfl(pidx, 0, 64);
-    fo = __shfl(fo, 0, 64);
-    vo = __shfl(vo, 0, 64);
     if (C.want_grad) face_moments(S, nc, npl, fmask, C, G, pidx);
     if (pidx < C.cap_piece) {
       if (l == 0) {
@@ -797,6 +806,8 @@ __global__ void __launch_bounds__(64) piece_kernel(GridView G, DomainView D, con
         C.piece_energy[pidx] = pe;
         C.piece_fstart[pidx] = C.emit ? fo : -1;
         C.piece_vstart[pidx] = C.emit ? vo : -1;
+        S.ar.pieces++;
+        if (C.emit) { S.ar.faces += nface; S.ar.verts += nc; }
       }
       if (C.emit && fo + nface <= C.cap_face && vo + nc <= C.cap_vert) {
         if (l < npl && ((fmask >> l) & 1ull))
@@ -822,7 +833,7 @@ __global__ void __launch_bounds__(64) piece_kernel(GridView G, DomainView D, con
         bool have = false;
         for (int e = l; e < nnb; e += 64) have = have || (S.nbl[e] == lab);
         if (!__ballot(have)) {
-          if (nnb >= VD_NB_MAX) { err = 2; break; }
+          if (nnb >= VD_NB_MAX) { err = 2; where = VD_STAGE_NEIGHBOURS; break; }
           __syncthreads();
           if (l == 0) S.nbl[nnb] = lab;
           nnb++;
@@ -833,7 +844,7 @@ __global__ void __launch_bounds__(64) piece_kernel(GridView G, DomainView D, con
         bool have = false;
         for (int e = l; e < nt; e += 64) have = have || (S.tq[e] == b);
         if (!__ballot(have)) {
-          if (nt >= VD_Q_MAX) { err = 2; break; }
+          if (nt >= VD_Q_MAX) { err = 2; where = VD_STAGE_SIMPLICES; break; }
           __syncthreads();
           if (l == 0) S.tq[nt] = b;
           nt++;
@@ -844,7 +855,7 @@ __global__ void __launch_bounds__(64) piece_kernel(GridView G, DomainView D, con
     __syncthreads();
   }
   // ---- per-site results ----
-  long long ns0 = 0;
+  const long long ns0 = arena_take(S.ar, C, AR_NBR, nnb);
   if (l == 0) {
     C.mass[orig] = Mv;
     C.mom[3 * (long long)orig + 0] = Mx + Mv * X.vx;
@@ -853,10 +864,17 @@ __global__ void __launch_bounds__(64) piece_kernel(GridView G, DomainView D, con
     C.energy[orig] = Me;
     C.pcount[orig] = npieces;
     C.ncount[orig] = nnb;
-    ns0 = (long long)atomicAdd(&C.cnt[CNT_NBRS], (unsigned long long)nnb);
     C.nstart[orig] = ns0;
+    S.ar.nbrs += nnb;
+    S.ar.queries += st.queries;
+    S.ar.cands += st.cands;
+    S.ar.clips += st.clips;
+    if (err) {
+      atomicAdd(&C.cnt[err == 2 ? CNT_ERR_CAP : CNT_ERR_DEG], 1ull);
+      atomicMin((int *)&C.cnt[CNT_BAD_SITE], orig);
+      atomicOr((unsigned long long *)&C.cnt[CNT_STAGES], 1ull << where);
+    }
   }
-  ns0 = __shfl(ns0, 0, 64);
   __syncthreads();
   if (ns0 + nnb <= C.cap_nbr) {
     // neighbours in ascending caller index: rank sort
@@ -867,33 +885,56 @@ __global__ void __launch_bounds__(64) piece_kernel(GridView G, DomainView D, con
       C.nbr_arena[ns0 + rk] = me;
     }
   }
-  if (l == 0) {
-    if (CARVE) {
-      atomicAdd(&C.cnt[CNT_QUERIES], (unsigned long long)st.queries);
-      atomicAdd(&C.cnt[CNT_CANDS], (unsigned long long)st.cands);
-    }
-    atomicAdd(&C.cnt[CNT_CLIPS], (unsigned long long)st.clips);
-    if (err) {
-      atomicAdd(&C.cnt[err == 2 ? CNT_ERR_CAP : CNT_ERR_DEG], 1ull);
-      atomicMin((int *)&C.cnt[CNT_BAD_SITE], orig);
-    }
+  __syncthreads();
+}
+
+// Persistent: every workgroup (one wave) takes sites from the queues until
+// all are done.
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) site_kernel(GridView G, DomainView D, const CellsDev *__restrict__ Cp) {
+  __shared__ WaveLds S;
+  const CellsDev &C = *Cp;
+  arena_init(S.ar);
+  for (;;) {
+    const int si = queue_next(S.ar, C, G.n);
+    if (si < 0) break;
+    do_site(S, G, D, C, si);
   }
+  arena_close(S.ar, C);
+}
+
+__global__ void queue_init(int *q, long long n) {
+  const int k = threadIdx.x;
+  const long long q8 = (n + VD_QUEUES - 1) / VD_QUEUES;
+  if (k < VD_QUEUES) q[k * VD_QSTRIDE] = (int)(k * q8 < n ? k * q8 : n);
+}
+
+int resident_workgroups() {
+  static int cache[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  int &w = cache[dev];
+  if (!w) {
+    int per_cu = 0, ncu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, site_kernel, 64, 0) != hipSuccess || per_cu < 1)
+      per_cu = 1;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1) ncu = 1;
+    w = per_cu * ncu;
+  }
+  return w;
 }
 
 }  // namespace
 
-void vd_launch_cells3d(const GridView &G, const CellsDev &C, hipStream_t st) {
-  const unsigned q8 = (unsigned)((G.n + 7) / 8);
-  CellArgs A;
-  A.P.improved = C.improved; A.P.straddle = C.straddle; A.P.max_iters = C.max_iters;
-  for (int k = 0; k < 3; k++) { A.box_lo[k] = C.box_lo[k]; A.box_hi[k] = C.box_hi[k]; }
-  A.facet = C.facet; A.nfacet = C.nfacet; A.cnt = C.cnt;
-  hipLaunchKernelGGL(cell_kernel, dim3(q8 * 8), dim3(64), 0, st, G, A);
+int vd_sites3d_workgroups(long long n) {
+  const int w = resident_workgroups();
+  return (int)(n < w ? (n > 0 ? n : 1) : w);
 }
 
-void vd_launch_pieces3d(const GridView &G, const DomainView &D, const CellsDev *Cdev, int carve_each,
-                        hipStream_t st) {
-  const unsigned q8 = (unsigned)((G.n + 7) / 8);
-  if (carve_each) hipLaunchKernelGGL(piece_kernel<true>, dim3(q8 * 8), dim3(64), 0, st, G, D, Cdev);
-  else hipLaunchKernelGGL(piece_kernel<false>, dim3(q8 * 8), dim3(64), 0, st, G, D, Cdev);
+void vd_launch_queue_init(int *queue, long long n, hipStream_t st) {
+  hipLaunchKernelGGL(queue_init, dim3(1), dim3(64), 0, st, queue, n);
+}
+
+void vd_launch_sites3d(const GridView &G, const DomainView &D, const CellsDev *Cdev, int workgroups,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(site_kernel, dim3(workgroups), dim3(64), 0, st, G, D, Cdev);
 }

@@ -16,7 +16,7 @@
 // Per-site sums (mass, centroid, energy, neighbours) are formed afterwards
 // from the pieces in a fixed order (site_reduce), so results do not depend on
 // the order in which waves finish.
-#include "vd_internal.h"
+#include "vd_arena.h"
 
 namespace {
 
@@ -32,6 +32,7 @@ struct __align__(16) TriLds {
   int ve[kSV];        // plane slot of the edge from vertex t to vertex t+1
   int vst[kSV];       // bit 0 inside, bit 1 tested, bits 8.. nearest site + 1
   int sq[kSS];        // sites of this triangle (sorted positions), breadth-first
+  WaveArena ar;       // output chunks, queue position, statistics
 };
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -313,12 +314,8 @@ __device__ int carve_s(TriLds &S, const GridView &G, const SParams C, int si, do
 
 __device__ __forceinline__ int conv(const GridView &G, int lab) { return lab >= 0 ? G.perm[lab] : lab; }
 
-__global__ void __launch_bounds__(64) surface_kernel(GridView G, DomainView D, const CellsDev *__restrict__ Cp) {
-  __shared__ TriLds S;
+__device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, const CellsDev &C, int a) {
   const int l = vd_lane();
-  const int a = blockIdx.x;
-  if (a >= D.m) return;
-  const CellsDev &C = *Cp;
   const SParams P = {C.improved, C.straddle, C.max_iters};
   SStats ss;
   int err = 0;
@@ -371,16 +368,10 @@ __global__ void __launch_bounds__(64) surface_kernel(GridView G, DomainView D, c
     pa = wave_sum(pa); pmx = wave_sum(pmx); pmy = wave_sum(pmy); pmz = wave_sum(pmz); pe = wave_sum(pe);
     if (!(pa > 0.0)) continue;
     const int orig = G.perm[si];
-    long long pidx = 0, fo = 0, vo = 0;
-    if (l == 0) {
-      pidx = (long long)atomicAdd(&C.cnt[CNT_PIECES], 1ull);
-      fo = (long long)atomicAdd(&C.cnt[CNT_FACES], (unsigned long long)nv);
-      vo = (long long)atomicAdd(&C.cnt[CNT_VERTS], (unsigned long long)nv);
-      atomicAdd(&C.pcount[orig], 1);
-    }
-    pidx = __shfl(pidx, 0, 64);
-    fo = __shfl(fo, 0, 64);
-    vo = __shfl(vo, 0, 64);
+    const long long pidx = arena_take(S.ar, C, AR_PIECE, 1);
+    const long long fo = arena_take(S.ar, C, AR_FACE, nv);
+    const long long vo = arena_take(S.ar, C, AR_VERT, nv);
+    if (l == 0) atomicAdd(&C.pcount[orig], 1);
     if (C.want_grad) {
       // segment moments of the bisector edges: a point of the edge moves in
       // the plane of T_a with speed (x - v_i).dv / (d s), s = |n - (n.N)N|
@@ -389,9 +380,7 @@ __global__ void __launch_bounds__(64) surface_kernel(GridView G, DomainView D, c
       const int lab = l < nv ? S.plab[S.ve[l]] : -1;
       const uint64_t pos = __ballot(lab >= 0);
       const int npos = __popcll(pos);
-      long long base = 0;
-      if (l == 0) base = (long long)atomicAdd(&C.cnt[CNT_FINT], (unsigned long long)npos);
-      base = __shfl(base, 0, 64);
+      const long long base = arena_take(S.ar, C, AR_FINT, npos);
       if (l == 0 && pidx < C.cap_piece) { C.piece_fint_start[pidx] = base; C.piece_nfint[pidx] = npos; }
       const long long r = base + __popcll(pos & lowm(l));
       if (lab >= 0 && r < C.cap_fint) {
@@ -437,6 +426,9 @@ __global__ void __launch_bounds__(64) surface_kernel(GridView G, DomainView D, c
         C.piece_energy[pidx] = pe;
         C.piece_fstart[pidx] = fo;
         C.piece_vstart[pidx] = vo;
+        S.ar.pieces++;
+        S.ar.faces += nv;
+        S.ar.verts += nv;
       }
       if (fo + nv <= C.cap_face && vo + nv <= C.cap_vert && l < nv) {
         const int prv = (l + nv - 1) % nv;
@@ -468,36 +460,42 @@ __global__ void __launch_bounds__(64) surface_kernel(GridView G, DomainView D, c
     __syncthreads();
   }
   if (l == 0) {
-    atomicAdd(&C.cnt[CNT_QUERIES], (unsigned long long)ss.queries);
-    atomicAdd(&C.cnt[CNT_CLIPS], (unsigned long long)ss.clips);
-    atomicAdd(&C.cnt[CNT_CANDS], (unsigned long long)ss.cands);
+    S.ar.queries += ss.queries;
+    S.ar.clips += ss.clips;
+    S.ar.cands += ss.cands;
     if (err) {
       atomicAdd(&C.cnt[err == 2 ? CNT_ERR_CAP : CNT_ERR_DEG], 1ull);
       atomicMin((int *)&C.cnt[CNT_BAD_SITE], a);
+      atomicOr((unsigned long long *)&C.cnt[CNT_STAGES], 1ull << VD_STAGE_TRIANGLE);
     }
   }
+  __syncthreads();
+}
+
+// Persistent: every workgroup (one wave) takes triangles from the queues.
+__global__ void __launch_bounds__(64) surface_kernel(GridView G, DomainView D, const CellsDev *__restrict__ Cp) {
+  __shared__ TriLds S;
+  const CellsDev &C = *Cp;
+  arena_init(S.ar);
+  for (;;) {
+    const int a = queue_next(S.ar, C, D.m);
+    if (a < 0) break;
+    do_triangle(S, G, D, C, a);
+  }
+  arena_close(S.ar, C);
 }
 
 // Per-site sums over the site's pieces (CSR order: ascending simplex) and the
-// sorted, de-duplicated positive edge flags as neighbour list.
+// sorted, de-duplicated positive edge flags as neighbour list: site_reduce
+// writes the sums and the list length, site_nbrs the list at its CSR offset.
 constexpr int kB = 256;
 constexpr int kNbLocal = 96;
 
-__global__ void __launch_bounds__(kB) site_reduce(long long n, const long long *__restrict__ poff,
-                                                  const int *__restrict__ pid, const CellsDev *__restrict__ Cp) {
-  const long long i = (long long)blockIdx.x * kB + threadIdx.x;
-  if (i >= n) return;
-  const CellsDev &C = *Cp;
-  double m = 0, mx = 0, my = 0, mz = 0, e = 0;
-  int nb[kNbLocal];
-  int cnt = 0, overflow = 0;
+__device__ __forceinline__ int site_neighbours(const CellsDev &C, const long long *__restrict__ poff,
+                                               const int *__restrict__ pid, long long i, int *nb, int &overflow) {
+  int cnt = 0;
   for (long long q = poff[i]; q < poff[i + 1]; q++) {
     const int p = pid[q];
-    m += C.piece_mass[p];
-    mx += C.piece_mom[3 * (long long)p + 0];
-    my += C.piece_mom[3 * (long long)p + 1];
-    mz += C.piece_mom[3 * (long long)p + 2];
-    e += C.piece_energy[p];
     const long long f0 = C.piece_fstart[p];
     for (int f = 0; f < C.piece_nface[p]; f++) {
       const int lab = C.face_label[f0 + f];
@@ -511,30 +509,85 @@ __global__ void __launch_bounds__(kB) site_reduce(long long n, const long long *
       cnt++;
     }
   }
+  return cnt;
+}
+
+__global__ void __launch_bounds__(kB) site_reduce(long long n, const long long *__restrict__ poff,
+                                                  const int *__restrict__ pid, const CellsDev *__restrict__ Cp) {
+  const long long i = (long long)blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+  const CellsDev &C = *Cp;
+  double m = 0, mx = 0, my = 0, mz = 0, e = 0;
+  for (long long q = poff[i]; q < poff[i + 1]; q++) {
+    const int p = pid[q];
+    m += C.piece_mass[p];
+    mx += C.piece_mom[3 * (long long)p + 0];
+    my += C.piece_mom[3 * (long long)p + 1];
+    mz += C.piece_mom[3 * (long long)p + 2];
+    e += C.piece_energy[p];
+  }
   C.mass[i] = m;
   C.mom[3 * i + 0] = mx;
   C.mom[3 * i + 1] = my;
   C.mom[3 * i + 2] = mz;
   C.energy[i] = e;
-  const long long s0 = (long long)atomicAdd(&C.cnt[CNT_NBRS], (unsigned long long)cnt);
-  C.ncount[i] = cnt;
-  C.nstart[i] = s0;
-  if (s0 + cnt <= C.cap_nbr)
-    for (int k = 0; k < cnt; k++) C.nbr_arena[s0 + k] = nb[k];
+  int nb[kNbLocal];
+  int overflow = 0;
+  C.ncount[i] = site_neighbours(C, poff, pid, i, nb, overflow);
   if (overflow) {
     atomicAdd(&C.cnt[CNT_ERR_CAP], 1ull);
     atomicMin((int *)&C.cnt[CNT_BAD_SITE], (int)i);
+    atomicOr((unsigned long long *)&C.cnt[CNT_STAGES], 1ull << VD_STAGE_NEIGHBOURS);
   }
+}
+
+__global__ void __launch_bounds__(kB) site_nbrs(long long n, const long long *__restrict__ poff,
+                                                const int *__restrict__ pid, const long long *__restrict__ noff,
+                                                int *__restrict__ nbr, const CellsDev *__restrict__ Cp) {
+  const long long i = (long long)blockIdx.x * kB + threadIdx.x;
+  if (i >= n) return;
+  int nb[kNbLocal];
+  int overflow = 0;
+  const int cnt = site_neighbours(*Cp, poff, pid, i, nb, overflow);
+  const long long o = noff[i];
+  for (int k = 0; k < cnt; k++) nbr[o + k] = nb[k];
+}
+
+int resident_workgroups() {
+  static int cache[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  int &w = cache[dev];
+  if (!w) {
+    int per_cu = 0, ncu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, surface_kernel, 64, 0) != hipSuccess || per_cu < 1)
+      per_cu = 1;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1) ncu = 1;
+    w = per_cu * ncu;
+  }
+  return w;
 }
 
 }  // namespace
 
-void vd_launch_surface(const GridView &G, const DomainView &D, const CellsDev *Cdev, hipStream_t st) {
-  hipLaunchKernelGGL(surface_kernel, dim3((unsigned)D.m), dim3(64), 0, st, G, D, Cdev);
+int vd_surface_workgroups(long long m) {
+  const int w = resident_workgroups();
+  return (int)(m < w ? (m > 0 ? m : 1) : w);
+}
+
+void vd_launch_surface(const GridView &G, const DomainView &D, const CellsDev *Cdev, int workgroups,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(surface_kernel, dim3((unsigned)workgroups), dim3(64), 0, st, G, D, Cdev);
 }
 
 void vd_launch_site_reduce(long long n, const long long *poff, const int *pid, const CellsDev *Cdev,
                            hipStream_t st) {
   const unsigned nb = (unsigned)((n + kB - 1) / kB > 0 ? (n + kB - 1) / kB : 1);
   hipLaunchKernelGGL(site_reduce, dim3(nb), dim3(kB), 0, st, n, poff, pid, Cdev);
+}
+
+void vd_launch_site_nbrs(long long n, const long long *poff, const int *pid, const long long *noff, int *nbr,
+                         const CellsDev *Cdev, hipStream_t st) {
+  const unsigned nb = (unsigned)((n + kB - 1) / kB > 0 ? (n + kB - 1) / kB : 1);
+  hipLaunchKernelGGL(site_nbrs, dim3(nb), dim3(kB), 0, st, n, poff, pid, noff, nbr, Cdev);
 }

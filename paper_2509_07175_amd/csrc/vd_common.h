@@ -213,3 +213,140 @@ __device__ __forceinline__ int nn_thread(const GridView &G, double qx, double qy
   out_d2 = bd;
   return bk;
 }
+
+// ---------------------------------------------------------------------------
+// Per-wave LDS copy of the sites in a block of grid cells around the site
+// being carved.  A query whose ball (centre q, radius = best distance found in
+// the copy) lies inside the block has its exact answer, with the same
+// tie-break, from the copy alone; otherwise the grid query continues from that
+// best candidate.  The block is the largest one (half-width <= 8 cells) whose
+// sites fit, sized from the density of the 3x3x3 block around the site.
+// ---------------------------------------------------------------------------
+#define VD_CACHE 224
+
+struct SiteCache {
+  double x[VD_CACHE], y[VD_CACHE], z[VD_CACHE];
+  int p[VD_CACHE];
+  int cnt;   // sites held; -1 = none for this site
+  int b[6];  // cell block x0, x1, y0, y1, z0, z1
+};
+
+__device__ __forceinline__ int wave_isum(int v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+// sites in the cell block (whole wave)
+__device__ __forceinline__ int block_count(const GridView &G, int x0, int x1, int y0, int y1, int z0, int z1) {
+  const int l = vd_lane();
+  const int nx = x1 - x0 + 1, ny = y1 - y0 + 1, R = ny * (z1 - z0 + 1);
+  int c = 0;
+  for (int r = l; r < R; r += 64) {
+    const int c0 = x0 + G.g[0] * ((y0 + r % ny) + G.g[1] * (z0 + r / ny));
+    c += G.cstart[c0 + nx] - G.cstart[c0];
+  }
+  return wave_isum(c);
+}
+
+__device__ void cache_fill(SiteCache &K, const GridView &G, double vx, double vy, double vz) {
+  const int l = vd_lane();
+  const int gx = G.g[0], gy = G.g[1], gz = G.g[2];
+  const int cx = cell_coord(vx, G.geom[0], G.geom[6], gx);
+  const int cy = cell_coord(vy, G.geom[1], G.geom[7], gy);
+  const int cz = cell_coord(vz, G.geom[2], G.geom[8], gz);
+  auto cells = [&](int r) {
+    return (long long)(min(cx + r, gx - 1) - max(cx - r, 0) + 1) * (min(cy + r, gy - 1) - max(cy - r, 0) + 1) *
+           (min(cz + r, gz - 1) - max(cz - r, 0) + 1);
+  };
+  auto count = [&](int r) {
+    return block_count(G, max(cx - r, 0), min(cx + r, gx - 1), max(cy - r, 0), min(cy + r, gy - 1),
+                       max(cz - r, 0), min(cz + r, gz - 1));
+  };
+  const int c1 = count(1);
+  int r = 1;
+  const double dens = (double)c1 / (double)cells(1);
+  while (r < 8 && (c1 == 0 || dens * (double)cells(r + 1) <= 0.7 * VD_CACHE)) r++;
+  int c = r == 1 ? c1 : count(r);
+  while (c > VD_CACHE && r > 0) c = count(--r);
+  __syncthreads();
+  if (c > VD_CACHE) {
+    if (l == 0) K.cnt = -1;
+    __syncthreads();
+    return;
+  }
+  const int x0 = max(cx - r, 0), x1 = min(cx + r, gx - 1), y0 = max(cy - r, 0), y1 = min(cy + r, gy - 1);
+  const int z0 = max(cz - r, 0), z1 = min(cz + r, gz - 1);
+  const int nx = x1 - x0 + 1, ny = y1 - y0 + 1, R = ny * (z1 - z0 + 1);
+  int off = 0;
+  for (int r0 = 0; r0 < R; r0 += 64) {
+    const int rr = r0 + l;
+    int st = 0, cnt = 0;
+    if (rr < R) {
+      const int c0 = x0 + gx * ((y0 + rr % ny) + gy * (z0 + rr / ny));
+      st = G.cstart[c0];
+      cnt = G.cstart[c0 + nx] - st;
+    }
+    const int inc = wave_incl_scan(cnt);
+    const int excl = inc - cnt;
+    const int total = __shfl(inc, 63, 64);
+    const int nrows = (R - r0) < 64 ? (R - r0) : 64;
+    for (int base = 0; base < total; base += 64) {
+      const int t = base + l;
+      int w = 0;
+      for (int step = 32; step >= 1; step >>= 1) {
+        const int cand = w + step;
+        const int v = __shfl(excl, cand & 63, 64);
+        if (cand < nrows && v <= t) w = cand;
+      }
+      const int rst = __shfl(st, w, 64);
+      const int rex = __shfl(excl, w, 64);
+      if (t < total) {
+        const int p = rst + (t - rex);
+        K.x[off + t] = G.sx[p];
+        K.y[off + t] = G.sy[p];
+        K.z[off + t] = G.sz[p];
+        K.p[off + t] = p;
+      }
+    }
+    off += total;
+  }
+  if (l == 0) {
+    K.cnt = off;
+    K.b[0] = x0; K.b[1] = x1; K.b[2] = y0; K.b[3] = y1; K.b[4] = z0; K.b[5] = z1;
+  }
+  __syncthreads();
+}
+
+// nearest site of q (group of gs lanes, q uniform in the group), seeded with
+// the candidate (r2, k0); exact, ties to the lowest sorted position
+__device__ __forceinline__ int nn_cached(const SiteCache &K, const GridView &G, int gs, double qx, double qy,
+                                         double qz, double r2, int k0, long long &ncand) {
+  const int n = K.cnt;
+  if (n >= 0) {
+    const int gl = vd_lane() & (gs - 1);
+    double bd = r2;
+    int bk = k0;
+    for (int t = gl; t < n; t += gs) {
+      const double dx = qx - K.x[t], dy = qy - K.y[t], dz = qz - K.z[t];
+      const double d = dx * dx + dy * dy + dz * dz;
+      const int p = K.p[t];
+      if (d < bd || (d == bd && p < bk)) { bd = d; bk = p; }
+    }
+    group_argmin(bd, bk, gs);
+    ncand += n;
+    const double rn = sqrt(bd);
+    const int gx = G.g[0], gy = G.g[1], gz = G.g[2];
+    const bool inside = cell_coord(qx - rn, G.geom[0], G.geom[6], gx) >= K.b[0] &&
+                        cell_coord(qx + rn, G.geom[0], G.geom[6], gx) <= K.b[1] &&
+                        cell_coord(qy - rn, G.geom[1], G.geom[7], gy) >= K.b[2] &&
+                        cell_coord(qy + rn, G.geom[1], G.geom[7], gy) <= K.b[3] &&
+                        cell_coord(qz - rn, G.geom[2], G.geom[8], gz) >= K.b[4] &&
+                        cell_coord(qz + rn, G.geom[2], G.geom[8], gz) <= K.b[5];
+    if (inside) return bk;
+    r2 = bd;
+    k0 = bk;
+  }
+  return nn_query(G, gs, qx, qy, qz, r2, k0, ncand);
+}
+

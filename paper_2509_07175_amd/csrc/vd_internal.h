@@ -13,14 +13,26 @@
 #define VD_C_MAX 128   // corners (two slots per lane)
 #define VD_Q_MAX 256   // tetrahedra visited for one site (4 per lane)
 #define VD_NB_MAX 96   // distinct neighbours of one site
-#define VD_F_MAX 48    // bisector facets of one cell (cell-first mode)
+#define VD_F_MAX 48    // planes of a saved cell (cell-first mode)
+#define VD_CB_MAX 96   // corners of a saved cell
 
-// device counters written by the clip kernels (one atomic per wave per field)
+// Output arenas.  Waves reserve chunks of an arena with one atomic on its
+// counter and hand out slots from the chunk, so a counter is the arena's
+// high-water mark (unused chunk tails included), not the number of records.
+enum { AR_PIECE = 0, AR_FACE, AR_VERT, AR_NBR, AR_FINT, AR_N };
+
+// device counters written by the clip kernels; the first AR_N are the arena
+// high-water marks (index = arena id), CNT_REAL_* the records actually written
 enum {
-  CNT_PIECES = 0, CNT_FACES, CNT_VERTS, CNT_NBRS, CNT_PLIST, CNT_FINT,
-  CNT_QUERIES, CNT_CLIPS, CNT_CANDS, CNT_ERR_CAP, CNT_ERR_DEG, CNT_ERR_LOC, CNT_BAD_SITE,
+  CNT_PIECES = AR_PIECE, CNT_FACES = AR_FACE, CNT_VERTS = AR_VERT, CNT_NBRS = AR_NBR, CNT_FINT = AR_FINT,
+  CNT_QUERIES = AR_N, CNT_CLIPS, CNT_CANDS, CNT_ERR_CAP, CNT_ERR_DEG, CNT_ERR_LOC, CNT_BAD_SITE,
+  CNT_REAL_PIECES, CNT_REAL_FACES, CNT_REAL_VERTS, CNT_REAL_NBRS, CNT_STAGES,
   CNT_N
 };
+
+// persistent kernels: one work queue per XCD (8 heads, one per 128-byte line)
+#define VD_QUEUES 8
+#define VD_QSTRIDE 32
 
 struct vd_grid_s {
   int64_t n = 0, cap_n = 0;
@@ -79,6 +91,7 @@ struct CellsDev {
   int straddle;    // Alg. 1 edges when available
   int max_iters;
   int mode;        // 0 per-simplex carve, 1 cell-first
+  int cache;       // LDS copy of the sites around each site for its queries
   double box_lo[3], box_hi[3];  // padded domain box (cell-first)
   unsigned long long *cnt;  // CNT_N counters
   // per site (caller index)
@@ -100,7 +113,8 @@ struct CellsDev {
   double *fint; int *fint_lab; long long cap_fint;
   long long *piece_fint_start; int *piece_nfint;
   int *seed;  // 3D: tetrahedron containing each site (sorted position order)
-  int *facet, *nfacet;  // cell-first: facet labels [n * VD_F_MAX], counts [n] (sorted order)
+  long long chunk[AR_N];  // slots a wave reserves at a time in each arena
+  int *queue;             // [VD_QUEUES * VD_QSTRIDE] work-queue heads
 };
 
 struct vd_cells_s {
@@ -133,10 +147,16 @@ void vd_launch_grid_build(vd_grid g, const double *sites, const double *bbox_hos
 void vd_launch_domain_locator(vd_domain d, hipStream_t st);
 void vd_launch_locate_sites(const GridView &G, const DomainView &D, int *seed, unsigned long long *cnt,
                             hipStream_t st);
-void vd_launch_cells3d(const GridView &G, const CellsDev &C, hipStream_t st);
-void vd_launch_pieces3d(const GridView &G, const DomainView &D, const CellsDev *Cdev, int carve_each,
-                        hipStream_t st);
-void vd_launch_surface(const GridView &G, const DomainView &D, const CellsDev *Cdev, hipStream_t st);
+// workgroups of the persistent 3D site kernel (resident waves of the device)
+int vd_sites3d_workgroups(long long n);
+void vd_launch_queue_init(int *queue, long long n, hipStream_t st);
+void vd_launch_sites3d(const GridView &G, const DomainView &D, const CellsDev *Cdev, int workgroups,
+                       hipStream_t st);
+int vd_surface_workgroups(long long m);
+void vd_launch_surface(const GridView &G, const DomainView &D, const CellsDev *Cdev, int workgroups,
+                       hipStream_t st);
+void vd_launch_site_nbrs(long long n, const long long *poff, const int *pid, const long long *noff, int *nbr,
+                         const CellsDev *Cdev, hipStream_t st);
 void vd_launch_site_reduce(long long n, const long long *poff, const int *pid, const CellsDev *Cdev,
                            hipStream_t st);
 void vd_launch_finalize(vd_cells c, hipStream_t st);

@@ -28,9 +28,22 @@ def run_gpu(sites, dom, bbox=(0, 0, 0, 1, 1, 1), surface_area=0.0, **opts):
         "nbr_off": view["nbr_off"].cpu().numpy(), "nbr": view["nbr"].cpu().numpy(),
         "cell_piece_off": view["cell_piece_off"].cpu().numpy(), "piece_id": view["piece_id"].cpu().numpy(),
         "raw_piece_site": view["piece_site"].cpu().numpy(),
+        "raw_piece_simplex": view["piece_simplex"].cpu().numpy(),
         "cells": c, "grid": g, "domain": d, "sites_t": s,
     }
     return out
+
+
+def assert_csr(gpu, n):
+    """The per-site CSR lists exactly the used piece slots, each under its own
+    site, by ascending simplex."""
+    off, pid, site = gpu["cell_piece_off"], gpu["piece_id"], gpu["raw_piece_site"]
+    assert off[0] == 0 and np.all(np.diff(off) >= 0)
+    assert np.array_equal(np.sort(pid), np.nonzero(site >= 0)[0])
+    owner = np.repeat(np.arange(n), np.diff(off))
+    assert np.array_equal(site[pid], owner)
+    simp = gpu["res"]["piece_simplex"]  # (site, simplex) order, same as the CSR
+    assert np.array_equal(gpu["raw_piece_simplex"][pid], simp)
 
 
 def gpu_neighbors(out, n):
@@ -73,6 +86,7 @@ def assert_parity(gpu, ref_res, ref_mom, n, sites_subset=None, xyz_tol=1e-10, re
     e_g, e_r = gpu["energy"][idx], ref_mom["energy"][idx]
     assert np.all(np.abs(e_g - e_r)[nz] <= rel * e_r[nz]), \
         f"energy max rel err {np.max(np.abs(e_g - e_r)[nz] / e_r[nz])}"
+    assert_csr(gpu, len(gpu["mass"]))
     nb = gpu_neighbors(gpu, len(gpu["mass"]))
     for i in idx:
         assert list(nb[i]) == list(ref_mom["neighbors"][i]), f"neighbours of site {i} differ"
