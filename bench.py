@@ -71,6 +71,8 @@ def main():
     ap.add_argument("--improved", type=int, default=1, choices=[0, 1])
     ap.add_argument("--straddle", type=int, default=1, choices=[0, 1])
     ap.add_argument("--site-cache", type=int, default=1, choices=[0, 1])
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU (asked for {args.gpus}); "
@@ -79,6 +81,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        # a kernel of known traffic: 2^30 bytes read and 2^30 bytes written per launch
+        src = torch.empty(2 ** 27, dtype=torch.float64, device="cuda:0").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_per_launch": 2 ** 30, "launches": 5}), flush=True)
+        return
 
     import paper_2509_07175_amd as vd
 
@@ -148,6 +160,7 @@ def main():
                      "kernel": dom_name, "kernel_ms": dom_ms},
         "counters": {"pieces": info["n_pieces"], "nn_queries": info["nn_queries"], "clips": info["clips"],
                      "candidates": info["candidates"], "queries_per_cell": info["nn_queries"] / n,
+                     "grid_queries": info["grid_queries"],
                      "mass_sum": total_mass},
     }
     if not args.no_cpu_baseline:

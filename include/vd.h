@@ -157,6 +157,7 @@ typedef struct {
   int64_t nn_queries;  /* point-in-cell tests (nearest-site queries) performed */
   int64_t clips;       /* clips applied */
   int64_t candidates;  /* sites examined by the nearest-site queries */
+  int64_t grid_queries; /* queries not answered by the per-wave site cache (0 for surfaces) */
   int32_t first_bad_site; /* -1, or a site whose carve hit a capacity/degeneracy */
   int32_t failed_stages;  /* bit mask of the stages that failed (VD_STAGE_*), 0 if none */
   int32_t status;         /* vd_status of the last clip */

@@ -55,7 +55,8 @@ class Options(C.Structure):
 class _Info(C.Structure):
     _fields_ = [("n_sites", C.c_int64), ("n_pieces", C.c_int64), ("n_faces", C.c_int64),
                 ("n_verts", C.c_int64), ("n_nbrs", C.c_int64), ("nn_queries", C.c_int64),
-                ("clips", C.c_int64), ("candidates", C.c_int64), ("first_bad_site", C.c_int32),
+                ("clips", C.c_int64), ("candidates", C.c_int64), ("grid_queries", C.c_int64),
+                ("first_bad_site", C.c_int32),
                 ("failed_stages", C.c_int32), ("status", C.c_int32), ("carve_ms", C.c_double),
                 ("split_ms", C.c_double)]
 

@@ -532,6 +532,7 @@ vd_status vd_cells_info(vd_cells c, vd_cells_info_t *info) {
   info->nn_queries = (int64_t)hc[CNT_QUERIES];
   info->clips = (int64_t)hc[CNT_CLIPS];
   info->candidates = (int64_t)hc[CNT_CANDS];
+  info->grid_queries = (int64_t)hc[CNT_GRIDQ];
   info->first_bad_site = c->first_bad;
   info->failed_stages = (int32_t)c->host_cnt[CNT_STAGES];
   info->status = c->status;

@@ -74,7 +74,7 @@ __device__ __forceinline__ uint64_t low_mask(int k) { return k >= 64 ? ~0ull : (
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 struct Stats {
-  long long queries = 0, cands = 0, clips = 0;
+  long long queries = 0, cands = 0, clips = 0, grid = 0;  // grid: queries not answered by the site cache
 };
 
 struct SiteCtx {
@@ -201,7 +201,7 @@ __device__ int clip_poly(WaveLds &S, int P, int pt, int &nc) {
   }
   const int cnt = __popc(em[0]) + __popc(em[1]);
   const int inc = wave_incl_scan(cnt);
-  const int nnew = __shfl(inc, 63, 64);
+  const int nnew = __builtin_amdgcn_readlane(inc, 63);
   const int base = inc - cnt;
   const int nsurv = nc - nR;
   if (nnew < 3) return 3;
@@ -409,9 +409,19 @@ __device__ int carve(WaveLds &S, const GridView &G, const CarveParams C, const S
     const int gs = mode == TEST ? 16 : 64;
     const double qx = X.vx + q0, qy = X.vy + q1, qz = X.vz + q2;
     const double dx = qx - X.vx, dy = qy - X.vy, dz = qz - X.vz;
-    const int kq = nn_cached(S.K, G, gs, qx, qy, qz, dx * dx + dy * dy + dz * dz, X.si, st.cands);
+    // sites the test treats like v_i: flags of the corner's planes (TEST), the
+    // candidate and the search edge's planes (SEARCH), the edge's planes (LAMBDA)
+    int e0 = ef0, e1 = ef1, e2 = mode == SEARCH ? j : -1;
+    if (mode == TEST) {
+      const int tpl = S.cpl[tslot >= 0 ? tslot : 0];
+      e0 = S.plab[p8(tpl, 0)]; e1 = S.plab[p8(tpl, 1)]; e2 = S.plab[p8(tpl, 2)];
+    }
+    bool on_grid;
+    const int kq = nn_cached(S.K, G, gs, qx, qy, qz, dx * dx + dy * dy + dz * dz, X.si, e0 < 0 ? -1 : e0,
+                             e1 < 0 ? -1 : e1, e2 < 0 ? -1 : e2, st.cands, on_grid);
     if (mode == TEST) {
       st.queries += nbatch;
+      st.grid += __popcll(__ballot(on_grid && (l & 15) == 0 && grp < nbatch));
       const int pl = tslot >= 0 ? S.cpl[tslot] : 0;
       const bool in = (kq == X.si) || (kq == S.plab[p8(pl, 0)]) || (kq == S.plab[p8(pl, 1)]) ||
                       (kq == S.plab[p8(pl, 2)]);
@@ -422,6 +432,7 @@ __device__ int carve(WaveLds &S, const GridView &G, const CarveParams C, const S
       continue;
     }
     st.queries++;
+    st.grid += on_grid ? 1 : 0;
     const int k = uni(kq);
     if (mode == LAMBDA) {
       if (k != X.si && k != ef0 && k != ef1) {
@@ -869,6 +880,7 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
     S.ar.queries += st.queries;
     S.ar.cands += st.cands;
     S.ar.clips += st.clips;
+    S.ar.gridq += st.grid;
     if (err) {
       atomicAdd(&C.cnt[err == 2 ? CNT_ERR_CAP : CNT_ERR_DEG], 1ull);
       atomicMin((int *)&C.cnt[CNT_BAD_SITE], orig);

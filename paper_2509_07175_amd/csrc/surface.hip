@@ -446,7 +446,7 @@ __device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, c
     uint64_t pos = __ballot(lab >= 0);
     for (; pos; pos &= pos - 1) {
       const int t = __ffsll((unsigned long long)pos) - 1;
-      const int j = uni(__shfl(lab, t, 64));
+      const int j = __builtin_amdgcn_readlane(lab, t);
       bool have = false;
       for (int e = l; e < nsq; e += 64) have = have || (S.sq[e] == j);
       if (!__ballot(have)) {

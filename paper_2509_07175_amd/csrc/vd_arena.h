@@ -19,7 +19,7 @@
 
 struct WaveArena {
   long long cur[AR_N], end[AR_N];
-  unsigned long long queries, cands, clips;
+  unsigned long long queries, cands, clips, gridq;
   unsigned long long pieces, faces, verts, nbrs;  // records written (real counts)
   int qi;                                         // queues tried so far
 };
@@ -27,7 +27,7 @@ struct WaveArena {
 __device__ __forceinline__ void arena_init(WaveArena &A) {
   if (vd_lane() == 0) {
     for (int r = 0; r < AR_N; r++) A.cur[r] = A.end[r] = 0;
-    A.queries = A.cands = A.clips = 0;
+    A.queries = A.cands = A.clips = A.gridq = 0;
     A.pieces = A.faces = A.verts = A.nbrs = 0;
     A.qi = 0;
   }
@@ -47,7 +47,7 @@ __device__ __forceinline__ long long arena_take(WaveArena &A, const CellsDev &C,
     A.cur[r] = cur + k;
     o = cur;
   }
-  return __shfl(o, 0, 64);
+  return readlane_ll(o, 0);
 }
 
 // Next work item in [0, n), or -1 when every queue is exhausted.
@@ -64,7 +64,7 @@ __device__ __forceinline__ int queue_next(WaveArena &A, const CellsDev &C, long 
       if (v < end) { r = v; break; }
     }
   }
-  return __shfl(r, 0, 64);
+  return __builtin_amdgcn_readlane(r, 0);
 }
 
 // End of a persistent wave: mark the unused tail of its piece chunk and add
@@ -77,6 +77,7 @@ __device__ __forceinline__ void arena_close(WaveArena &A, const CellsDev &C) {
     atomicAdd(&C.cnt[CNT_QUERIES], A.queries);
     atomicAdd(&C.cnt[CNT_CANDS], A.cands);
     atomicAdd(&C.cnt[CNT_CLIPS], A.clips);
+    atomicAdd(&C.cnt[CNT_GRIDQ], A.gridq);
     atomicAdd(&C.cnt[CNT_REAL_PIECES], A.pieces);
     atomicAdd(&C.cnt[CNT_REAL_FACES], A.faces);
     atomicAdd(&C.cnt[CNT_REAL_VERTS], A.verts);

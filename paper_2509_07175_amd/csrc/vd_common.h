@@ -31,42 +31,124 @@ __device__ __forceinline__ bool bit128(uint64_t lo, uint64_t hi, int s) {
   return s < 64 ? ((lo >> s) & 1ull) : ((hi >> (s - 64)) & 1ull);
 }
 
+// ---------------------------------------------------------------------------
+// Wave primitives on DPP (row = 16 lanes) and lane reads.  The reductions
+// combine within rows with quad_perm / row_half_mirror / row_mirror moves and
+// across the four rows with v_readlane, so they cost a few VALU latencies
+// instead of one LDS round trip (ds_bpermute) per step.  Every lane of the
+// wave must be active (of the row, for the row_ variants).
+// ---------------------------------------------------------------------------
+#define VD_DPP_QUAD_XOR1 0xB1   // quad_perm [1,0,3,2]
+#define VD_DPP_QUAD_XOR2 0x4E   // quad_perm [2,3,0,1]
+#define VD_DPP_ROW_HALF_MIRROR 0x141
+#define VD_DPP_ROW_MIRROR 0x140
+#define VD_DPP_ROW_SHR(k) (0x110 + (k))
+#define VD_DPP_ROW_BCAST15 0x142
+#define VD_DPP_ROW_BCAST31 0x143
+
+// lanes whose source is outside the row get `old`
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int old, int v) {
+  return __builtin_amdgcn_update_dpp(old, v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double old, double v) {
+  const uint64_t o = (uint64_t)__double_as_longlong(old), b = (uint64_t)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(o >> 32), (int)(uint32_t)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+__device__ __forceinline__ long long readlane_ll(long long v, int lane) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), lane);
+  return (long long)(((uint64_t)hi << 32) | lo);
+}
+
+// inclusive prefix sum over the wave
 __device__ __forceinline__ int wave_incl_scan(int v) {
-  const int l = vd_lane();
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    int o = __shfl_up(v, d, 64);
-    if (l >= d) v += o;
-  }
+  v += dpp_i<VD_DPP_ROW_SHR(1)>(0, v);
+  v += dpp_i<VD_DPP_ROW_SHR(2)>(0, v);
+  v += dpp_i<VD_DPP_ROW_SHR(4)>(0, v);
+  v += dpp_i<VD_DPP_ROW_SHR(8)>(0, v);
+  v += __builtin_amdgcn_update_dpp(0, v, VD_DPP_ROW_BCAST15, 0xa, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, VD_DPP_ROW_BCAST31, 0xc, 0xf, false);
   return v;
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+// inclusive prefix sum within each row of 16 lanes
+__device__ __forceinline__ int row_incl_scan(int v) {
+  v += dpp_i<VD_DPP_ROW_SHR(1)>(0, v);
+  v += dpp_i<VD_DPP_ROW_SHR(2)>(0, v);
+  v += dpp_i<VD_DPP_ROW_SHR(4)>(0, v);
+  v += dpp_i<VD_DPP_ROW_SHR(8)>(0, v);
   return v;
+}
+
+// sum over the wave, the same value in every lane (fixed combination order)
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_d<VD_DPP_QUAD_XOR1>(0.0, v);
+  v += dpp_d<VD_DPP_QUAD_XOR2>(0.0, v);
+  v += dpp_d<VD_DPP_ROW_HALF_MIRROR>(0.0, v);
+  v += dpp_d<VD_DPP_ROW_MIRROR>(0.0, v);
+  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+
+__device__ __forceinline__ int wave_isum(int v) {
+  v += dpp_i<VD_DPP_QUAD_XOR1>(0, v);
+  v += dpp_i<VD_DPP_QUAD_XOR2>(0, v);
+  v += dpp_i<VD_DPP_ROW_HALF_MIRROR>(0, v);
+  v += dpp_i<VD_DPP_ROW_MIRROR>(0, v);
+  return (__builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16)) +
+         (__builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48));
 }
 
 __device__ __forceinline__ uint64_t wave_or64(uint64_t v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
-    unsigned lo = (unsigned)v, hi = (unsigned)(v >> 32);
-    lo |= (unsigned)__shfl_xor((int)lo, m, 64);
-    hi |= (unsigned)__shfl_xor((int)hi, m, 64);
-    v = ((uint64_t)hi << 32) | lo;
-  }
-  return v;
+  int lo = (int)(uint32_t)v, hi = (int)(uint32_t)(v >> 32);
+  lo |= dpp_i<VD_DPP_QUAD_XOR1>(lo, lo); hi |= dpp_i<VD_DPP_QUAD_XOR1>(hi, hi);
+  lo |= dpp_i<VD_DPP_QUAD_XOR2>(lo, lo); hi |= dpp_i<VD_DPP_QUAD_XOR2>(hi, hi);
+  lo |= dpp_i<VD_DPP_ROW_HALF_MIRROR>(lo, lo); hi |= dpp_i<VD_DPP_ROW_HALF_MIRROR>(hi, hi);
+  lo |= dpp_i<VD_DPP_ROW_MIRROR>(lo, lo); hi |= dpp_i<VD_DPP_ROW_MIRROR>(hi, hi);
+  const uint32_t L = (uint32_t)(__builtin_amdgcn_readlane(lo, 0) | __builtin_amdgcn_readlane(lo, 16) |
+                                __builtin_amdgcn_readlane(lo, 32) | __builtin_amdgcn_readlane(lo, 48));
+  const uint32_t H = (uint32_t)(__builtin_amdgcn_readlane(hi, 0) | __builtin_amdgcn_readlane(hi, 16) |
+                                __builtin_amdgcn_readlane(hi, 32) | __builtin_amdgcn_readlane(hi, 48));
+  return ((uint64_t)H << 32) | L;
 }
 
-// Lexicographic (distance^2, sorted position) minimum over the wave; every
-// lane ends with the result.
+// Lexicographic (distance^2, sorted position) minimum within each row of 16
+// lanes; every lane of the row ends with the row's result.
+template <int CTRL>
+__device__ __forceinline__ void argmin_step(double &d, int &k) {
+  const double od = dpp_d<CTRL>(d, d);
+  const int ok = dpp_i<CTRL>(k, k);
+  if (od < d || (od == d && ok < k)) { d = od; k = ok; }
+}
+__device__ __forceinline__ void row_argmin(double &d, int &k) {
+  argmin_step<VD_DPP_QUAD_XOR1>(d, k);
+  argmin_step<VD_DPP_QUAD_XOR2>(d, k);
+  argmin_step<VD_DPP_ROW_HALF_MIRROR>(d, k);
+  argmin_step<VD_DPP_ROW_MIRROR>(d, k);
+}
+
+// ... over the wave; every lane ends with the result
 __device__ __forceinline__ void wave_argmin(double &d, int &k) {
+  row_argmin(d, k);
+  double bd = readlane_d(d, 0);
+  int bk = __builtin_amdgcn_readlane(k, 0);
 #pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
-    double od = __shfl_xor(d, m, 64);
-    int ok = __shfl_xor(k, m, 64);
-    if (od < d || (od == d && ok < k)) { d = od; k = ok; }
+  for (int r = 1; r < 4; r++) {
+    const double od = readlane_d(d, 16 * r);
+    const int ok = __builtin_amdgcn_readlane(k, 16 * r);
+    if (od < bd || (od == bd && ok < bk)) { bd = od; bk = ok; }
   }
+  d = bd;
+  k = bk;
 }
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
@@ -100,13 +182,9 @@ __device__ __forceinline__ void scan_box(const GridView &G, int gs, int x0, int 
       st = G.cstart[c0];
       cnt = G.cstart[c0 + nx] - st;
     }
-    int inc = cnt;
-    for (int d = 1; d < gs; d <<= 1) {
-      const int o = __shfl_up(inc, d, gs);
-      if (gl >= d) inc += o;
-    }
+    const int inc = gs == 64 ? wave_incl_scan(cnt) : row_incl_scan(cnt);
     const int excl = inc - cnt;
-    const int total = __shfl(inc, gs - 1, gs);
+    const int total = gs == 64 ? __builtin_amdgcn_readlane(inc, 63) : __shfl(inc, gs - 1, gs);
     const int nrows = (R - r0) < gs ? (R - r0) : gs;
     ncand += total;
     for (int base = 0; base < total; base += gs) {
@@ -130,11 +208,8 @@ __device__ __forceinline__ void scan_box(const GridView &G, int gs, int x0, int 
 }
 
 __device__ __forceinline__ void group_argmin(double &d, int &k, int gs) {
-  for (int m = gs >> 1; m >= 1; m >>= 1) {
-    const double od = __shfl_xor(d, m, 64);
-    const int ok = __shfl_xor(k, m, 64);
-    if (od < d || (od == d && ok < k)) { d = od; k = ok; }
-  }
+  if (gs == 64) wave_argmin(d, k);
+  else row_argmin(d, k);  // gs == 16: a group is a DPP row
 }
 
 __device__ __forceinline__ int nn_query(const GridView &G, int gs, double qx, double qy, double qz, double r2,
@@ -215,27 +290,27 @@ __device__ __forceinline__ int nn_thread(const GridView &G, double qx, double qy
 }
 
 // ---------------------------------------------------------------------------
-// Per-wave LDS copy of the sites in a block of grid cells around the site
-// being carved.  A query whose ball (centre q, radius = best distance found in
-// the copy) lies inside the block has its exact answer, with the same
-// tie-break, from the copy alone; otherwise the grid query continues from that
-// best candidate.  The block is the largest one (half-width <= 8 cells) whose
-// sites fit, sized from the density of the 3x3x3 block around the site.
+// Per-wave LDS copy of the sites in a block of grid cells around the site v
+// being carved, sorted by distance to v.  Every site within rc of v is held
+// (rc = distance from v to the block's boundary, less a margin for the
+// rounding of cell assignment).  A query q only scans entries up to distance
+// |q - v| + d from v (d = best distance so far: farther sites cannot be
+// nearer to q), and its answer is exact, with the same tie-break, when
+// |q - v| + d < rc; otherwise the grid query continues from that best
+// candidate.  The block is the largest one (half-width <= 8 cells) whose sites
+// fit, sized from the density of the 3x3x3 block around the site.
 // ---------------------------------------------------------------------------
 #define VD_CACHE 224
 
 struct SiteCache {
   double x[VD_CACHE], y[VD_CACHE], z[VD_CACHE];
   int p[VD_CACHE];
-  int cnt;   // sites held; -1 = none for this site
-  int b[6];  // cell block x0, x1, y0, y1, z0, z1
+  double vx, vy, vz;  // the site
+  double rc;          // radius around the site within which every site is held
+  int cnt;            // sites held; -1 = none for this site
+  int b[6];           // the cell block x0, x1, y0, y1, z0, z1
 };
 
-__device__ __forceinline__ int wave_isum(int v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-  return v;
-}
 
 // sites in the cell block (whole wave)
 __device__ __forceinline__ int block_count(const GridView &G, int x0, int x1, int y0, int y1, int z0, int z1) {
@@ -289,7 +364,7 @@ __device__ void cache_fill(SiteCache &K, const GridView &G, double vx, double vy
     }
     const int inc = wave_incl_scan(cnt);
     const int excl = inc - cnt;
-    const int total = __shfl(inc, 63, 64);
+    const int total = __builtin_amdgcn_readlane(inc, 63);
     const int nrows = (R - r0) < 64 ? (R - r0) : 64;
     for (int base = 0; base < total; base += 64) {
       const int t = base + l;
@@ -311,42 +386,116 @@ __device__ void cache_fill(SiteCache &K, const GridView &G, double vx, double vy
     }
     off += total;
   }
+  __syncthreads();
+  // sort by (distance^2 to v, slot): each lane ranks its entries against all
+  double ex[4], ey[4], ez[4], ek[4];
+  int ep[4], rk[4];
+#pragma unroll
+  for (int h = 0; h < 4; h++) {
+    const int t = l + 64 * h;
+    ex[h] = ey[h] = ez[h] = 0.0; ek[h] = 0.0; ep[h] = 0; rk[h] = 0;
+    if (t < off) {
+      ex[h] = K.x[t]; ey[h] = K.y[t]; ez[h] = K.z[t]; ep[h] = K.p[t];
+      const double ax = ex[h] - vx, ay = ey[h] - vy, az = ez[h] - vz;
+      ek[h] = ax * ax + ay * ay + az * az;
+    }
+  }
+  for (int o = 0; o < off; o++) {
+    const double ax = K.x[o] - vx, ay = K.y[o] - vy, az = K.z[o] - vz;
+    const double ko = ax * ax + ay * ay + az * az;
+#pragma unroll
+    for (int h = 0; h < 4; h++) rk[h] += (ko < ek[h] || (ko == ek[h] && o < l + 64 * h)) ? 1 : 0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int h = 0; h < 4; h++) {
+    if (l + 64 * h < off) {
+      K.x[rk[h]] = ex[h]; K.y[rk[h]] = ey[h]; K.z[rk[h]] = ez[h]; K.p[rk[h]] = ep[h];
+    }
+  }
   if (l == 0) {
+    // distance from v to the block boundary; a side at the grid's edge is open
+    const double *lo = G.geom, *h = G.geom + 3;
+    double rc = 1e300;
+    if (x0 > 0) rc = fmin(rc, vx - (lo[0] + x0 * h[0]));
+    if (x1 < gx - 1) rc = fmin(rc, lo[0] + (x1 + 1) * h[0] - vx);
+    if (y0 > 0) rc = fmin(rc, vy - (lo[1] + y0 * h[1]));
+    if (y1 < gy - 1) rc = fmin(rc, lo[1] + (y1 + 1) * h[1] - vy);
+    if (z0 > 0) rc = fmin(rc, vz - (lo[2] + z0 * h[2]));
+    if (z1 < gz - 1) rc = fmin(rc, lo[2] + (z1 + 1) * h[2] - vz);
+    rc -= 1e-9 * fmin(h[0], fmin(h[1], h[2]));
+    K.rc = rc > 0.0 ? rc : 0.0;
+    K.vx = vx; K.vy = vy; K.vz = vz;
     K.cnt = off;
     K.b[0] = x0; K.b[1] = x1; K.b[2] = y0; K.b[3] = y1; K.b[4] = z0; K.b[5] = z1;
   }
   __syncthreads();
 }
 
-// nearest site of q (group of gs lanes, q uniform in the group), seeded with
-// the candidate (r2, k0); exact, ties to the lowest sorted position
+// Point-in-cell query of q (group of gs lanes, q uniform in the group) for the
+// site k0 at squared distance r2 from q, where the sites e0, e1, e2 (-1: none)
+// are those the caller treats like k0 (the flags of the planes through q).
+// Returns either the nearest site of q (ties to the lowest sorted position) or
+// a witness: a cached site strictly nearer to q than k0 and every e.  A witness
+// decides the caller's test as the nearest site would (the nearest site is
+// then none of k0, e0, e1, e2), and it is a valid next site for the bisector
+// search, which only needs a site nearer to its outer point than v_i.
+// Distances are computed by one formula everywhere, so "strictly nearer"
+// holds for the nearest site too.
+__device__ __forceinline__ double sq_dist(const GridView &G, int e, double qx, double qy, double qz) {
+  const double dx = qx - G.sx[e], dy = qy - G.sy[e], dz = qz - G.sz[e];
+  return dx * dx + dy * dy + dz * dz;
+}
+
 __device__ __forceinline__ int nn_cached(const SiteCache &K, const GridView &G, int gs, double qx, double qy,
-                                         double qz, double r2, int k0, long long &ncand) {
+                                         double qz, double r2, int k0, int e0, int e1, int e2, long long &ncand,
+                                         bool &on_grid) {
   const int n = K.cnt;
+  on_grid = false;
   if (n >= 0) {
     const int gl = vd_lane() & (gs - 1);
+    const double wx = qx - K.vx, wy = qy - K.vy, wz = qz - K.vz;
+    const double dq = sqrt(wx * wx + wy * wy + wz * wz);
+    double wit = r2;
+    if (e0 >= 0) wit = fmin(wit, sq_dist(G, e0, qx, qy, qz));
+    if (e1 >= 0) wit = fmin(wit, sq_dist(G, e1, qx, qy, qz));
+    if (e2 >= 0) wit = fmin(wit, sq_dist(G, e2, qx, qy, qz));
     double bd = r2;
     int bk = k0;
-    for (int t = gl; t < n; t += gs) {
-      const double dx = qx - K.x[t], dy = qy - K.y[t], dz = qz - K.z[t];
-      const double d = dx * dx + dy * dy + dz * dz;
-      const int p = K.p[t];
-      if (d < bd || (d == bd && p < bk)) { bd = d; bk = p; }
+    for (int base = 0; base < n; base += gs) {
+      const int t = base + gl;
+      if (t < n) {
+        const double dx = qx - K.x[t], dy = qy - K.y[t], dz = qz - K.z[t];
+        const double d = dx * dx + dy * dy + dz * dz;
+        const int p = K.p[t];
+        if (d < bd || (d == bd && p < bk)) { bd = d; bk = p; }
+      }
+      group_argmin(bd, bk, gs);
+      ncand += (n - base) < gs ? (n - base) : gs;
+      if (bd < wit) return bk;  // witness
+      const int u = base + gs;
+      if (u >= n) break;
+      // entries are sorted by distance to v: stop once it exceeds |q - v| + d
+      const double ax = K.x[u] - K.vx, ay = K.y[u] - K.vy, az = K.z[u] - K.vz;
+      if (sqrt(ax * ax + ay * ay + az * az) > (dq + sqrt(bd)) * (1.0 + 1e-12)) break;
     }
-    group_argmin(bd, bk, gs);
-    ncand += n;
     const double rn = sqrt(bd);
-    const int gx = G.g[0], gy = G.g[1], gz = G.g[2];
-    const bool inside = cell_coord(qx - rn, G.geom[0], G.geom[6], gx) >= K.b[0] &&
-                        cell_coord(qx + rn, G.geom[0], G.geom[6], gx) <= K.b[1] &&
-                        cell_coord(qy - rn, G.geom[1], G.geom[7], gy) >= K.b[2] &&
-                        cell_coord(qy + rn, G.geom[1], G.geom[7], gy) <= K.b[3] &&
-                        cell_coord(qz - rn, G.geom[2], G.geom[8], gz) >= K.b[4] &&
-                        cell_coord(qz + rn, G.geom[2], G.geom[8], gz) <= K.b[5];
-    if (inside) return bk;
+    if ((dq + rn) * (1.0 + 1e-12) < K.rc) return bk;
+    // or the ball of q lies inside the block (same cell arithmetic as the
+    // grid's binning): every site in it is cached, and every cached site in
+    // it lies within |q - v| + d of v, so it was scanned
+    {
+      const double r = rn * (1.0 + 1e-12);
+      const int gx = G.g[0], gy = G.g[1], gz = G.g[2];
+      if (cell_coord(qx - r, G.geom[0], G.geom[6], gx) >= K.b[0] && cell_coord(qx + r, G.geom[0], G.geom[6], gx) <= K.b[1] &&
+          cell_coord(qy - r, G.geom[1], G.geom[7], gy) >= K.b[2] && cell_coord(qy + r, G.geom[1], G.geom[7], gy) <= K.b[3] &&
+          cell_coord(qz - r, G.geom[2], G.geom[8], gz) >= K.b[4] && cell_coord(qz + r, G.geom[2], G.geom[8], gz) <= K.b[5])
+        return bk;
+    }
     r2 = bd;
     k0 = bk;
   }
+  on_grid = true;
   return nn_query(G, gs, qx, qy, qz, r2, k0, ncand);
 }
 

@@ -26,7 +26,7 @@ enum { AR_PIECE = 0, AR_FACE, AR_VERT, AR_NBR, AR_FINT, AR_N };
 enum {
   CNT_PIECES = AR_PIECE, CNT_FACES = AR_FACE, CNT_VERTS = AR_VERT, CNT_NBRS = AR_NBR, CNT_FINT = AR_FINT,
   CNT_QUERIES = AR_N, CNT_CLIPS, CNT_CANDS, CNT_ERR_CAP, CNT_ERR_DEG, CNT_ERR_LOC, CNT_BAD_SITE,
-  CNT_REAL_PIECES, CNT_REAL_FACES, CNT_REAL_VERTS, CNT_REAL_NBRS, CNT_STAGES,
+  CNT_REAL_PIECES, CNT_REAL_FACES, CNT_REAL_VERTS, CNT_REAL_NBRS, CNT_STAGES, CNT_GRIDQ,
   CNT_N
 };
 
