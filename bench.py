@@ -58,6 +58,141 @@ def cpu_baseline(sites, dom, target_s=15.0):
                       f"{elapsed:.2f} s wall on {threads} threads"}
 
 
+def bench_batched(steps, warmup, log):
+    """256 independent diagrams: sequential plain calls vs one autotuned batch
+    (grid build + clip + moments) captured in a HIP graph and replayed."""
+    import numpy as np
+    import torch
+
+    import paper_2509_07175_amd as vd
+    import vdgen
+    from paper_2509_07175_amd import tune as vdtune
+    items = vdgen.config_c4()
+    B = len(items)
+    so = np.concatenate([[0], np.cumsum([len(s) for s, _ in items])])
+    n = int(so[-1])
+    boxes = [(0.0, 0.0, 0.0, 1.0, 1.0, 1.0)] * B
+    log(f"batched: {B} diagrams, {n} sites, {sum(len(d.simplices) for _, d in items)} tetrahedra")
+    # --- sequential plain calls (one vd_build_grid + vd_clip_cells + vd_cell_moments per diagram)
+    plain = []
+    for s, d in items:
+        t = torch.as_tensor(s, dtype=torch.float64, device="cuda")
+        plain.append((t, vd.Domain.from_vdgen(d), vd.Grid(), vd.Cells(),
+                      torch.empty(len(s), dtype=torch.float64, device="cuda"),
+                      torch.empty((len(s), 3), dtype=torch.float64, device="cuda"),
+                      torch.empty(len(s), dtype=torch.float64, device="cuda")))
+    popt = vd.Options.default()
+
+    def plain_pass():
+        for t, dom, g, c, m, ce, e in plain:
+            vd.build_grid(t, bbox=boxes[0], grid=g)
+            vd.clip_cells(g, dom, popt, cells=c)
+            c.moments(m, ce, e)
+
+    for _ in range(max(1, warmup)):
+        plain_pass()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plain_pass()
+    torch.cuda.synchronize()
+    plain_ms = 1e3 * (time.perf_counter() - t0) / steps
+    log(f"batched: sequential plain calls {plain_ms:.1f} ms per pass")
+    # --- the batch: autotune, then capture and replay
+    sites = torch.as_tensor(np.concatenate([s for s, _ in items]), dtype=torch.float64, device="cuda")
+    dom = vd.Domain.batch_from_vdgen([d for _, d in items])
+    best, table = vdtune.tune(sites, dom, site_off=so, bboxes=boxes, log=log)
+    best = dict(best)
+    rho = best.pop("sites_per_cell")
+    side = torch.cuda.Stream()
+    grid, cells = vd.Grid(), vd.Cells()
+    mass = torch.empty(n, dtype=torch.float64, device="cuda")
+    cent = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    en = torch.empty(n, dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(side):
+        vd.build_grid_batch(sites, so, bboxes=boxes, sites_per_cell=rho, grid=grid)
+        vd.clip_cells(grid, dom, vd.Options.default(time_kernels=1, **best), cells=cells)
+        kernel_ms = cells.info()["carve_ms"]
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        vd.build_grid_batch(sites, so, bboxes=boxes, sites_per_cell=rho, grid=grid)
+        vd.clip_cells(grid, dom, vd.Options.default(no_sync=1, **best), cells=cells)
+        cells.moments(mass, cent, en)
+    for _ in range(max(1, warmup)):
+        graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    batch_ms = 1e3 * (time.perf_counter() - t0) / steps
+    info = cells.info()
+    if info["status"] != 0:
+        raise RuntimeError(f"batched replay failed: {info}")
+    vols = [float(mass[so[b]:so[b + 1]].sum().item()) for b in range(B)]
+    log(f"batched: graph replay {batch_ms:.1f} ms, site kernel {kernel_ms:.1f} ms")
+    return {"workload": f"{B} diagrams, {n} sites (1,000-64,000 each, log-uniform), jittered 8^3-24^3 "
+                        f"cube grids x 6 tetrahedra", "sites": n, "diagrams": B,
+            "plain_sequential_ms": plain_ms, "plain_sequential_cells_per_s": n / (plain_ms * 1e-3),
+            "batched_graph_ms": batch_ms, "batched_cells_per_s": n / (batch_ms * 1e-3),
+            "speedup_vs_plain": plain_ms / batch_ms, "site_kernel_ms": kernel_ms,
+            "tuned": dict(best, sites_per_cell=rho), "tuning": [[k, ms] for k, ms in table],
+            "max_volume_error": max(abs(v - 1.0) for v in vols)}
+
+
+def bench_backward(sites_t, dom_h, rho, steps, warmup, log):
+    """Forward with face moments + vd_cell_moments_backward (CVT energy and a
+    random linear loss on mass and centroid) vs the plain forward."""
+    import torch
+
+    import paper_2509_07175_amd as vd
+    n = sites_t.shape[0]
+    bbox = (0.0, 0.0, 0.0, 1.0, 1.0, 1.0)
+    grid, cells = vd.Grid(), vd.Cells()
+    mass = torch.empty(n, dtype=torch.float64, device="cuda")
+    cent = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    en = torch.empty(n, dtype=torch.float64, device="cuda")
+    gen = torch.Generator(device="cuda").manual_seed(9)
+    gm = torch.randn(n, dtype=torch.float64, device="cuda", generator=gen)
+    gc = torch.randn((n, 3), dtype=torch.float64, device="cuda", generator=gen)
+    ge = torch.ones(n, dtype=torch.float64, device="cuda")
+    gs = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    opt = vd.Options.default(want_grad=1, time_kernels=1)
+
+    def step():
+        vd.build_grid(sites_t, bbox=bbox, sites_per_cell=rho, grid=grid)
+        vd.clip_cells(grid, dom_h, opt, cells=cells)
+        cells.moments(mass, cent, en)
+        cells.backward(gm, gc, ge, out=gs)
+
+    for _ in range(max(1, warmup)):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    # adjoint alone
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(steps):
+        cells.backward(gm, gc, ge, out=gs)
+    ev1.record()
+    torch.cuda.synchronize()
+    adj_ms = ev0.elapsed_time(ev1) / steps
+    # the CVT part of the gradient is 2 m (v - c): check it on this run
+    ref = 2 * mass[:, None] * (sites_t - cent)
+    cells.backward(None, None, ge, out=gs)
+    torch.cuda.synchronize()
+    err = float((gs - ref).abs().max().item() / ref.abs().max().item())
+    log(f"backward: forward+grad+adjoint {ms:.1f} ms per step, adjoint {adj_ms:.2f} ms, CVT check {err:.1e}")
+    return {"forward_with_face_moments_plus_adjoint_ms": ms, "cells_per_s": n / (ms * 1e-3),
+            "adjoint_kernel_ms": adj_ms, "adjoint_cells_per_s": n / (adj_ms * 1e-3),
+            "site_kernel_ms_with_face_moments": cells.info()["carve_ms"], "cvt_gradient_rel_err": err}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +206,8 @@ def main():
     ap.add_argument("--improved", type=int, default=1, choices=[0, 1])
     ap.add_argument("--straddle", type=int, default=1, choices=[0, 1])
     ap.add_argument("--site-cache", type=int, default=1, choices=[0, 1])
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-diagrams comparison")
+    ap.add_argument("--no-backward", action="store_true", help="skip the adjoint throughput")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -163,6 +300,12 @@ def main():
                      "grid_queries": info["grid_queries"],
                      "mass_sum": total_mass},
     }
+    log = lambda m: print(f"bench: {m}", file=sys.stderr, flush=True)  # noqa: E731
+    if not args.no_backward:
+        out["backward"] = bench_backward(s, d, rho, max(1, min(args.steps, 5)), 1, log)
+        out["backward"]["vs_plain_forward"] = ms / out["backward"]["forward_with_face_moments_plus_adjoint_ms"]
+    if not args.no_batched:
+        out["batched"] = bench_batched(max(1, min(args.steps, 5)), 1, log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sites, dom)
     print(json.dumps(out), flush=True)

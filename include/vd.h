@@ -82,6 +82,12 @@ typedef struct {
                                  bounding box of the domain (Sec. 5.2), then each piece is
                                  T_a cut by the cell's certified bisector facets.  Both
                                  give the same pieces. */
+  int32_t no_sync;            /* 1: vd_clip_cells only enqueues work (no host synchronisation,
+                                 no allocation), so it can be captured into a HIP graph.
+                                 Needs a tetrahedral domain and a handle sized by an earlier
+                                 synchronous clip of the same sites and options; errors and
+                                 arena overflow are reported by vd_cells_info, which then
+                                 synchronises the stream.  Default 0. */
   int32_t site_cache;         /* 1 (default): each wave keeps the sites of a block of grid
                                  cells around its site in LDS and answers a nearest-site
                                  query there when the query's ball lies inside the block
@@ -131,6 +137,44 @@ vd_status vd_domain_create(const double *verts, int64_t nv, const int32_t *simpl
                            const int32_t *adjacency, int64_t m, int32_t simplex_dim,
                            void *stream, vd_domain *out);
 void vd_domain_free(vd_domain d);
+
+/* ---------------------------------------------------------------------
+ * Batches of independent diagrams (each with its own sites and its own
+ * domain, uneven sizes).  Diagram b owns the sites [site_off[b], site_off[b+1]),
+ * the vertices [vert_off[b], vert_off[b+1]) and the simplices
+ * [simp_off[b], simp_off[b+1]) of the concatenated arrays.  A batch is handled
+ * as one disjoint union: every diagram keeps its own grid and location grid,
+ * nearest-site queries only see the diagram's own sites, and one persistent
+ * launch covers the sites of all diagrams.  Results use the concatenated
+ * numbering: site indices (neighbours, positive flags) and simplex indices
+ * (piece_simplex, -(b+1) flags) are global; subtract site_off / simp_off for
+ * diagram-local ones.  A plain call is the batch of one.
+ * --------------------------------------------------------------------- */
+typedef struct {
+  int32_t num;              /* diagrams, >= 1 */
+  const int64_t *site_off;  /* [num+1] host, site_off[0] = 0 */
+  const int64_t *vert_off;  /* [num+1] host, vert_off[0] = 0 */
+  const int64_t *simp_off;  /* [num+1] host, simp_off[0] = 0 */
+} vd_batch;
+
+/* vd_build_grid for a batch: one counting sort over all sites, each diagram
+ * with its own cells (sites_per_cell per cell of its own box).
+ *   sites      [site_off[num]*3] device.
+ *   bbox_host  [6*num] host boxes (as in vd_build_grid) or NULL.
+ * Repeated calls with the same batch layout enqueue kernels only (no host
+ * copies, no allocation), so they can be captured into a HIP graph.
+ * Errors as vd_build_grid, plus VD_ERR_INVALID_ARG for offsets that are not
+ * increasing from 0. */
+vd_status vd_build_grid_batch(const double *sites, const vd_batch *batch, const double *bbox_host,
+                              double sites_per_cell, void *stream, vd_grid *out);
+
+/* vd_domain_create for a batch: simplices and adjacency hold diagram-local
+ * indices (vertex indices into the diagram's vertices, adjacency into its
+ * simplices, -1 boundary); they are stored shifted to global indices.
+ * Synchronises `stream`.  Errors as vd_domain_create. */
+vd_status vd_domain_create_batch(const double *verts, const int32_t *simplices,
+                                 const int32_t *adjacency, const vd_batch *batch,
+                                 int32_t simplex_dim, void *stream, vd_domain *out);
 
 /* ---------------------------------------------------------------------
  * vd_clip_cells -- all domain-cell intersections P_{a,i} (Sec. 3.1).

@@ -39,7 +39,7 @@ class Options(C.Structure):
     _fields_ = [("sites_per_cell", C.c_double), ("improved_search", C.c_int32),
                 ("use_straddle_edges", C.c_int32), ("max_search_iters", C.c_int32),
                 ("emit_polytopes", C.c_int32), ("want_grad", C.c_int32), ("time_kernels", C.c_int32),
-                ("carve_mode", C.c_int32), ("site_cache", C.c_int32)]
+                ("carve_mode", C.c_int32), ("no_sync", C.c_int32), ("site_cache", C.c_int32)]
 
     @classmethod
     def default(cls, **kw) -> "Options":
@@ -59,6 +59,32 @@ class _Info(C.Structure):
                 ("first_bad_site", C.c_int32),
                 ("failed_stages", C.c_int32), ("status", C.c_int32), ("carve_ms", C.c_double),
                 ("split_ms", C.c_double)]
+
+
+class _Batch(C.Structure):
+    _fields_ = [("num", C.c_int32), ("site_off", C.POINTER(C.c_int64)), ("vert_off", C.POINTER(C.c_int64)),
+                ("simp_off", C.POINTER(C.c_int64))]
+
+
+def _batch(site_off=None, vert_off=None, simp_off=None):
+    """vd_batch from host offset arrays (kept alive on the returned struct)."""
+    def arr(x):
+        if x is None:
+            return None, None
+        a = (C.c_int64 * len(x))(*[int(v) for v in x])
+        return a, C.cast(a, C.POINTER(C.c_int64))
+    keep = []
+    num = None
+    b = _Batch()
+    for name, x in (("site_off", site_off), ("vert_off", vert_off), ("simp_off", simp_off)):
+        a, ptr = arr(x)
+        if a is not None:
+            keep.append(a)
+            setattr(b, name, ptr)
+            num = len(x) - 1
+    b.num = num if num is not None else 0
+    b._keep = keep
+    return b
 
 
 class _View(C.Structure):
@@ -84,6 +110,8 @@ def load():
         "vd_last_error": (C.c_char_p, []),
         "vd_status_string": (C.c_char_p, [C.c_int]),
         "vd_build_grid": (C.c_int, [vp, i64, vp, d, d, vp, C.POINTER(vp)]),
+        "vd_build_grid_batch": (C.c_int, [vp, C.POINTER(_Batch), vp, d, vp, C.POINTER(vp)]),
+        "vd_domain_create_batch": (C.c_int, [vp, vp, vp, C.POINTER(_Batch), i32, vp, C.POINTER(vp)]),
         "vd_grid_free": (None, [vp]),
         "vd_domain_create": (C.c_int, [vp, i64, vp, vp, i64, i32, vp, C.POINTER(vp)]),
         "vd_domain_free": (None, [vp]),
@@ -104,7 +132,7 @@ def load():
 
 def exported_symbols():
     return ["vd_options_default", "vd_last_error", "vd_status_string", "vd_build_grid", "vd_grid_free",
-            "vd_domain_create", "vd_domain_free", "vd_clip_cells", "vd_cells_free", "vd_cells_info",
+            "vd_build_grid_batch", "vd_domain_create_batch", "vd_domain_create", "vd_domain_free", "vd_clip_cells", "vd_cells_free", "vd_cells_info",
             "vd_cells_view", "vd_cell_moments", "vd_cell_moments_backward"]
 
 
@@ -191,6 +219,24 @@ def build_grid(sites, bbox=None, sites_per_cell=0.0, surface_area=0.0, grid: Gri
     return g.build(sites, bbox, sites_per_cell, surface_area, stream)
 
 
+def build_grid_batch(sites, site_off, bboxes=None, sites_per_cell=0.0, grid: Grid | None = None,
+                     stream=None) -> Grid:
+    """vd_build_grid_batch: one grid per diagram over the concatenated sites
+    (diagram b owns sites[site_off[b]:site_off[b+1]])."""
+    import torch
+    g = grid if grid is not None else Grid()
+    b = _batch(site_off=site_off)
+    bb = None
+    if bboxes is not None:
+        flat = [float(x) for box in bboxes for x in box]
+        bb = (C.c_double * len(flat))(*flat)
+    _check(load().vd_build_grid_batch(_dptr(sites, torch.float64, 3), C.byref(b), bb, float(sites_per_cell),
+                                      _stream_ptr(stream), C.byref(g.h)))
+    g.sites = sites
+    g.site_off = list(site_off)
+    return g
+
+
 class Domain:
     """vd_domain_create handle: a simplex domain staged on the device."""
 
@@ -207,6 +253,39 @@ class Domain:
         _check(load().vd_domain_create(_dptr(verts, torch.float64, 3), verts.shape[0],
                                        _dptr(simplices, torch.int32), _dptr(adjacency, torch.int32),
                                        simplices.shape[0], self.dim, _stream_ptr(stream), C.byref(self.h)))
+
+    @classmethod
+    def batch(cls, verts, simplices, adjacency, vert_off, simp_off, dim: int, stream=None):
+        """vd_domain_create_batch: concatenated domains with diagram-local indices."""
+        import torch
+        self = cls.__new__(cls)
+        self.h = C.c_void_p()
+        self.dim = int(dim)
+        self.verts = verts
+        self.simplices = simplices
+        self.m = simplices.shape[0]
+        self.vert_off = list(vert_off)
+        self.simp_off = list(simp_off)
+        b = _batch(vert_off=vert_off, simp_off=simp_off)
+        _check(load().vd_domain_create_batch(_dptr(verts, torch.float64, 3), _dptr(simplices, torch.int32),
+                                             _dptr(adjacency, torch.int32), C.byref(b), self.dim,
+                                             _stream_ptr(stream), C.byref(self.h)))
+        return self
+
+    @classmethod
+    def batch_from_vdgen(cls, doms):
+        """Concatenates vdgen domains (diagram-local indices kept) into one batch."""
+        import numpy as np
+        import torch
+        vo, so = [0], [0]
+        for d in doms:
+            vo.append(vo[-1] + len(d.verts))
+            so.append(so[-1] + len(d.simplices))
+        verts = np.concatenate([d.verts for d in doms])
+        simp = np.concatenate([d.simplices for d in doms]).astype(np.int32)
+        adj = np.concatenate([d.adj for d in doms]).astype(np.int32)
+        t = lambda x, dt: torch.as_tensor(x, dtype=dt, device="cuda").contiguous()
+        return cls.batch(t(verts, torch.float64), t(simp, torch.int32), t(adj, torch.int32), vo, so, doms[0].dim)
 
     @classmethod
     def from_vdgen(cls, dom):

@@ -9,12 +9,15 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "vd_internal.h"
 
 void vd_launch_domain_fill(vd_domain d, hipStream_t st);
+void vd_launch_domain_offsets(vd_domain d, int *flags, hipStream_t st);
 void vd_launch_domain_validate(vd_domain d, int *flags, double *measure, hipStream_t st);
 void vd_launch_vert_bbox(vd_domain d, double *out, hipStream_t st);
 void vd_launch_fill_int(int *p, long long n, int v, hipStream_t st);
@@ -99,29 +102,44 @@ void vd_options_default(vd_options *opt) {
   opt->time_kernels = 0;
   opt->carve_mode = 1;
   opt->site_cache = 1;
+  opt->no_sync = 0;
 }
 
 // ---------------------------------------------------------------------------
 // grid
 // ---------------------------------------------------------------------------
-vd_status vd_build_grid(const double *sites, int64_t n, const double *bbox_host, double sites_per_cell,
-                        double surface_area, void *stream, vd_grid *out) {
-  if (!out) return fail(VD_ERR_INVALID_ARG, "vd_build_grid: out is NULL");
-  if (!sites || n < 1) return fail(VD_ERR_INVALID_ARG, "vd_build_grid: sites NULL or n < 1");
-  if (n > (int64_t)INT_MAX / 4) return fail(VD_ERR_INVALID_ARG, "vd_build_grid: n too large");
-  if (bbox_host)
-    for (int k = 0; k < 3; k++)
-      if (!(bbox_host[3 + k] >= bbox_host[k]) || !std::isfinite(bbox_host[k]) || !std::isfinite(bbox_host[3 + k]))
-        return fail(VD_ERR_INVALID_ARG, "vd_build_grid: invalid bbox");
-  const double rho = sites_per_cell > 0 ? sites_per_cell : 3.5;
-  int g[3];
-  if (surface_area > 0 && bbox_host) {
+}  // extern "C"
+
+namespace {
+
+// copies host data to device memory only when it differs from what was sent
+// last (so repeated calls with the same batch layout enqueue no copies, and
+// can be captured into a graph)
+template <typename T>
+hipError_t upload_if_changed(T *dev, const T *host, size_t count, std::vector<T> &shadow, hipStream_t st) {
+  if (shadow.size() == count && std::memcmp(shadow.data(), host, sizeof(T) * count) == 0) return hipSuccess;
+  shadow.assign(host, host + count);
+  return hipMemcpyAsync(dev, shadow.data(), sizeof(T) * count, hipMemcpyHostToDevice, st);
+}
+
+struct GridShadow {
+  std::vector<long long> site_off, cell_off;
+  std::vector<int> dims;
+  std::vector<double> user_box;
+  std::vector<unsigned char> views;
+};
+std::mutex g_shadow_mu;
+std::unordered_map<const void *, GridShadow> g_grid_shadow;
+
+// cells of one diagram of n sites (box: host bounding box or NULL)
+void diagram_dims(int64_t n, const double *box, double rho, double surface_area, int g[3]) {
+  if (surface_area > 0 && box) {
     const double h = std::sqrt(rho * surface_area / (double)n);
-    for (int k = 0; k < 3; k++) g[k] = std::max(1, (int)std::ceil((bbox_host[3 + k] - bbox_host[k]) / h));
-  } else if (bbox_host) {
+    for (int k = 0; k < 3; k++) g[k] = std::max(1, (int)std::ceil((box[3 + k] - box[k]) / h));
+  } else if (box) {
     double vol = 1.0;
     double ext[3];
-    for (int k = 0; k < 3; k++) { ext[k] = std::max(bbox_host[3 + k] - bbox_host[k], 1e-300); vol *= ext[k]; }
+    for (int k = 0; k < 3; k++) { ext[k] = std::max(box[3 + k] - box[k], 1e-300); vol *= ext[k]; }
     const double h = std::cbrt(vol * rho / (double)n);
     for (int k = 0; k < 3; k++) g[k] = std::max(1, (int)std::ceil(ext[k] / h));
   } else {
@@ -129,26 +147,59 @@ vd_status vd_build_grid(const double *sites, int64_t n, const double *bbox_host,
     g[0] = g[1] = g[2] = gg;
   }
   // keep the cell count sane for degenerate boxes
-  while ((double)g[0] * g[1] * g[2] > 16.0 * (double)n + 4096.0) {
+  while ((double)g[0] * g[1] * g[2] > 16.0 * (double)n + 4096.0)
     for (int k = 0; k < 3; k++) g[k] = std::max(1, g[k] / 2);
+}
+
+vd_status build_grid_impl(const double *sites, int64_t n, int nb, const int64_t *off_host, const double *bbox_host,
+                          double sites_per_cell, double surface_area, void *stream, vd_grid *out, const char *who) {
+  if (!out) return fail(VD_ERR_INVALID_ARG, "%s: out is NULL", who);
+  if (!sites || n < 1) return fail(VD_ERR_INVALID_ARG, "%s: sites NULL or n < 1", who);
+  if (n > (int64_t)INT_MAX / 4) return fail(VD_ERR_INVALID_ARG, "%s: n too large", who);
+  if (nb < 1) return fail(VD_ERR_INVALID_ARG, "%s: no diagrams", who);
+  std::vector<int64_t> off(nb + 1);
+  if (off_host) {
+    for (int b = 0; b <= nb; b++) off[b] = off_host[b];
+    if (off[0] != 0 || off[nb] != n) return fail(VD_ERR_INVALID_ARG, "%s: site offsets must run from 0 to n", who);
+    for (int b = 0; b < nb; b++)
+      if (off[b + 1] <= off[b]) return fail(VD_ERR_INVALID_ARG, "%s: diagram %d has no sites", who, b);
+  } else {
+    off[0] = 0; off[1] = n;
   }
+  if (bbox_host)
+    for (int b = 0; b < nb; b++)
+      for (int k = 0; k < 3; k++) {
+        const double lo = bbox_host[6 * b + k], hi = bbox_host[6 * b + 3 + k];
+        if (!(hi >= lo) || !std::isfinite(lo) || !std::isfinite(hi))
+          return fail(VD_ERR_INVALID_ARG, "%s: invalid bbox of diagram %d", who, b);
+      }
+  const double rho = sites_per_cell > 0 ? sites_per_cell : 3.5;
+  std::vector<int> dims(3 * (size_t)nb);
+  std::vector<int64_t> coff(nb + 1, 0);
+  for (int b = 0; b < nb; b++) {
+    diagram_dims(off[b + 1] - off[b], bbox_host ? bbox_host + 6 * b : nullptr, rho, surface_area, &dims[3 * b]);
+    coff[b + 1] = coff[b] + (int64_t)dims[3 * b] * dims[3 * b + 1] * dims[3 * b + 2];
+  }
+  if (coff[nb] > (int64_t)INT_MAX / 2) return fail(VD_ERR_INVALID_ARG, "%s: too many grid cells", who);
   vd_grid G = *out;
   if (!G) G = new vd_grid_s();
-  G->n = n;
-  G->g[0] = g[0]; G->g[1] = g[1]; G->g[2] = g[2];
-  G->ncell = (int64_t)g[0] * g[1] * g[2];
-  hipStream_t st = as_stream(stream);
-  vd_status s = VD_OK;
   auto fin = [&](vd_status r) {
-    if (r != VD_OK && !*out) { vd_grid_free(G); }
+    if (r != VD_OK && !*out) vd_grid_free(G);
     else *out = G;
     return r;
   };
+  G->n = n;
+  G->nb = nb;
+  G->site_off = off;
+  G->cell_off = coff;
+  G->dims = dims;
+  G->g[0] = dims[0]; G->g[1] = dims[1]; G->g[2] = dims[2];
+  G->ncell = coff[nb];
+  hipStream_t st = as_stream(stream);
+  hipError_t e = hipSuccess;
   {
-    int64_t capn = G->cap_n, capc = G->cap_cell;
-    hipError_t e = hipSuccess;
     int64_t tmp;
-    if (capn < n) {
+    if (G->cap_n < n) {
       tmp = 0; if ((e = ensure(G->sx, tmp, n)) != hipSuccess) goto herr;
       tmp = 0; if ((e = ensure(G->sy, tmp, n)) != hipSuccess) goto herr;
       tmp = 0; if ((e = ensure(G->sz, tmp, n)) != hipSuccess) goto herr;
@@ -156,30 +207,72 @@ vd_status vd_build_grid(const double *sites, int64_t n, const double *bbox_host,
       tmp = 0; if ((e = ensure(G->perm, tmp, n)) != hipSuccess) goto herr;
       tmp = 0; if ((e = ensure(G->rank, tmp, n)) != hipSuccess) goto herr;
       tmp = 0; if ((e = ensure(G->cellid, tmp, n)) != hipSuccess) goto herr;
+      tmp = 0; if ((e = ensure(G->diag, tmp, n)) != hipSuccess) goto herr;
       G->cap_n = n;
     }
-    if (capc < G->ncell) {
+    if (G->cap_cell < G->ncell) {
       tmp = 0; if ((e = ensure(G->cstart, tmp, G->ncell + 1)) != hipSuccess) goto herr;
       tmp = 0; if ((e = ensure(G->ccount, tmp, G->ncell)) != hipSuccess) goto herr;
       tmp = 0; if ((e = ensure(G->fill, tmp, G->ncell)) != hipSuccess) goto herr;
       tmp = 0; if ((e = ensure(G->scan_tmp, tmp, G->ncell / 1024 + 2)) != hipSuccess) goto herr;
       G->cap_cell = G->ncell;
     }
-    if ((e = ensure_fixed(G->geom, 9)) != hipSuccess) goto herr;
-    if ((e = ensure_fixed(G->bbox_part, 6 * 256)) != hipSuccess) goto herr;
+    if (G->cap_nb < nb) {
+      tmp = 0; if ((e = ensure(G->geom, tmp, 9 * (int64_t)nb)) != hipSuccess) goto herr;
+      tmp = 0; if ((e = ensure(G->d_site_off, tmp, nb + 1)) != hipSuccess) goto herr;
+      tmp = 0; if ((e = ensure(G->d_cell_off, tmp, nb + 1)) != hipSuccess) goto herr;
+      tmp = 0; if ((e = ensure(G->d_dims, tmp, 3 * (int64_t)nb)) != hipSuccess) goto herr;
+      tmp = 0; if ((e = ensure(G->d_user_box, tmp, 6 * (int64_t)nb)) != hipSuccess) goto herr;
+      tmp = 0; if ((e = ensure(G->d_views, tmp, nb)) != hipSuccess) goto herr;
+      tmp = 0; if ((e = ensure(G->bbox_part, tmp, 6 * (int64_t)std::max(nb, 256))) != hipSuccess) goto herr;
+      G->cap_nb = nb;
+    }
+    GridShadow *sh;
+    {
+      std::lock_guard<std::mutex> lk(g_shadow_mu);
+      sh = &g_grid_shadow[G];
+    }
+    static_assert(sizeof(long long) == sizeof(int64_t), "offsets");
+    if ((e = upload_if_changed(G->d_site_off, (const long long *)off.data(), off.size(), sh->site_off, st)) != hipSuccess) goto herr;
+    if ((e = upload_if_changed(G->d_cell_off, (const long long *)coff.data(), coff.size(), sh->cell_off, st)) != hipSuccess) goto herr;
+    if ((e = upload_if_changed(G->d_dims, dims.data(), dims.size(), sh->dims, st)) != hipSuccess) goto herr;
+    if (bbox_host && (e = upload_if_changed(G->d_user_box, bbox_host, 6 * (size_t)nb, sh->user_box, st)) != hipSuccess) goto herr;
+    {
+      std::vector<GridView> v(nb);
+      for (int b = 0; b < nb; b++) v[b] = G->view_of(b);
+      std::vector<unsigned char> bytes((const unsigned char *)v.data(), (const unsigned char *)(v.data() + nb));
+      if (sh->views != bytes) {
+        sh->views = bytes;
+        if ((e = hipMemcpyAsync(G->d_views, sh->views.data(), bytes.size(), hipMemcpyHostToDevice, st)) != hipSuccess)
+          goto herr;
+      }
+    }
     goto ok;
   herr:
-    s = fail(e == hipErrorOutOfMemory ? VD_ERR_OUT_OF_MEMORY : VD_ERR_HIP, "vd_build_grid: %s",
-             hipGetErrorString(e));
-    return fin(s);
+    return fin(fail(e == hipErrorOutOfMemory ? VD_ERR_OUT_OF_MEMORY : VD_ERR_HIP, "%s: %s", who, hipGetErrorString(e)));
   }
 ok:
-  vd_launch_grid_build(G, sites, bbox_host, st);
-  {
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return fin(fail(VD_ERR_HIP, "vd_build_grid launch: %s", hipGetErrorString(e)));
-  }
+  vd_launch_grid_build(G, sites, bbox_host ? G->d_user_box : nullptr, st);
+  e = hipGetLastError();
+  if (e != hipSuccess) return fin(fail(VD_ERR_HIP, "%s launch: %s", who, hipGetErrorString(e)));
   return fin(VD_OK);
+}
+
+}  // namespace
+
+extern "C" {
+
+vd_status vd_build_grid(const double *sites, int64_t n, const double *bbox_host, double sites_per_cell,
+                        double surface_area, void *stream, vd_grid *out) {
+  return build_grid_impl(sites, n, 1, nullptr, bbox_host, sites_per_cell, surface_area, stream, out, "vd_build_grid");
+}
+
+vd_status vd_build_grid_batch(const double *sites, const vd_batch *batch, const double *bbox_host,
+                              double sites_per_cell, void *stream, vd_grid *out) {
+  if (!batch || batch->num < 1 || !batch->site_off)
+    return fail(VD_ERR_INVALID_ARG, "vd_build_grid_batch: missing batch or site offsets");
+  return build_grid_impl(sites, batch->site_off[batch->num], batch->num, batch->site_off, bbox_host, sites_per_cell,
+                         0.0, stream, out, "vd_build_grid_batch");
 }
 
 void vd_grid_free(vd_grid G) {
@@ -187,19 +280,36 @@ void vd_grid_free(vd_grid G) {
   hipFree(G->geom); hipFree(G->bbox_part); hipFree(G->sx); hipFree(G->sy); hipFree(G->sz);
   hipFree(G->delta); hipFree(G->perm); hipFree(G->rank); hipFree(G->cellid); hipFree(G->fill);
   hipFree(G->cstart); hipFree(G->ccount); hipFree(G->scan_tmp);
+  hipFree(G->d_site_off); hipFree(G->d_cell_off); hipFree(G->d_dims); hipFree(G->diag); hipFree(G->d_user_box);
+  hipFree(G->d_views);
+  {
+    std::lock_guard<std::mutex> lk(g_shadow_mu);
+    g_grid_shadow.erase(G);
+  }
   delete G;
 }
 
 // ---------------------------------------------------------------------------
 // domain
 // ---------------------------------------------------------------------------
-vd_status vd_domain_create(const double *verts, int64_t nv, const int32_t *simplices, const int32_t *adjacency,
-                           int64_t m, int32_t simplex_dim, void *stream, vd_domain *out) {
-  if (!out) return fail(VD_ERR_INVALID_ARG, "vd_domain_create: out is NULL");
+}  // extern "C"
+
+namespace {
+
+vd_status domain_create_impl(const double *verts, const int32_t *simplices, const int32_t *adjacency, int nb,
+                             const int64_t *vert_off_host, const int64_t *simp_off_host, int32_t simplex_dim,
+                             void *stream, vd_domain *out, const char *who) {
+  if (!out) return fail(VD_ERR_INVALID_ARG, "%s: out is NULL", who);
+  if (nb < 1) return fail(VD_ERR_INVALID_ARG, "%s: no diagrams", who);
+  const int64_t nv = vert_off_host[nb], m = simp_off_host[nb];
   if (!verts || !simplices || !adjacency || nv < 1 || m < 1)
-    return fail(VD_ERR_INVALID_ARG, "vd_domain_create: NULL array or empty domain");
-  if (simplex_dim != 2 && simplex_dim != 3) return fail(VD_ERR_INVALID_ARG, "vd_domain_create: simplex_dim must be 2 or 3");
-  if (m > INT_MAX / 8 || nv > INT_MAX / 4) return fail(VD_ERR_INVALID_ARG, "vd_domain_create: domain too large");
+    return fail(VD_ERR_INVALID_ARG, "%s: NULL array or empty domain", who);
+  if (simplex_dim != 2 && simplex_dim != 3) return fail(VD_ERR_INVALID_ARG, "%s: simplex_dim must be 2 or 3", who);
+  if (m > INT_MAX / 8 || nv > INT_MAX / 4) return fail(VD_ERR_INVALID_ARG, "%s: domain too large", who);
+  if (vert_off_host[0] != 0 || simp_off_host[0] != 0) return fail(VD_ERR_INVALID_ARG, "%s: offsets must start at 0", who);
+  for (int b = 0; b < nb; b++)
+    if (vert_off_host[b + 1] <= vert_off_host[b] || simp_off_host[b + 1] <= simp_off_host[b])
+      return fail(VD_ERR_INVALID_ARG, "%s: diagram %d has an empty domain", who, b);
   hipStream_t st = as_stream(stream);
   vd_domain D = *out ? *out : new vd_domain_s();
   auto bail = [&](vd_status r) {
@@ -214,7 +324,15 @@ vd_status vd_domain_create(const double *verts, int64_t nv, const int32_t *simpl
     HIP_TRY(hipMalloc((void **)&D->simp, sizeof(int) * k * m));
     HIP_TRY(hipMalloc((void **)&D->adj, sizeof(int) * k * m));
   }
-  D->m = m; D->nv = nv; D->dim = simplex_dim;
+  D->m = m; D->nv = nv; D->dim = simplex_dim; D->nb = nb;
+  D->vert_off.assign(vert_off_host, vert_off_host + nb + 1);
+  D->simp_off.assign(simp_off_host, simp_off_host + nb + 1);
+  hipFree(D->d_simp_off); hipFree(D->d_vert_off); hipFree(D->d_loc_off); hipFree(D->d_lg); hipFree(D->d_views);
+  D->d_simp_off = D->d_vert_off = D->d_loc_off = nullptr; D->d_lg = nullptr; D->d_views = nullptr;
+  HIP_TRY(hipMalloc((void **)&D->d_simp_off, sizeof(long long) * (nb + 1)));
+  HIP_TRY(hipMalloc((void **)&D->d_vert_off, sizeof(long long) * (nb + 1)));
+  HIP_TRY(hipMemcpy(D->d_simp_off, D->simp_off.data(), sizeof(long long) * (nb + 1), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(D->d_vert_off, D->vert_off.data(), sizeof(long long) * (nb + 1), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpyAsync(D->verts, verts, sizeof(double) * 3 * nv, hipMemcpyDeviceToDevice, st));
   HIP_TRY(hipMemcpyAsync(D->simp, simplices, sizeof(int) * k * m, hipMemcpyDeviceToDevice, st));
   HIP_TRY(hipMemcpyAsync(D->adj, adjacency, sizeof(int) * k * m, hipMemcpyDeviceToDevice, st));
@@ -222,48 +340,62 @@ vd_status vd_domain_create(const double *verts, int64_t nv, const int32_t *simpl
   double *measure = nullptr, *bbox = nullptr;
   HIP_TRY(hipMalloc((void **)&flags, sizeof(int) * 2));
   HIP_TRY(hipMalloc((void **)&measure, sizeof(double) * m));
-  HIP_TRY(hipMalloc((void **)&bbox, sizeof(double) * 6));
+  HIP_TRY(hipMalloc((void **)&bbox, sizeof(double) * 6 * nb));
   vd_launch_fill_int(flags, 2, 0, st);
+  vd_launch_domain_offsets(D, flags, st);
   vd_launch_domain_validate(D, flags, measure, st);
   vd_launch_vert_bbox(D, bbox, st);
   int hflags[2] = {0, 0};
-  double hbox[6];
+  std::vector<double> hbox(6 * (size_t)nb);
   std::vector<double> hmeas((size_t)m);
   HIP_TRY(hipMemcpyAsync(hflags, flags, sizeof hflags, hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(hbox, bbox, sizeof hbox, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(hbox.data(), bbox, sizeof(double) * 6 * nb, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(hmeas.data(), measure, sizeof(double) * m, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   hipFree(flags); hipFree(measure); hipFree(bbox);
-  if (hflags[0]) return bail(fail(VD_ERR_INVALID_ARG, "vd_domain_create: vertex or adjacency index out of range"));
+  if (hflags[0]) return bail(fail(VD_ERR_INVALID_ARG, "%s: vertex or adjacency index out of range", who));
   if (hflags[1])
-    return bail(fail(VD_ERR_INVALID_ARG, simplex_dim == 3 ? "vd_domain_create: a tetrahedron has non-positive volume"
-                                                          : "vd_domain_create: a degenerate triangle"));
+    return bail(fail(VD_ERR_INVALID_ARG, simplex_dim == 3 ? "%s: a tetrahedron has non-positive volume"
+                                                          : "%s: a degenerate triangle", who));
   double tot = 0;
   for (double v : hmeas) tot += v;
   D->area = tot;
-  for (int a = 0; a < 6; a++) D->bbox[a] = hbox[a];
+  D->bbox = hbox;
+  hipFree(D->lgeom); hipFree(D->lstart); hipFree(D->lcount); hipFree(D->lfill); hipFree(D->scan_tmp); hipFree(D->litems);
+  D->lgeom = nullptr; D->lstart = D->lcount = D->lfill = D->scan_tmp = D->litems = nullptr;
+  D->lg.assign(3 * (size_t)nb, 1);
+  D->loc_off.assign(nb + 1, 0);
   if (simplex_dim == 3) {
-    // location grid: about 2 tetrahedra per cell over the vertex bounding box
-    double ext[3], vol = 1;
-    for (int a = 0; a < 3; a++) { ext[a] = std::max(hbox[3 + a] - hbox[a], 1e-300); vol *= ext[a]; }
-    const double h = std::cbrt(vol * 2.0 / (double)m);
-    for (int a = 0; a < 3; a++) D->lg[a] = std::max(1, std::min(1024, (int)std::ceil(ext[a] / h)));
-    double geom[9];
-    for (int a = 0; a < 3; a++) {
-      const double pad = 1e-9 * ext[a];
-      geom[a] = hbox[a] - pad;
-      geom[3 + a] = (ext[a] + 2 * pad) / D->lg[a];
-      geom[6 + a] = 1.0 / geom[3 + a];
+    // location grid of each diagram: about 2 tetrahedra per cell over its vertex box
+    std::vector<double> geom(9 * (size_t)nb);
+    for (int b = 0; b < nb; b++) {
+      const double *bx = &hbox[6 * b];
+      const int64_t mb = simp_off_host[b + 1] - simp_off_host[b];
+      double ext[3], vol = 1;
+      for (int a = 0; a < 3; a++) { ext[a] = std::max(bx[3 + a] - bx[a], 1e-300); vol *= ext[a]; }
+      const double h = std::cbrt(vol * 2.0 / (double)mb);
+      for (int a = 0; a < 3; a++) D->lg[3 * b + a] = std::max(1, std::min(1024, (int)std::ceil(ext[a] / h)));
+      for (int a = 0; a < 3; a++) {
+        const double pad = 1e-9 * ext[a];
+        geom[9 * b + a] = bx[a] - pad;
+        geom[9 * b + 3 + a] = (ext[a] + 2 * pad) / D->lg[3 * b + a];
+        geom[9 * b + 6 + a] = 1.0 / geom[9 * b + 3 + a];
+      }
+      D->loc_off[b + 1] = D->loc_off[b] + (int64_t)D->lg[3 * b] * D->lg[3 * b + 1] * D->lg[3 * b + 2];
     }
-    const int64_t ncell = (int64_t)D->lg[0] * D->lg[1] * D->lg[2];
-    hipFree(D->lgeom); hipFree(D->lstart); hipFree(D->lcount); hipFree(D->lfill); hipFree(D->scan_tmp); hipFree(D->litems);
-    D->lgeom = nullptr; D->lstart = D->lcount = D->lfill = D->scan_tmp = D->litems = nullptr;
-    HIP_TRY(hipMalloc((void **)&D->lgeom, sizeof(double) * 9));
+    const int64_t ncell = D->loc_off[nb];
+    if (ncell > (int64_t)INT_MAX / 2) return bail(fail(VD_ERR_INVALID_ARG, "%s: location grid too large", who));
+    D->ncell = ncell;
+    HIP_TRY(hipMalloc((void **)&D->lgeom, sizeof(double) * 9 * nb));
+    HIP_TRY(hipMalloc((void **)&D->d_lg, sizeof(int) * 3 * nb));
+    HIP_TRY(hipMalloc((void **)&D->d_loc_off, sizeof(long long) * (nb + 1)));
     HIP_TRY(hipMalloc((void **)&D->lstart, sizeof(int) * (ncell + 1)));
     HIP_TRY(hipMalloc((void **)&D->lcount, sizeof(int) * ncell));
     HIP_TRY(hipMalloc((void **)&D->lfill, sizeof(int) * ncell));
     HIP_TRY(hipMalloc((void **)&D->scan_tmp, sizeof(int) * (ncell / 1024 + 2)));
-    HIP_TRY(hipMemcpyAsync(D->lgeom, geom, sizeof geom, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpy(D->lgeom, geom.data(), sizeof(double) * 9 * nb, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(D->d_lg, D->lg.data(), sizeof(int) * 3 * nb, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(D->d_loc_off, D->loc_off.data(), sizeof(long long) * (nb + 1), hipMemcpyHostToDevice));
     vd_launch_domain_locator(D, st);
     int total = 0;
     HIP_TRY(hipMemcpyAsync(&total, D->lstart + ncell, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -271,16 +403,41 @@ vd_status vd_domain_create(const double *verts, int64_t nv, const int32_t *simpl
     D->nitems = total;
     HIP_TRY(hipMalloc((void **)&D->litems, sizeof(int) * std::max(total, 1)));
     vd_launch_domain_fill(D, st);
-    HIP_TRY(hipStreamSynchronize(st));
   }
+  {
+    std::vector<DomainView> v(nb);
+    for (int b = 0; b < nb; b++) v[b] = D->view_of(b);
+    HIP_TRY(hipMalloc((void **)&D->d_views, sizeof(DomainView) * nb));
+    HIP_TRY(hipMemcpy(D->d_views, v.data(), sizeof(DomainView) * nb, hipMemcpyHostToDevice));
+  }
+  HIP_TRY(hipStreamSynchronize(st));
   *out = D;
   return VD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vd_status vd_domain_create(const double *verts, int64_t nv, const int32_t *simplices, const int32_t *adjacency,
+                           int64_t m, int32_t simplex_dim, void *stream, vd_domain *out) {
+  const int64_t voff[2] = {0, nv}, soff[2] = {0, m};
+  return domain_create_impl(verts, simplices, adjacency, 1, voff, soff, simplex_dim, stream, out, "vd_domain_create");
+}
+
+vd_status vd_domain_create_batch(const double *verts, const int32_t *simplices, const int32_t *adjacency,
+                                 const vd_batch *batch, int32_t simplex_dim, void *stream, vd_domain *out) {
+  if (!batch || batch->num < 1 || !batch->vert_off || !batch->simp_off)
+    return fail(VD_ERR_INVALID_ARG, "vd_domain_create_batch: missing batch or offsets");
+  return domain_create_impl(verts, simplices, adjacency, batch->num, batch->vert_off, batch->simp_off, simplex_dim,
+                            stream, out, "vd_domain_create_batch");
 }
 
 void vd_domain_free(vd_domain D) {
   if (!D) return;
   hipFree(D->verts); hipFree(D->simp); hipFree(D->adj); hipFree(D->lgeom); hipFree(D->lstart);
   hipFree(D->litems); hipFree(D->lcount); hipFree(D->lfill); hipFree(D->scan_tmp);
+  hipFree(D->d_simp_off); hipFree(D->d_vert_off); hipFree(D->d_loc_off); hipFree(D->d_lg); hipFree(D->d_views);
   delete D;
 }
 
@@ -314,6 +471,12 @@ hipError_t alloc_cells(vd_cells c, int64_t n, const Caps &want) {
   }
   if ((e = ensure_fixed(d.cnt, CNT_N)) != hipSuccess) return e;
   if ((e = ensure_fixed(d.queue, VD_QUEUES * VD_QSTRIDE)) != hipSuccess) return e;
+  if (!c->host_cnt) {
+    if ((e = hipHostMalloc((void **)&c->host_cnt, sizeof(unsigned long long) * CNT_N, hipHostMallocDefault)) !=
+        hipSuccess)
+      return e;
+    std::memset(c->host_cnt, 0, sizeof(unsigned long long) * CNT_N);
+  }
   int64_t cp = d.cap_piece;
   if (cp < want.piece) {
     int64_t t;
@@ -362,10 +525,48 @@ hipError_t alloc_cells(vd_cells c, int64_t n, const Caps &want) {
   return hipSuccess;
 }
 
+// Status of a finished clip from its counters (arena overflow included when
+// `overflow_is_error`: a no-sync clip cannot grow its arenas).
+vd_status check_counts(vd_cells c, bool overflow_is_error) {
+  const unsigned long long *hc = c->host_cnt;
+  const CellsDev &d = c->d;
+  int bad = (int)(hc[CNT_BAD_SITE] & 0xffffffffull);
+  c->first_bad = bad == 0x7fffffff ? -1 : bad;
+  if (hc[CNT_ERR_LOC])
+    return (vd_status)(c->status = fail(VD_ERR_INVALID_ARG, "vd_clip_cells: %llu site(s) outside every tetrahedron (first: %d)",
+                            (unsigned long long)hc[CNT_ERR_LOC], c->first_bad));
+  if (hc[CNT_ERR_CAP])
+    return (vd_status)(c->status = fail(VD_ERR_CAPACITY,
+                            "vd_clip_cells: %llu site(s) exceeded a per-wave capacity (first: %d, stages 0x%llx)",
+                            (unsigned long long)hc[CNT_ERR_CAP], c->first_bad, (unsigned long long)hc[CNT_STAGES]));
+  if (hc[CNT_ERR_DEG])
+    return (vd_status)(c->status = fail(VD_ERR_DEGENERATE,
+                            "vd_clip_cells: %llu site(s) hit a non-converging search (first: %d, stages 0x%llx)",
+                            (unsigned long long)hc[CNT_ERR_DEG], c->first_bad, (unsigned long long)hc[CNT_STAGES]));
+  if (overflow_is_error &&
+      ((int64_t)hc[CNT_PIECES] > d.cap_piece || (int64_t)hc[CNT_NBRS] > d.cap_nbr ||
+       (d.face_label && (int64_t)hc[CNT_FACES] > d.cap_face) || (d.vert_xyz && (int64_t)hc[CNT_VERTS] > d.cap_vert) ||
+       (d.fint && (int64_t)hc[CNT_FINT] > d.cap_fint)))
+    return (vd_status)(c->status = fail(VD_ERR_CAPACITY, "vd_clip_cells: an output arena overflowed in a no-sync clip "
+                                             "(run a synchronous clip on this handle to grow it)"));
+  c->status = VD_OK;
+  return VD_OK;
+}
+
 }  // namespace
 
 vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void *stream, vd_cells *out) {
   if (!out || !g || !dom) return fail(VD_ERR_INVALID_ARG, "vd_clip_cells: NULL handle");
+  if (g->nb != dom->nb)
+    return fail(VD_ERR_INVALID_ARG, "vd_clip_cells: the grid holds %d diagram(s), the domain %d", g->nb, dom->nb);
+  if (opt_in && opt_in->no_sync) {
+    vd_cells c0 = *out;
+    if (dom->dim != 3) return fail(VD_ERR_INVALID_ARG, "vd_clip_cells: no_sync needs a tetrahedral domain");
+    if (!c0 || c0->n != g->n || c0->cap_n < g->n || c0->d.cap_piece <= 0 ||
+        (opt_in->emit_polytopes && !c0->d.face_label) || (opt_in->want_grad && !c0->d.fint))
+      return fail(VD_ERR_INVALID_ARG, "vd_clip_cells: no_sync needs a handle sized by a synchronous clip of the "
+                                      "same sites and options");
+  }
   vd_options opt;
   vd_options_default(&opt);
   if (opt_in) opt = *opt_in;
@@ -374,6 +575,7 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
   vd_cells c = *out ? *out : new vd_cells_s();
   const int64_t n = g->n;
   c->n = n;
+  c->pending = false;
   c->dim = dom->dim;
   c->opt = opt;
   c->grid = g;
@@ -389,6 +591,13 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
   want.face = keep_faces ? std::max<int64_t>(c->d.cap_face, 10 * want.piece) : 0;
   want.vert = keep_faces ? std::max<int64_t>(c->d.cap_vert, 16 * want.piece) : 0;
   want.fint = opt.want_grad ? std::max<int64_t>(c->d.cap_fint, 4 * want.piece) : 0;
+  if (opt.no_sync) {
+    // no allocation: the arenas keep the sizes of the synchronous clip before
+    want.piece = c->d.cap_piece; want.nbr = c->d.cap_nbr;
+    want.face = keep_faces ? c->d.cap_face : 0;
+    want.vert = keep_faces ? c->d.cap_vert : 0;
+    want.fint = opt.want_grad ? c->d.cap_fint : 0;
+  }
   for (int attempt = 0; attempt < 4; attempt++) {
     hipError_t e = alloc_cells(c, n, want);
     if (e != hipSuccess)
@@ -403,19 +612,16 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
     d.max_iters = opt.max_search_iters;
     d.mode = (dom->dim == 3 && opt.carve_mode == 1) ? 1 : 0;
     d.cache = opt.site_cache ? 1 : 0;
-    for (int a = 0; a < 3; a++) {
-      // The box strictly contains the domain so no box plane meets a simplex.
-      // The six paddings differ so that no box edge lies on a plane of
-      // symmetry of the domain (e.g. the diagonal planes of cube grids split
-      // into tetrahedra), where a tetrahedron plane would contain the edge.
-      const double ext = std::max(dom->bbox[3 + a] - dom->bbox[a], 1e-12);
-      d.box_lo[a] = dom->bbox[a] - (1.01e-3 + 0.12e-3 * a) * ext - 1e-9;
-      d.box_hi[a] = dom->bbox[3 + a] + (1.07e-3 + 0.14e-3 * a) * ext + 1e-9;
-    }
     // persistent 3D kernel: each wave reserves output chunks of about 1/8 of an
     // arena's share per wave, so unused chunk tails stay within 1/8 of it
     const int64_t items = dom->dim == 3 ? n : dom->m;  // sites, or triangles
     const int wg = dom->dim == 3 ? vd_sites3d_workgroups(n) : vd_surface_workgroups(dom->m);
+    if (dom->dim == 3 && c->cap_spill < wg) {
+      if (opt.no_sync) return bail(fail(VD_ERR_INVALID_ARG, "vd_clip_cells: no_sync on an unsized handle"));
+      int64_t t = 0;
+      HIP_TRY(ensure(d.tq_spill, t, (int64_t)wg * VD_Q_SPILL));
+      c->cap_spill = wg;
+    }
     {
       const int64_t caps[AR_N] = {d.cap_piece, d.cap_face, d.cap_vert, d.cap_nbr, d.cap_fint};
       for (int r = 0; r < AR_N; r++)
@@ -442,6 +648,19 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
     else vd_launch_surface(G, D, c->d_dev, wg, st);
     if (opt.time_kernels) HIP_TRY(hipEventRecord(c->ev1, st));
     HIP_TRY(hipGetLastError());
+    if (opt.no_sync) {
+      // stream-ordered only: finalize from the device counters, copy them to
+      // pinned host memory, and check them in vd_cells_info
+      c->pending = true;
+      c->last_stream = st;
+      c->carve_ms = c->split_ms = -1.0;
+      vd_launch_finalize(c, st);
+      HIP_TRY(hipMemcpyAsync(c->host_cnt, d.cnt, sizeof(unsigned long long) * CNT_N, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipGetLastError());
+      c->status = VD_OK;
+      *out = c;
+      return VD_OK;
+    }
     HIP_TRY(hipMemcpyAsync(c->host_cnt, d.cnt, sizeof(unsigned long long) * CNT_N, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     c->carve_ms = c->split_ms = -1.0;
@@ -461,27 +680,12 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
     if (keep_faces && (int64_t)hc[CNT_VERTS] > d.cap_vert) { need.vert = up(hc[CNT_VERTS]); grow = true; }
     if (opt.want_grad && (int64_t)hc[CNT_FINT] > d.cap_fint) { need.fint = up(hc[CNT_FINT]); grow = true; }
     if (grow) { want = need; continue; }
-    int bad = (int)(hc[CNT_BAD_SITE] & 0xffffffffull);
-    c->first_bad = bad == 0x7fffffff ? -1 : bad;
-    if (hc[CNT_ERR_LOC]) {
-      c->status = VD_ERR_INVALID_ARG;
-      *out = c;
-      return fail(VD_ERR_INVALID_ARG, "vd_clip_cells: %llu site(s) outside every tetrahedron (first: %d)",
-                  (unsigned long long)hc[CNT_ERR_LOC], c->first_bad);
-    }
-    if (hc[CNT_ERR_CAP]) {
-      c->status = VD_ERR_CAPACITY;
-      *out = c;
-      return fail(VD_ERR_CAPACITY,
-                  "vd_clip_cells: %llu site(s) exceeded a per-wave capacity (first: %d, stages 0x%llx)",
-                  (unsigned long long)hc[CNT_ERR_CAP], c->first_bad, (unsigned long long)hc[CNT_STAGES]);
-    }
-    if (hc[CNT_ERR_DEG]) {
-      c->status = VD_ERR_DEGENERATE;
-      *out = c;
-      return fail(VD_ERR_DEGENERATE,
-                  "vd_clip_cells: %llu site(s) hit a non-converging search (first: %d, stages 0x%llx)",
-                  (unsigned long long)hc[CNT_ERR_DEG], c->first_bad, (unsigned long long)hc[CNT_STAGES]);
+    {
+      const vd_status r = check_counts(c, false);
+      if (r != VD_OK) {
+        *out = c;
+        return r;
+      }
     }
     if (dom->dim == 2) {
       // a site's neighbours are distinct flags of its pieces' edges: the
@@ -511,13 +715,20 @@ void vd_cells_free(vd_cells c) {
   if (c->ev0) hipEventDestroy(c->ev0);
   if (c->ev1) hipEventDestroy(c->ev1);
   if (c->ev2) hipEventDestroy(c->ev2);
-  hipFree(c->d_dev); hipFree(d.queue);
+  hipFree(c->d_dev); hipFree(d.queue); hipFree(d.tq_spill);
+  if (c->host_cnt) hipHostFree(c->host_cnt);
   hipFree(d.fint_lab); hipFree(d.piece_fint_start); hipFree(d.piece_nfint); hipFree(c->wbuf);
   delete c;
 }
 
 vd_status vd_cells_info(vd_cells c, vd_cells_info_t *info) {
   if (!c || !info) return fail(VD_ERR_INVALID_ARG, "vd_cells_info: NULL");
+  if (c->pending) {
+    // a no-sync clip (possibly replayed from a graph on another stream, which
+    // the caller synchronises): its counters reach host_cnt in stream order
+    HIP_TRY(hipStreamSynchronize(c->last_stream));
+    check_counts(c, true);
+  }
   const unsigned long long *hc = c->host_cnt;
   info->n_sites = c->n;
   info->n_pieces = (int64_t)hc[CNT_REAL_PIECES];

@@ -6,6 +6,8 @@
 // of the per-site counts and a gather (one thread per site).  Moments convert
 // the per-site mass / first moment / energy sums (accumulated in a fixed order
 // inside each wave) into mass, centroid and energy.
+#include <algorithm>
+
 #include "vd_internal.h"
 #include "vd_scan.h"
 
@@ -26,11 +28,15 @@ __global__ void __launch_bounds__(kB) gather_lists(long long n, const int *__res
   for (int k = 0; k < c; k++) out[o + k] = arena[s + k];
 }
 
-__global__ void __launch_bounds__(kB) scatter_pieces(long long np, const int *__restrict__ site,
+// piece slots in use: the arena's high-water mark (read on the device, so the
+// launch needs no host copy of it), at most its capacity
+__global__ void __launch_bounds__(kB) scatter_pieces(const unsigned long long *__restrict__ cnt, long long cap,
+                                                     const int *__restrict__ site,
                                                      const long long *__restrict__ off, int *__restrict__ fill,
                                                      int *__restrict__ out) {
   const long long p = (long long)blockIdx.x * kB + threadIdx.x;
-  if (p >= np) return;
+  const long long used = (long long)cnt[CNT_PIECES];
+  if (p >= (used < cap ? used : cap)) return;
   const int s = site[p];
   if (s < 0) return;  // unused slot of a wave's chunk
   out[off[s] + atomicAdd(&fill[s], 1)] = (int)p;
@@ -85,11 +91,13 @@ void vd_launch_fill_int(int *p, long long n, int v, hipStream_t st);
 void vd_launch_finalize(vd_cells c, hipStream_t st) {
   const long long n = c->n;
   const CellsDev &d = c->d;
-  const long long npieces = (long long)c->host_cnt[CNT_PIECES];
+  // slots to scan: the high-water mark when the host has read it, else the capacity
+  const long long npieces = c->pending ? d.cap_piece : std::min<long long>((long long)c->host_cnt[CNT_PIECES], d.cap_piece);
   // pieces: counting sort by site, then by simplex inside each site
   vdscan::exclusive_scan<int, long long>(d.pcount, n, c->piece_off, c->scan_tmp, st);
   vd_launch_fill_int(c->fillc, n, 0, st);
-  hipLaunchKernelGGL(scatter_pieces, dim3(blocks(npieces)), dim3(kB), 0, st, npieces, (const int *)d.piece_site,
+  hipLaunchKernelGGL(scatter_pieces, dim3(blocks(npieces)), dim3(kB), 0, st, (const unsigned long long *)d.cnt,
+                     (long long)d.cap_piece, (const int *)d.piece_site,
                      (const long long *)c->piece_off, c->fillc, c->piece_id);
   hipLaunchKernelGGL(sort_segments, dim3(blocks(n)), dim3(kB), 0, st, n, (const long long *)c->piece_off,
                      (const int *)d.piece_simplex, c->piece_id);

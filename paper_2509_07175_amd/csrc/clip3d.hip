@@ -397,7 +397,6 @@ __device__ int carve(WaveLds &S, const GridView &G, const CarveParams C, const S
         if (C.improved && L > 0 && 2.0 * X.delta < L) {
           u0 = d0 / L; u1 = d1 / L; u2 = d2 / L;
           lam = 2;
-          q0 = A0 + 2.0 * X.delta * u0; q1 = A1 + 2.0 * X.delta * u1; q2 = A2 + 2.0 * X.delta * u2;
           mode = LAMBDA;
         } else {
           bisector_point();
@@ -406,7 +405,16 @@ __device__ int carve(WaveLds &S, const GridView &G, const CarveParams C, const S
       }
     }
     // ---- the one nearest-site query of this iteration ----
-    const int gs = mode == TEST ? 16 : 64;
+    // LAMBDA: the four 16-lane groups test lambda .. lambda+3 at once; the
+    // smallest one found outside is the step the sequential search would stop at
+    bool lv = true;
+    if (mode == LAMBDA) {
+      const int lg = lam + grp;
+      lv = lg < 2 + C.max_iters && lg * X.delta < L;
+      const double tt = (lv ? lg : lam) * X.delta;
+      q0 = A0 + tt * u0; q1 = A1 + tt * u1; q2 = A2 + tt * u2;
+    }
+    const int gs = (mode == TEST || mode == LAMBDA) ? 16 : 64;
     const double qx = X.vx + q0, qy = X.vy + q1, qz = X.vz + q2;
     const double dx = qx - X.vx, dy = qy - X.vy, dz = qz - X.vz;
     // sites the test treats like v_i: flags of the corner's planes (TEST), the
@@ -431,24 +439,26 @@ __device__ int carve(WaveLds &S, const GridView &G, const CarveParams C, const S
       mode = PICK;
       continue;
     }
-    st.queries++;
-    st.grid += on_grid ? 1 : 0;
-    const int k = uni(kq);
     if (mode == LAMBDA) {
-      if (k != X.si && k != ef0 && k != ef1) {
-        j = k; g0 = q0; g1 = q1; g2 = q2;
+      const bool lead = (l & 15) == 0;
+      st.queries += __popcll(__ballot(lv && lead));
+      st.grid += __popcll(__ballot(lv && lead && on_grid));
+      const uint64_t hit = __ballot(lv && lead && kq != X.si && kq != ef0 && kq != ef1);
+      if (hit) {
+        const int src = __ffsll((unsigned long long)hit) - 1;  // lowest group found outside
+        j = __builtin_amdgcn_readlane(kq, src);
+        g0 = readlane_d(q0, src); g1 = readlane_d(q1, src); g2 = readlane_d(q2, src);
       } else {
-        lam++;
-        if (lam < 2 + C.max_iters && lam * X.delta < L) {
-          const double tt = lam * X.delta;
-          q0 = A0 + tt * u0; q1 = A1 + tt * u1; q2 = A2 + tt * u2;
-          continue;
-        }
+        lam += 4;
+        if (lam < 2 + C.max_iters && lam * X.delta < L) continue;
       }
       bisector_point();
       mode = SEARCH;
       continue;
     }
+    st.queries++;
+    st.grid += on_grid ? 1 : 0;
+    const int k = uni(kq);
     // SEARCH: q lies on the boundary of Omega_i -> B_ij is a face of the cell
     if (!(k == X.si || k == j || k == ef0 || k == ef1)) {
       if (++nstep >= C.max_iters) return 3;
@@ -672,6 +682,22 @@ __device__ void face_moments(WaveLds &S, int nc, int npl, uint64_t fmask, const 
   }
 }
 
+// Entries VD_Q_MAX.. of a site's simplex queue live in this wave's part of a
+// global buffer (cells that meet more simplices than the LDS queue holds).
+// Out of line: the common case never touches them.
+__device__ __forceinline__ int spill_get(const CellsDev &C, int i) {
+  return C.tq_spill[(long long)blockIdx.x * VD_Q_SPILL + i - VD_Q_MAX];
+}
+__device__ __forceinline__ bool spill_has(const CellsDev &C, int b, int nt) {
+  const int*q = C.tq_spill + (long long)blockIdx.x * VD_Q_SPILL - VD_Q_MAX;
+  bool have = false;
+  for (int e = VD_Q_MAX + vd_lane(); e < nt; e += 64) have = have || (q[e] == b);
+  return have;
+}
+__device__ __forceinline__ void spill_put(const CellsDev &C, int i, int b) {
+  if (vd_lane() == 0) C.tq_spill[(long long)blockIdx.x * VD_Q_SPILL + i - VD_Q_MAX] = b;
+}
+
 // ---------------------------------------------------------------------------
 // One site: its pieces, per-site sums and neighbour list.  The tetrahedra of
 // the cell are visited breadth-first through negative face flags from the
@@ -714,12 +740,13 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
     int a = -1, npl = 4, nc = 4;
     bool empty = false, need_carve = true;
     if (cell_job) {
-      init_box(S, X, C.box_lo, C.box_hi);
+      init_box(S, X, D.box_lo, D.box_hi);
       npl = 6;
       nc = 8;
     } else {
       if (head >= nt || err) break;
-      a = S.tq[head++];
+      a = head < VD_Q_MAX ? S.tq[head] : spill_get(C, head);
+      head++;
       if (saved) {
         restore_cell(S, npl0, nc0, D, X, a);
         npl = npl0 + 4;
@@ -853,11 +880,17 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
       } else if (lab > VD_BND_BASE + 3) {
         const int b = -lab - 1;
         bool have = false;
-        for (int e = l; e < nt; e += 64) have = have || (S.tq[e] == b);
+        const int nl = nt < VD_Q_MAX ? nt : VD_Q_MAX;
+        for (int e = l; e < nl; e += 64) have = have || (S.tq[e] == b);
+        if (nt > VD_Q_MAX) have = have || spill_has(C, b, nt);
         if (!__ballot(have)) {
-          if (nt >= VD_Q_MAX) { err = 2; where = VD_STAGE_SIMPLICES; break; }
+          if (nt >= VD_Q_MAX + VD_Q_SPILL) { err = 2; where = VD_STAGE_SIMPLICES; break; }
           __syncthreads();
-          if (l == 0) S.tq[nt] = b;
+          if (nt < VD_Q_MAX) {
+            if (l == 0) S.tq[nt] = b;
+          } else {
+            spill_put(C, nt, b);  // large cells: the queue continues in global memory
+          }
           nt++;
           __syncthreads();
         }
@@ -909,7 +942,10 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2)))
   for (;;) {
     const int si = queue_next(S.ar, C, G.n);
     if (si < 0) break;
-    do_site(S, G, D, C, si);
+    // the site's own diagram (a batch) or the only one; one call site keeps
+    // the per-site code inlined once
+    const int b = G.nb > 1 ? diagram_of(G.site_off, G.nb, si) : 0;
+    do_site(S, G.views[b], D.views[b], C, si);
   }
   arena_close(S.ar, C);
 }

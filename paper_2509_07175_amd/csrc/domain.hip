@@ -6,6 +6,10 @@
 // tetrahedron (the one containing it) is then found by barycentric tests over
 // one cell's list; the lowest containing index wins, so the result does not
 // depend on atomic ordering.
+//
+// A batch of domains is staged as one disjoint union: local vertex and simplex
+// indices are shifted by the diagram's offsets, and each diagram gets its own
+// bounding box and location grid (a block of the shared cell offsets).
 #include "vd_internal.h"
 #include "vd_scan.h"
 
@@ -18,6 +22,23 @@ inline unsigned blocks(long long n) { return (unsigned)((n + kB - 1) / kB > 0 ? 
 __global__ void __launch_bounds__(kB) fill_int(int *__restrict__ p, long long n, int v) {
   const long long i = (long long)blockIdx.x * kB + threadIdx.x;
   if (i < n) p[i] = v;
+}
+
+// Shift diagram-local indices to global ones and check their range:
+// vertex indices in [0, nv_b), adjacency in [-1, m_b).  flags[0] set on error.
+__global__ void __launch_bounds__(kB) offset_indices(int *__restrict__ simp, int *__restrict__ adj, long long m,
+                                                     int k, int nb, const long long *__restrict__ simp_off,
+                                                     const long long *__restrict__ vert_off, int *__restrict__ flags) {
+  const long long a = (long long)blockIdx.x * kB + threadIdx.x;
+  if (a >= m) return;
+  const int b = diagram_of(simp_off, nb, a);
+  const long long vo = vert_off[b], nvb = vert_off[b + 1] - vo, so = simp_off[b], mb = simp_off[b + 1] - so;
+  for (int u = 0; u < k; u++) {
+    const int v = simp[a * k + u], w = adj[a * k + u];
+    if (v < 0 || v >= nvb || w < -1 || w >= mb) { atomicOr(&flags[0], 1); return; }
+    simp[a * k + u] = (int)(v + vo);
+    adj[a * k + u] = w < 0 ? -1 : (int)(w + so);
+  }
 }
 
 // flags[0]: bad index; flags[1]: non-positive tet volume / degenerate triangle.
@@ -50,11 +71,13 @@ __global__ void __launch_bounds__(kB) validate(DomainView D, int *__restrict__ f
   measure[a] = mval;
 }
 
-__global__ void __launch_bounds__(kB) vert_bbox(const double *__restrict__ v, long long nv,
-                                                double *__restrict__ out) {
-  if (blockIdx.x != 0) return;
+// vertex bounding box of each diagram (one block per diagram)
+__global__ void __launch_bounds__(kB) vert_bbox(const double *__restrict__ v, const long long *__restrict__ vert_off,
+                                                double *__restrict__ out_all) {
+  const int b = blockIdx.x;
+  double *out = out_all + 6 * b;
   double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-  for (long long i = threadIdx.x; i < nv; i += kB)
+  for (long long i = vert_off[b] + threadIdx.x; i < vert_off[b + 1]; i += kB)
     for (int k = 0; k < 3; k++) { lo[k] = fmin(lo[k], v[3 * i + k]); hi[k] = fmax(hi[k], v[3 * i + k]); }
   __shared__ double red[6][kB];
   for (int k = 0; k < 3; k++) { red[k][threadIdx.x] = lo[k]; red[3 + k][threadIdx.x] = hi[k]; }
@@ -70,38 +93,56 @@ __global__ void __launch_bounds__(kB) vert_bbox(const double *__restrict__ v, lo
   if (threadIdx.x < 6) out[threadIdx.x] = red[threadIdx.x][0];
 }
 
-__device__ __forceinline__ void tet_cell_range(const DomainView &D, long long a, int *c0, int *c1) {
+// location cells of diagram b overlapped by the bounding box of tetrahedron a
+__device__ __forceinline__ void tet_cell_range(const double *__restrict__ verts, const int *__restrict__ simp,
+                                               long long a, const double *lgeom, const int *lg, int *c0, int *c1) {
   double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
   for (int u = 0; u < 4; u++) {
-    const double *p = &D.verts[3 * (long long)D.simp[a * 4 + u]];
+    const double *p = &verts[3 * (long long)simp[a * 4 + u]];
     for (int k = 0; k < 3; k++) { lo[k] = fmin(lo[k], p[k]); hi[k] = fmax(hi[k], p[k]); }
   }
   for (int k = 0; k < 3; k++) {
-    c0[k] = cell_coord(lo[k], D.lgeom[k], D.lgeom[6 + k], D.lg[k]);
-    c1[k] = cell_coord(hi[k], D.lgeom[k], D.lgeom[6 + k], D.lg[k]);
+    c0[k] = cell_coord(lo[k], lgeom[k], lgeom[6 + k], lg[k]);
+    c1[k] = cell_coord(hi[k], lgeom[k], lgeom[6 + k], lg[k]);
   }
 }
 
-__global__ void __launch_bounds__(kB) loc_count(DomainView D, int *__restrict__ count) {
+struct LocArgs {
+  const double *verts;
+  const int *simp;
+  long long m;
+  int nb;
+  const long long *simp_off, *loc_off;
+  const double *lgeom;  // [9 nb]
+  const int *lg;        // [3 nb]
+};
+
+__global__ void __launch_bounds__(kB) loc_count(LocArgs L, int *__restrict__ count) {
   const long long a = (long long)blockIdx.x * kB + threadIdx.x;
-  if (a >= D.m) return;
+  if (a >= L.m) return;
+  const int b = diagram_of(L.simp_off, L.nb, a);
+  const int *lg = L.lg + 3 * b;
   int c0[3], c1[3];
-  tet_cell_range(D, a, c0, c1);
+  tet_cell_range(L.verts, L.simp, a, L.lgeom + 9 * b, lg, c0, c1);
+  int *cnt = count + L.loc_off[b];
   for (int z = c0[2]; z <= c1[2]; z++)
     for (int y = c0[1]; y <= c1[1]; y++)
-      for (int x = c0[0]; x <= c1[0]; x++) atomicAdd(&count[x + D.lg[0] * (y + D.lg[1] * z)], 1);
+      for (int x = c0[0]; x <= c1[0]; x++) atomicAdd(&cnt[x + lg[0] * (y + lg[1] * z)], 1);
 }
 
-__global__ void __launch_bounds__(kB) loc_fill(DomainView D, const int *__restrict__ start,
-                                               int *__restrict__ fill, int *__restrict__ items) {
+__global__ void __launch_bounds__(kB) loc_fill(LocArgs L, const int *__restrict__ start, int *__restrict__ fill,
+                                               int *__restrict__ items) {
   const long long a = (long long)blockIdx.x * kB + threadIdx.x;
-  if (a >= D.m) return;
+  if (a >= L.m) return;
+  const int b = diagram_of(L.simp_off, L.nb, a);
+  const int *lg = L.lg + 3 * b;
   int c0[3], c1[3];
-  tet_cell_range(D, a, c0, c1);
+  tet_cell_range(L.verts, L.simp, a, L.lgeom + 9 * b, lg, c0, c1);
+  const long long base = L.loc_off[b];
   for (int z = c0[2]; z <= c1[2]; z++)
     for (int y = c0[1]; y <= c1[1]; y++)
       for (int x = c0[0]; x <= c1[0]; x++) {
-        const int c = x + D.lg[0] * (y + D.lg[1] * z);
+        const long long c = base + x + lg[0] * (y + lg[1] * z);
         items[start[c] + atomicAdd(&fill[c], 1)] = (int)a;
       }
 }
@@ -109,10 +150,11 @@ __global__ void __launch_bounds__(kB) loc_fill(DomainView D, const int *__restri
 // Seed tetrahedron of each site (by sorted position): lowest index among the
 // tetrahedra of its location cell whose barycentric coordinates are all
 // >= -1e-12 (relative).
-__global__ void __launch_bounds__(kB) locate_sites(GridView G, DomainView D, int *__restrict__ seed,
+__global__ void __launch_bounds__(kB) locate_sites(GridView G, DomainView Dall, int *__restrict__ seed,
                                                    unsigned long long *__restrict__ cnt) {
   const long long p = (long long)blockIdx.x * kB + threadIdx.x;
   if (p >= G.n) return;
+  const DomainView D = domain_of(Dall, G.nb > 1 ? diagram_of(G.site_off, G.nb, p) : 0);
   const double q[3] = {G.sx[p], G.sy[p], G.sz[p]};
   int cc[3];
   for (int k = 0; k < 3; k++) cc[k] = cell_coord(q[k], D.lgeom[k], D.lgeom[6 + k], D.lg[k]);
@@ -154,19 +196,31 @@ __global__ void __launch_bounds__(kB) locate_sites(GridView G, DomainView D, int
 
 }  // namespace
 
+namespace {
+LocArgs loc_args(vd_domain d) {
+  LocArgs L;
+  L.verts = d->verts; L.simp = d->simp; L.m = d->m; L.nb = d->nb;
+  L.simp_off = d->d_simp_off; L.loc_off = d->d_loc_off; L.lgeom = d->lgeom; L.lg = d->d_lg;
+  return L;
+}
+}  // namespace
+
 void vd_launch_domain_locator(vd_domain d, hipStream_t st) {
-  DomainView D = d->view();
-  const long long ncell = (long long)d->lg[0] * d->lg[1] * d->lg[2];
+  const long long ncell = d->ncell;
   hipLaunchKernelGGL(fill_int, dim3(blocks(ncell)), dim3(kB), 0, st, d->lcount, ncell, 0);
   hipLaunchKernelGGL(fill_int, dim3(blocks(ncell)), dim3(kB), 0, st, d->lfill, ncell, 0);
-  hipLaunchKernelGGL(loc_count, dim3(blocks(d->m)), dim3(kB), 0, st, D, d->lcount);
+  hipLaunchKernelGGL(loc_count, dim3(blocks(d->m)), dim3(kB), 0, st, loc_args(d), d->lcount);
   vdscan::exclusive_scan<int, int>(d->lcount, ncell, d->lstart, d->scan_tmp, st);
 }
 
 void vd_launch_domain_fill(vd_domain d, hipStream_t st) {
-  DomainView D = d->view();
-  hipLaunchKernelGGL(loc_fill, dim3(blocks(d->m)), dim3(kB), 0, st, D, (const int *)d->lstart, d->lfill,
+  hipLaunchKernelGGL(loc_fill, dim3(blocks(d->m)), dim3(kB), 0, st, loc_args(d), (const int *)d->lstart, d->lfill,
                      d->litems);
+}
+
+void vd_launch_domain_offsets(vd_domain d, int *flags, hipStream_t st) {
+  hipLaunchKernelGGL(offset_indices, dim3(blocks(d->m)), dim3(kB), 0, st, d->simp, d->adj, (long long)d->m,
+                     d->dim + 1, d->nb, (const long long *)d->d_simp_off, (const long long *)d->d_vert_off, flags);
 }
 
 void vd_launch_domain_validate(vd_domain d, int *flags, double *measure, hipStream_t st) {
@@ -174,7 +228,8 @@ void vd_launch_domain_validate(vd_domain d, int *flags, double *measure, hipStre
 }
 
 void vd_launch_vert_bbox(vd_domain d, double *out, hipStream_t st) {
-  hipLaunchKernelGGL(vert_bbox, dim3(1), dim3(kB), 0, st, (const double *)d->verts, (long long)d->nv, out);
+  hipLaunchKernelGGL(vert_bbox, dim3(d->nb), dim3(kB), 0, st, (const double *)d->verts,
+                     (const long long *)d->d_vert_off, out);
 }
 
 void vd_launch_locate_sites(const GridView &G, const DomainView &D, int *seed, unsigned long long *cnt,

@@ -4,6 +4,10 @@
 // histogram, exclusive scan, scatter into cell order, and an in-cell sort by
 // the caller's index so the layout is deterministic.  A sixth launch computes
 // delta_i = half the distance to the nearest other site (Sec. 6.1).
+//
+// A batch of diagrams is sorted in one pass: diagram b has its own bounding
+// box and cell block [cell_off[b], cell_off[b+1]) of the shared offsets, so
+// its sites land on the sorted positions [site_off[b], site_off[b+1]).
 #include "vd_internal.h"
 #include "vd_scan.h"
 
@@ -35,47 +39,84 @@ __global__ void __launch_bounds__(kB) bbox_partial(const double *__restrict__ s,
   if (threadIdx.x < 6) part[6 * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
 }
 
-struct Box6 { double v[6]; };
+// bounding box of each diagram's sites: one block per diagram
+__global__ void __launch_bounds__(kB) bbox_seg(const double *__restrict__ s, const long long *__restrict__ off,
+                                               double *__restrict__ part) {
+  const int b = blockIdx.x;
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (long long i = off[b] + threadIdx.x; i < off[b + 1]; i += kB) {
+    for (int k = 0; k < 3; k++) {
+      const double x = s[3 * i + k];
+      lo[k] = fmin(lo[k], x);
+      hi[k] = fmax(hi[k], x);
+    }
+  }
+  __shared__ double red[6][kB];
+  for (int k = 0; k < 3; k++) { red[k][threadIdx.x] = lo[k]; red[3 + k][threadIdx.x] = hi[k]; }
+  __syncthreads();
+  for (int d = kB / 2; d > 0; d >>= 1) {
+    if (threadIdx.x < (unsigned)d)
+      for (int k = 0; k < 3; k++) {
+        red[k][threadIdx.x] = fmin(red[k][threadIdx.x], red[k][threadIdx.x + d]);
+        red[3 + k][threadIdx.x] = fmax(red[3 + k][threadIdx.x], red[3 + k][threadIdx.x + d]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) part[6 * b + threadIdx.x] = red[threadIdx.x][0];
+}
 
-__global__ void bbox_final(const double *__restrict__ part, int nb, Box6 user, int has_user, int gx,
-                           int gy, int gz, double *__restrict__ geom) {
-  if (threadIdx.x != 0) return;
+// Geometry of diagram b (thread b): the union of its sites' box (ppd partial
+// boxes) and the caller's box (user, nullable), padded so points on the upper
+// faces fall inside the last cells; h = extent / cells.
+__global__ void grid_geom(const double *__restrict__ part, int ppd, int nb, const double *__restrict__ user,
+                          const int *__restrict__ dims, double *__restrict__ geom) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
   double lo[3], hi[3];
   for (int k = 0; k < 3; k++) {
-    lo[k] = has_user ? user.v[k] : 1e300;
-    hi[k] = has_user ? user.v[3 + k] : -1e300;
+    lo[k] = user ? user[6 * b + k] : 1e300;
+    hi[k] = user ? user[6 * b + 3 + k] : -1e300;
   }
-  for (int b = 0; b < nb; b++)
+  for (int q = 0; q < ppd; q++)
     for (int k = 0; k < 3; k++) {
-      lo[k] = fmin(lo[k], part[6 * b + k]);
-      hi[k] = fmax(hi[k], part[6 * b + 3 + k]);
+      lo[k] = fmin(lo[k], part[6 * (b * ppd + q) + k]);
+      hi[k] = fmax(hi[k], part[6 * (b * ppd + q) + 3 + k]);
     }
-  const int g[3] = {gx, gy, gz};
   double ext = 0;
   for (int k = 0; k < 3; k++) ext = fmax(ext, hi[k] - lo[k]);
   if (!(ext > 0)) ext = 1.0;
   for (int k = 0; k < 3; k++) {
-    // pad so that points on the upper face fall inside the last cell
     double e = hi[k] - lo[k];
     if (!(e > 1e-12 * ext)) e = 1e-12 * ext;
     const double pad = 1e-9 * e;
     const double l = lo[k] - pad;
-    const double h = (e + 2 * pad) / g[k];
-    geom[k] = l;
-    geom[3 + k] = h;
-    geom[6 + k] = 1.0 / h;
+    const double h = (e + 2 * pad) / dims[3 * b + k];
+    geom[9 * b + k] = l;
+    geom[9 * b + 3 + k] = h;
+    geom[9 * b + 6 + k] = 1.0 / h;
   }
 }
 
+// diagram of every caller index
+__global__ void __launch_bounds__(kB) site_diag(long long n, const long long *__restrict__ off, int nb,
+                                                int *__restrict__ diag) {
+  const long long i = (long long)blockIdx.x * kB + threadIdx.x;
+  if (i < n) diag[i] = diagram_of(off, nb, i);
+}
+
 __global__ void __launch_bounds__(kB) grid_hist(const double *__restrict__ s, long long n,
-                                                const double *__restrict__ geom, int gx, int gy, int gz,
+                                                const int *__restrict__ diag, const double *__restrict__ geom_all,
+                                                const int *__restrict__ dims, const long long *__restrict__ cell_off,
                                                 int *__restrict__ cellid, int *__restrict__ count) {
   const long long i = (long long)blockIdx.x * kB + threadIdx.x;
   if (i >= n) return;
+  const int b = diag ? diag[i] : 0;
+  const double *geom = geom_all + 9 * b;
+  const int gx = dims[3 * b], gy = dims[3 * b + 1], gz = dims[3 * b + 2];
   const int cx = cell_coord(s[3 * i + 0], geom[0], geom[6], gx);
   const int cy = cell_coord(s[3 * i + 1], geom[1], geom[7], gy);
   const int cz = cell_coord(s[3 * i + 2], geom[2], geom[8], gz);
-  const int c = cx + gx * (cy + gy * cz);
+  const int c = (int)cell_off[b] + cx + gx * (cy + gy * cz);
   cellid[i] = c;
   atomicAdd(&count[c], 1);
 }
@@ -125,7 +166,8 @@ __global__ void __launch_bounds__(kB) grid_delta(GridView G, double *__restrict_
   const long long p = (long long)blockIdx.x * kB + threadIdx.x;
   if (p >= G.n) return;
   double d2;
-  const int k = nn_thread(G, G.sx[p], G.sy[p], G.sz[p], (int)p, d2);
+  const GridView Gb = grid_of(G, p);
+  const int k = nn_thread(Gb, G.sx[p], G.sy[p], G.sz[p], (int)p, d2);
   delta[p] = k >= 0 ? 0.5 * sqrt(d2) : 1e300;
 }
 
@@ -135,18 +177,25 @@ inline unsigned blocks(long long n) { return (unsigned)((n + kB - 1) / kB > 0 ? 
 
 void vd_launch_fill_int(int *p, long long n, int v, hipStream_t st);
 
-void vd_launch_grid_build(vd_grid g, const double *sites, const double *bbox_host, hipStream_t st) {
+void vd_launch_grid_build(vd_grid g, const double *sites, const double *user_box, hipStream_t st) {
   const long long n = g->n;
-  const int nb = 256;
-  hipLaunchKernelGGL(bbox_partial, dim3(nb), dim3(kB), 0, st, sites, n, g->bbox_part);
-  Box6 u;
-  for (int k = 0; k < 6; k++) u.v[k] = bbox_host ? bbox_host[k] : 0.0;
-  hipLaunchKernelGGL(bbox_final, dim3(1), dim3(64), 0, st, (const double *)g->bbox_part, nb, u,
-                     bbox_host ? 1 : 0, g->g[0], g->g[1], g->g[2], g->geom);
+  const int nb = g->nb;
+  int ppd;
+  if (nb == 1) {
+    ppd = 256;
+    hipLaunchKernelGGL(bbox_partial, dim3(ppd), dim3(kB), 0, st, sites, n, g->bbox_part);
+  } else {
+    ppd = 1;
+    hipLaunchKernelGGL(bbox_seg, dim3(nb), dim3(kB), 0, st, sites, (const long long *)g->d_site_off, g->bbox_part);
+    hipLaunchKernelGGL(site_diag, dim3(blocks(n)), dim3(kB), 0, st, n, (const long long *)g->d_site_off, nb, g->diag);
+  }
+  hipLaunchKernelGGL(grid_geom, dim3((nb + 63) / 64), dim3(64), 0, st, (const double *)g->bbox_part, ppd, nb,
+                     user_box, (const int *)g->d_dims, g->geom);
   vd_launch_fill_int(g->ccount, g->ncell, 0, st);
   vd_launch_fill_int(g->fill, g->ncell, 0, st);
-  hipLaunchKernelGGL(grid_hist, dim3(blocks(n)), dim3(kB), 0, st, sites, n, (const double *)g->geom,
-                     g->g[0], g->g[1], g->g[2], g->cellid, g->ccount);
+  hipLaunchKernelGGL(grid_hist, dim3(blocks(n)), dim3(kB), 0, st, sites, n, nb == 1 ? (const int *)nullptr : g->diag,
+                     (const double *)g->geom, (const int *)g->d_dims, (const long long *)g->d_cell_off, g->cellid,
+                     g->ccount);
   vdscan::exclusive_scan<int, int>(g->ccount, g->ncell, g->cstart, g->scan_tmp, st);
   hipLaunchKernelGGL(grid_scatter, dim3(blocks(n)), dim3(kB), 0, st, sites, n, (const int *)g->cellid,
                      (const int *)g->cstart, g->fill, g->sx, g->sy, g->sz, g->perm);

@@ -480,7 +480,9 @@ __global__ void __launch_bounds__(64) surface_kernel(GridView G, DomainView D, c
   for (;;) {
     const int a = queue_next(S.ar, C, D.m);
     if (a < 0) break;
-    do_triangle(S, G, D, C, a);
+    // the triangle's own diagram (a batch) or the only one
+    const int b = D.nb > 1 ? diagram_of(D.simp_off, D.nb, a) : 0;
+    do_triangle(S, G.views[b], D.views[b], C, a);
   }
   arena_close(S.ar, C);
 }

@@ -13,15 +13,37 @@
 // order; "sorted position" indexes sx/sy/sz/delta, perm maps it back to the
 // caller's index.  geom = {lo[3], h[3], ih[3]} lives in device memory because
 // the bounding box is reduced on the device.
+//
+// A batch of independent diagrams is one disjoint union: diagram b owns the
+// sorted positions [site_off[b], site_off[b+1]) and its own block of grid
+// cells; views[b] is its view (its cstart points into the shared offsets, so
+// positions stay global).  A plain grid is the batch of one, views = NULL.
 struct GridView {
-  int n;
+  int n;       // sites of this view (all sites for the batch view)
   int g[3];
   const double *geom;
   const double *sx, *sy, *sz;
   const int *cstart;  // [g0*g1*g2 + 1]
   const int *perm;    // sorted position -> caller index
   const double *delta;  // half nearest-other-site distance, by sorted position
+  int nb;                      // diagrams (1: plain)
+  const GridView *views;       // [nb] per-diagram views (nb > 1)
+  const long long *site_off;   // [nb + 1] sorted-position offsets (nb > 1)
 };
+
+// diagram of the uniform item x: largest b with off[b] <= x
+__device__ __forceinline__ int diagram_of(const long long *off, int nb, long long x) {
+  int lo = 0, hi = nb;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= x) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ GridView grid_of(const GridView &G, long long si) {
+  return G.nb > 1 ? G.views[diagram_of(G.site_off, G.nb, si)] : G;
+}
 
 __device__ __forceinline__ int vd_lane() {
   return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/vd.h"
 #include "vd_common.h"
 
@@ -11,7 +13,8 @@
 // ---------------------------------------------------------------------------
 #define VD_P_MAX 64    // planes of one intermediate polytope
 #define VD_C_MAX 128   // corners (two slots per lane)
-#define VD_Q_MAX 256   // tetrahedra visited for one site (4 per lane)
+#define VD_Q_MAX 256   // tetrahedra visited for one site in LDS (4 per lane) ...
+#define VD_Q_SPILL 3840  // ... and after them in a per-wave global buffer
 #define VD_NB_MAX 96   // distinct neighbours of one site
 #define VD_F_MAX 48    // planes of a saved cell (cell-first mode)
 #define VD_CB_MAX 96   // corners of a saved cell
@@ -36,47 +39,100 @@ enum {
 
 struct vd_grid_s {
   int64_t n = 0, cap_n = 0;
-  int g[3] = {1, 1, 1};
-  int64_t ncell = 0, cap_cell = 0;
-  double *geom = nullptr;     // lo[3], h[3], ih[3]
+  int g[3] = {1, 1, 1};       // dims of diagram 0 (the plain grid)
+  int64_t ncell = 0, cap_cell = 0;  // cells of all diagrams
+  double *geom = nullptr;     // [9 nb]: lo[3], h[3], ih[3] per diagram
   double *bbox_part = nullptr;  // per-block partial boxes
   double *sx = nullptr, *sy = nullptr, *sz = nullptr, *delta = nullptr;
   int *perm = nullptr, *rank = nullptr, *cellid = nullptr, *fill = nullptr;
   int *cstart = nullptr, *ccount = nullptr, *scan_tmp = nullptr;
-  GridView view() const {
+  // batch of nb diagrams (nb = 1: plain)
+  int nb = 1, cap_nb = 0;
+  std::vector<int64_t> site_off, cell_off;  // host [nb + 1]
+  std::vector<int> dims;                    // host [3 nb]
+  long long *d_site_off = nullptr, *d_cell_off = nullptr;  // device [nb + 1]
+  int *d_dims = nullptr, *diag = nullptr;   // [3 nb]; diagram of each caller index [n]
+  double *d_user_box = nullptr;             // [6 nb]
+  GridView *d_views = nullptr;              // [nb]
+  std::vector<GridView> h_views;            // host copy last uploaded
+  GridView view_of(int b) const {
     GridView v;
-    v.n = (int)n; v.g[0] = g[0]; v.g[1] = g[1]; v.g[2] = g[2];
-    v.geom = geom; v.sx = sx; v.sy = sy; v.sz = sz; v.cstart = cstart; v.perm = perm; v.delta = delta;
+    v.n = (int)(site_off[b + 1] - site_off[b]);
+    v.g[0] = dims[3 * b]; v.g[1] = dims[3 * b + 1]; v.g[2] = dims[3 * b + 2];
+    v.geom = geom + 9 * b; v.sx = sx; v.sy = sy; v.sz = sz; v.cstart = cstart + cell_off[b];
+    v.perm = perm; v.delta = delta;
+    v.nb = 1; v.views = nullptr; v.site_off = nullptr;
+    return v;
+  }
+  // the view the kernels get: all sites; views[b] for each diagram (also for
+  // a plain grid, whose views[0] is itself)
+  GridView view() const {
+    GridView v = view_of(0);
+    v.n = (int)n; v.nb = nb; v.views = d_views; v.site_off = d_site_off;
     return v;
   }
 };
 
+// Device view of a domain.  A batch of domains is one disjoint union with
+// global vertex and simplex indices; views[b] holds diagram b's point-location
+// grid and bounding box.
 struct DomainView {
-  int m, nv, dim;
+  int m, nv, dim;       // all simplices / vertices of the (batched) domain
   const double *verts;
   const int *simp, *adj;
   // point location grid over the simplices (tetrahedra only)
   int lg[3];
   const double *lgeom;  // lo[3], h[3], ih[3]
   const int *lstart, *litems;
+  double box_lo[3], box_hi[3];  // padded bounding box (cell-first carve)
+  int nb;
+  const DomainView *views;      // [nb] (nb > 1)
+  const long long *simp_off;    // [nb + 1] (nb > 1)
 };
+
+__device__ __forceinline__ DomainView domain_of(const DomainView &D, int b) { return D.nb > 1 ? D.views[b] : D; }
 
 struct vd_domain_s {
   int64_t m = 0, nv = 0;
   int dim = 3;
   double *verts = nullptr;
   int *simp = nullptr, *adj = nullptr;
-  int lg[3] = {1, 1, 1};
-  double *lgeom = nullptr;
+  double *lgeom = nullptr;  // [9 nb]
   int *lstart = nullptr, *litems = nullptr, *lcount = nullptr, *lfill = nullptr, *scan_tmp = nullptr;
-  int64_t nitems = 0;
-  double area = 0.0;  // surface area (triangles) or volume (tets)
-  double bbox[6] = {0, 0, 0, 0, 0, 0};  // vertex bounding box
-  DomainView view() const {
+  int64_t nitems = 0, ncell = 0;
+  double area = 0.0;  // surface area (triangles) or volume (tets), all diagrams
+  // batch of nb domains (nb = 1: plain)
+  int nb = 1;
+  std::vector<int64_t> vert_off, simp_off, loc_off;  // host [nb + 1]
+  std::vector<int> lg;                               // host [3 nb] location grid dims
+  std::vector<double> bbox;                          // host [6 nb] vertex bounding boxes
+  long long *d_simp_off = nullptr, *d_vert_off = nullptr, *d_loc_off = nullptr;
+  int *d_lg = nullptr;
+  DomainView *d_views = nullptr;
+  DomainView view_of(int b) const {
     DomainView d;
     d.m = (int)m; d.nv = (int)nv; d.dim = dim; d.verts = verts; d.simp = simp; d.adj = adj;
-    d.lg[0] = lg[0]; d.lg[1] = lg[1]; d.lg[2] = lg[2];
-    d.lgeom = lgeom; d.lstart = lstart; d.litems = litems;
+    d.lg[0] = lg.empty() ? 1 : lg[3 * b]; d.lg[1] = lg.empty() ? 1 : lg[3 * b + 1];
+    d.lg[2] = lg.empty() ? 1 : lg[3 * b + 2];
+    d.lgeom = lgeom ? lgeom + 9 * b : nullptr;
+    d.lstart = lstart ? lstart + (loc_off.empty() ? 0 : loc_off[b]) : nullptr;
+    d.litems = litems;
+    for (int a = 0; a < 3; a++) {
+      // The box strictly contains the domain so no box plane meets a simplex.
+      // The six paddings differ so that no box edge lies on a plane of
+      // symmetry of the domain (e.g. the diagonal planes of cube grids split
+      // into tetrahedra), where a tetrahedron plane would contain the edge.
+      const double lo = bbox.empty() ? 0.0 : bbox[6 * b + a], hi = bbox.empty() ? 0.0 : bbox[6 * b + 3 + a];
+      const double ext = hi - lo > 1e-12 ? hi - lo : 1e-12;
+      d.box_lo[a] = lo - (1.01e-3 + 0.12e-3 * a) * ext - 1e-9;
+      d.box_hi[a] = hi + (1.07e-3 + 0.14e-3 * a) * ext + 1e-9;
+    }
+    d.nb = 1; d.views = nullptr; d.simp_off = nullptr;
+    return d;
+  }
+  DomainView view() const {
+    DomainView d = view_of(0);
+    d.nb = nb; d.views = d_views; d.simp_off = d_simp_off;
     return d;
   }
 };
@@ -92,7 +148,6 @@ struct CellsDev {
   int max_iters;
   int mode;        // 0 per-simplex carve, 1 cell-first
   int cache;       // LDS copy of the sites around each site for its queries
-  double box_lo[3], box_hi[3];  // padded domain box (cell-first)
   unsigned long long *cnt;  // CNT_N counters
   // per site (caller index)
   double *mass, *mom, *energy;
@@ -115,6 +170,7 @@ struct CellsDev {
   int *seed;  // 3D: tetrahedron containing each site (sorted position order)
   long long chunk[AR_N];  // slots a wave reserves at a time in each arena
   int *queue;             // [VD_QUEUES * VD_QSTRIDE] work-queue heads
+  int *tq_spill;          // [workgroups * VD_Q_SPILL] overflow of the per-site simplex queue
 };
 
 struct vd_cells_s {
@@ -122,7 +178,9 @@ struct vd_cells_s {
   int dim = 3;
   vd_options opt;
   CellsDev d{};
-  unsigned long long host_cnt[CNT_N] = {0};
+  unsigned long long *host_cnt = nullptr;  // [CNT_N] pinned host copy of the counters
+  bool pending = false;                    // a no-sync clip whose counters are not checked yet
+  hipStream_t last_stream = nullptr;
   // capacities (host copy) and allocations
   int64_t cap_n = 0;
   long long *piece_off = nullptr, *nbr_off = nullptr;  // CSR [n+1]
@@ -137,13 +195,14 @@ struct vd_cells_s {
   hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;  // kernel timing (time_kernels)
   double carve_ms = -1.0, split_ms = -1.0;
   CellsDev *d_dev = nullptr;  // device copy of d (read by the piece kernel)
+  int64_t cap_spill = 0;      // workgroups covered by d.tq_spill
   CellsDev d_shadow{};        // host copy last sent to d_dev
   double *wbuf = nullptr;     // adjoint weights [5n]
   int64_t cap_w = 0;
 };
 
 // launchers (defined in the .hip files)
-void vd_launch_grid_build(vd_grid g, const double *sites, const double *bbox_host, hipStream_t st);
+void vd_launch_grid_build(vd_grid g, const double *sites, const double *user_box, hipStream_t st);
 void vd_launch_domain_locator(vd_domain d, hipStream_t st);
 void vd_launch_locate_sites(const GridView &G, const DomainView &D, int *seed, unsigned long long *cnt,
                             hipStream_t st);
