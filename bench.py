@@ -20,7 +20,39 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # MI355X dense FP64 vector
+HBM_PEAK_GBPS = 8000.0           # MI355X HBM3E
+# algorithmic FP64 work, per counted unit
 FLOPS_PER_CANDIDATE = 8          # |q - s|^2: 3 sub + 3 mul/fma (fma = 2) + compare
+FLOPS_PER_CLIP = 480             # ~30 corner distances (8 each) + ~4 new corners by 3x3 solves (60 each)
+FLOPS_PER_PIECE_VERTEX = 120     # 3 fan tetrahedra per piece corner, 40 flops each (volume, moment, energy)
+# algorithmic HBM bytes, per counted unit
+BYTES_PER_SITE = 110 + 48        # inputs (site, sorted copy, perm, grid, simplices share) + per-site outputs
+BYTES_PER_PIECE = 72             # piece record
+BYTES_PER_FACE = 4               # face label
+BYTES_PER_VERT = 36              # vertex coordinates + 3 labels
+BYTES_PER_NBR = 8                # neighbour (arena + CSR)
+KERNEL_FILES = ("clip3d.hip", "vd_common.h", "vd_arena.h", "vd_internal.h")
+
+
+def recorded_traffic():
+    """HBM bytes per site_kernel launch from the committed counter profile, if
+    the kernel sources are still the profiled ones (else None)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_FILES:
+        with open(os.path.join(ROOT, "paper_2509_07175_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    path = os.path.join(ROOT, "profiles", "site_kernel_c3_counters.md")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "kernel_source_sha256"):
+            k, v = line.split(":", 1)
+            rec[k.strip()] = v.strip()
+    if rec.get("kernel_source_sha256") != h.hexdigest():
+        return None
+    return float(rec["traffic_bytes_per_launch"])
 
 
 def workload(name):
@@ -271,8 +303,12 @@ def main():
     ms = 1e3 * wall / args.steps
     # the dominant kernel: the persistent per-site kernel (cell carve + pieces)
     dom_ms, dom_name = float(np.mean(kern)), "site_kernel"
-    flops = FLOPS_PER_CANDIDATE * info["candidates"]
+    flops = (FLOPS_PER_CANDIDATE * info["candidates"] + FLOPS_PER_CLIP * info["clips"] +
+             FLOPS_PER_PIECE_VERTEX * info["n_verts"])
     achieved = flops / (dom_ms * 1e-3) / 1e12
+    alg_bytes = (BYTES_PER_SITE * n + BYTES_PER_PIECE * info["n_pieces"] + BYTES_PER_FACE * info["n_faces"] +
+                 BYTES_PER_VERT * info["n_verts"] + BYTES_PER_NBR * info["n_nbrs"])
+    traffic = recorded_traffic() if args.workload == "c3" and not args.no_emit else None
     total_mass = float(mass.sum().item())
 
     out = {
@@ -293,8 +329,12 @@ def main():
                    "improved_search": args.improved, "straddle_edges": args.straddle,
                    "site_cache": args.site_cache},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
-                     "kernel": dom_name, "kernel_ms": dom_ms},
+                     "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": traffic,
+                     "kernel": dom_name, "kernel_ms": dom_ms, "algorithmic_flops": flops,
+                     "hbm": {"algorithmic_bytes": alg_bytes,
+                             "achieved": alg_bytes / (dom_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                             "frac": alg_bytes / (dom_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                             "measured": None if traffic is None else traffic / (dom_ms * 1e-3) / 1e9}},
         "counters": {"pieces": info["n_pieces"], "nn_queries": info["nn_queries"], "clips": info["clips"],
                      "candidates": info["candidates"], "queries_per_cell": info["nn_queries"] / n,
                      "grid_queries": info["grid_queries"],

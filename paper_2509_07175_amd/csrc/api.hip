@@ -584,7 +584,9 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
     return r;
   };
   Caps want;
-  want.piece = std::max<int64_t>(std::max<int64_t>(c->d.cap_piece, 6 * n + 1024), dom->dim == 2 ? 2 * dom->m + 6 * n : 0);
+  // a site's cell meets a few simplices when simplices and cells are alike in
+  // size, many when simplices are much smaller: 8 per site plus 3 per simplex
+  want.piece = std::max<int64_t>(c->d.cap_piece, 8 * n + 3 * dom->m + 1024);
   want.nbr = std::max<int64_t>(c->d.cap_nbr, 20 * n + 1024);
   // surfaces always keep the edge flags of their pieces (the per-site pass reads them)
   const bool keep_faces = opt.emit_polytopes || dom->dim == 2;
