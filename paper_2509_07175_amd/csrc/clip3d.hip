@@ -141,8 +141,8 @@ __device__ int compact_planes(WaveLds &S, int npl, int nc) {
 }
 
 // Clip by plane slot P, removing R_p: the connected set of corners strictly
-// outside P that contains corner pt (Sec. 6.3); pt < 0 picks the corner
-// farthest outside (geometric cut).  New corners are created on every dual edge
+// outside P that contains corner pt (Sec. 6.3); pt < 0 removes every corner
+// outside P (a cut of a convex polytope).  New corners are created on every dual edge
 // leaving R_p and form the fan of the new face.
 // Returns 0 (nothing outside: unchanged), 1 empty, 2 capacity, 3 degenerate,
 // 4 cut (nc updated).
@@ -165,18 +165,18 @@ __device__ int clip_poly(WaveLds &S, int P, int pt, int &nc) {
   }
   const uint64_t olo = __ballot(o[0]), ohi = __ballot(o[1]);
   if (!(olo | ohi)) return pt < 0 ? 0 : 3;
+  uint64_t Rlo, Rhi;
   if (pt < 0) {
-    // farthest outside corner (ties: lowest slot)
-    double best = -sd[0];
-    int bs = l;
-    if (-sd[1] < best) { best = -sd[1]; bs = l + 64; }
-    group_argmin(best, bs, 64);
-    pt = uni(bs);
-  } else if (!bit128(olo, ohi, pt)) {
-    return 3;
+    // a cut of a convex polytope: every outside corner goes (an outside set
+    // that rounding made disconnected gives a non-simple boundary, caught below)
+    Rlo = olo;
+    Rhi = ohi;
+  } else {
+    if (!bit128(olo, ohi, pt)) return 3;
+    Rlo = pt < 64 ? (1ull << pt) : 0ull;
+    Rhi = pt >= 64 ? (1ull << (pt - 64)) : 0ull;
   }
-  uint64_t Rlo = pt < 64 ? (1ull << pt) : 0ull, Rhi = pt >= 64 ? (1ull << (pt - 64)) : 0ull;
-  for (int it = 0; it < VD_C_MAX; it++) {
+  for (int it = 0; pt >= 0 && it < VD_C_MAX; it++) {
     bool j[2];
     for (int h = 0; h < 2; h++) {
       const int s = l + 64 * h;
@@ -532,6 +532,8 @@ __device__ void init_tet(WaveLds &S, const DomainView &D, const SiteCtx &X, int 
   __syncthreads();
 }
 
+static_assert(VD_C_MAX * 3 >= VD_CACHE, "the corner array doubles as the site cache's sort scratch");
+
 // cell-first: keep the carved cell (npl planes, nc corners) ...
 __device__ void save_cell(WaveLds &S, int npl, int nc) {
   const int l = vd_lane();
@@ -726,7 +728,7 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
   bool cell_job = C.mode == 1, saved = false;
   double Mv = 0, Mx = 0, My = 0, Mz = 0, Me = 0;
   if (C.cache) {
-    cache_fill(S.K, G, X.vx, X.vy, X.vz);
+    cache_fill(S.K, G, X.vx, X.vy, X.vz, &S.cy[0][0]);  // the corner array is free until the carve
   } else {
     if (l == 0) S.K.cnt = -1;
   }

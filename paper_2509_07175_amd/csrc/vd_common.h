@@ -346,7 +346,8 @@ __device__ __forceinline__ int block_count(const GridView &G, int x0, int x1, in
   return wave_isum(c);
 }
 
-__device__ void cache_fill(SiteCache &K, const GridView &G, double vx, double vy, double vz) {
+// scratch: VD_CACHE doubles of LDS the caller does not use during the call
+__device__ void cache_fill(SiteCache &K, const GridView &G, double vx, double vy, double vz, double *scratch) {
   const int l = vd_lane();
   const int gx = G.g[0], gy = G.g[1], gz = G.g[2];
   const int cx = cell_coord(vx, G.geom[0], G.geom[6], gx);
@@ -420,11 +421,12 @@ __device__ void cache_fill(SiteCache &K, const GridView &G, double vx, double vy
       ex[h] = K.x[t]; ey[h] = K.y[t]; ez[h] = K.z[t]; ep[h] = K.p[t];
       const double ax = ex[h] - vx, ay = ey[h] - vy, az = ez[h] - vz;
       ek[h] = ax * ax + ay * ay + az * az;
+      scratch[t] = ek[h];
     }
   }
+  __syncthreads();
   for (int o = 0; o < off; o++) {
-    const double ax = K.x[o] - vx, ay = K.y[o] - vy, az = K.z[o] - vz;
-    const double ko = ax * ax + ay * ay + az * az;
+    const double ko = scratch[o];
 #pragma unroll
     for (int h = 0; h < 4; h++) rk[h] += (ko < ek[h] || (ko == ek[h] && o < l + 64 * h)) ? 1 : 0;
   }
