@@ -347,41 +347,20 @@ __device__ __forceinline__ int block_count(const GridView &G, int x0, int x1, in
 }
 
 // scratch: VD_CACHE doubles of LDS the caller does not use during the call
-__device__ void cache_fill(SiteCache &K, const GridView &G, double vx, double vy, double vz, double *scratch) {
+// Calls f(p, t) for every site of the cell block, p its sorted position and t
+// its index in block order (rows of x-cells, contiguous site ranges); the
+// whole wave takes part, lane l handling t = l, l + 64, ...
+template <class F>
+__device__ __forceinline__ void for_block_sites(const GridView &G, int x0, int x1, int y0, int y1, int z0, int z1,
+                                                F f) {
   const int l = vd_lane();
-  const int gx = G.g[0], gy = G.g[1], gz = G.g[2];
-  const int cx = cell_coord(vx, G.geom[0], G.geom[6], gx);
-  const int cy = cell_coord(vy, G.geom[1], G.geom[7], gy);
-  const int cz = cell_coord(vz, G.geom[2], G.geom[8], gz);
-  auto cells = [&](int r) {
-    return (long long)(min(cx + r, gx - 1) - max(cx - r, 0) + 1) * (min(cy + r, gy - 1) - max(cy - r, 0) + 1) *
-           (min(cz + r, gz - 1) - max(cz - r, 0) + 1);
-  };
-  auto count = [&](int r) {
-    return block_count(G, max(cx - r, 0), min(cx + r, gx - 1), max(cy - r, 0), min(cy + r, gy - 1),
-                       max(cz - r, 0), min(cz + r, gz - 1));
-  };
-  const int c1 = count(1);
-  int r = 1;
-  const double dens = (double)c1 / (double)cells(1);
-  while (r < 8 && (c1 == 0 || dens * (double)cells(r + 1) <= 0.7 * VD_CACHE)) r++;
-  int c = r == 1 ? c1 : count(r);
-  while (c > VD_CACHE && r > 0) c = count(--r);
-  __syncthreads();
-  if (c > VD_CACHE) {
-    if (l == 0) K.cnt = -1;
-    __syncthreads();
-    return;
-  }
-  const int x0 = max(cx - r, 0), x1 = min(cx + r, gx - 1), y0 = max(cy - r, 0), y1 = min(cy + r, gy - 1);
-  const int z0 = max(cz - r, 0), z1 = min(cz + r, gz - 1);
   const int nx = x1 - x0 + 1, ny = y1 - y0 + 1, R = ny * (z1 - z0 + 1);
   int off = 0;
   for (int r0 = 0; r0 < R; r0 += 64) {
     const int rr = r0 + l;
     int st = 0, cnt = 0;
     if (rr < R) {
-      const int c0 = x0 + gx * ((y0 + rr % ny) + gy * (z0 + rr / ny));
+      const int c0 = x0 + G.g[0] * ((y0 + rr % ny) + G.g[1] * (z0 + rr / ny));
       st = G.cstart[c0];
       cnt = G.cstart[c0 + nx] - st;
     }
@@ -399,16 +378,107 @@ __device__ void cache_fill(SiteCache &K, const GridView &G, double vx, double vy
       }
       const int rst = __shfl(st, w, 64);
       const int rex = __shfl(excl, w, 64);
-      if (t < total) {
-        const int p = rst + (t - rex);
-        K.x[off + t] = G.sx[p];
-        K.y[off + t] = G.sy[p];
-        K.z[off + t] = G.sz[p];
-        K.p[off + t] = p;
-      }
+      f(t < total ? rst + (t - rex) : -1, off + t);
     }
     off += total;
   }
+}
+
+// The block is sized from the density of the 3x3x3 block around v so that it
+// holds about 2.5 VD_CACHE sites.  If more than VD_CACHE of them are nearer to v
+// than the block boundary, only the nearest are kept: a 64-bucket histogram of
+// squared distances picks the largest radius T whose ball holds at most
+// VD_CACHE sites, every site with d^2 < T^2 is kept, and rc = T.
+__device__ void cache_fill(SiteCache &K, const GridView &G, double vx, double vy, double vz, double *scratch) {
+  const int l = vd_lane();
+  const int gx = G.g[0], gy = G.g[1], gz = G.g[2];
+  const int cx = cell_coord(vx, G.geom[0], G.geom[6], gx);
+  const int cy = cell_coord(vy, G.geom[1], G.geom[7], gy);
+  const int cz = cell_coord(vz, G.geom[2], G.geom[8], gz);
+  auto cells = [&](int r) {
+    return (long long)(min(cx + r, gx - 1) - max(cx - r, 0) + 1) * (min(cy + r, gy - 1) - max(cy - r, 0) + 1) *
+           (min(cz + r, gz - 1) - max(cz - r, 0) + 1);
+  };
+  auto count = [&](int r) {
+    return block_count(G, max(cx - r, 0), min(cx + r, gx - 1), max(cy - r, 0), min(cy + r, gy - 1),
+                       max(cz - r, 0), min(cz + r, gz - 1));
+  };
+  constexpr int kMaxBlock = 4 * VD_CACHE;  // candidates read at most
+  const int c1 = count(1);
+  int r = 1;
+  const double dens = (double)c1 / (double)cells(1);
+  while (r < 8 && (c1 == 0 || dens * (double)cells(r + 1) <= 2.5 * VD_CACHE)) r++;
+  int c = r == 1 ? c1 : count(r);
+  while (c > kMaxBlock && r > 0) c = count(--r);
+  __syncthreads();
+  if (c > kMaxBlock) {
+    if (l == 0) K.cnt = -1;
+    __syncthreads();
+    return;
+  }
+  const int x0 = max(cx - r, 0), x1 = min(cx + r, gx - 1), y0 = max(cy - r, 0), y1 = min(cy + r, gy - 1);
+  const int z0 = max(cz - r, 0), z1 = min(cz + r, gz - 1);
+  // distance from v to the block boundary (a side at the grid's edge is open),
+  // less a margin for the rounding of cell assignment
+  double rcb = 1e300;
+  {
+    const double *lo = G.geom, *h = G.geom + 3;
+    if (x0 > 0) rcb = fmin(rcb, vx - (lo[0] + x0 * h[0]));
+    if (x1 < gx - 1) rcb = fmin(rcb, lo[0] + (x1 + 1) * h[0] - vx);
+    if (y0 > 0) rcb = fmin(rcb, vy - (lo[1] + y0 * h[1]));
+    if (y1 < gy - 1) rcb = fmin(rcb, lo[1] + (y1 + 1) * h[1] - vy);
+    if (z0 > 0) rcb = fmin(rcb, vz - (lo[2] + z0 * h[2]));
+    if (z1 < gz - 1) rcb = fmin(rcb, lo[2] + (z1 + 1) * h[2] - vz);
+    rcb -= 1e-9 * fmin(h[0], fmin(h[1], h[2]));
+    if (rcb < 0.0) rcb = 0.0;
+  }
+  auto d2of = [&](int p) {
+    const double ax = G.sx[p] - vx, ay = G.sy[p] - vy, az = G.sz[p] - vz;
+    return ax * ax + ay * ay + az * az;
+  };
+  // the keep threshold on d^2 (all sites when they fit)
+  bool select = c > VD_CACHE;
+  double keep2 = 1e300;
+  if (select) {
+    constexpr int NB = 64;
+    int *hist = reinterpret_cast<int *>(scratch);
+    // histogram range: the block's inscribed ball, or (sides open at the grid's
+    // edge) a ball around v that contains the whole block
+    const double hm = fmax(G.geom[3], fmax(G.geom[4], G.geom[5]));
+    const double rc2 = fmin(rcb * rcb, 3.0 * ((r + 1) * hm) * ((r + 1) * hm));
+    const double step = rc2 / NB;
+    if (l < NB + 1) hist[l] = 0;
+    __syncthreads();
+    // bucket k holds k*step <= d^2 < (k+1)*step; NB: beyond the block's ball
+    for_block_sites(G, x0, x1, y0, y1, z0, z1, [&](int p, int) {
+      if (p < 0) return;
+      const double d2 = d2of(p);
+      int k = rc2 > 0.0 ? (int)fmin((double)NB, floor(d2 / step)) : NB;
+      if (k < NB && d2 >= (k + 1) * step) k++;
+      if (k > 0 && k <= NB && d2 < k * step) k--;
+      atomicAdd(&hist[k], 1);
+    });
+    __syncthreads();
+    const int cnt = l < NB ? hist[l] : 0;
+    const int cum = wave_incl_scan(cnt);
+    // buckets 0 .. B-1 fit (cum is non-decreasing, so the fitting lanes are a prefix)
+    const int B = __popcll(__ballot(l < NB && cum <= VD_CACHE));
+    keep2 = B * step;
+    __syncthreads();
+  }
+  int off = 0;
+  for_block_sites(G, x0, x1, y0, y1, z0, z1, [&](int p, int) {
+    bool take = p >= 0;
+    if (take && select) take = d2of(p) < keep2;
+    const int pos = off + wave_incl_scan(take ? 1 : 0) - (take ? 1 : 0);
+    if (take) {
+      K.x[pos] = G.sx[p];
+      K.y[pos] = G.sy[p];
+      K.z[pos] = G.sz[p];
+      K.p[pos] = p;
+    }
+    off += __popcll(__ballot(take));
+  });
   __syncthreads();
   // sort by (distance^2 to v, slot): each lane ranks its entries against all
   double ex[4], ey[4], ez[4], ek[4];
@@ -438,20 +508,13 @@ __device__ void cache_fill(SiteCache &K, const GridView &G, double vx, double vy
     }
   }
   if (l == 0) {
-    // distance from v to the block boundary; a side at the grid's edge is open
-    const double *lo = G.geom, *h = G.geom + 3;
-    double rc = 1e300;
-    if (x0 > 0) rc = fmin(rc, vx - (lo[0] + x0 * h[0]));
-    if (x1 < gx - 1) rc = fmin(rc, lo[0] + (x1 + 1) * h[0] - vx);
-    if (y0 > 0) rc = fmin(rc, vy - (lo[1] + y0 * h[1]));
-    if (y1 < gy - 1) rc = fmin(rc, lo[1] + (y1 + 1) * h[1] - vy);
-    if (z0 > 0) rc = fmin(rc, vz - (lo[2] + z0 * h[2]));
-    if (z1 < gz - 1) rc = fmin(rc, lo[2] + (z1 + 1) * h[2] - vz);
-    rc -= 1e-9 * fmin(h[0], fmin(h[1], h[2]));
-    K.rc = rc > 0.0 ? rc : 0.0;
+    // every site within rc of v is held; the block test holds only when the
+    // whole block was kept
+    K.rc = select ? fmin(rcb, sqrt(keep2) * (1.0 - 1e-12)) : rcb;
     K.vx = vx; K.vy = vy; K.vz = vz;
     K.cnt = off;
     K.b[0] = x0; K.b[1] = x1; K.b[2] = y0; K.b[3] = y1; K.b[4] = z0; K.b[5] = z1;
+    if (select) { K.b[0] = 1; K.b[1] = 0; }  // an empty x-range: never inside
   }
   __syncthreads();
 }
