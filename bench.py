@@ -225,6 +225,65 @@ def bench_backward(sites_t, dom_h, rho, steps, warmup, log):
             "site_kernel_ms_with_face_moments": cells.info()["carve_ms"], "cvt_gradient_rel_err": err}
 
 
+def bench_surface(steps, warmup, log):
+    """Restricted VD on the sphere (200,000 sites, 81,920-triangle icosphere):
+    plain forward, forward with face moments + adjoint, adjoint alone."""
+    import numpy as np
+    import torch
+
+    import paper_2509_07175_amd as vd
+    import vdgen
+    sites, dom = vdgen.config_c5()
+    n = len(sites)
+    q = dom.verts[dom.simplices]
+    area = float(0.5 * np.linalg.norm(np.cross(q[:, 1] - q[:, 0], q[:, 2] - q[:, 0]), axis=1).sum())
+    s = torch.as_tensor(sites, dtype=torch.float64, device="cuda")
+    d = vd.Domain.from_vdgen(dom)
+    bbox = (-1.01, -1.01, -1.01, 1.01, 1.01, 1.01)
+    grid, cells = vd.Grid(), vd.Cells()
+    mass = torch.empty(n, dtype=torch.float64, device="cuda")
+    cent = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    en = torch.empty(n, dtype=torch.float64, device="cuda")
+    ge = torch.ones(n, dtype=torch.float64, device="cuda")
+    gs = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+
+    def timed(fn):
+        for _ in range(max(1, warmup)):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0) / steps
+
+    plain_opt = vd.Options.default()
+    grad_opt = vd.Options.default(want_grad=1)
+
+    def fwd():
+        vd.build_grid(s, bbox=bbox, surface_area=area, grid=grid)
+        vd.clip_cells(grid, d, plain_opt, cells=cells)
+        cells.moments(mass, cent, en)
+
+    def fwd_bwd():
+        vd.build_grid(s, bbox=bbox, surface_area=area, grid=grid)
+        vd.clip_cells(grid, d, grad_opt, cells=cells)
+        cells.moments(mass, cent, en)
+        cells.backward(None, None, ge, out=gs)
+
+    f_ms = timed(fwd)
+    fb_ms = timed(fwd_bwd)
+    b_ms = timed(lambda: cells.backward(None, None, ge, out=gs))
+    ref = 2 * mass[:, None] * (s - cent)
+    err = float((gs - ref).abs().max().item() / ref.abs().max().item())
+    log(f"surface: forward {f_ms:.1f} ms, forward+adjoint {fb_ms:.1f} ms, adjoint {b_ms:.2f} ms, CVT check {err:.1e}")
+    return {"workload": f"{n} sites on the unit sphere, icosphere of {dom.m} triangles",
+            "forward_ms": f_ms, "forward_cells_per_s": n / (f_ms * 1e-3),
+            "forward_plus_adjoint_ms": fb_ms, "forward_plus_adjoint_cells_per_s": n / (fb_ms * 1e-3),
+            "adjoint_ms": b_ms, "adjoint_cells_per_s": n / (b_ms * 1e-3),
+            "forward_plus_adjoint_vs_forward": f_ms / fb_ms, "cvt_gradient_rel_err": err}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -235,7 +294,7 @@ def main():
     ap.add_argument("--no-emit", action="store_true", help="skip writing per-piece polytopes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--carve-mode", type=int, default=1, choices=[0, 1])
-    ap.add_argument("--improved", type=int, default=1, choices=[0, 1])
+    ap.add_argument("--improved", type=int, default=0, choices=[0, 1])
     ap.add_argument("--straddle", type=int, default=1, choices=[0, 1])
     ap.add_argument("--site-cache", type=int, default=1, choices=[0, 1])
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-diagrams comparison")
@@ -344,6 +403,8 @@ def main():
     if not args.no_backward:
         out["backward"] = bench_backward(s, d, rho, max(1, min(args.steps, 5)), 1, log)
         out["backward"]["vs_plain_forward"] = ms / out["backward"]["forward_with_face_moments_plus_adjoint_ms"]
+    if not args.no_backward:
+        out["backward_surface"] = bench_surface(max(1, min(args.steps, 5)), 1, log)
     if not args.no_batched:
         out["batched"] = bench_batched(max(1, min(args.steps, 5)), 1, log)
     if not args.no_cpu_baseline:

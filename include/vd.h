@@ -68,7 +68,10 @@ enum {
 typedef struct {
   double sites_per_cell;   /* unused by vd_clip_cells (the grid density is an argument
                               of vd_build_grid); kept for callers that store it here */
-  int32_t improved_search; /* 1: shorten search edges by lambda*delta steps (Sec. 6.1) */
+  int32_t improved_search; /* 1: shorten search edges by lambda*delta steps (Sec. 6.1).
+                              Default 0: with the per-wave site cache a far query costs
+                              about what a near one does, so the extra lambda queries
+                              no longer pay (same results either way) */
   int32_t use_straddle_edges; /* 1: prefer edges with one inside end (Alg. 1);
                                  0: virtual edges from the site only (Alg. 3) */
   int32_t max_search_iters;   /* cap of the bisector search and of the lambda loop */

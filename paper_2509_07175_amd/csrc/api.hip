@@ -94,7 +94,7 @@ const char *vd_status_string(vd_status s) {
 void vd_options_default(vd_options *opt) {
   if (!opt) return;
   opt->sites_per_cell = 3.5;
-  opt->improved_search = 1;
+  opt->improved_search = 0;
   opt->use_straddle_edges = 1;
   opt->max_search_iters = 64;
   opt->emit_polytopes = 1;
