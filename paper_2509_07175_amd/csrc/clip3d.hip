@@ -532,7 +532,7 @@ __device__ void init_tet(WaveLds &S, const DomainView &D, const SiteCtx &X, int 
   __syncthreads();
 }
 
-static_assert(VD_C_MAX * 3 >= VD_CACHE, "the corner array doubles as the site cache's sort scratch");
+static_assert(VD_C_MAX * 3 >= VD_CACHE_SCRATCH, "the corner array doubles as the site cache's sort scratch");
 
 // cell-first: keep the carved cell (npl planes, nc corners) ...
 __device__ void save_cell(WaveLds &S, int npl, int nc) {

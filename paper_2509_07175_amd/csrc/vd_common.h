@@ -49,6 +49,9 @@ __device__ __forceinline__ int vd_lane() {
   return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
 }
 
+// lanes below this one
+__device__ __forceinline__ unsigned long long low_mask_lt(int l) { return (1ull << l) - 1ull; }
+
 __device__ __forceinline__ bool bit128(uint64_t lo, uint64_t hi, int s) {
   return s < 64 ? ((lo >> s) & 1ull) : ((hi >> (s - 64)) & 1ull);
 }
@@ -313,20 +316,26 @@ __device__ __forceinline__ int nn_thread(const GridView &G, double qx, double qy
 
 // ---------------------------------------------------------------------------
 // Per-wave LDS copy of the sites in a block of grid cells around the site v
-// being carved, sorted by distance to v.  Every site within rc of v is held
+// being carved, ordered by distance to v in 64 buckets of squared distance
+// (bucket k: k*step <= d^2 < (k+1)*step; the last one is unbounded), in
+// block order within a bucket.  Every site within rc of v is held
 // (rc = distance from v to the block's boundary, less a margin for the
 // rounding of cell assignment).  A query q only scans entries up to distance
-// |q - v| + d from v (d = best distance so far: farther sites cannot be
+// |q - v| + d from v, judged by the bucket bound of the next entry (d = best
+// distance so far: farther sites cannot be
 // nearer to q), and its answer is exact, with the same tie-break, when
 // |q - v| + d < rc; otherwise the grid query continues from that best
 // candidate.  The block is the largest one (half-width <= 8 cells) whose sites
 // fit, sized from the density of the 3x3x3 block around the site.
 // ---------------------------------------------------------------------------
 #define VD_CACHE 224
+#define VD_CACHE_SCRATCH 288  // doubles of scratch cache_fill needs (bucket starts, bucket sets)
 
 struct SiteCache {
   double x[VD_CACHE], y[VD_CACHE], z[VD_CACHE];
   int p[VD_CACHE];
+  unsigned char kb[VD_CACHE];  // distance bucket of each entry (non-decreasing)
+  double step;        // bucket width in squared distance
   double vx, vy, vz;  // the site
   double rc;          // radius around the site within which every site is held
   int cnt;            // sites held; -1 = none for this site
@@ -346,7 +355,7 @@ __device__ __forceinline__ int block_count(const GridView &G, int x0, int x1, in
   return wave_isum(c);
 }
 
-// scratch: VD_CACHE doubles of LDS the caller does not use during the call
+// scratch: VD_CACHE_SCRATCH doubles of LDS the caller does not use during the call
 // Calls f(p, t) for every site of the cell block, p its sorted position and t
 // its index in block order (rows of x-cells, contiguous site ranges); the
 // whole wave takes part, lane l handling t = l, l + 64, ...
@@ -436,81 +445,95 @@ __device__ void cache_fill(SiteCache &K, const GridView &G, double vx, double vy
     const double ax = G.sx[p] - vx, ay = G.sy[p] - vy, az = G.sz[p] - vz;
     return ax * ax + ay * ay + az * az;
   };
-  // the keep threshold on d^2 (all sites when they fit)
-  bool select = c > VD_CACHE;
-  double keep2 = 1e300;
-  if (select) {
-    constexpr int NB = 64;
-    int *hist = reinterpret_cast<int *>(scratch);
-    // histogram range: the block's inscribed ball, or (sides open at the grid's
-    // edge) a ball around v that contains the whole block
-    const double hm = fmax(G.geom[3], fmax(G.geom[4], G.geom[5]));
-    const double rc2 = fmin(rcb * rcb, 3.0 * ((r + 1) * hm) * ((r + 1) * hm));
-    const double step = rc2 / NB;
-    if (l < NB + 1) hist[l] = 0;
-    __syncthreads();
-    // bucket k holds k*step <= d^2 < (k+1)*step; NB: beyond the block's ball
-    for_block_sites(G, x0, x1, y0, y1, z0, z1, [&](int p, int) {
-      if (p < 0) return;
-      const double d2 = d2of(p);
-      int k = rc2 > 0.0 ? (int)fmin((double)NB, floor(d2 / step)) : NB;
-      if (k < NB && d2 >= (k + 1) * step) k++;
-      if (k > 0 && k <= NB && d2 < k * step) k--;
-      atomicAdd(&hist[k], 1);
-    });
-    __syncthreads();
-    const int cnt = l < NB ? hist[l] : 0;
-    const int cum = wave_incl_scan(cnt);
-    // buckets 0 .. B-1 fit (cum is non-decreasing, so the fitting lanes are a prefix)
-    const int B = __popcll(__ballot(l < NB && cum <= VD_CACHE));
-    keep2 = B * step;
-    __syncthreads();
-  }
+  // buckets of squared distance: NB - 1 of width step over [0, rc2), the last
+  // one beyond.  Range: the block's inscribed ball when some sites may have to
+  // go, else (and for sides open at the grid's edge) a ball holding the block.
+  constexpr int NB = 64;
+  const bool select = c > VD_CACHE;
+  const double hm = fmax(G.geom[3], fmax(G.geom[4], G.geom[5]));
+  const double rcw2 = 3.0 * ((r + 1) * hm) * ((r + 1) * hm);
+  const double rc2 = select ? fmin(rcb * rcb, rcw2) : rcw2;
+  const double step = rc2 / (NB - 1);
+  const double istep = rc2 > 0.0 ? (NB - 1) / rc2 : 0.0;
+  auto bucket = [&](double d2) {
+    int k = rc2 > 0.0 ? (int)fmin((double)(NB - 1), floor(d2 * istep)) : NB - 1;
+    if (k < NB - 1 && d2 >= (k + 1) * step) k++;
+    if (k > 0 && d2 < k * step) k--;
+    return k;
+  };
+  // scratch: bucket counts (then starts), and per bucket a 256-bit set of the
+  // entries in it (stable order within a bucket)
+  int *hist = reinterpret_cast<int *>(scratch);
+  unsigned long long *bits = reinterpret_cast<unsigned long long *>(scratch) + NB / 2;
+  hist[l] = 0;
+#pragma unroll
+  for (int w = 0; w < 4; w++) bits[l * 4 + w] = 0ull;
+  __syncthreads();
+  for_block_sites(G, x0, x1, y0, y1, z0, z1, [&](int p, int) {
+    if (p >= 0) atomicAdd(&hist[bucket(d2of(p))], 1);
+  });
+  __syncthreads();
+  const int cnt = hist[l];
+  const int cum = wave_incl_scan(cnt);
+  // buckets 0 .. B-1 are kept (cum is non-decreasing, so the fitting lanes are a prefix)
+  const int B = select ? __popcll(__ballot(l < NB - 1 && cum <= VD_CACHE)) : NB;
+  const double keep2 = B * step;
+  __syncthreads();
+  hist[l] = cum - cnt;
+  __syncthreads();
+  // kept sites in block order, with their buckets
   int off = 0;
   for_block_sites(G, x0, x1, y0, y1, z0, z1, [&](int p, int) {
-    bool take = p >= 0;
-    if (take && select) take = d2of(p) < keep2;
+    int k = NB;
+    if (p >= 0) k = bucket(d2of(p));
+    const bool take = k < B;
     const int pos = off + wave_incl_scan(take ? 1 : 0) - (take ? 1 : 0);
     if (take) {
       K.x[pos] = G.sx[p];
       K.y[pos] = G.sy[p];
       K.z[pos] = G.sz[p];
       K.p[pos] = p;
+      K.kb[pos] = (unsigned char)k;
     }
     off += __popcll(__ballot(take));
   });
   __syncthreads();
-  // sort by (distance^2 to v, slot): each lane ranks its entries against all
-  double ex[4], ey[4], ez[4], ek[4];
-  int ep[4], rk[4];
+  // counting sort by bucket: position = bucket start + earlier entries of the bucket
+  double ex[4], ey[4], ez[4];
+  int ep[4], ek[4];
 #pragma unroll
   for (int h = 0; h < 4; h++) {
     const int t = l + 64 * h;
-    ex[h] = ey[h] = ez[h] = 0.0; ek[h] = 0.0; ep[h] = 0; rk[h] = 0;
+    ex[h] = ey[h] = ez[h] = 0.0; ep[h] = 0; ek[h] = 0;
     if (t < off) {
-      ex[h] = K.x[t]; ey[h] = K.y[t]; ez[h] = K.z[t]; ep[h] = K.p[t];
-      const double ax = ex[h] - vx, ay = ey[h] - vy, az = ez[h] - vz;
-      ek[h] = ax * ax + ay * ay + az * az;
-      scratch[t] = ek[h];
+      ex[h] = K.x[t]; ey[h] = K.y[t]; ez[h] = K.z[t]; ep[h] = K.p[t]; ek[h] = K.kb[t];
+      atomicOr(&bits[ek[h] * 4 + h], 1ull << l);
     }
   }
   __syncthreads();
-  for (int o = 0; o < off; o++) {
-    const double ko = scratch[o];
+  int rk[4];
 #pragma unroll
-    for (int h = 0; h < 4; h++) rk[h] += (ko < ek[h] || (ko == ek[h] && o < l + 64 * h)) ? 1 : 0;
+  for (int h = 0; h < 4; h++) {
+    rk[h] = 0;
+    if (l + 64 * h < off) {
+      int r0 = hist[ek[h]];
+      for (int w = 0; w < h; w++) r0 += __popcll(bits[ek[h] * 4 + w]);
+      rk[h] = r0 + __popcll(bits[ek[h] * 4 + h] & low_mask_lt(l));
+    }
   }
   __syncthreads();
 #pragma unroll
   for (int h = 0; h < 4; h++) {
     if (l + 64 * h < off) {
       K.x[rk[h]] = ex[h]; K.y[rk[h]] = ey[h]; K.z[rk[h]] = ez[h]; K.p[rk[h]] = ep[h];
+      K.kb[rk[h]] = (unsigned char)ek[h];
     }
   }
   if (l == 0) {
     // every site within rc of v is held; the block test holds only when the
     // whole block was kept
     K.rc = select ? fmin(rcb, sqrt(keep2) * (1.0 - 1e-12)) : rcb;
+    K.step = step;
     K.vx = vx; K.vy = vy; K.vz = vz;
     K.cnt = off;
     K.b[0] = x0; K.b[1] = x1; K.b[2] = y0; K.b[3] = y1; K.b[4] = z0; K.b[5] = z1;
@@ -562,9 +585,10 @@ __device__ __forceinline__ int nn_cached(const SiteCache &K, const GridView &G, 
       if (bd < wit) return bk;  // witness
       const int u = base + gs;
       if (u >= n) break;
-      // entries are sorted by distance to v: stop once it exceeds |q - v| + d
-      const double ax = K.x[u] - K.vx, ay = K.y[u] - K.vy, az = K.z[u] - K.vz;
-      if (sqrt(ax * ax + ay * ay + az * az) > (dq + sqrt(bd)) * (1.0 + 1e-12)) break;
+      // entries from u on lie at least sqrt(kb[u] * step) from v: stop once
+      // that exceeds |q - v| + d
+      const double reach = (dq + sqrt(bd)) * (1.0 + 1e-12);
+      if ((double)K.kb[u] * K.step * (1.0 - 1e-12) > reach * reach) break;
     }
     const double rn = sqrt(bd);
     if ((dq + rn) * (1.0 + 1e-12) < K.rc) return bk;
