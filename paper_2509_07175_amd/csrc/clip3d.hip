@@ -313,7 +313,7 @@ __device__ int carve(WaveLds &S, const GridView &G, const CarveParams C, const S
   double q0 = 0, q1 = 0, q2 = 0;  // query point relative to v_i (per group for TEST)
   // crossing of [A, g] with B_ij (j = current candidate)
   auto bisector_point = [&]() {
-    n0 = G.sx[j] - X.vx; n1 = G.sy[j] - X.vy; n2 = G.sz[j] - X.vz;
+    n0 = GL(G.sx)[j] - X.vx; n1 = GL(G.sy)[j] - X.vy; n2 = GL(G.sz)[j] - X.vz;
     nc3 = 0.5 * (n0 * n0 + n1 * n1 + n2 * n2);
     const double e0 = g0 - A0, e1 = g1 - A1, e2 = g2 - A2;
     const double den = n0 * e0 + n1 * e1 + n2 * e2;
@@ -493,20 +493,20 @@ __device__ int carve(WaveLds &S, const GridView &G, const CarveParams C, const S
 // vertex, 6 bits per face (no indexed local arrays).
 __device__ __forceinline__ void tet_plane(const DomainView &D, const SiteCtx &X, int a, int f, double *pl,
                                           int &lab) {
-  const int *tv = &D.simp[(long long)a * 4];
+  const auto tv = &GL(D.simp)[(long long)a * 4];
   const unsigned loops = (1u | 2u << 2 | 3u << 4) | (0u | 3u << 2 | 2u << 4) << 6 |
                          (0u | 1u << 2 | 3u << 4) << 12 | (0u | 2u << 2 | 1u << 4) << 18;
   const unsigned lf = loops >> (6 * f);
-  const double *pA = &D.verts[3 * (long long)tv[lf & 3]];
-  const double *pB = &D.verts[3 * (long long)tv[(lf >> 2) & 3]];
-  const double *pC = &D.verts[3 * (long long)tv[(lf >> 4) & 3]];
+  const auto pA = &GL(D.verts)[3 * (long long)tv[lf & 3]];
+  const auto pB = &GL(D.verts)[3 * (long long)tv[(lf >> 2) & 3]];
+  const auto pC = &GL(D.verts)[3 * (long long)tv[(lf >> 4) & 3]];
   const double A0 = pA[0] - X.vx, A1 = pA[1] - X.vy, A2 = pA[2] - X.vz;
   const double ab0 = pB[0] - pA[0], ab1 = pB[1] - pA[1], ab2 = pB[2] - pA[2];
   const double ac0 = pC[0] - pA[0], ac1 = pC[1] - pA[1], ac2 = pC[2] - pA[2];
   const double n0 = ab1 * ac2 - ab2 * ac1, n1 = ab2 * ac0 - ab0 * ac2, n2 = ab0 * ac1 - ab1 * ac0;
   pl[0] = n0; pl[1] = n1; pl[2] = n2;
   pl[3] = n0 * A0 + n1 * A1 + n2 * A2;
-  const int b = D.adj[(long long)a * 4 + f];
+  const int b = GL(D.adj)[(long long)a * 4 + f];
   lab = b >= 0 ? -(b + 1) : VD_BND_BASE + f;
 }
 
@@ -526,7 +526,7 @@ __device__ void init_tet(WaveLds &S, const DomainView &D, const SiteCtx &X, int 
     S.cpl[l] = l == 0 ? pack3(1, 3, 2) : (l == 1 ? pack3(0, 2, 3) : (l == 2 ? pack3(0, 3, 1) : pack3(0, 1, 2)));
     S.cnb[l] = l == 0 ? pack3(2, 1, 3) : (l == 1 ? pack3(3, 0, 2) : (l == 2 ? pack3(1, 0, 3) : pack3(2, 0, 1)));
     S.cst[l] = tested ? 3 : 0;
-    const double *p = &D.verts[3 * (long long)D.simp[(long long)a * 4 + l]];
+    const auto p = &GL(D.verts)[3 * (long long)GL(D.simp)[(long long)a * 4 + l]];
     S.cy[l][0] = p[0] - X.vx; S.cy[l][1] = p[1] - X.vy; S.cy[l][2] = p[2] - X.vz;
   }
   __syncthreads();
@@ -604,7 +604,7 @@ __device__ void init_box(WaveLds &S, const SiteCtx &X, const double *lo, const d
   __syncthreads();
 }
 
-__device__ __forceinline__ int convert_label(const GridView &G, int lab) { return lab >= 0 ? G.perm[lab] : lab; }
+__device__ __forceinline__ int convert_label(const GridView &G, int lab) { return lab >= 0 ? GL(G.perm)[lab] : lab; }
 
 // Face moments of the bisector faces of the piece in LDS, for the adjoint:
 // for face x on B_ik, I0 = int y dA/d, I1 = int y y^T dA/d, I2 = int |y|^2 y dA/d
@@ -630,7 +630,7 @@ __device__ void face_moments(WaveLds &S, int nc, int npl, uint64_t fmask, const 
   const uint64_t pos = __ballot(mine);
   const int npos = __popcll(pos);
   const long long base = arena_take(S.ar, C, AR_FINT, npos);
-  if (l == 0 && pidx < C.cap_piece) { C.piece_fint_start[pidx] = base; C.piece_nfint[pidx] = npos; }
+  if (l == 0 && pidx < C.cap_piece) { GL(C.piece_fint_start)[pidx] = base; GL(C.piece_nfint)[pidx] = npos; }
   if (!mine) return;
   const int x = l;
   const double n0 = S.pn[x][0], n1 = S.pn[x][1], n2 = S.pn[x][2], cc = S.pn[x][3];
@@ -679,8 +679,8 @@ __device__ void face_moments(WaveLds &S, int nc, int npl, uint64_t fmask, const 
   const long long r = base + __popcll(pos & low_mask(l));
   if (r < C.cap_fint) {
     const double id = 1.0 / d;
-    for (int k = 0; k < 12; k++) C.fint[12 * r + k] = I[k] * id;
-    C.fint_lab[r] = G.perm[S.plab[x]];
+    for (int k = 0; k < 12; k++) GL(C.fint)[12 * r + k] = I[k] * id;
+    GL(C.fint_lab)[r] = GL(G.perm)[S.plab[x]];
   }
 }
 
@@ -688,7 +688,7 @@ __device__ void face_moments(WaveLds &S, int nc, int npl, uint64_t fmask, const 
 // global buffer (cells that meet more simplices than the LDS queue holds).
 // Out of line: the common case never touches them.
 __device__ __forceinline__ int spill_get(const CellsDev &C, int i) {
-  return C.tq_spill[(long long)blockIdx.x * VD_Q_SPILL + i - VD_Q_MAX];
+  return GL(C.tq_spill)[(long long)blockIdx.x * VD_Q_SPILL + i - VD_Q_MAX];
 }
 __device__ __forceinline__ bool spill_has(const CellsDev &C, int b, int nt) {
   const int*q = C.tq_spill + (long long)blockIdx.x * VD_Q_SPILL - VD_Q_MAX;
@@ -697,7 +697,7 @@ __device__ __forceinline__ bool spill_has(const CellsDev &C, int b, int nt) {
   return have;
 }
 __device__ __forceinline__ void spill_put(const CellsDev &C, int i, int b) {
-  if (vd_lane() == 0) C.tq_spill[(long long)blockIdx.x * VD_Q_SPILL + i - VD_Q_MAX] = b;
+  if (vd_lane() == 0) GL(C.tq_spill)[(long long)blockIdx.x * VD_Q_SPILL + i - VD_Q_MAX] = b;
 }
 
 // ---------------------------------------------------------------------------
@@ -715,11 +715,11 @@ __device__ __forceinline__ void spill_put(const CellsDev &C, int i, int b) {
 __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, const CellsDev &C, int si) {
   const int l = vd_lane();
   SiteCtx X;
-  X.vx = G.sx[si]; X.vy = G.sy[si]; X.vz = G.sz[si];
-  X.delta = G.delta[si];
+  X.vx = GL(G.sx)[si]; X.vy = GL(G.sy)[si]; X.vz = GL(G.sz)[si];
+  X.delta = GL(G.delta)[si];
   X.si = si;
-  const int orig = G.perm[si];
-  const int seed = C.seed[si];
+  const int orig = GL(G.perm)[si];
+  const int seed = GL(C.seed)[si];
   const CarveParams P = {C.improved, C.straddle, C.max_iters};
   Stats st;
   int err = 0;  // 2 capacity, 3 degenerate
@@ -835,31 +835,31 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
     if (C.want_grad) face_moments(S, nc, npl, fmask, C, G, pidx);
     if (pidx < C.cap_piece) {
       if (l == 0) {
-        C.piece_site[pidx] = orig;
-        C.piece_simplex[pidx] = a;
-        C.piece_nface[pidx] = nface;
-        C.piece_nvert[pidx] = nc;
-        C.piece_mass[pidx] = pv;
-        C.piece_mom[3 * pidx + 0] = pmx + pv * X.vx;
-        C.piece_mom[3 * pidx + 1] = pmy + pv * X.vy;
-        C.piece_mom[3 * pidx + 2] = pmz + pv * X.vz;
-        C.piece_energy[pidx] = pe;
-        C.piece_fstart[pidx] = C.emit ? fo : -1;
-        C.piece_vstart[pidx] = C.emit ? vo : -1;
+        GL(C.piece_site)[pidx] = orig;
+        GL(C.piece_simplex)[pidx] = a;
+        GL(C.piece_nface)[pidx] = nface;
+        GL(C.piece_nvert)[pidx] = nc;
+        GL(C.piece_mass)[pidx] = pv;
+        GL(C.piece_mom)[3 * pidx + 0] = pmx + pv * X.vx;
+        GL(C.piece_mom)[3 * pidx + 1] = pmy + pv * X.vy;
+        GL(C.piece_mom)[3 * pidx + 2] = pmz + pv * X.vz;
+        GL(C.piece_energy)[pidx] = pe;
+        GL(C.piece_fstart)[pidx] = C.emit ? fo : -1;
+        GL(C.piece_vstart)[pidx] = C.emit ? vo : -1;
         S.ar.pieces++;
         if (C.emit) { S.ar.faces += nface; S.ar.verts += nc; }
       }
       if (C.emit && fo + nface <= C.cap_face && vo + nc <= C.cap_vert) {
         if (l < npl && ((fmask >> l) & 1ull))
-          C.face_label[fo + __popcll(fmask & low_mask(l))] = convert_label(G, S.plab[l]);
+          GL(C.face_label)[fo + __popcll(fmask & low_mask(l))] = convert_label(G, S.plab[l]);
         for (int h = 0; h < 2; h++) {
           const int s = l + 64 * h;
           if (s < nc) {
             const int pl = S.cpl[s];
-            C.vert_xyz[3 * (vo + s) + 0] = S.cy[s][0] + X.vx;
-            C.vert_xyz[3 * (vo + s) + 1] = S.cy[s][1] + X.vy;
-            C.vert_xyz[3 * (vo + s) + 2] = S.cy[s][2] + X.vz;
-            for (int e = 0; e < 3; e++) C.vert_label[3 * (vo + s) + e] = convert_label(G, S.plab[p8(pl, e)]);
+            GL(C.vert_xyz)[3 * (vo + s) + 0] = S.cy[s][0] + X.vx;
+            GL(C.vert_xyz)[3 * (vo + s) + 1] = S.cy[s][1] + X.vy;
+            GL(C.vert_xyz)[3 * (vo + s) + 2] = S.cy[s][2] + X.vz;
+            for (int e = 0; e < 3; e++) GL(C.vert_label)[3 * (vo + s) + e] = convert_label(G, S.plab[p8(pl, e)]);
           }
         }
       }
@@ -903,14 +903,14 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
   // ---- per-site results ----
   const long long ns0 = arena_take(S.ar, C, AR_NBR, nnb);
   if (l == 0) {
-    C.mass[orig] = Mv;
-    C.mom[3 * (long long)orig + 0] = Mx + Mv * X.vx;
-    C.mom[3 * (long long)orig + 1] = My + Mv * X.vy;
-    C.mom[3 * (long long)orig + 2] = Mz + Mv * X.vz;
-    C.energy[orig] = Me;
-    C.pcount[orig] = npieces;
-    C.ncount[orig] = nnb;
-    C.nstart[orig] = ns0;
+    GL(C.mass)[orig] = Mv;
+    GL(C.mom)[3 * (long long)orig + 0] = Mx + Mv * X.vx;
+    GL(C.mom)[3 * (long long)orig + 1] = My + Mv * X.vy;
+    GL(C.mom)[3 * (long long)orig + 2] = Mz + Mv * X.vz;
+    GL(C.energy)[orig] = Me;
+    GL(C.pcount)[orig] = npieces;
+    GL(C.ncount)[orig] = nnb;
+    GL(C.nstart)[orig] = ns0;
     S.ar.nbrs += nnb;
     S.ar.queries += st.queries;
     S.ar.cands += st.cands;
@@ -926,10 +926,10 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
   if (ns0 + nnb <= C.cap_nbr) {
     // neighbours in ascending caller index: rank sort
     for (int e = l; e < nnb; e += 64) {
-      const int me = G.perm[S.nbl[e]];
+      const int me = GL(G.perm)[S.nbl[e]];
       int rk = 0;
-      for (int o = 0; o < nnb; o++) rk += (G.perm[S.nbl[o]] < me) ? 1 : 0;
-      C.nbr_arena[ns0 + rk] = me;
+      for (int o = 0; o < nnb; o++) rk += (GL(G.perm)[S.nbl[o]] < me) ? 1 : 0;
+      GL(C.nbr_arena)[ns0 + rk] = me;
     }
   }
   __syncthreads();

@@ -41,7 +41,8 @@ __device__ __forceinline__ long long arena_take(WaveArena &A, const CellsDev &C,
     long long cur = A.cur[r];
     if (cur + k > A.end[r]) {
       const long long t = k > C.chunk[r] ? k : C.chunk[r];
-      cur = (long long)atomicAdd(&C.cnt[r], (unsigned long long)t);
+      cur = (long long)__hip_atomic_fetch_add(GL(C.cnt) + r, (unsigned long long)t, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
       A.end[r] = cur + t;
     }
     A.cur[r] = cur + k;
@@ -60,7 +61,7 @@ __device__ __forceinline__ int queue_next(WaveArena &A, const CellsDev &C, long 
       const int k = (x + A.qi) % VD_QUEUES;
       const long long end = (k + 1) * q8 < n ? (k + 1) * q8 : n;
       if (k * q8 >= end) continue;
-      const int v = atomicAdd(&C.queue[k * VD_QSTRIDE], 1);
+      const int v = __hip_atomic_fetch_add(GL(C.queue) + k * VD_QSTRIDE, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (v < end) { r = v; break; }
     }
   }
@@ -72,7 +73,7 @@ __device__ __forceinline__ int queue_next(WaveArena &A, const CellsDev &C, long 
 __device__ __forceinline__ void arena_close(WaveArena &A, const CellsDev &C) {
   const int l = vd_lane();
   const long long a = A.cur[AR_PIECE], b = A.end[AR_PIECE] < C.cap_piece ? A.end[AR_PIECE] : C.cap_piece;
-  for (long long p = a + l; p < b; p += 64) C.piece_site[p] = -1;
+  for (long long p = a + l; p < b; p += 64) GL(C.piece_site)[p] = -1;
   if (l == 0) {
     atomicAdd(&C.cnt[CNT_QUERIES], A.queries);
     atomicAdd(&C.cnt[CNT_CANDS], A.cands);

@@ -6,7 +6,16 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #define VD_WAVE 64
+
+// The views' arrays are device allocations: device code reads and writes them
+// through global (address space 1) pointers, so the accesses are global_*
+// instructions.  Through the generic pointers of the view structs they would
+// be flat_* accesses, which also count against the LDS wait counter: every
+// wait for an LDS result would then wait for outstanding memory loads too.
+#define GL(p) ((__attribute__((address_space(1))) std::remove_pointer_t<decltype(p)> *)(p))
 #define VD_BND_BASE (-2147483647 - 1)
 
 // Device view of the nearest-site grid (Sec. 6.2).  Sites are stored in cell
@@ -204,8 +213,8 @@ __device__ __forceinline__ void scan_box(const GridView &G, int gs, int x0, int 
     if (r < R) {
       const int yy = y0 + r % ny, zz = z0 + r / ny;
       const int c0 = x0 + G.g[0] * (yy + G.g[1] * zz);
-      st = G.cstart[c0];
-      cnt = G.cstart[c0 + nx] - st;
+      st = GL(G.cstart)[c0];
+      cnt = GL(G.cstart)[c0 + nx] - st;
     }
     const int inc = gs == 64 ? wave_incl_scan(cnt) : row_incl_scan(cnt);
     const int excl = inc - cnt;
@@ -224,7 +233,7 @@ __device__ __forceinline__ void scan_box(const GridView &G, int gs, int x0, int 
       const int rex = __shfl(excl, rr, gs);
       if (t < total) {
         const int p = rst + (t - rex);
-        const double dx = qx - G.sx[p], dy = qy - G.sy[p], dz = qz - G.sz[p];
+        const double dx = qx - GL(G.sx)[p], dy = qy - GL(G.sy)[p], dz = qz - GL(G.sz)[p];
         const double d = dx * dx + dy * dy + dz * dz;
         if (d < bd || (d == bd && p < bk)) { bd = d; bk = p; }
       }
@@ -239,8 +248,8 @@ __device__ __forceinline__ void group_argmin(double &d, int &k, int gs) {
 
 __device__ __forceinline__ int nn_query(const GridView &G, int gs, double qx, double qy, double qz, double r2,
                                         int k0, long long &ncand) {
-  const double lox = G.geom[0], loy = G.geom[1], loz = G.geom[2];
-  const double ihx = G.geom[6], ihy = G.geom[7], ihz = G.geom[8];
+  const double lox = GL(G.geom)[0], loy = GL(G.geom)[1], loz = GL(G.geom)[2];
+  const double ihx = GL(G.geom)[6], ihy = GL(G.geom)[7], ihz = GL(G.geom)[8];
   const int gx = G.g[0], gy = G.g[1], gz = G.g[2];
   double bd = r2;
   int bk = k0;
@@ -274,9 +283,9 @@ __device__ __forceinline__ int nn_query(const GridView &G, int gs, double qx, do
 // Rings of cells around q's cell until the ring distance exceeds the best.
 __device__ __forceinline__ int nn_thread(const GridView &G, double qx, double qy, double qz, int excl,
                                          double &out_d2) {
-  const double lox = G.geom[0], loy = G.geom[1], loz = G.geom[2];
-  const double hx = G.geom[3], hy = G.geom[4], hz = G.geom[5];
-  const double ihx = G.geom[6], ihy = G.geom[7], ihz = G.geom[8];
+  const double lox = GL(G.geom)[0], loy = GL(G.geom)[1], loz = GL(G.geom)[2];
+  const double hx = GL(G.geom)[3], hy = GL(G.geom)[4], hz = GL(G.geom)[5];
+  const double ihx = GL(G.geom)[6], ihy = GL(G.geom)[7], ihz = GL(G.geom)[8];
   const int gx = G.g[0], gy = G.g[1], gz = G.g[2];
   const int cx = cell_coord(qx, lox, ihx, gx), cy = cell_coord(qy, loy, ihy, gy),
             cz = cell_coord(qz, loz, ihz, gz);
@@ -297,9 +306,9 @@ __device__ __forceinline__ int nn_thread(const GridView &G, double qx, double qy
           if (x < 0 || x >= gx) continue;
           any = true;
           const int c = x + gx * (y + gy * z);
-          for (int p = G.cstart[c]; p < G.cstart[c + 1]; p++) {
+          for (int p = GL(G.cstart)[c]; p < GL(G.cstart)[c + 1]; p++) {
             if (p == excl) continue;
-            const double dx = qx - G.sx[p], dy = qy - G.sy[p], dz = qz - G.sz[p];
+            const double dx = qx - GL(G.sx)[p], dy = qy - GL(G.sy)[p], dz = qz - GL(G.sz)[p];
             const double d = dx * dx + dy * dy + dz * dz;
             if (d < bd || (d == bd && p < bk)) { bd = d; bk = p; }
           }
@@ -350,7 +359,7 @@ __device__ __forceinline__ int block_count(const GridView &G, int x0, int x1, in
   int c = 0;
   for (int r = l; r < R; r += 64) {
     const int c0 = x0 + G.g[0] * ((y0 + r % ny) + G.g[1] * (z0 + r / ny));
-    c += G.cstart[c0 + nx] - G.cstart[c0];
+    c += GL(G.cstart)[c0 + nx] - GL(G.cstart)[c0];
   }
   return wave_isum(c);
 }
@@ -370,8 +379,8 @@ __device__ __forceinline__ void for_block_sites(const GridView &G, int x0, int x
     int st = 0, cnt = 0;
     if (rr < R) {
       const int c0 = x0 + G.g[0] * ((y0 + rr % ny) + G.g[1] * (z0 + rr / ny));
-      st = G.cstart[c0];
-      cnt = G.cstart[c0 + nx] - st;
+      st = GL(G.cstart)[c0];
+      cnt = GL(G.cstart)[c0 + nx] - st;
     }
     const int inc = wave_incl_scan(cnt);
     const int excl = inc - cnt;
@@ -401,9 +410,9 @@ __device__ __forceinline__ void for_block_sites(const GridView &G, int x0, int x
 __device__ void cache_fill(SiteCache &K, const GridView &G, double vx, double vy, double vz, double *scratch) {
   const int l = vd_lane();
   const int gx = G.g[0], gy = G.g[1], gz = G.g[2];
-  const int cx = cell_coord(vx, G.geom[0], G.geom[6], gx);
-  const int cy = cell_coord(vy, G.geom[1], G.geom[7], gy);
-  const int cz = cell_coord(vz, G.geom[2], G.geom[8], gz);
+  const int cx = cell_coord(vx, GL(G.geom)[0], GL(G.geom)[6], gx);
+  const int cy = cell_coord(vy, GL(G.geom)[1], GL(G.geom)[7], gy);
+  const int cz = cell_coord(vz, GL(G.geom)[2], GL(G.geom)[8], gz);
   auto cells = [&](int r) {
     return (long long)(min(cx + r, gx - 1) - max(cx - r, 0) + 1) * (min(cy + r, gy - 1) - max(cy - r, 0) + 1) *
            (min(cz + r, gz - 1) - max(cz - r, 0) + 1);
@@ -431,7 +440,7 @@ __device__ void cache_fill(SiteCache &K, const GridView &G, double vx, double vy
   // less a margin for the rounding of cell assignment
   double rcb = 1e300;
   {
-    const double *lo = G.geom, *h = G.geom + 3;
+    const auto lo = GL(G.geom), h = GL(G.geom) + 3;
     if (x0 > 0) rcb = fmin(rcb, vx - (lo[0] + x0 * h[0]));
     if (x1 < gx - 1) rcb = fmin(rcb, lo[0] + (x1 + 1) * h[0] - vx);
     if (y0 > 0) rcb = fmin(rcb, vy - (lo[1] + y0 * h[1]));
@@ -442,7 +451,7 @@ __device__ void cache_fill(SiteCache &K, const GridView &G, double vx, double vy
     if (rcb < 0.0) rcb = 0.0;
   }
   auto d2of = [&](int p) {
-    const double ax = G.sx[p] - vx, ay = G.sy[p] - vy, az = G.sz[p] - vz;
+    const double ax = GL(G.sx)[p] - vx, ay = GL(G.sy)[p] - vy, az = GL(G.sz)[p] - vz;
     return ax * ax + ay * ay + az * az;
   };
   // buckets of squared distance: NB - 1 of width step over [0, rc2), the last
@@ -450,7 +459,7 @@ __device__ void cache_fill(SiteCache &K, const GridView &G, double vx, double vy
   // go, else (and for sides open at the grid's edge) a ball holding the block.
   constexpr int NB = 64;
   const bool select = c > VD_CACHE;
-  const double hm = fmax(G.geom[3], fmax(G.geom[4], G.geom[5]));
+  const double hm = fmax(GL(G.geom)[3], fmax(GL(G.geom)[4], GL(G.geom)[5]));
   const double rcw2 = 3.0 * ((r + 1) * hm) * ((r + 1) * hm);
   const double rc2 = select ? fmin(rcb * rcb, rcw2) : rcw2;
   const double step = rc2 / (NB - 1);
@@ -489,9 +498,9 @@ __device__ void cache_fill(SiteCache &K, const GridView &G, double vx, double vy
     const bool take = k < B;
     const int pos = off + wave_incl_scan(take ? 1 : 0) - (take ? 1 : 0);
     if (take) {
-      K.x[pos] = G.sx[p];
-      K.y[pos] = G.sy[p];
-      K.z[pos] = G.sz[p];
+      K.x[pos] = GL(G.sx)[p];
+      K.y[pos] = GL(G.sy)[p];
+      K.z[pos] = GL(G.sz)[p];
       K.p[pos] = p;
       K.kb[pos] = (unsigned char)k;
     }
@@ -553,7 +562,7 @@ __device__ void cache_fill(SiteCache &K, const GridView &G, double vx, double vy
 // Distances are computed by one formula everywhere, so "strictly nearer"
 // holds for the nearest site too.
 __device__ __forceinline__ double sq_dist(const GridView &G, int e, double qx, double qy, double qz) {
-  const double dx = qx - G.sx[e], dy = qy - G.sy[e], dz = qz - G.sz[e];
+  const double dx = qx - GL(G.sx)[e], dy = qy - GL(G.sy)[e], dz = qz - GL(G.sz)[e];
   return dx * dx + dy * dy + dz * dz;
 }
 
@@ -598,9 +607,9 @@ __device__ __forceinline__ int nn_cached(const SiteCache &K, const GridView &G, 
     {
       const double r = rn * (1.0 + 1e-12);
       const int gx = G.g[0], gy = G.g[1], gz = G.g[2];
-      if (cell_coord(qx - r, G.geom[0], G.geom[6], gx) >= K.b[0] && cell_coord(qx + r, G.geom[0], G.geom[6], gx) <= K.b[1] &&
-          cell_coord(qy - r, G.geom[1], G.geom[7], gy) >= K.b[2] && cell_coord(qy + r, G.geom[1], G.geom[7], gy) <= K.b[3] &&
-          cell_coord(qz - r, G.geom[2], G.geom[8], gz) >= K.b[4] && cell_coord(qz + r, G.geom[2], G.geom[8], gz) <= K.b[5])
+      if (cell_coord(qx - r, GL(G.geom)[0], GL(G.geom)[6], gx) >= K.b[0] && cell_coord(qx + r, GL(G.geom)[0], GL(G.geom)[6], gx) <= K.b[1] &&
+          cell_coord(qy - r, GL(G.geom)[1], GL(G.geom)[7], gy) >= K.b[2] && cell_coord(qy + r, GL(G.geom)[1], GL(G.geom)[7], gy) <= K.b[3] &&
+          cell_coord(qz - r, GL(G.geom)[2], GL(G.geom)[8], gz) >= K.b[4] && cell_coord(qz + r, GL(G.geom)[2], GL(G.geom)[8], gz) <= K.b[5])
         return bk;
     }
     r2 = bd;
