@@ -58,9 +58,9 @@ __device__ __forceinline__ void solve_s(const TriLds &S, int a, int b, double *y
 // P <- T_a relative to site v (slot 0 = supporting plane)
 __device__ void init_tri(TriLds &S, const DomainView &D, int a, double vx, double vy, double vz) {
   const int l = vd_lane();
-  const int *tv = &D.simp[(long long)a * 3];
-  const double *p0 = &D.verts[3 * (long long)tv[0]], *p1 = &D.verts[3 * (long long)tv[1]],
-               *p2 = &D.verts[3 * (long long)tv[2]];
+  const auto tv = &GL(D.simp)[(long long)a * 3];
+  const auto p0 = &GL(D.verts)[3 * (long long)tv[0]], p1 = &GL(D.verts)[3 * (long long)tv[1]],
+               p2 = &GL(D.verts)[3 * (long long)tv[2]];
   const double e1[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
   const double e2[3] = {p2[0] - p0[0], p2[1] - p0[1], p2[2] - p0[2]};
   const double N[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
@@ -71,16 +71,16 @@ __device__ void init_tri(TriLds &S, const DomainView &D, int a, double vx, doubl
   }
   if (l >= 1 && l <= 3) {
     const int e = l - 1;  // edge opposite vertex e: from q_{e+1} to q_{e+2}
-    const double *A = &D.verts[3 * (long long)tv[(e + 1) % 3]], *B = &D.verts[3 * (long long)tv[(e + 2) % 3]];
+    const auto A = &GL(D.verts)[3 * (long long)tv[(e + 1) % 3]], B = &GL(D.verts)[3 * (long long)tv[(e + 2) % 3]];
     const double d[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
     const double n[3] = {d[1] * N[2] - d[2] * N[1], d[2] * N[0] - d[0] * N[2], d[0] * N[1] - d[1] * N[0]};
     S.pn[l][0] = n[0]; S.pn[l][1] = n[1]; S.pn[l][2] = n[2];
     S.pn[l][3] = n[0] * (A[0] - vx) + n[1] * (A[1] - vy) + n[2] * (A[2] - vz);
-    const int b = D.adj[(long long)a * 3 + e];
+    const int b = GL(D.adj)[(long long)a * 3 + e];
     S.plab[l] = b >= 0 ? -(b + 1) : VD_BND_BASE + e;
   }
   if (l < 3) {
-    const double *p = &D.verts[3 * (long long)tv[l]];
+    const auto p = &GL(D.verts)[3 * (long long)tv[l]];
     S.vy[l][0] = p[0] - vx; S.vy[l][1] = p[1] - vy; S.vy[l][2] = p[2] - vz;
     S.ve[l] = 1 + (l + 2) % 3;  // edge from q_l to q_{l+1} is opposite q_{l+2}
     S.vst[l] = 0;
@@ -182,7 +182,7 @@ __device__ int carve_s(TriLds &S, const GridView &G, const SParams C, int si, do
   double A0 = 0, A1 = 0, A2 = 0, g0 = 0, g1 = 0, g2 = 0, u0 = 0, u1 = 0, u2 = 0, L = 0;
   double n0 = 0, n1 = 0, n2 = 0, nc3 = 0, q0 = 0, q1 = 0, q2 = 0;
   auto bisector_point = [&]() {
-    n0 = G.sx[j] - vx; n1 = G.sy[j] - vy; n2 = G.sz[j] - vz;
+    n0 = GL(G.sx)[j] - vx; n1 = GL(G.sy)[j] - vy; n2 = GL(G.sz)[j] - vz;
     nc3 = 0.5 * (n0 * n0 + n1 * n1 + n2 * n2);
     const double e0 = g0 - A0, e1 = g1 - A1, e2 = g2 - A2;
     const double den = n0 * e0 + n1 * e1 + n2 * e2;
@@ -312,7 +312,7 @@ __device__ int carve_s(TriLds &S, const GridView &G, const SParams C, int si, do
   return 3;
 }
 
-__device__ __forceinline__ int conv(const GridView &G, int lab) { return lab >= 0 ? G.perm[lab] : lab; }
+__device__ __forceinline__ int conv(const GridView &G, int lab) { return lab >= 0 ? GL(G.perm)[lab] : lab; }
 
 __device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, const CellsDev &C, int a) {
   const int l = vd_lane();
@@ -322,9 +322,9 @@ __device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, c
   // seed: nearest site of the centroid (Alg. 4)
   int nsq = 0, head = 0;
   {
-    const int *tv = &D.simp[(long long)a * 3];
-    const double *p0 = &D.verts[3 * (long long)tv[0]], *p1 = &D.verts[3 * (long long)tv[1]],
-                 *p2 = &D.verts[3 * (long long)tv[2]];
+    const auto tv = &GL(D.simp)[(long long)a * 3];
+    const auto p0 = &GL(D.verts)[3 * (long long)tv[0]], p1 = &GL(D.verts)[3 * (long long)tv[1]],
+                 p2 = &GL(D.verts)[3 * (long long)tv[2]];
     const double cx = (p0[0] + p1[0] + p2[0]) / 3.0, cy = (p0[1] + p1[1] + p2[1]) / 3.0,
                  cz = (p0[2] + p1[2] + p2[2]) / 3.0;
     const int k = uni(nn_query(G, 64, cx, cy, cz, 1e300, -1, ss.cands));
@@ -339,7 +339,7 @@ __device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, c
   __syncthreads();
   while (head < nsq && !err) {
     const int si = S.sq[head++];
-    const double vx = G.sx[si], vy = G.sy[si], vz = G.sz[si], delta = G.delta[si];
+    const double vx = GL(G.sx)[si], vy = GL(G.sy)[si], vz = GL(G.sz)[si], delta = GL(G.delta)[si];
     init_tri(S, D, a, vx, vy, vz);
     int npl = 4, nv = 3;
     const int rc = carve_s(S, G, P, si, vx, vy, vz, delta, npl, nv, ss);
@@ -367,11 +367,11 @@ __device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, c
     }
     pa = wave_sum(pa); pmx = wave_sum(pmx); pmy = wave_sum(pmy); pmz = wave_sum(pmz); pe = wave_sum(pe);
     if (!(pa > 0.0)) continue;
-    const int orig = G.perm[si];
+    const int orig = GL(G.perm)[si];
     const long long pidx = arena_take(S.ar, C, AR_PIECE, 1);
     const long long fo = arena_take(S.ar, C, AR_FACE, nv);
     const long long vo = arena_take(S.ar, C, AR_VERT, nv);
-    if (l == 0) atomicAdd(&C.pcount[orig], 1);
+    if (l == 0) __hip_atomic_fetch_add(GL(C.pcount) + orig, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (C.want_grad) {
       // segment moments of the bisector edges: a point of the edge moves in
       // the plane of T_a with speed (x - v_i).dv / (d s), s = |n - (n.N)N|
@@ -381,11 +381,11 @@ __device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, c
       const uint64_t pos = __ballot(lab >= 0);
       const int npos = __popcll(pos);
       const long long base = arena_take(S.ar, C, AR_FINT, npos);
-      if (l == 0 && pidx < C.cap_piece) { C.piece_fint_start[pidx] = base; C.piece_nfint[pidx] = npos; }
+      if (l == 0 && pidx < C.cap_piece) { GL(C.piece_fint_start)[pidx] = base; GL(C.piece_nfint)[pidx] = npos; }
       const long long r = base + __popcll(pos & lowm(l));
       if (lab >= 0 && r < C.cap_fint) {
         const int t2 = (l + 1) % nv;
-        const double n0 = G.sx[lab] - vx, n1 = G.sy[lab] - vy, n2 = G.sz[lab] - vz;
+        const double n0 = GL(G.sx)[lab] - vx, n1 = GL(G.sy)[lab] - vy, n2 = GL(G.sz)[lab] - vz;
         const double d = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
         const double h0 = n0 / d, h1 = n1 / d, h2 = n2 / d;
         const double M0 = N0 * inrm, M1 = N1 * inrm, M2 = N2 * inrm;
@@ -409,36 +409,36 @@ __device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, c
           I[9] += w * yy * y0; I[10] += w * yy * y1; I[11] += w * yy * y2;
         }
         const double sc = 1.0 / (d * sfac);
-        for (int k = 0; k < 12; k++) C.fint[12 * r + k] = I[k] * sc;
-        C.fint_lab[r] = G.perm[lab];
+        for (int k = 0; k < 12; k++) GL(C.fint)[12 * r + k] = I[k] * sc;
+        GL(C.fint_lab)[r] = GL(G.perm)[lab];
       }
     }
     if (pidx < C.cap_piece) {
       if (l == 0) {
-        C.piece_site[pidx] = orig;
-        C.piece_simplex[pidx] = a;
-        C.piece_nface[pidx] = nv;
-        C.piece_nvert[pidx] = nv;
-        C.piece_mass[pidx] = pa;
-        C.piece_mom[3 * pidx + 0] = pmx + pa * vx;
-        C.piece_mom[3 * pidx + 1] = pmy + pa * vy;
-        C.piece_mom[3 * pidx + 2] = pmz + pa * vz;
-        C.piece_energy[pidx] = pe;
-        C.piece_fstart[pidx] = fo;
-        C.piece_vstart[pidx] = vo;
+        GL(C.piece_site)[pidx] = orig;
+        GL(C.piece_simplex)[pidx] = a;
+        GL(C.piece_nface)[pidx] = nv;
+        GL(C.piece_nvert)[pidx] = nv;
+        GL(C.piece_mass)[pidx] = pa;
+        GL(C.piece_mom)[3 * pidx + 0] = pmx + pa * vx;
+        GL(C.piece_mom)[3 * pidx + 1] = pmy + pa * vy;
+        GL(C.piece_mom)[3 * pidx + 2] = pmz + pa * vz;
+        GL(C.piece_energy)[pidx] = pe;
+        GL(C.piece_fstart)[pidx] = fo;
+        GL(C.piece_vstart)[pidx] = vo;
         S.ar.pieces++;
         S.ar.faces += nv;
         S.ar.verts += nv;
       }
       if (fo + nv <= C.cap_face && vo + nv <= C.cap_vert && l < nv) {
         const int prv = (l + nv - 1) % nv;
-        C.face_label[fo + l] = conv(G, S.plab[S.ve[l]]);
-        C.vert_xyz[3 * (vo + l) + 0] = S.vy[l][0] + vx;
-        C.vert_xyz[3 * (vo + l) + 1] = S.vy[l][1] + vy;
-        C.vert_xyz[3 * (vo + l) + 2] = S.vy[l][2] + vz;
-        C.vert_label[3 * (vo + l) + 0] = conv(G, S.plab[S.ve[prv]]);
-        C.vert_label[3 * (vo + l) + 1] = conv(G, S.plab[S.ve[l]]);
-        C.vert_label[3 * (vo + l) + 2] = 2147483647;
+        GL(C.face_label)[fo + l] = conv(G, S.plab[S.ve[l]]);
+        GL(C.vert_xyz)[3 * (vo + l) + 0] = S.vy[l][0] + vx;
+        GL(C.vert_xyz)[3 * (vo + l) + 1] = S.vy[l][1] + vy;
+        GL(C.vert_xyz)[3 * (vo + l) + 2] = S.vy[l][2] + vz;
+        GL(C.vert_label)[3 * (vo + l) + 0] = conv(G, S.plab[S.ve[prv]]);
+        GL(C.vert_label)[3 * (vo + l) + 1] = conv(G, S.plab[S.ve[l]]);
+        GL(C.vert_label)[3 * (vo + l) + 2] = 2147483647;
       }
     }
     // ---- propagate over positive edge flags (Alg. 4) ----
@@ -498,9 +498,9 @@ __device__ __forceinline__ int site_neighbours(const CellsDev &C, const long lon
   int cnt = 0;
   for (long long q = poff[i]; q < poff[i + 1]; q++) {
     const int p = pid[q];
-    const long long f0 = C.piece_fstart[p];
-    for (int f = 0; f < C.piece_nface[p]; f++) {
-      const int lab = C.face_label[f0 + f];
+    const long long f0 = GL(C.piece_fstart)[p];
+    for (int f = 0; f < GL(C.piece_nface)[p]; f++) {
+      const int lab = GL(C.face_label)[f0 + f];
       if (lab < 0) continue;
       int k = 0;
       while (k < cnt && nb[k] < lab) k++;
@@ -522,20 +522,20 @@ __global__ void __launch_bounds__(kB) site_reduce(long long n, const long long *
   double m = 0, mx = 0, my = 0, mz = 0, e = 0;
   for (long long q = poff[i]; q < poff[i + 1]; q++) {
     const int p = pid[q];
-    m += C.piece_mass[p];
-    mx += C.piece_mom[3 * (long long)p + 0];
-    my += C.piece_mom[3 * (long long)p + 1];
-    mz += C.piece_mom[3 * (long long)p + 2];
-    e += C.piece_energy[p];
+    m += GL(C.piece_mass)[p];
+    mx += GL(C.piece_mom)[3 * (long long)p + 0];
+    my += GL(C.piece_mom)[3 * (long long)p + 1];
+    mz += GL(C.piece_mom)[3 * (long long)p + 2];
+    e += GL(C.piece_energy)[p];
   }
-  C.mass[i] = m;
-  C.mom[3 * i + 0] = mx;
-  C.mom[3 * i + 1] = my;
-  C.mom[3 * i + 2] = mz;
-  C.energy[i] = e;
+  GL(C.mass)[i] = m;
+  GL(C.mom)[3 * i + 0] = mx;
+  GL(C.mom)[3 * i + 1] = my;
+  GL(C.mom)[3 * i + 2] = mz;
+  GL(C.energy)[i] = e;
   int nb[kNbLocal];
   int overflow = 0;
-  C.ncount[i] = site_neighbours(C, poff, pid, i, nb, overflow);
+  GL(C.ncount)[i] = site_neighbours(C, poff, pid, i, nb, overflow);
   if (overflow) {
     atomicAdd(&C.cnt[CNT_ERR_CAP], 1ull);
     atomicMin((int *)&C.cnt[CNT_BAD_SITE], (int)i);

@@ -155,13 +155,21 @@ __device__ __forceinline__ uint64_t wave_or64(uint64_t v) {
   return ((uint64_t)H << 32) | L;
 }
 
+// (d, k) <- the lexicographic minimum of (d, k) and (od, ok).  Bitwise, not
+// short-circuit, logic and selects: no branch, no exec-mask juggling.
+__device__ __forceinline__ void lexmin(double &d, int &k, double od, int ok) {
+  const bool take = (od < d) | ((od == d) & (ok < k));
+  d = take ? od : d;
+  k = take ? ok : k;
+}
+
 // Lexicographic (distance^2, sorted position) minimum within each row of 16
 // lanes; every lane of the row ends with the row's result.
 template <int CTRL>
 __device__ __forceinline__ void argmin_step(double &d, int &k) {
   const double od = dpp_d<CTRL>(d, d);
   const int ok = dpp_i<CTRL>(k, k);
-  if (od < d || (od == d && ok < k)) { d = od; k = ok; }
+  lexmin(d, k, od, ok);
 }
 __device__ __forceinline__ void row_argmin(double &d, int &k) {
   argmin_step<VD_DPP_QUAD_XOR1>(d, k);
@@ -179,7 +187,7 @@ __device__ __forceinline__ void wave_argmin(double &d, int &k) {
   for (int r = 1; r < 4; r++) {
     const double od = readlane_d(d, 16 * r);
     const int ok = __builtin_amdgcn_readlane(k, 16 * r);
-    if (od < bd || (od == bd && ok < bk)) { bd = od; bk = ok; }
+    lexmin(bd, bk, od, ok);
   }
   d = bd;
   k = bk;
@@ -235,7 +243,7 @@ __device__ __forceinline__ void scan_box(const GridView &G, int gs, int x0, int 
         const int p = rst + (t - rex);
         const double dx = qx - GL(G.sx)[p], dy = qy - GL(G.sy)[p], dz = qz - GL(G.sz)[p];
         const double d = dx * dx + dy * dy + dz * dz;
-        if (d < bd || (d == bd && p < bk)) { bd = d; bk = p; }
+        lexmin(bd, bk, d, p);
       }
     }
   }
@@ -310,7 +318,7 @@ __device__ __forceinline__ int nn_thread(const GridView &G, double qx, double qy
             if (p == excl) continue;
             const double dx = qx - GL(G.sx)[p], dy = qy - GL(G.sy)[p], dz = qz - GL(G.sz)[p];
             const double d = dx * dx + dy * dy + dz * dz;
-            if (d < bd || (d == bd && p < bk)) { bd = d; bk = p; }
+            lexmin(bd, bk, d, p);
           }
         }
       }
@@ -587,7 +595,7 @@ __device__ __forceinline__ int nn_cached(const SiteCache &K, const GridView &G, 
         const double dx = qx - K.x[t], dy = qy - K.y[t], dz = qz - K.z[t];
         const double d = dx * dx + dy * dy + dz * dz;
         const int p = K.p[t];
-        if (d < bd || (d == bd && p < bk)) { bd = d; bk = p; }
+        lexmin(bd, bk, d, p);
       }
       group_argmin(bd, bk, gs);
       ncand += (n - base) < gs ? (n - base) : gs;
