@@ -92,6 +92,19 @@ __device__ __forceinline__ double dpp_d(double old, double v) {
   const int hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(o >> 32), (int)(uint32_t)(b >> 32), CTRL, 0xf, 0xf, false);
   return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
 }
+// permutations within a row (quad_perm, row mirrors): every lane has a source,
+// so no `old` value has to be kept in the destination register
+template <int CTRL>
+__device__ __forceinline__ int perm_i(int v) {
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xf, 0xf, true);
+}
+template <int CTRL>
+__device__ __forceinline__ double perm_d(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)b, CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, 0xf, 0xf, true);
+  return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
 __device__ __forceinline__ double readlane_d(double v, int lane) {
   const uint64_t b = (uint64_t)__double_as_longlong(v);
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
@@ -126,28 +139,28 @@ __device__ __forceinline__ int row_incl_scan(int v) {
 
 // sum over the wave, the same value in every lane (fixed combination order)
 __device__ __forceinline__ double wave_sum(double v) {
-  v += dpp_d<VD_DPP_QUAD_XOR1>(0.0, v);
-  v += dpp_d<VD_DPP_QUAD_XOR2>(0.0, v);
-  v += dpp_d<VD_DPP_ROW_HALF_MIRROR>(0.0, v);
-  v += dpp_d<VD_DPP_ROW_MIRROR>(0.0, v);
+  v += perm_d<VD_DPP_QUAD_XOR1>(v);
+  v += perm_d<VD_DPP_QUAD_XOR2>(v);
+  v += perm_d<VD_DPP_ROW_HALF_MIRROR>(v);
+  v += perm_d<VD_DPP_ROW_MIRROR>(v);
   return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
 
 __device__ __forceinline__ int wave_isum(int v) {
-  v += dpp_i<VD_DPP_QUAD_XOR1>(0, v);
-  v += dpp_i<VD_DPP_QUAD_XOR2>(0, v);
-  v += dpp_i<VD_DPP_ROW_HALF_MIRROR>(0, v);
-  v += dpp_i<VD_DPP_ROW_MIRROR>(0, v);
+  v += perm_i<VD_DPP_QUAD_XOR1>(v);
+  v += perm_i<VD_DPP_QUAD_XOR2>(v);
+  v += perm_i<VD_DPP_ROW_HALF_MIRROR>(v);
+  v += perm_i<VD_DPP_ROW_MIRROR>(v);
   return (__builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16)) +
          (__builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48));
 }
 
 __device__ __forceinline__ uint64_t wave_or64(uint64_t v) {
   int lo = (int)(uint32_t)v, hi = (int)(uint32_t)(v >> 32);
-  lo |= dpp_i<VD_DPP_QUAD_XOR1>(lo, lo); hi |= dpp_i<VD_DPP_QUAD_XOR1>(hi, hi);
-  lo |= dpp_i<VD_DPP_QUAD_XOR2>(lo, lo); hi |= dpp_i<VD_DPP_QUAD_XOR2>(hi, hi);
-  lo |= dpp_i<VD_DPP_ROW_HALF_MIRROR>(lo, lo); hi |= dpp_i<VD_DPP_ROW_HALF_MIRROR>(hi, hi);
-  lo |= dpp_i<VD_DPP_ROW_MIRROR>(lo, lo); hi |= dpp_i<VD_DPP_ROW_MIRROR>(hi, hi);
+  lo |= perm_i<VD_DPP_QUAD_XOR1>(lo); hi |= perm_i<VD_DPP_QUAD_XOR1>(hi);
+  lo |= perm_i<VD_DPP_QUAD_XOR2>(lo); hi |= perm_i<VD_DPP_QUAD_XOR2>(hi);
+  lo |= perm_i<VD_DPP_ROW_HALF_MIRROR>(lo); hi |= perm_i<VD_DPP_ROW_HALF_MIRROR>(hi);
+  lo |= perm_i<VD_DPP_ROW_MIRROR>(lo); hi |= perm_i<VD_DPP_ROW_MIRROR>(hi);
   const uint32_t L = (uint32_t)(__builtin_amdgcn_readlane(lo, 0) | __builtin_amdgcn_readlane(lo, 16) |
                                 __builtin_amdgcn_readlane(lo, 32) | __builtin_amdgcn_readlane(lo, 48));
   const uint32_t H = (uint32_t)(__builtin_amdgcn_readlane(hi, 0) | __builtin_amdgcn_readlane(hi, 16) |
@@ -167,8 +180,8 @@ __device__ __forceinline__ void lexmin(double &d, int &k, double od, int ok) {
 // lanes; every lane of the row ends with the row's result.
 template <int CTRL>
 __device__ __forceinline__ void argmin_step(double &d, int &k) {
-  const double od = dpp_d<CTRL>(d, d);
-  const int ok = dpp_i<CTRL>(k, k);
+  const double od = perm_d<CTRL>(d);
+  const int ok = perm_i<CTRL>(k);
   lexmin(d, k, od, ok);
 }
 __device__ __forceinline__ void row_argmin(double &d, int &k) {
@@ -569,6 +582,15 @@ __device__ void cache_fill(SiteCache &K, const GridView &G, double vx, double vy
 // search, which only needs a site nearer to its outer point than v_i.
 // Distances are computed by one formula everywhere, so "strictly nearer"
 // holds for the nearest site too.
+// sqrt(x) to about 1e-13 relative (hardware reciprocal square root and one
+// Newton step), for bounds that carry a wider margin of their own
+__device__ __forceinline__ double sqrt_bound(double x) {
+  if (!(x > 0.0)) return 0.0;
+  const double r = __builtin_amdgcn_rsq(x);
+  const double s0 = x * r;
+  return fma(0.5 * r, fma(-s0, s0, x), s0);
+}
+
 __device__ __forceinline__ double sq_dist(const GridView &G, int e, double qx, double qy, double qz) {
   const double dx = qx - GL(G.sx)[e], dy = qy - GL(G.sy)[e], dz = qz - GL(G.sz)[e];
   return dx * dx + dy * dy + dz * dz;
@@ -604,7 +626,7 @@ __device__ __forceinline__ int nn_cached(const SiteCache &K, const GridView &G, 
       if (u >= n) break;
       // entries from u on lie at least sqrt(kb[u] * step) from v: stop once
       // that exceeds |q - v| + d
-      const double reach = (dq + sqrt(bd)) * (1.0 + 1e-12);
+      const double reach = (dq + sqrt_bound(bd)) * (1.0 + 1e-9);
       if ((double)K.kb[u] * K.step * (1.0 - 1e-12) > reach * reach) break;
     }
     const double rn = sqrt(bd);
