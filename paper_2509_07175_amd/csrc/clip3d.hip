@@ -726,6 +726,10 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
   int where = 0;  // failing stage (VD_STAGE_*)
   int nt = 0, head = 0, nnb = 0, npieces = 0, npl0 = 0, nc0 = 0;
   bool cell_job = C.mode == 1, saved = false;
+  // pieces cut from the saved cell: their bisector faces are cell planes, so
+  // the neighbours found are a mask over the cell's plane slots (cellpos: the
+  // slots whose flag is a site), turned into a list once per site
+  uint64_t cellpos = 0, nbmask = 0;
   double Mv = 0, Mx = 0, My = 0, Mz = 0, Me = 0;
   if (C.cache) {
     cache_fill(S.K, G, X.vx, X.vy, X.vz, &S.cy[0][0]);  // the corner array is free until the carve
@@ -783,6 +787,7 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
           npl0 = npl;
           nc0 = nc;
           saved = true;
+          cellpos = __ballot(l < npl && S.plab[l] >= 0);
         }
         continue;
       }
@@ -866,7 +871,11 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
     }
     npieces++;
     // ---- propagate: neighbours (positive flags), tetrahedra (negative flags) ----
-    for (uint64_t m = fmask; m; m &= m - 1) {
+    // A piece cut from the saved cell adds its cell planes to the mask; only
+    // the four planes of T_a can lead to other tetrahedra.
+    const bool from_cell = saved && !need_carve;
+    if (from_cell) nbmask |= fmask & cellpos;
+    for (uint64_t m = from_cell ? fmask & (15ull << npl0) : fmask; m; m &= m - 1) {
       const int x = __ffsll((unsigned long long)m) - 1;
       const int lab = uni(S.plab[x]);
       if (lab >= 0) {
@@ -899,6 +908,19 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
       }
     }
     __syncthreads();
+  }
+  // neighbours of the pieces cut from the saved cell
+  for (uint64_t m = nbmask; m && !err; m &= m - 1) {
+    const int lab = uni(S.bplab[__ffsll((unsigned long long)m) - 1]);
+    bool have = false;
+    for (int e = l; e < nnb; e += 64) have = have || (S.nbl[e] == lab);
+    if (!__ballot(have)) {
+      if (nnb >= VD_NB_MAX) { err = 2; where = VD_STAGE_NEIGHBOURS; break; }
+      __syncthreads();
+      if (l == 0) S.nbl[nnb] = lab;
+      nnb++;
+      __syncthreads();
+    }
   }
   // ---- per-site results ----
   const long long ns0 = arena_take(S.ar, C, AR_NBR, nnb);
