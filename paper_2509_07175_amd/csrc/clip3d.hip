@@ -256,7 +256,7 @@ __device__ int clip_poly(WaveLds &S, int P, int pt, int &nc) {
         S.cy[ns][0] = y[h][0]; S.cy[ns][1] = y[h][1]; S.cy[ns][2] = y[h][2];
       }
       if (r[h])
-#pragma unroll 1
+#pragma unroll
         for (int e = 0; e < 3; e++)
           if (em[h] & (1 << e)) {
             const int u = p8(pl[h], e), w = p8(pl[h], (e + 1) % 3);
@@ -264,13 +264,20 @@ __device__ int clip_poly(WaveLds &S, int P, int pt, int &nc) {
             S.cpl[ns] = pack3(u, w, P);
             S.cnb[ns] = pack3(rank(p8(nb[h], e)), S.byFirst[w], S.bySecond[u]);
             S.cst[ns] = 0;
-            double yy[3];
-            solve3(S, u, w, P, yy);
-            nf = nf || !isfinite(yy[0] + yy[1] + yy[2]);
-            S.cy[ns][0] = yy[0]; S.cy[ns][1] = yy[1]; S.cy[ns][2] = yy[2];
             t++;
           }
     }
+  }
+  __syncthreads();
+  // coordinates of the new corners, one per lane (a removed corner may own up
+  // to three of them)
+  for (int t = l; t < nnew; t += 64) {
+    const int ns = nsurv + t;
+    const int cp = S.cpl[ns];
+    double yy[3];
+    solve3(S, p8(cp, 0), p8(cp, 1), p8(cp, 2), yy);
+    nf = nf || !isfinite(yy[0] + yy[1] + yy[2]);
+    S.cy[ns][0] = yy[0]; S.cy[ns][1] = yy[1]; S.cy[ns][2] = yy[2];
   }
   __syncthreads();
   nc = nsurv + nnew;
