@@ -212,30 +212,28 @@ __device__ int clip_poly(WaveLds &S, int P, int pt, int &nc) {
     return s < 64 ? __popcll(Slo & low_mask(s)) : __popcll(Slo) + __popcll(Shi & low_mask(s - 64));
   };
   // every plane is "first" (resp. "second") of at most one new corner when the
-  // boundary of R_p is a simple loop; the tables give the fan adjacency
+  // boundary of R_p is a simple loop; the tables give the fan adjacency.  A
+  // plane that is first (second) of two new corners shows as fewer distinct
+  // first (second) planes than new corners.
   __syncthreads();
+  uint64_t fm = 0, sm = 0;
   {
     int t = base;
     for (int h = 0; h < 2; h++)
       for (int e = 0; e < 3; e++)
         if (em[h] & (1 << e)) {
-          S.byFirst[p8(pl[h], e)] = (unsigned char)(nsurv + t);
-          S.bySecond[p8(pl[h], (e + 1) % 3)] = (unsigned char)(nsurv + t);
+          const int u = p8(pl[h], e), w = p8(pl[h], (e + 1) % 3);
+          S.byFirst[u] = (unsigned char)(nsurv + t);
+          S.bySecond[w] = (unsigned char)(nsurv + t);
+          fm |= 1ull << u;
+          sm |= 1ull << w;
           t++;
         }
   }
+  fm = wave_or64(fm);
+  sm = wave_or64(sm);
+  if (__popcll(fm) != nnew || __popcll(sm) != nnew) return 3;
   __syncthreads();
-  bool bad = false;
-  {
-    int t = base;
-    for (int h = 0; h < 2; h++)
-      for (int e = 0; e < 3; e++)
-        if (em[h] & (1 << e)) {
-          if (S.byFirst[p8(pl[h], e)] != nsurv + t || S.bySecond[p8(pl[h], (e + 1) % 3)] != nsurv + t) bad = true;
-          t++;
-        }
-  }
-  if (__ballot(bad)) return 3;
   // all old corner data sits in registers: write the new layout
   bool nf = false;
   {
