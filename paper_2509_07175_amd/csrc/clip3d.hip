@@ -208,9 +208,6 @@ __device__ int clip_poly(WaveLds &S, int P, int pt, int &nc) {
   if (nsurv + nnew > VD_C_MAX) return 2;
   const uint64_t vlo = low_mask(nc < 64 ? nc : 64), vhi = low_mask(nc > 64 ? nc - 64 : 0);
   const uint64_t Slo = vlo & ~Rlo, Shi = vhi & ~Rhi;
-  auto rank = [&](int s) -> int {
-    return s < 64 ? __popcll(Slo & low_mask(s)) : __popcll(Slo) + __popcll(Shi & low_mask(s - 64));
-  };
   // every plane is "first" (resp. "second") of at most one new corner when the
   // boundary of R_p is a simple loop; the tables give the fan adjacency.  A
   // plane that is first (second) of two new corners shows as fewer distinct
@@ -237,16 +234,33 @@ __device__ int clip_poly(WaveLds &S, int P, int pt, int &nc) {
   // all old corner data sits in registers: write the new layout
   bool nf = false;
   {
+    // new slot of every surviving corner (lane l: slots l and l + 64), and of
+    // the three neighbours of each corner, fetched from their owning lanes
+    const int nlo = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(Slo >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)Slo, 0u));
+    const int nhi = __popcll(Slo) +
+                    (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(Shi >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)Shi, 0u));
+    int nbn[2][3];
+#pragma unroll
+    for (int h = 0; h < 2; h++)
+#pragma unroll
+      for (int e = 0; e < 3; e++) {
+        const int m = p8(nb[h], e);
+        int x = __shfl(nlo, m & 63, 64);
+        if (nc > 64) {
+          const int y = __shfl(nhi, m & 63, 64);
+          x = m < 64 ? x : y;
+        }
+        nbn[h][e] = x;
+      }
     int t = base;
 #pragma unroll
     for (int h = 0; h < 2; h++) {
-      const int s = l + 64 * h;
       if (v[h] && !r[h]) {
-        const int ns = rank(s);
+        const int ns = h ? nhi : nlo;
         int nbo[3];
         for (int e = 0; e < 3; e++) {
           const int m = p8(nb[h], e);
-          nbo[e] = bit128(Rlo, Rhi, m) ? S.byFirst[p8(pl[h], (e + 1) % 3)] : rank(m);
+          nbo[e] = bit128(Rlo, Rhi, m) ? S.byFirst[p8(pl[h], (e + 1) % 3)] : nbn[h][e];
         }
         S.cpl[ns] = pl[h];
         S.cnb[ns] = pack3(nbo[0], nbo[1], nbo[2]);
@@ -260,7 +274,7 @@ __device__ int clip_poly(WaveLds &S, int P, int pt, int &nc) {
             const int u = p8(pl[h], e), w = p8(pl[h], (e + 1) % 3);
             const int ns = nsurv + t;
             S.cpl[ns] = pack3(u, w, P);
-            S.cnb[ns] = pack3(rank(p8(nb[h], e)), S.byFirst[w], S.bySecond[u]);
+            S.cnb[ns] = pack3(nbn[h][e], S.byFirst[w], S.bySecond[u]);
             S.cst[ns] = 0;
             t++;
           }
