@@ -412,7 +412,7 @@ __device__ int carve(WaveLds &S, const GridView &G, const CarveParams C, const S
         }
         nstep = 0;
         const double d0 = g0 - A0, d1 = g1 - A1, d2 = g2 - A2;
-        L = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        L = C.improved ? sqrt(d0 * d0 + d1 * d1 + d2 * d2) : 0.0;
         if (C.improved && L > 0 && 2.0 * X.delta < L) {
           u0 = d0 / L; u1 = d1 / L; u2 = d2 / L;
           lam = 2;
