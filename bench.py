@@ -284,6 +284,74 @@ def bench_surface(steps, warmup, log):
             "forward_plus_adjoint_vs_forward": f_ms / fb_ms, "cvt_gradient_rel_err": err}
 
 
+def measured_peaks(log):
+    """Measured ceilings on this GPU: FP64 FMA rate (a HIP probe of eight
+    independent v_fma_f64 chains per lane) and device-to-device copy rate
+    (1 GiB read + 1 GiB written).  None where the probe is unavailable."""
+    import ctypes
+    import torch
+    out = {"fp64_fma_tflops": None, "copy_gbs": None}
+    src = torch.empty(2 ** 27, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    out["copy_gbs"] = 5 * 2 * 2 ** 30 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    lib_path = os.path.join(ROOT, "paper_2509_07175_amd", "libvd_probe.so")
+    if os.path.exists(lib_path):
+        lib = ctypes.CDLL(lib_path)
+        lib.vd_probe_fma_f64.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_double)]
+        blocks, iters = 8192, 20000
+        buf = torch.empty(blocks * 256, dtype=torch.float64, device="cuda")
+        ms, fl = ctypes.c_float(0.0), ctypes.c_double(0.0)
+        if lib.vd_probe_fma_f64(blocks, iters, ctypes.c_void_p(buf.data_ptr()), ctypes.byref(ms), ctypes.byref(fl)) == 0:
+            out["fp64_fma_tflops"] = fl.value / (ms.value * 1e-3) / 1e12
+    log(f"measured peaks: FP64 FMA {out['fp64_fma_tflops']} TFLOP/s, copy {out['copy_gbs']:.0f} GB/s")
+    return out
+
+
+def bench_plain_other(log):
+    """Plain build_grid + clip + moments on the small cube workloads."""
+    import torch
+    import paper_2509_07175_amd as vd
+    res = {}
+    for name in ("c1", "c2"):
+        sites, dom, desc, rho = workload(name)
+        n = len(sites)
+        s = torch.as_tensor(sites, dtype=torch.float64, device="cuda")
+        d = vd.Domain.from_vdgen(dom)
+        grid, cells = vd.Grid(), vd.Cells()
+        mass = torch.empty(n, dtype=torch.float64, device="cuda")
+        cent = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+        en = torch.empty(n, dtype=torch.float64, device="cuda")
+        opt = vd.Options.default()
+
+        def step():
+            vd.build_grid(s, bbox=(0.0, 0.0, 0.0, 1.0, 1.0, 1.0), sites_per_cell=rho, grid=grid)
+            vd.clip_cells(grid, d, opt, cells=cells)
+            cells.moments(mass, cent, en)
+
+        for _ in range(3):
+            step()
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(20):
+            t0 = time.perf_counter()
+            step()
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        med = float(sorted(times)[len(times) // 2])
+        res[name] = {"workload": desc, "median_ms": 1e3 * med, "cells_per_s": n / med}
+        log(f"{name}: {1e3 * med:.2f} ms median, {n / med:.3g} cells/s")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -299,6 +367,8 @@ def main():
     ap.add_argument("--site-cache", type=int, default=1, choices=[0, 1])
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-diagrams comparison")
     ap.add_argument("--no-backward", action="store_true", help="skip the adjoint throughput")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the measured FMA / copy peaks")
+    ap.add_argument("--no-small", action="store_true", help="skip the 1k- and 100k-site cube workloads")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -337,6 +407,8 @@ def main():
     cent = torch.empty((n, 3), dtype=torch.float64, device=dev)
     en = torch.empty(n, dtype=torch.float64, device=dev)
     bbox = (0.0, 0.0, 0.0, 1.0, 1.0, 1.0)
+    torch.cuda.synchronize()
+    free_before, _ = torch.cuda.mem_get_info()  # the library's grid and output arenas come after
 
     def step():
         vd.build_grid(s, bbox=bbox, sites_per_cell=rho, grid=grid)
@@ -349,15 +421,19 @@ def main():
         step()
         torch.cuda.synchronize()
         print(f"bench: warmup {w} {1e3 * (time.perf_counter() - t1):.1f} ms", file=sys.stderr, flush=True)
-    kern = []
+    kern, step_ms = [], []
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
+        ts = time.perf_counter()
         step()
-        inf = cells.info()
+        inf = cells.info()  # waits for the step (the piece counts it reports come from the device)
+        step_ms.append(1e3 * (time.perf_counter() - ts))
         kern.append(inf["carve_ms"])
         print(f"bench: step {len(kern)} site kernel {inf['carve_ms']:.2f} ms", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    free_after, _ = torch.cuda.mem_get_info()
     info = cells.info()
     ms = 1e3 * wall / args.steps
     # the dominant kernel: the persistent per-site kernel (cell carve + pieces)
@@ -394,12 +470,24 @@ def main():
                              "achieved": alg_bytes / (dom_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                              "frac": alg_bytes / (dom_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
                              "measured": None if traffic is None else traffic / (dom_ms * 1e-3) / 1e9}},
+        "step_ms_percentiles": {"p10": float(np.percentile(step_ms, 10)), "p50": float(np.percentile(step_ms, 50)),
+                                "p90": float(np.percentile(step_ms, 90))},
+        "device_memory_bytes": int(free_before - free_after),
         "counters": {"pieces": info["n_pieces"], "nn_queries": info["nn_queries"], "clips": info["clips"],
                      "candidates": info["candidates"], "queries_per_cell": info["nn_queries"] / n,
                      "grid_queries": info["grid_queries"],
                      "mass_sum": total_mass},
     }
     log = lambda m: print(f"bench: {m}", file=sys.stderr, flush=True)  # noqa: E731
+    if not args.no_peaks:
+        pk = measured_peaks(log)
+        out["measured_peaks"] = pk
+        if pk["fp64_fma_tflops"]:
+            out["roofline"]["frac_of_measured_peak"] = achieved / pk["fp64_fma_tflops"]
+        if pk["copy_gbs"]:
+            out["roofline"]["hbm"]["frac_of_measured_copy"] = out["roofline"]["hbm"]["achieved"] / pk["copy_gbs"]
+    if not args.no_small:
+        out["plain_small"] = bench_plain_other(log)
     if not args.no_backward:
         out["backward"] = bench_backward(s, d, rho, max(1, min(args.steps, 5)), 1, log)
         out["backward"]["vs_plain_forward"] = ms / out["backward"]["forward_with_face_moments_plus_adjoint_ms"]

@@ -1,4 +1,5 @@
-"""Builds libvd.so (all HIP sources, gfx950) in this package directory.
+"""Builds libvd.so (all HIP sources, gfx950) in this package directory, and
+libvd_probe.so (measured chip peaks for the benchmark's roofline report).
 
 Usage: python -m paper_2509_07175_amd.build  (or build() from Python).
 Every kernel is compiled for gfx950 only, with packed FP32 instructions
@@ -14,6 +15,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvd.so")
+PROBE_SRC = os.path.join(HERE, "probe", "peak_probe.hip")
+PROBE_LIB = os.path.join(HERE, "libvd_probe.so")
 ARCH = os.environ.get("VD_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
@@ -53,6 +56,12 @@ def build(verbose: bool = False) -> str:
             os.remove(o)
         except OSError:
             pass
+    cmd = [hipcc, *FLAGS[:-1], PROBE_SRC, "-o", PROBE_LIB + ".tmp"]
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout.decode(errors="replace"))
+        raise RuntimeError("build of libvd_probe.so failed")
+    os.replace(PROBE_LIB + ".tmp", PROBE_LIB)
     return LIB
 
 
