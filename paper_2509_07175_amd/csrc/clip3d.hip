@@ -874,16 +874,21 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
         if (C.emit) { S.ar.faces += nface; S.ar.verts += nc; }
       }
       if (C.emit && fo + nface <= C.cap_face && vo + nc <= C.cap_vert) {
-        if (l < npl && ((fmask >> l) & 1ull))
-          GL(C.face_label)[fo + __popcll(fmask & low_mask(l))] = convert_label(G, S.plab[l]);
+        // caller-index flag of plane l, read once; corners fetch theirs from the plane's lane
+        const int lab = l < npl && ((fmask >> l) & 1ull) ? convert_label(G, S.plab[l]) : 0;
+        if (l < npl && ((fmask >> l) & 1ull)) GL(C.face_label)[fo + __popcll(fmask & low_mask(l))] = lab;
         for (int h = 0; h < 2; h++) {
+          if (64 * h >= nc) break;
           const int s = l + 64 * h;
+          const int pl = s < nc ? S.cpl[s] : 0;
+          const int l0 = __shfl(lab, p8(pl, 0), 64), l1 = __shfl(lab, p8(pl, 1), 64), l2 = __shfl(lab, p8(pl, 2), 64);
           if (s < nc) {
-            const int pl = S.cpl[s];
             GL(C.vert_xyz)[3 * (vo + s) + 0] = S.cy[s][0] + X.vx;
             GL(C.vert_xyz)[3 * (vo + s) + 1] = S.cy[s][1] + X.vy;
             GL(C.vert_xyz)[3 * (vo + s) + 2] = S.cy[s][2] + X.vz;
-            for (int e = 0; e < 3; e++) GL(C.vert_label)[3 * (vo + s) + e] = convert_label(G, S.plab[p8(pl, e)]);
+            GL(C.vert_label)[3 * (vo + s) + 0] = l0;
+            GL(C.vert_label)[3 * (vo + s) + 1] = l1;
+            GL(C.vert_label)[3 * (vo + s) + 2] = l2;
           }
         }
       }
