@@ -34,6 +34,43 @@ def run_gpu(sites, dom, bbox=(0, 0, 0, 1, 1, 1), surface_area=0.0, **opts):
     return out
 
 
+def sampled_result(view, sample):
+    """The pieces of the sites in `sample` (caller indices), gathered on the
+    device, in the oracle's layout (sorted by site, then simplex): for
+    workloads whose full polytope output is too large to copy to the host."""
+    import torch
+    off = view["cell_piece_off"].cpu().numpy()
+    pid_all = view["piece_id"]
+    ids = np.concatenate([pid_all[off[i]:off[i + 1]].cpu().numpy() for i in sample]).astype(np.int64)
+    dev = pid_all.device
+    idt = torch.as_tensor(ids, device=dev)
+
+    def take(name):
+        return view[name][idt].cpu().numpy()
+    site, simp = take("piece_site"), take("piece_simplex")
+    order = np.lexsort((simp, site))
+    ids, site, simp = ids[order], site[order], simp[order]
+    idt = torch.as_tensor(ids, device=dev)
+    nface = view["piece_nface"][idt].cpu().numpy().astype(np.int64)
+    nvert = view["piece_nvert"][idt].cpu().numpy().astype(np.int64)
+    fst = view["piece_face_start"][idt].cpu().numpy()
+    vst = view["piece_vert_start"][idt].cpu().numpy()
+    fidx = np.concatenate([np.arange(a, a + c) for a, c in zip(fst, nface)]) if len(ids) else np.zeros(0, np.int64)
+    vidx = np.concatenate([np.arange(a, a + c) for a, c in zip(vst, nvert)]) if len(ids) else np.zeros(0, np.int64)
+    ft, vt = torch.as_tensor(fidx, device=dev), torch.as_tensor(vidx, device=dev)
+    return {
+        "piece_site": site, "piece_simplex": simp,
+        "piece_mass": view["piece_mass"][idt].cpu().numpy(),
+        "piece_moment": view["piece_moment"][idt].cpu().numpy(),
+        "piece_energy": view["piece_energy"][idt].cpu().numpy(),
+        "piece_face_off": np.concatenate([[0], np.cumsum(nface)]).astype(np.int64),
+        "piece_vert_off": np.concatenate([[0], np.cumsum(nvert)]).astype(np.int64),
+        "face_label": view["face_label"][ft].cpu().numpy(),
+        "vert_xyz": view["vert_xyz"][vt].cpu().numpy(),
+        "vert_label": view["vert_label"][vt].cpu().numpy(),
+    }
+
+
 def assert_csr(gpu, n):
     """The per-site CSR lists exactly the used piece slots, each under its own
     site, by ascending simplex."""

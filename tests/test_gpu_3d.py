@@ -9,7 +9,8 @@ import numpy as np
 import pytest
 
 import vdgen
-from gpu_util import assert_parity, gpu_neighbors, log, run_gpu
+from canon import canon_pieces
+from gpu_util import assert_parity, gpu_neighbors, log, run_gpu, sampled_result
 
 pytestmark = pytest.mark.gpu
 
@@ -105,3 +106,62 @@ def test_c2_full_size_sampled(oracle_mod):
     for i in rng.choice(n, size=2000, replace=False):
         for j in nb[i]:
             assert i in set(nb[j].tolist())
+
+
+def test_c3_full_size_sampled(oracle_mod):
+    """The headline workload in the benchmark's launch configuration: 1,000,000
+    clustered sites in 750,000 tetrahedra, grid at 0.25 sites per cell, default
+    options.  All sites: total and per-tetrahedron volume, CSR consistency.
+    Sampled sites (random, the smallest cells of the cluster cores, the
+    largest cells of the background): pieces, face labels and vertex label
+    triples bit-exact, vertices, masses, centroids and energies against the
+    oracle."""
+    import torch
+    import paper_2509_07175_amd as vd
+    sites, dom = vdgen.config_c3()
+    n = len(sites)
+    s = torch.as_tensor(sites, dtype=torch.float64, device="cuda")
+    d = vd.Domain.from_vdgen(dom)
+    g = vd.build_grid(s, bbox=(0.0, 0.0, 0.0, 1.0, 1.0, 1.0), sites_per_cell=0.25)
+    c = vd.clip_cells(g, d, vd.Options.default())
+    m, ce, e = c.moments()
+    torch.cuda.synchronize()
+    info = c.info()
+    log(f"C3 info {info}")
+    assert info["status"] == 0
+    mass, cent, en = m.cpu().numpy(), ce.cpu().numpy(), e.cpu().numpy()
+    assert abs(mass.sum() - 1.0) < 1e-10
+    view = c.view()
+    psite = view["piece_site"].cpu().numpy()
+    used = psite >= 0
+    psimp = view["piece_simplex"].cpu().numpy()[used]
+    pmass = view["piece_mass"].cpu().numpy()[used]
+    q = dom.verts[dom.simplices]
+    tv = np.einsum("ij,ij->i", np.cross(q[:, 1] - q[:, 0], q[:, 2] - q[:, 0]), q[:, 3] - q[:, 0]) / 6
+    per = np.bincount(psimp, weights=pmass, minlength=dom.m)
+    assert np.allclose(per, tv, rtol=1e-10, atol=0)
+    off = view["cell_piece_off"].cpu().numpy()
+    assert off[0] == 0 and off[-1] == used.sum() and np.all(np.diff(off) >= 1)
+    rng = np.random.default_rng(3003)
+    order = np.argsort(mass)
+    sample = np.unique(np.concatenate([rng.choice(n, size=24, replace=False), order[:12], order[-12:]]))
+    ref = oracle_mod.compute(sites, dom, only_sites=sample)
+    mom = oracle_mod.site_moments(ref, sites)
+    a = canon_pieces(sampled_result(view, sample))
+    b = {k: v for k, v in canon_pieces(ref).items() if k[0] in set(sample.tolist())}
+    assert set(a) == set(b), "piece sets differ"
+    md = 0.0
+    for k in b:
+        assert a[k][0] == b[k][0] and a[k][1] == b[k][1], f"combinatorics differ at {k}"
+        if len(b[k][2]):
+            md = max(md, float(np.abs(a[k][2] - b[k][2]).max()))
+    assert md <= 1e-10, f"vertex coordinates differ by {md}"
+    for i in sample:
+        assert abs(mass[i] - mom["mass"][i]) <= 1e-9 * mom["mass"][i]
+        assert np.linalg.norm(cent[i] - mom["centroid"][i]) <= 1e-9 * np.linalg.norm(mom["centroid"][i])
+        assert abs(en[i] - mom["energy"][i]) <= 1e-9 * mom["energy"][i]
+    nbo, nb = view["nbr_off"].cpu().numpy(), view["nbr"].cpu().numpy()
+    for i in sample:
+        assert list(nb[nbo[i]:nbo[i + 1]]) == list(mom["neighbors"][i]), f"neighbours of site {i} differ"
+        for j in nb[nbo[i]:nbo[i + 1]]:
+            assert i in set(nb[nbo[j]:nbo[j + 1]].tolist()), f"neighbour symmetry {i} {j}"
