@@ -53,6 +53,33 @@ def test_two_sites(oracle_mod):
     _check_case(oracle_mod, s, dom)
 
 
+def test_cell_over_many_tetrahedra(oracle_mod):
+    """One site in 8^3 x 6 = 3,072 tetrahedra: the cell's simplex queue goes on
+    in global memory past the 256 entries a wave keeps in LDS."""
+    dom = vdgen.kuhn_cube_grid(8)
+    s = np.array([[0.31, 0.47, 0.59]])
+    gpu, _, _ = _check_case(oracle_mod, s, dom)
+    assert abs(gpu["mass"][0] - 1.0) < 1e-12
+    assert len(gpu["res"]["piece_site"]) == dom.m
+
+
+def test_simplex_capacity_is_reported(oracle_mod):
+    """One site in 9^3 x 6 = 4,374 tetrahedra exceeds the per-wave simplex queue
+    (256 in LDS + 3,840 in global memory): the clip reports VD_ERR_CAPACITY
+    and the stage, and the library keeps working."""
+    import torch
+    import paper_2509_07175_amd as vd
+    dom = vdgen.kuhn_cube_grid(9)
+    s = torch.as_tensor(np.array([[0.31, 0.47, 0.59]]), dtype=torch.float64, device="cuda")
+    g = vd.build_grid(s, bbox=(0, 0, 0, 1, 1, 1))
+    with pytest.raises(vd.VDError) as ei:
+        vd.clip_cells(g, vd.Domain.from_vdgen(dom), vd.Options.default())
+    assert ei.value.status == 4 and "stages 0x20" in str(ei.value), str(ei.value)
+    torch.cuda.synchronize()
+    sites, dom2 = vdgen.small_case(300, 3, seed=5)
+    _check_case(oracle_mod, sites, dom2, brute=False)
+
+
 @pytest.mark.parametrize("mode", [1, 0])
 @pytest.mark.parametrize("n,k,seed", [(300, 3, 5), (2000, 4, 6), (777, 5, 7)])
 def test_multi_tet_parity(oracle_mod, n, k, seed, mode):
