@@ -63,6 +63,10 @@ def workload(name):
     if name == "c2":
         s, d = vdgen.config_c2()
         return s, d, "C2: 100,000 uniform sites, 20^3 cubes x 6 = 48,000 tetrahedra", 3.5
+    if name == "cube5m":
+        # the shape of the paper's own GPU headline run (white noise in a cube); context only
+        s = vdgen.uniform_cube_sites(5_000_000, seed=108, jitter=1e-7)
+        return s, vdgen.kuhn_cube_grid(1), "5,000,000 uniform sites, unit cube as 6 tetrahedra", 2.0
     s, d = vdgen.config_c3()
     return (s, d, "C3: 1,000,000 clustered sites (8 Gaussians sigma 0.05 + 10% uniform), "
                   "50^3 cubes x 6 = 750,000 tetrahedra", 0.25)
@@ -357,7 +361,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3"])
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "cube5m"])
     ap.add_argument("--rho", type=float, default=None, help="grid sites per cell")
     ap.add_argument("--no-emit", action="store_true", help="skip writing per-piece polytopes")
     ap.add_argument("--no-cpu-baseline", action="store_true")
