@@ -424,10 +424,11 @@ __device__ __forceinline__ void for_block_sites(const GridView &G, int x0, int x
 }
 
 // The block is sized from the density of the 3x3x3 block around v so that it
-// holds about 2.5 VD_CACHE sites.  If more than VD_CACHE of them are nearer to v
-// than the block boundary, only the nearest are kept: a 64-bucket histogram of
-// squared distances picks the largest radius T whose ball holds at most
-// VD_CACHE sites, every site with d^2 < T^2 is kept, and rc = T.
+// holds about 2.5 VD_CACHE sites.  Its sites are counted in 64 buckets of
+// squared distance to v.  If more than VD_CACHE of them are in the block, only
+// a prefix of buckets that fits is kept (every site with d^2 < T^2, rc = T).
+// The kept sites are stored in bucket order (a counting sort; within a bucket
+// in block order, so the cache is the same on every run).
 __device__ void cache_fill(SiteCache &K, const GridView &G, double vx, double vy, double vz, double *scratch) {
   const int l = vd_lane();
   const int gx = G.g[0], gy = G.g[1], gz = G.g[2];
