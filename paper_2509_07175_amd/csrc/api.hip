@@ -622,6 +622,8 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
       if (opt.no_sync) return bail(fail(VD_ERR_INVALID_ARG, "vd_clip_cells: no_sync on an unsized handle"));
       int64_t t = 0;
       HIP_TRY(ensure(d.tq_spill, t, (int64_t)wg * VD_Q_SPILL));
+      t = 0;
+      HIP_TRY(ensure(d.saved, t, (int64_t)wg * VD_SAVE_DOUBLES));
       c->cap_spill = wg;
     }
     {
@@ -717,7 +719,7 @@ void vd_cells_free(vd_cells c) {
   if (c->ev0) hipEventDestroy(c->ev0);
   if (c->ev1) hipEventDestroy(c->ev1);
   if (c->ev2) hipEventDestroy(c->ev2);
-  hipFree(c->d_dev); hipFree(d.queue); hipFree(d.tq_spill);
+  hipFree(c->d_dev); hipFree(d.queue); hipFree(d.tq_spill); hipFree(d.saved);
   if (c->host_cnt) hipHostFree(c->host_cnt);
   hipFree(d.fint_lab); hipFree(d.piece_fint_start); hipFree(d.piece_nfint); hipFree(c->wbuf);
   delete c;

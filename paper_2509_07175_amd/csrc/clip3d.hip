@@ -61,11 +61,6 @@ struct __align__(16) WaveLds {
   int pfirst[VD_P_MAX];      // lowest corner slot on each plane (face walks)
   WaveArena ar;              // output chunks, queue position, statistics
   SiteCache K;               // sites around v_i for the nearest-site queries
-  // cell-first: the carved cell, restored before each tetrahedron
-  double bpn[VD_F_MAX][4];
-  double bcy[VD_CB_MAX][3];
-  int bplab[VD_F_MAX];
-  int bcpl[VD_CB_MAX], bcnb[VD_CB_MAX];
 };
 
 __device__ __forceinline__ int p8(int packed, int e) { return (packed >> (8 * e)) & 0xff; }
@@ -553,28 +548,48 @@ __device__ void init_tet(WaveLds &S, const DomainView &D, const SiteCtx &X, int 
 
 static_assert(VD_C_MAX * 3 >= VD_CACHE_SCRATCH, "the corner array doubles as the site cache's sort scratch");
 
-// cell-first: keep the carved cell (npl planes, nc corners) ...
-__device__ void save_cell(WaveLds &S, int npl, int nc) {
+// cell-first: keep the carved cell (npl planes, nc corners) in this wave's
+// part of a global buffer (it stays in the L2 of the wave's XCD) ...
+struct SavedCell {
+  __attribute__((address_space(1))) double *pn, *cy;
+  __attribute__((address_space(1))) int *plab, *cpl, *cnb;
+};
+__device__ __forceinline__ SavedCell saved_cell(const CellsDev &C) {
+  SavedCell B;
+  double *base = C.saved + (long long)blockIdx.x * VD_SAVE_DOUBLES;
+  B.pn = GL(base);
+  B.cy = GL(base + VD_F_MAX * 4);
+  int *ib = reinterpret_cast<int *>(base + VD_F_MAX * 4 + VD_CB_MAX * 3);
+  B.plab = GL(ib);
+  B.cpl = GL(ib + VD_F_MAX);
+  B.cnb = GL(ib + VD_F_MAX + VD_CB_MAX);
+  return B;
+}
+
+__device__ void save_cell(WaveLds &S, const CellsDev &C, int npl, int nc) {
   const int l = vd_lane();
+  const SavedCell B = saved_cell(C);
   if (l < npl) {
-    for (int k = 0; k < 4; k++) S.bpn[l][k] = S.pn[l][k];
-    S.bplab[l] = S.plab[l];
+    for (int k = 0; k < 4; k++) B.pn[4 * l + k] = S.pn[l][k];
+    B.plab[l] = S.plab[l];
   }
   for (int s = l; s < nc; s += 64) {
-    S.bcpl[s] = S.cpl[s];
-    S.bcnb[s] = S.cnb[s];
-    for (int k = 0; k < 3; k++) S.bcy[s][k] = S.cy[s][k];
+    B.cpl[s] = S.cpl[s];
+    B.cnb[s] = S.cnb[s];
+    for (int k = 0; k < 3; k++) B.cy[3 * s + k] = S.cy[s][k];
   }
-  __syncthreads();
+  __threadfence_block();  // the wave reads it back: stores complete first
 }
 
 // ... and start a piece from it: the cell plus the four planes of T_a in
 // slots npl .. npl+3 (not yet cut)
-__device__ void restore_cell(WaveLds &S, int npl, int nc, const DomainView &D, const SiteCtx &X, int a) {
+__device__ void restore_cell(WaveLds &S, const CellsDev &C, int npl, int nc, const DomainView &D, const SiteCtx &X,
+                             int a) {
   const int l = vd_lane();
+  const SavedCell B = saved_cell(C);
   if (l < npl) {
-    for (int k = 0; k < 4; k++) S.pn[l][k] = S.bpn[l][k];
-    S.plab[l] = S.bplab[l];
+    for (int k = 0; k < 4; k++) S.pn[l][k] = B.pn[4 * l + k];
+    S.plab[l] = B.plab[l];
   } else if (l < npl + 4) {
     double pl[4];
     int lab;
@@ -583,10 +598,10 @@ __device__ void restore_cell(WaveLds &S, int npl, int nc, const DomainView &D, c
     S.plab[l] = lab;
   }
   for (int s = l; s < nc; s += 64) {
-    S.cpl[s] = S.bcpl[s];
-    S.cnb[s] = S.bcnb[s];
+    S.cpl[s] = B.cpl[s];
+    S.cnb[s] = B.cnb[s];
     S.cst[s] = 3;
-    for (int k = 0; k < 3; k++) S.cy[s][k] = S.bcy[s][k];
+    for (int k = 0; k < 3; k++) S.cy[s][k] = B.cy[3 * s + k];
   }
   __syncthreads();
 }
@@ -749,6 +764,7 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
   // the neighbours found are a mask over the cell's plane slots (cellpos: the
   // slots whose flag is a site), turned into a list once per site
   uint64_t cellpos = 0, nbmask = 0;
+  int cell_lab = 0;  // lane x: the flag of the cell's plane x
   double Mv = 0, Mx = 0, My = 0, Mz = 0, Me = 0;
   if (C.cache) {
     cache_fill(S.K, G, X.vx, X.vy, X.vz, &S.cy[0][0]);  // the corner array is free until the carve
@@ -773,7 +789,7 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
       a = head < VD_Q_MAX ? S.tq[head] : spill_get(C, head);
       head++;
       if (saved) {
-        restore_cell(S, npl0, nc0, D, X, a);
+        restore_cell(S, C, npl0, nc0, D, X, a);
         npl = npl0 + 4;
         nc = nc0;
         need_carve = false;
@@ -802,11 +818,12 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
         if (rc == 2) continue;                           // too large: carve per simplex
         npl = compact_planes(S, npl, nc);
         if (npl <= VD_F_MAX && npl + 4 <= VD_P_MAX && nc <= VD_CB_MAX) {
-          save_cell(S, npl, nc);
+          save_cell(S, C, npl, nc);
           npl0 = npl;
           nc0 = nc;
           saved = true;
           cellpos = __ballot(l < npl && S.plab[l] >= 0);
+          cell_lab = l < npl ? S.plab[l] : 0;
         }
         continue;
       }
@@ -935,7 +952,7 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
   }
   // neighbours of the pieces cut from the saved cell
   for (uint64_t m = nbmask; m && !err; m &= m - 1) {
-    const int lab = uni(S.bplab[__ffsll((unsigned long long)m) - 1]);
+    const int lab = __builtin_amdgcn_readlane(cell_lab, __ffsll((unsigned long long)m) - 1);
     bool have = false;
     for (int e = l; e < nnb; e += 64) have = have || (S.nbl[e] == lab);
     if (!__ballot(have)) {
@@ -983,7 +1000,7 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
 
 // Persistent: every workgroup (one wave) takes sites from the queues until
 // all are done.
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) site_kernel(GridView G, DomainView D, const CellsDev *__restrict__ Cp) {
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3))) site_kernel(GridView G, DomainView D, const CellsDev *__restrict__ Cp) {
   __shared__ WaveLds S;
   const CellsDev &C = *Cp;
   arena_init(S.ar);

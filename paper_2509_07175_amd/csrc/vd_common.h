@@ -358,7 +358,7 @@ __device__ __forceinline__ int nn_thread(const GridView &G, double qx, double qy
 // candidate.  The block is the largest one (half-width <= 8 cells) whose sites
 // fit, sized from the density of the 3x3x3 block around the site.
 // ---------------------------------------------------------------------------
-#define VD_CACHE 224
+#define VD_CACHE 128
 #define VD_CACHE_SCRATCH 288  // doubles of scratch cache_fill needs (bucket starts, bucket sets)
 
 struct SiteCache {

@@ -18,6 +18,9 @@
 #define VD_NB_MAX 96   // distinct neighbours of one site
 #define VD_F_MAX 48    // planes of a saved cell (cell-first mode)
 #define VD_CB_MAX 96   // corners of a saved cell
+// doubles of one wave's saved cell in global memory: planes (4 doubles each),
+// corners (3 doubles each), then plane flags and corner planes / neighbours
+#define VD_SAVE_DOUBLES (VD_F_MAX * 4 + VD_CB_MAX * 3 + (VD_F_MAX + 2 * VD_CB_MAX + 1) / 2)
 
 // Output arenas.  Waves reserve chunks of an arena with one atomic on its
 // counter and hand out slots from the chunk, so a counter is the arena's
@@ -171,6 +174,7 @@ struct CellsDev {
   long long chunk[AR_N];  // slots a wave reserves at a time in each arena
   int *queue;             // [VD_QUEUES * VD_QSTRIDE] work-queue heads
   int *tq_spill;          // [workgroups * VD_Q_SPILL] overflow of the per-site simplex queue
+  double *saved;          // [workgroups * VD_SAVE_DOUBLES] each wave's carved cell (cell-first mode)
 };
 
 struct vd_cells_s {
