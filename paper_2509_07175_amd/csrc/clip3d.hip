@@ -61,6 +61,10 @@ struct __align__(16) WaveLds {
   int pfirst[VD_P_MAX];      // lowest corner slot on each plane (face walks)
   WaveArena ar;              // output chunks, queue position, statistics
   SiteCache K;               // sites around v_i for the nearest-site queries
+  // per-site sums and neighbour masks (uniform; kept here rather than in
+  // registers that would be live across the whole carve)
+  double acc[5];             // volume, first moment (relative to v_i), energy
+  unsigned long long cellpos, nbmask;
 };
 
 __device__ __forceinline__ int p8(int packed, int e) { return (packed >> (8 * e)) & 0xff; }
@@ -763,9 +767,13 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
   // pieces cut from the saved cell: their bisector faces are cell planes, so
   // the neighbours found are a mask over the cell's plane slots (cellpos: the
   // slots whose flag is a site), turned into a list once per site
-  uint64_t cellpos = 0, nbmask = 0;
+  if (l == 0) {
+    for (int k = 0; k < 5; k++) S.acc[k] = 0.0;
+    S.cellpos = 0ull;
+    S.nbmask = 0ull;
+  }
   int cell_lab = 0;  // lane x: the flag of the cell's plane x
-  double Mv = 0, Mx = 0, My = 0, Mz = 0, Me = 0;
+
   if (C.cache) {
     cache_fill(S.K, G, X.vx, X.vy, X.vz, &S.cy[0][0]);  // the corner array is free until the carve
   } else {
@@ -822,7 +830,10 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
           npl0 = npl;
           nc0 = nc;
           saved = true;
-          cellpos = __ballot(l < npl && S.plab[l] >= 0);
+          {
+            const uint64_t cp = __ballot(l < npl && S.plab[l] >= 0);
+            if (l == 0) S.cellpos = cp;
+          }
           cell_lab = l < npl ? S.plab[l] : 0;
         }
         continue;
@@ -864,7 +875,7 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
     pv = wave_sum(pv); pmx = wave_sum(pmx); pmy = wave_sum(pmy); pmz = wave_sum(pmz); pe = wave_sum(pe);
     fmask = wave_or64(fmask);
     if (!(pv > 0.0)) continue;
-    Mv += pv; Mx += pmx; My += pmy; Mz += pmz; Me += pe;
+    if (l == 0) { S.acc[0] += pv; S.acc[1] += pmx; S.acc[2] += pmy; S.acc[3] += pmz; S.acc[4] += pe; }
     // ---- emit the piece ----
     const int nface = __popcll(fmask);
     const long long pidx = arena_take(S.ar, C, AR_PIECE, 1);
@@ -915,7 +926,7 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
     // A piece cut from the saved cell adds its cell planes to the mask; only
     // the four planes of T_a can lead to other tetrahedra.
     const bool from_cell = saved && !need_carve;
-    if (from_cell) nbmask |= fmask & cellpos;
+    if (from_cell && l == 0) S.nbmask |= fmask & S.cellpos;
     for (uint64_t m = from_cell ? fmask & (15ull << npl0) : fmask; m; m &= m - 1) {
       const int x = __ffsll((unsigned long long)m) - 1;
       const int lab = uni(S.plab[x]);
@@ -951,7 +962,8 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
     __syncthreads();
   }
   // neighbours of the pieces cut from the saved cell
-  for (uint64_t m = nbmask; m && !err; m &= m - 1) {
+  __syncthreads();
+  for (uint64_t m = S.nbmask; m && !err; m &= m - 1) {
     const int lab = __builtin_amdgcn_readlane(cell_lab, __ffsll((unsigned long long)m) - 1);
     bool have = false;
     for (int e = l; e < nnb; e += 64) have = have || (S.nbl[e] == lab);
@@ -966,11 +978,12 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
   // ---- per-site results ----
   const long long ns0 = arena_take(S.ar, C, AR_NBR, nnb);
   if (l == 0) {
+    const double Mv = S.acc[0];
     GL(C.mass)[orig] = Mv;
-    GL(C.mom)[3 * (long long)orig + 0] = Mx + Mv * X.vx;
-    GL(C.mom)[3 * (long long)orig + 1] = My + Mv * X.vy;
-    GL(C.mom)[3 * (long long)orig + 2] = Mz + Mv * X.vz;
-    GL(C.energy)[orig] = Me;
+    GL(C.mom)[3 * (long long)orig + 0] = S.acc[1] + Mv * X.vx;
+    GL(C.mom)[3 * (long long)orig + 1] = S.acc[2] + Mv * X.vy;
+    GL(C.mom)[3 * (long long)orig + 2] = S.acc[3] + Mv * X.vz;
+    GL(C.energy)[orig] = S.acc[4];
     GL(C.pcount)[orig] = npieces;
     GL(C.ncount)[orig] = nnb;
     GL(C.nstart)[orig] = ns0;

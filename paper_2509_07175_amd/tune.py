@@ -14,7 +14,7 @@ from __future__ import annotations
 import itertools
 
 DEFAULT_SPACE = {
-    "sites_per_cell": (2.0, 3.5, 6.0),
+    "sites_per_cell": (1.0, 2.0, 3.5),
     "site_cache": (1, 0),
     "improved_search": (1, 0),
     "use_straddle_edges": (1,),
