@@ -473,7 +473,9 @@ __device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, c
 }
 
 // Persistent: every workgroup (one wave) takes triangles from the queues.
-__global__ void __launch_bounds__(64) surface_kernel(GridView G, DomainView D, const CellsDev *__restrict__ Cp) {
+// Four waves per SIMD (128 VGPRs, a few spilled values): the polygon carve is
+// latency-bound, and the extra wave hides more of it than the spills cost.
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) surface_kernel(GridView G, DomainView D, const CellsDev *__restrict__ Cp) {
   __shared__ TriLds S;
   const CellsDev &C = *Cp;
   arena_init(S.ar);
