@@ -94,6 +94,30 @@ def cpu_baseline(sites, dom, target_s=15.0):
                       f"{elapsed:.2f} s wall on {threads} threads"}
 
 
+def cpu_single_thread(log):
+    """The oracle on one host thread: the 1,000-site cube in full (brute force,
+    every bisector, and pruned) and 2,000 sampled sites of the 100,000-site
+    workload (pruned)."""
+    import numpy as np
+    import oracle
+    import vdgen
+    oracle.build(force=False)
+    out = {}
+    s1, d1 = vdgen.config_c1()
+    for mode, brute in (("c1_brute", True), ("c1_pruned", False)):
+        t0 = time.perf_counter()
+        oracle.compute(s1, d1, brute=brute, threads=1)
+        out[mode + "_cells_per_s"] = len(s1) / (time.perf_counter() - t0)
+    s2, d2 = vdgen.config_c2()
+    sample = np.sort(np.random.default_rng(6).choice(len(s2), size=2000, replace=False)).astype(np.int32)
+    t0 = time.perf_counter()
+    oracle.compute(s2, d2, only_sites=sample, threads=1)
+    out["c2_sample_cells_per_s"] = len(sample) / (time.perf_counter() - t0)
+    out["cores"] = 1
+    log(f"oracle on one thread: {out}")
+    return out
+
+
 def bench_batched(steps, warmup, log):
     """256 independent diagrams: sequential plain calls vs one autotuned batch
     (grid build + clip + moments) captured in a HIP graph and replayed."""
@@ -501,6 +525,7 @@ def main():
         out["batched"] = bench_batched(max(1, min(args.steps, 5)), 1, log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sites, dom)
+        out["cpu_single_thread"] = cpu_single_thread(log)
     print(json.dumps(out), flush=True)
 
 
