@@ -180,6 +180,20 @@ def test_monte_carlo_nearest_site_labelling(oracle_mod):
     assert np.all(np.abs(frac - m["mass"]) <= 5 * sigma + 1e-12)
 
 
+def test_parity_inputs_are_in_general_position(oracle_mod):
+    """The inputs of the bit-exact parity tests keep every decisive sign of the
+    oracle's cuts well away from zero (relative margin |signed distance| /
+    (|n| (|x| + |n|)) far above the FP64 error of the predicate), so their piece
+    sets and labels are unique and any correct implementation must reproduce
+    them exactly."""
+    cases = [vdgen.small_case(300, 3, seed=5), vdgen.small_case(777, 5, seed=7),
+             vdgen.small_case(2000, 4, seed=6), vdgen.config_c1(),
+             vdgen.small_case(1500, 6, seed=9, jitter_domain=0.1)]
+    for sites, dom in cases:
+        r = oracle_mod.compute(sites, dom, brute=False)
+        assert r["min_margin"] > 1e-9, r["min_margin"]
+
+
 def test_invariants(oracle_mod):
     sites, dom = vdgen.small_case(150, 3, seed=8)
     r = oracle_mod.compute(sites, dom, brute=True)
