@@ -397,6 +397,8 @@ def main():
     ap.add_argument("--no-backward", action="store_true", help="skip the adjoint throughput")
     ap.add_argument("--no-peaks", action="store_true", help="skip the measured FMA / copy peaks")
     ap.add_argument("--no-small", action="store_true", help="skip the 1k- and 100k-site cube workloads")
+    ap.add_argument("--lloyd", type=int, default=0,
+                    help="also time this many Lloyd iterations (sites <- centroids) on the workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -507,6 +509,20 @@ def main():
                      "mass_sum": total_mass},
     }
     log = lambda m: print(f"bench: {m}", file=sys.stderr, flush=True)  # noqa: E731
+    if args.lloyd > 0:
+        ls = torch.as_tensor(sites, dtype=torch.float64, device=dev).contiguous()
+        vd.lloyd(ls, d, 1, options=vd.Options.default(), bbox=bbox, sites_per_cell=rho)  # sizes the arenas
+        ls.copy_(torch.as_tensor(sites, dtype=torch.float64))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, energies = vd.lloyd(ls, d, args.lloyd, options=vd.Options.default(), bbox=bbox, sites_per_cell=rho,
+                               energy=True)
+        torch.cuda.synchronize()
+        lt = time.perf_counter() - t0
+        out["lloyd"] = {"iterations": args.lloyd, "s_per_iteration": lt / args.lloyd,
+                        "cells_per_s": n * args.lloyd / lt, "energy_first": energies[0], "energy_last": energies[-1]}
+        log(f"lloyd: {args.lloyd} iterations, {lt / args.lloyd * 1e3:.1f} ms each, energy {energies[0]:.6g} -> "
+            f"{energies[-1]:.6g}")
     if not args.no_peaks:
         pk = measured_peaks(log)
         out["measured_peaks"] = pk

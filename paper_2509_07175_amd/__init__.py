@@ -18,7 +18,7 @@ import os
 
 import numpy as np
 
-__all__ = ["load", "Options", "Grid", "Domain", "Cells", "build_grid", "clip_cells",
+__all__ = ["load", "Options", "Grid", "Domain", "Cells", "build_grid", "clip_cells", "lloyd",
            "VoronoiMoments", "VDError", "BOUNDARY_BASE"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -384,6 +384,38 @@ def clip_cells(grid: Grid, domain: Domain, options: Options | None = None, cells
                stream=None) -> Cells:
     c = cells if cells is not None else Cells()
     return c.clip(grid, domain, options, stream)
+
+
+def lloyd(sites, domain: Domain, iterations: int, options: Options | None = None, bbox=None,
+          sites_per_cell: float = 0.0, surface_area: float = 0.0, energy: bool = False, stream=None):
+    """Lloyd iterations towards a centroidal Voronoi tessellation with density 1
+    (Sec. 7.4): every iteration builds the grid, clips the cells and moves each
+    site to its cell's centroid.  The centroids are written by the moments
+    kernel straight over `sites` (n x 3 float64 on the device), which is updated
+    in place and returned; with energy=True, the CVT energy (Eq. 3) of every
+    iteration's diagram is returned as well.
+
+    A site must stay inside the domain, which holds for convex domains (a cell's
+    centroid lies in the cell).  For a surface, centroids are not projected back
+    onto it."""
+    import torch
+    if sites.dtype != torch.float64 or not sites.is_cuda or sites.dim() != 2 or sites.shape[1] != 3:
+        raise ValueError("sites must be an (n, 3) float64 CUDA tensor")
+    if not sites.is_contiguous():
+        raise ValueError("sites must be contiguous (it is updated in place)")
+    n = sites.shape[0]
+    grid, cells = Grid(), Cells()
+    mass = torch.empty(n, dtype=torch.float64, device=sites.device)
+    en = torch.empty(n, dtype=torch.float64, device=sites.device)
+    energies = []
+    for _ in range(int(iterations)):
+        build_grid(sites, bbox=bbox, sites_per_cell=sites_per_cell, surface_area=surface_area, grid=grid,
+                   stream=stream)
+        clip_cells(grid, domain, options, cells=cells, stream=stream)
+        cells.moments(mass, sites, en, stream=stream)  # the grid holds its own sorted copy of the sites
+        if energy:
+            energies.append(float(en.sum().item()))
+    return (sites, energies) if energy else sites
 
 
 def pieces_as_result(view: dict) -> dict:
