@@ -105,10 +105,10 @@ const char *vd_status_string(vd_status s);
 /* ---------------------------------------------------------------------
  * vd_build_grid -- uniform grid over the sites for nearest-site queries
  * (Sec. 6.2), built by counting sort: per-site cell ids and a histogram,
- * an exclusive scan into cell offsets, a scatter of the coordinates into
- * cell order (sites of one cell ordered by index), and for every site
- * delta_i = |N_i - v_i| / 2, half the distance to its nearest other site
- * (Sec. 6.1).
+ * an exclusive scan into cell offsets and a scatter of the coordinates into
+ * cell order (sites of one cell ordered by index).  delta_i = |N_i - v_i| / 2,
+ * half the distance to its nearest other site (Sec. 6.1), is computed on the
+ * grid by the first vd_clip_cells with improved_search = 1 after a build.
  *   sites      [n*3] device, caller-owned; read during the call's stream work only.
  *   n          >= 1.
  *   bbox_host  [6] host (xmin,ymin,zmin,xmax,ymax,zmax) or NULL; the grid box

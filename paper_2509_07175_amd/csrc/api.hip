@@ -610,6 +610,7 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
     d.emit = opt.emit_polytopes ? 1 : 0;
     d.want_grad = opt.want_grad ? 1 : 0;
     d.improved = opt.improved_search ? 1 : 0;
+    if (d.improved && !g->delta_valid) vd_launch_grid_delta(g, st);
     d.straddle = opt.use_straddle_edges ? 1 : 0;
     d.max_iters = opt.max_search_iters;
     d.mode = (dom->dim == 3 && opt.carve_mode == 1) ? 1 : 0;

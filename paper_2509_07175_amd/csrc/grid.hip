@@ -202,5 +202,11 @@ void vd_launch_grid_build(vd_grid g, const double *sites, const double *user_box
   hipLaunchKernelGGL(grid_sort_cells, dim3(blocks(g->ncell)), dim3(kB), 0, st, (long long)g->ncell,
                      (const int *)g->cstart, g->sx, g->sy, g->sz, g->perm);
   hipLaunchKernelGGL(grid_rank, dim3(blocks(n)), dim3(kB), 0, st, n, (const int *)g->perm, g->rank);
-  hipLaunchKernelGGL(grid_delta, dim3(blocks(n)), dim3(kB), 0, st, g->view(), g->delta);
+  g->delta_valid = false;
+}
+
+// delta_i of every site (only the improved search of Sec. 6.1 reads it)
+void vd_launch_grid_delta(vd_grid g, hipStream_t st) {
+  hipLaunchKernelGGL(grid_delta, dim3(blocks(g->n)), dim3(kB), 0, st, g->view(), g->delta);
+  g->delta_valid = true;
 }

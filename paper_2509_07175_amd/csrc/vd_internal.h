@@ -47,6 +47,7 @@ struct vd_grid_s {
   double *geom = nullptr;     // [9 nb]: lo[3], h[3], ih[3] per diagram
   double *bbox_part = nullptr;  // per-block partial boxes
   double *sx = nullptr, *sy = nullptr, *sz = nullptr, *delta = nullptr;
+  bool delta_valid = false;   // delta is computed by the first clip that needs it after a build
   int *perm = nullptr, *rank = nullptr, *cellid = nullptr, *fill = nullptr;
   int *cstart = nullptr, *ccount = nullptr, *scan_tmp = nullptr;
   // batch of nb diagrams (nb = 1: plain)
@@ -207,6 +208,7 @@ struct vd_cells_s {
 
 // launchers (defined in the .hip files)
 void vd_launch_grid_build(vd_grid g, const double *sites, const double *user_box, hipStream_t st);
+void vd_launch_grid_delta(vd_grid g, hipStream_t st);
 void vd_launch_domain_locator(vd_domain d, hipStream_t st);
 void vd_launch_locate_sites(const GridView &G, const DomainView &D, int *seed, unsigned long long *cnt,
                             hipStream_t st);
