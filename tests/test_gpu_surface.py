@@ -49,6 +49,16 @@ def test_sphere_search_variants(oracle_mod, straddle, improved):
                   improved_search=improved)
 
 
+def test_planar_l_polygon(oracle_mod):
+    """A 2D clipped Voronoi diagram on a non-convex polygon (an L of 0.75 area,
+    6 x 6 squares of 2 triangles minus a quarter): sites in the plane of a flat
+    mesh, whose restricted cells are the 2D clipped cells."""
+    dom = vdgen.planar_l_polygon(6)
+    s = vdgen.planar_l_sites(500, seed=31)
+    gpu = _surface_case(oracle_mod, s, dom, brute=True)
+    assert abs(gpu["mass"].sum() - 0.75) < 1e-12
+
+
 def test_sites_off_the_surface(oracle_mod):
     """Sites at radius 0.8..1.2 around the sphere mesh (not on it)."""
     rng = np.random.default_rng(21)

@@ -268,6 +268,43 @@ def config_c5():
     return sphere_sites(200_000, seed=106), icosphere(6)
 
 
+def planar_l_polygon(k: int) -> Domain:
+    """L-shaped polygon in the plane z = 0: the unit square without its upper
+    right quarter, on a k x k grid of squares (k even), each split into two
+    counter-clockwise triangles.  A 2D clipped Voronoi diagram of sites in the
+    plane is the restricted diagram of this flat mesh."""
+    assert k % 2 == 0
+    used = {}
+    verts, tris = [], []
+
+    def vid(x, y):
+        if (x, y) not in used:
+            used[(x, y)] = len(verts)
+            verts.append((x / k, y / k, 0.0))
+        return used[(x, y)]
+    for y in range(k):
+        for x in range(k):
+            if x >= k // 2 and y >= k // 2:
+                continue
+            a, b, c, d = vid(x, y), vid(x + 1, y), vid(x + 1, y + 1), vid(x, y + 1)
+            tris += [[a, b, c], [a, c, d]]
+    tris = np.array(tris, dtype=np.int32)
+    return Domain(verts=np.array(verts, dtype=np.float64), simplices=tris, adj=adjacency(tris), dim=2)
+
+
+def planar_l_sites(n: int, seed: int) -> np.ndarray:
+    """n uniform sites in the L-shaped polygon (rejection), jittered off the grid lines."""
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < n:
+        p = rng.uniform(1e-6, 1 - 1e-6, size=2)
+        if p[0] >= 0.5 and p[1] >= 0.5:
+            continue
+        out.append(p)
+    p2 = np.array(out)
+    return np.c_[p2, np.zeros(n)]
+
+
 def small_case(n: int, k: int, seed: int, jitter_domain: float = 0.0):
     """Small 3D case used by tests: n uniform sites in a k^3-cube Kuhn grid."""
     return (uniform_cube_sites(n, seed=seed, jitter=1e-7),
