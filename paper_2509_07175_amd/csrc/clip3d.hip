@@ -1012,7 +1012,9 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
 }
 
 // Persistent: every workgroup (one wave) takes sites from the queues until
-// all are done.
+// all are done.  Three waves per SIMD: 168 VGPRs (a few values spill around
+// the carve) and 12.7 KB of LDS per wave (the carved cell is kept in a global
+// buffer); the third wave hides more LDS and memory latency than that costs.
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3))) site_kernel(GridView G, DomainView D, const CellsDev *__restrict__ Cp) {
   __shared__ WaveLds S;
   const CellsDev &C = *Cp;
