@@ -135,6 +135,30 @@ def test_c2_full_size_sampled(oracle_mod):
             assert i in set(nb[j].tolist())
 
 
+@pytest.mark.parametrize("mode", [1, 0])
+def test_near_degenerate_lattice(oracle_mod, mode):
+    """Cube-centre lattice of 8^3 sites with a 1e-7 jitter (every lattice
+    vertex is then nearly equidistant to eight sites): the near-degenerate
+    case of the method.  Several encodings of the vanishing faces are correct,
+    so only the moments are compared: per site with the oracle to 1e-9
+    relative, and with the closed forms of the lattice (mass h^3, energy h^5/4)
+    to O(jitter)."""
+    k = 8
+    s = vdgen.lattice_sites(k, 1e-7, seed=3)
+    dom = vdgen.kuhn_cube_grid(4)
+    gpu = run_gpu(s, dom, carve_mode=mode)
+    ref = oracle_mod.site_moments(oracle_mod.compute(s, dom, brute=False), s)
+    log(f"lattice info {gpu['info']}")
+    assert abs(gpu["mass"].sum() - 1.0) < 1e-12
+    assert np.all(np.abs(gpu["mass"] - ref["mass"]) <= 1e-9 * ref["mass"])
+    cerr = np.linalg.norm(gpu["centroid"] - ref["centroid"], axis=1) / np.linalg.norm(ref["centroid"], axis=1)
+    assert cerr.max() <= 1e-9
+    assert np.all(np.abs(gpu["energy"] - ref["energy"]) <= 1e-9 * ref["energy"])
+    h = 1.0 / k
+    assert np.allclose(gpu["mass"], h ** 3, rtol=1e-5)
+    assert np.allclose(gpu["energy"], h ** 5 / 4, rtol=1e-4)
+
+
 def test_c3_full_size_sampled(oracle_mod):
     """The headline workload in the benchmark's launch configuration: 1,000,000
     clustered sites in 750,000 tetrahedra, grid at 0.25 sites per cell, default
