@@ -59,10 +59,10 @@ def workload(name):
     import vdgen
     if name == "c1":
         s, d = vdgen.config_c1()
-        return s, d, "C1: 1,000 uniform sites, unit cube as 6 tetrahedra", 3.5
+        return s, d, "C1: 1,000 uniform sites, unit cube as 6 tetrahedra", 2.0
     if name == "c2":
         s, d = vdgen.config_c2()
-        return s, d, "C2: 100,000 uniform sites, 20^3 cubes x 6 = 48,000 tetrahedra", 3.5
+        return s, d, "C2: 100,000 uniform sites, 20^3 cubes x 6 = 48,000 tetrahedra", 2.0
     if name == "cube5m":
         # the shape of the paper's own GPU headline run (white noise in a cube); context only
         s = vdgen.uniform_cube_sites(5_000_000, seed=108, jitter=1e-7)

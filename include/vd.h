@@ -113,7 +113,7 @@ const char *vd_status_string(vd_status s);
  *   n          >= 1.
  *   bbox_host  [6] host (xmin,ymin,zmin,xmax,ymax,zmax) or NULL; the grid box
  *              is the union of this box and the sites' bounding box.
- *   sites_per_cell  mean sites per grid cell (<= 0 -> 3.5).
+ *   sites_per_cell  mean sites per grid cell (<= 0 -> 2 in 3D, 3.5 for a surface).
  *   surface_area    > 0 for sites spread over a surface of this area: the
  *              cell size then targets sites_per_cell per non-empty cell.
  *   out        *out == NULL -> a new handle; else the handle is rebuilt in place.

@@ -93,7 +93,7 @@ const char *vd_status_string(vd_status s) {
 
 void vd_options_default(vd_options *opt) {
   if (!opt) return;
-  opt->sites_per_cell = 3.5;
+  opt->sites_per_cell = 2.0;
   opt->improved_search = 0;
   opt->use_straddle_edges = 1;
   opt->max_search_iters = 64;
@@ -173,7 +173,9 @@ vd_status build_grid_impl(const double *sites, int64_t n, int nb, const int64_t 
         if (!(hi >= lo) || !std::isfinite(lo) || !std::isfinite(hi))
           return fail(VD_ERR_INVALID_ARG, "%s: invalid bbox of diagram %d", who, b);
       }
-  const double rho = sites_per_cell > 0 ? sites_per_cell : 3.5;
+  // defaults: 2 sites per cell in 3D (the per-wave site cache covers the near
+  // ring, so smaller cells than the paper's 3-4 pay), 3.5 per non-empty cell on a surface
+  const double rho = sites_per_cell > 0 ? sites_per_cell : (surface_area > 0 ? 3.5 : 2.0);
   std::vector<int> dims(3 * (size_t)nb);
   std::vector<int64_t> coff(nb + 1, 0);
   for (int b = 0; b < nb; b++) {

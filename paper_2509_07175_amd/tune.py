@@ -37,7 +37,7 @@ def tune(sites, domain, site_off=None, bboxes=None, bbox=None, space: dict | Non
     grid, cells = Grid(), Cells()
     for combo in itertools.product(*(space[k] for k in keys)):
         knobs = dict(zip(keys, combo))
-        rho = knobs.get("sites_per_cell", 3.5)
+        rho = knobs.get("sites_per_cell", 2.0)
         opt_kw = dict(base_options or {})
         opt_kw.update({k: v for k, v in knobs.items() if k != "sites_per_cell"})
         opt_kw["time_kernels"] = 1
