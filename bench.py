@@ -509,6 +509,23 @@ def main():
                      "mass_sum": total_mass},
     }
     log = lambda m: print(f"bench: {m}", file=sys.stderr, flush=True)  # noqa: E731
+    # the same step with the other search variants of the paper (identical results)
+    variants = {}
+    for name, kw in (("improved_search", dict(improved_search=1)), ("virtual_edges_only", dict(use_straddle_edges=0))):
+        vopt = vd.Options.default(time_kernels=1, emit_polytopes=0 if args.no_emit else 1, carve_mode=args.carve_mode,
+                                  site_cache=args.site_cache, **kw)
+        vg, vc = vd.Grid(), vd.Cells()
+        best = None
+        for _ in range(2):
+            vd.build_grid(s, bbox=bbox, sites_per_cell=rho, grid=vg)
+            vd.clip_cells(vg, d, vopt, cells=vc)
+            vi = vc.info()
+            best = vi["carve_ms"] if best is None else min(best, vi["carve_ms"])
+        variants[name] = {"site_kernel_ms": best, "nn_queries": vi["nn_queries"], "clips": vi["clips"],
+                          "n_pieces": vi["n_pieces"]}
+        log(f"variant {name}: site kernel {best:.2f} ms, {vi['nn_queries'] / n:.1f} queries per cell")
+        del vg, vc
+    out["search_variants"] = variants
     if args.lloyd > 0:
         ls = torch.as_tensor(sites, dtype=torch.float64, device=dev).contiguous()
         vd.lloyd(ls, d, 1, options=vd.Options.default(), bbox=bbox, sites_per_cell=rho)  # sizes the arenas
