@@ -391,7 +391,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--carve-mode", type=int, default=1, choices=[0, 1])
     ap.add_argument("--improved", type=int, default=0, choices=[0, 1])
-    ap.add_argument("--straddle", type=int, default=1, choices=[0, 1])
+    ap.add_argument("--straddle", type=int, default=0, choices=[0, 1])
     ap.add_argument("--site-cache", type=int, default=1, choices=[0, 1])
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-diagrams comparison")
     ap.add_argument("--no-backward", action="store_true", help="skip the adjoint throughput")
@@ -511,7 +511,7 @@ def main():
     log = lambda m: print(f"bench: {m}", file=sys.stderr, flush=True)  # noqa: E731
     # the same step with the other search variants of the paper (identical results)
     variants = {}
-    for name, kw in (("improved_search", dict(improved_search=1)), ("virtual_edges_only", dict(use_straddle_edges=0))):
+    for name, kw in (("improved_search", dict(improved_search=1)), ("straddling_edges", dict(use_straddle_edges=1))):
         vopt = vd.Options.default(time_kernels=1, emit_polytopes=0 if args.no_emit else 1, carve_mode=args.carve_mode,
                                   site_cache=args.site_cache, **kw)
         vg, vc = vd.Grid(), vd.Cells()

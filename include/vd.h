@@ -73,7 +73,9 @@ typedef struct {
                               about what a near one does, so the extra lambda queries
                               no longer pay (same results either way) */
   int32_t use_straddle_edges; /* 1: prefer edges with one inside end (Alg. 1);
-                                 0: virtual edges from the site only (Alg. 3) */
+                                 0: virtual edges from the site only (Alg. 3).
+                                 Default 0: the same number of queries and a
+                                 simpler edge choice (same results either way) */
   int32_t max_search_iters;   /* cap of the bisector search and of the lambda loop */
   int32_t emit_polytopes;     /* 1: write per-piece faces and vertices */
   int32_t want_grad;          /* 1: also store the face integrals the adjoint needs */

@@ -95,7 +95,7 @@ void vd_options_default(vd_options *opt) {
   if (!opt) return;
   opt->sites_per_cell = 2.0;
   opt->improved_search = 0;
-  opt->use_straddle_edges = 1;
+  opt->use_straddle_edges = 0;
   opt->max_search_iters = 64;
   opt->emit_polytopes = 1;
   opt->want_grad = 0;

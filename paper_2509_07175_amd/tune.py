@@ -17,7 +17,7 @@ DEFAULT_SPACE = {
     "sites_per_cell": (1.0, 2.0, 3.5),
     "site_cache": (1, 0),
     "improved_search": (1, 0),
-    "use_straddle_edges": (1,),
+    "use_straddle_edges": (0,),
 }
 
 

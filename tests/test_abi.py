@@ -31,7 +31,7 @@ def test_host_only_entry_points():
     import paper_2509_07175_amd as vd
     lib = vd.load()
     o = vd.Options.default()
-    assert o.sites_per_cell == 2.0 and o.improved_search == 0 and o.use_straddle_edges == 1
+    assert o.sites_per_cell == 2.0 and o.improved_search == 0 and o.use_straddle_edges == 0
     assert lib.vd_status_string(4) == b"VD_ERR_CAPACITY"
     # argument checks happen before any device work
     h = C.c_void_p()
