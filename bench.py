@@ -394,6 +394,7 @@ def main():
     ap.add_argument("--straddle", type=int, default=0, choices=[0, 1])
     ap.add_argument("--site-cache", type=int, default=1, choices=[0, 1])
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-diagrams comparison")
+    ap.add_argument("--no-variants", action="store_true", help="skip timing the other search variants")
     ap.add_argument("--no-backward", action="store_true", help="skip the adjoint throughput")
     ap.add_argument("--no-peaks", action="store_true", help="skip the measured FMA / copy peaks")
     ap.add_argument("--no-small", action="store_true", help="skip the 1k- and 100k-site cube workloads")
@@ -511,7 +512,8 @@ def main():
     log = lambda m: print(f"bench: {m}", file=sys.stderr, flush=True)  # noqa: E731
     # the same step with the other search variants of the paper (identical results)
     variants = {}
-    for name, kw in (("improved_search", dict(improved_search=1)), ("straddling_edges", dict(use_straddle_edges=1))):
+    for name, kw in () if args.no_variants else (("improved_search", dict(improved_search=1)),
+                                                  ("straddling_edges", dict(use_straddle_edges=1))):
         vopt = vd.Options.default(time_kernels=1, emit_polytopes=0 if args.no_emit else 1, carve_mode=args.carve_mode,
                                   site_cache=args.site_cache, **kw)
         vg, vc = vd.Grid(), vd.Cells()
@@ -525,7 +527,8 @@ def main():
                           "n_pieces": vi["n_pieces"]}
         log(f"variant {name}: site kernel {best:.2f} ms, {vi['nn_queries'] / n:.1f} queries per cell")
         del vg, vc
-    out["search_variants"] = variants
+    if variants:
+        out["search_variants"] = variants
     if args.lloyd > 0:
         ls = torch.as_tensor(sites, dtype=torch.float64, device=dev).contiguous()
         vd.lloyd(ls, d, 1, options=vd.Options.default(), bbox=bbox, sites_per_cell=rho)  # sizes the arenas

@@ -255,22 +255,31 @@ static int clip3(const opoly *P, const opl *h, opoly *Q, double *margin) {
 }
 
 /* Moments of a polytope relative to the site: volume, first moment and
- * integral of |y|^2, on a fan of tetrahedra (origin, y0, yj, yj+1). */
+ * integral of |y|^2, on a fan of tetrahedra (o, y0, yj, yj+1) whose apex o
+ * is a vertex of the polytope.  Any apex gives the same sums in exact
+ * arithmetic; an apex on the polytope keeps the rounding error of the volume
+ * proportional to the polytope's own size, so a piece far smaller than its
+ * distance to the site still gets a volume of the right sign. */
 static void poly_moments3(const opoly *P, double *vol, double *mom, double *en) {
   double V = 0, M[3] = {0, 0, 0}, E = 0;
+  const double *o = P->vx[0].y;
   for (int f = 0; f < P->nfc; f++) {
     const ofc *F = &P->fc[f];
     const double *a = P->vx[F->v[0]].y;
+    double ao[3];
+    sub3(a, o, ao);
     for (int t = 1; t + 1 < F->nv; t++) {
       const double *b = P->vx[F->v[t]].y, *c = P->vx[F->v[t + 1]].y;
-      double bc[3];
-      cross3(b, c, bc);
-      double v6 = dot3(a, bc) / 6.0;
-      double S[3] = {a[0] + b[0] + c[0], a[1] + b[1] + c[1], a[2] + b[2] + c[2]};
+      double bo[3], co[3], bc[3];
+      sub3(b, o, bo);
+      sub3(c, o, co);
+      cross3(bo, co, bc);
+      double v6 = dot3(ao, bc) / 6.0;
+      double S[3] = {o[0] + a[0] + b[0] + c[0], o[1] + a[1] + b[1] + c[1], o[2] + a[2] + b[2] + c[2]};
       V += v6;
       for (int k = 0; k < 3; k++) M[k] += v6 * S[k] / 4.0;
-      /* integral of |y|^2 over tet (0,a,b,c) = V/20 (sum |y_k|^2 + |sum y_k|^2) */
-      E += v6 / 20.0 * (dot3(a, a) + dot3(b, b) + dot3(c, c) + dot3(S, S));
+      /* integral of |y|^2 over tet (o,a,b,c) = V/20 (sum |y_k|^2 + |sum y_k|^2) */
+      E += v6 / 20.0 * (dot3(o, o) + dot3(a, a) + dot3(b, b) + dot3(c, c) + dot3(S, S));
     }
   }
   *vol = V;

@@ -36,8 +36,8 @@
 // fill of R_p, the fan of the new face and compaction are wave-parallel;
 // tested/inside/removed sets are 128-bit ballot masks.
 //
-// Moments of a piece: a fan of tetrahedra (v_i, foot of the face plane,
-// corner, next corner around the face), three per corner, reduced across the
+// Moments of a piece: a fan of tetrahedra (corner 0 of the piece, foot of the
+// face plane, corner, next corner around the face), three per corner, reduced across the
 // wave with butterfly shuffles (fixed order, no floating-point atomics).
 #include <type_traits>
 
@@ -843,15 +843,22 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
     }
     if (err) break;
     if (empty) continue;
-    // ---- moments of the piece ----
+    // ---- moments of the piece: fan of tetrahedra (o, foot of plane x seen
+    // from o, corner, next corner) with the apex o at corner 0, so that the
+    // volume's rounding error scales with the piece and not with its distance
+    // to v_i (a tip of the cell in a far tetrahedron keeps a positive volume)
     double pv = 0, pmx = 0, pmy = 0, pmz = 0, pe = 0;
     uint64_t fmask = 0;
+    const double o0 = S.cy[0][0], o1 = S.cy[0][1], o2 = S.cy[0][2];
+    const double oo = o0 * o0 + o1 * o1 + o2 * o2;
 #pragma unroll 1
     for (int h = 0; h < 2; h++) {
       const int s = l + 64 * h;
       if (s >= nc) continue;
       const int pl = S.cpl[s], nb = S.cnb[s];
-      const double y0 = S.cy[s][0], y1 = S.cy[s][1], y2 = S.cy[s][2];
+      const double Y0 = S.cy[s][0], Y1 = S.cy[s][1], Y2 = S.cy[s][2];
+      const double y0 = Y0 - o0, y1 = Y1 - o1, y2 = Y2 - o2;
+      const double YY = Y0 * Y0 + Y1 * Y1 + Y2 * Y2;
       fmask |= (1ull << p8(pl, 0)) | (1ull << p8(pl, 1)) | (1ull << p8(pl, 2));
       // plane p8(pl,e) continues around its face to the corner across edge (e+2)%3
 #pragma unroll 1
@@ -859,17 +866,19 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
         const int x = p8(pl, e);
         const int nx_ = p8(nb, (e + 2) % 3);
         const double n0 = S.pn[x][0], n1 = S.pn[x][1], n2 = S.pn[x][2], cc = S.pn[x][3];
-        const double f = cc / (n0 * n0 + n1 * n1 + n2 * n2);
+        const double f = (cc - (n0 * o0 + n1 * o1 + n2 * o2)) / (n0 * n0 + n1 * n1 + n2 * n2);
         const double r0 = n0 * f, r1 = n1 * f, r2 = n2 * f;
-        const double z0 = S.cy[nx_][0], z1 = S.cy[nx_][1], z2 = S.cy[nx_][2];
+        const double Z0 = S.cy[nx_][0], Z1 = S.cy[nx_][1], Z2 = S.cy[nx_][2];
+        const double z0 = Z0 - o0, z1 = Z1 - o1, z2 = Z2 - o2;
         const double det = r0 * (y1 * z2 - y2 * z1) - r1 * (y0 * z2 - y2 * z0) + r2 * (y0 * z1 - y1 * z0);
         const double vol = det / 6.0;
-        const double s0 = r0 + y0 + z0, s1 = r1 + y1 + z1, s2 = r2 + y2 + z2;
+        // the tetrahedron's corners relative to v_i: o, o + r, Y, Z
+        const double R0 = o0 + r0, R1 = o1 + r1, R2 = o2 + r2;
+        const double s0 = o0 + R0 + Y0 + Z0, s1 = o1 + R1 + Y1 + Z1, s2 = o2 + R2 + Y2 + Z2;
         pv += vol;
         pmx += vol * s0 * 0.25; pmy += vol * s1 * 0.25; pmz += vol * s2 * 0.25;
         pe += vol * (1.0 / 20.0) *
-              (r0 * r0 + r1 * r1 + r2 * r2 + y0 * y0 + y1 * y1 + y2 * y2 + z0 * z0 + z1 * z1 + z2 * z2 +
-               s0 * s0 + s1 * s1 + s2 * s2);
+              (oo + R0 * R0 + R1 * R1 + R2 * R2 + YY + Z0 * Z0 + Z1 * Z1 + Z2 * Z2 + s0 * s0 + s1 * s1 + s2 * s2);
       }
     }
     pv = wave_sum(pv); pmx = wave_sum(pmx); pmy = wave_sum(pmy); pmz = wave_sum(pmz); pe = wave_sum(pe);

@@ -345,24 +345,24 @@ __device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, c
     const int rc = carve_s(S, G, P, si, vx, vy, vz, delta, npl, nv, ss);
     if (rc == 1) continue;
     if (rc) { err = rc; break; }
-    // ---- moments: fan from the foot of v_i on the supporting plane ----
-    const double N0 = S.pn[0][0], N1 = S.pn[0][1], N2 = S.pn[0][2], Nc = S.pn[0][3];
-    const double nn2 = N0 * N0 + N1 * N1 + N2 * N2;
-    const double fN = Nc / nn2, inrm = 1.0 / sqrt(nn2);
-    const double r0 = N0 * fN, r1 = N1 * fN, r2 = N2 * fN;
+    // ---- moments: fan from corner 0 of the piece, so that the area's rounding
+    // error scales with the piece and not with its distance to v_i ----
+    const double N0 = S.pn[0][0], N1 = S.pn[0][1], N2 = S.pn[0][2];
+    const double inrm = 1.0 / sqrt(N0 * N0 + N1 * N1 + N2 * N2);
+    const double o0 = S.vy[0][0], o1 = S.vy[0][1], o2 = S.vy[0][2];
     double pa = 0, pmx = 0, pmy = 0, pmz = 0, pe = 0;
     if (l < nv) {
       const int t2 = (l + 1) % nv;
-      const double a0 = S.vy[l][0] - r0, a1 = S.vy[l][1] - r1, a2 = S.vy[l][2] - r2;
-      const double b0 = S.vy[t2][0] - r0, b1 = S.vy[t2][1] - r1, b2 = S.vy[t2][2] - r2;
-      const double cr0 = a1 * b2 - a2 * b1, cr1 = a2 * b0 - a0 * b2, cr2 = a0 * b1 - a1 * b0;
-      const double ar = 0.5 * (cr0 * N0 + cr1 * N1 + cr2 * N2) * inrm;
       const double y0 = S.vy[l][0], y1 = S.vy[l][1], y2 = S.vy[l][2];
       const double z0 = S.vy[t2][0], z1 = S.vy[t2][1], z2 = S.vy[t2][2];
-      const double s0 = r0 + y0 + z0, s1 = r1 + y1 + z1, s2 = r2 + y2 + z2;
+      const double a0 = y0 - o0, a1 = y1 - o1, a2 = y2 - o2;
+      const double b0 = z0 - o0, b1 = z1 - o1, b2 = z2 - o2;
+      const double cr0 = a1 * b2 - a2 * b1, cr1 = a2 * b0 - a0 * b2, cr2 = a0 * b1 - a1 * b0;
+      const double ar = 0.5 * (cr0 * N0 + cr1 * N1 + cr2 * N2) * inrm;
+      const double s0 = o0 + y0 + z0, s1 = o1 + y1 + z1, s2 = o2 + y2 + z2;
       pa = ar;
       pmx = ar * s0 / 3.0; pmy = ar * s1 / 3.0; pmz = ar * s2 / 3.0;
-      pe = ar / 12.0 * (r0 * r0 + r1 * r1 + r2 * r2 + y0 * y0 + y1 * y1 + y2 * y2 + z0 * z0 + z1 * z1 + z2 * z2 +
+      pe = ar / 12.0 * (o0 * o0 + o1 * o1 + o2 * o2 + y0 * y0 + y1 * y1 + y2 * y2 + z0 * z0 + z1 * z1 + z2 * z2 +
                         s0 * s0 + s1 * s1 + s2 * s2);
     }
     pa = wave_sum(pa); pmx = wave_sum(pmx); pmy = wave_sum(pmy); pmz = wave_sum(pmz); pe = wave_sum(pe);

@@ -136,6 +136,33 @@ def test_c2_full_size_sampled(oracle_mod):
 
 
 @pytest.mark.parametrize("mode", [1, 0])
+def test_tiny_tetrahedra_far_from_their_sites(oracle_mod, mode):
+    """The 2x2x2 Kuhn grid with its middle coordinate moved to 2^-20: a corner
+    cube of six tetrahedra of volume eps^3/6 (and thin slabs beside it), ~1.5
+    away from the six sites.  Every such piece is emitted with its exact
+    volume; a moment fan with its apex at the site rounds these volumes to
+    noise of either sign and drops pieces."""
+    eps = 2.0 ** -20
+    base = vdgen.kuhn_cube_grid(2)
+    v = base.verts.copy()
+    v[v == 0.5] = eps
+    dom = vdgen.Domain(verts=v, simplices=base.simplices, adj=base.adj, dim=3)
+    rng = np.random.default_rng(7)
+    s = 0.75 + 0.2 * rng.random((6, 3))
+    gpu = run_gpu(s, dom, carve_mode=mode)
+    ref = oracle_mod.compute(s, dom, brute=True)
+    # the slab tetrahedra beside the corner cube have dihedral angles ~eps, so
+    # a vertex on two of their planes is conditioned ~1/eps: two FP64
+    # evaluations agree to ~1e-16/eps = 1e-10, checked here with 100x room
+    assert_parity(gpu, ref, oracle_mod.site_moments(ref, s), len(s), xyz_tol=1e-8)
+    corner = np.nonzero(ref["piece_simplex"] < 6)[0]
+    assert len(corner) == 6
+    assert np.allclose(ref["piece_mass"][corner], eps ** 3 / 6, rtol=1e-9, atol=0)
+    got = gpu["res"]["piece_mass"][gpu["res"]["piece_simplex"] < 6]
+    assert len(got) == 6 and np.allclose(got, eps ** 3 / 6, rtol=1e-9, atol=0)
+
+
+@pytest.mark.parametrize("mode", [1, 0])
 def test_near_degenerate_lattice(oracle_mod, mode):
     """Cube-centre lattice of 8^3 sites with a 1e-7 jitter (every lattice
     vertex is then nearly equidistant to eight sites): the near-degenerate
@@ -195,7 +222,9 @@ def test_c3_full_size_sampled(oracle_mod):
     assert off[0] == 0 and off[-1] == used.sum() and np.all(np.diff(off) >= 1)
     rng = np.random.default_rng(3003)
     order = np.argsort(mass)
-    sample = np.unique(np.concatenate([rng.choice(n, size=24, replace=False), order[:12], order[-12:]]))
+    # site 908627: a vertex of its cell lies 1.4e-8 inside tetrahedron 718229,
+    # a piece of volume 1.8e-23 about 0.015 from the site
+    sample = np.unique(np.concatenate([rng.choice(n, size=24, replace=False), order[:12], order[-12:], [908627]]))
     ref = oracle_mod.compute(sites, dom, only_sites=sample)
     mom = oracle_mod.site_moments(ref, sites)
     a = canon_pieces(sampled_result(view, sample))

@@ -107,6 +107,32 @@ def test_single_site_is_whole_domain(oracle_mod):
     assert len(r["piece_site"]) == dom.m
 
 
+def test_tiny_piece_far_from_its_site(oracle_mod):
+    """A piece whose size is far below its distance to the site: with one site
+    every piece is a whole tetrahedron, so the volume of a corner tetrahedron
+    with legs 2^-20 placed ~1.7 away is eps^3/6 exactly.  A fan whose apex is
+    the site carries ~1e-16 of rounding here (|y|^3 * machine epsilon), 1000x
+    the volume itself, which flips the sign of the volume and drops the
+    piece; an apex on the piece keeps the error ~1e-9 relative."""
+    cube = vdgen.kuhn_cube_grid(1)
+    eps = 2.0 ** -20
+    p0 = np.array([1.25, 1.5, 1.75])
+    tiny = np.stack([p0, p0 + [eps, 0, 0], p0 + [0, eps, 0], p0 + [0, 0, eps]])
+    nv = len(cube.verts)
+    verts = np.concatenate([cube.verts, tiny])
+    tets = np.concatenate([cube.simplices, np.array([[nv, nv + 1, nv + 2, nv + 3]], dtype=cube.simplices.dtype)])
+    dom = vdgen.Domain(verts=verts, simplices=tets, adj=vdgen.adjacency(tets), dim=3)
+    v = np.array([[0.3, 0.6, 0.45]])
+    r = oracle_mod.compute(v, dom, brute=True)
+    assert len(r["piece_site"]) == dom.m
+    k = int(np.nonzero(r["piece_simplex"] == dom.m - 1)[0][0])
+    vol = eps ** 3 / 6
+    assert abs(r["piece_mass"][k] - vol) <= 1e-8 * vol
+    cen = p0 + eps / 4
+    assert np.allclose(r["piece_moment"][k] / r["piece_mass"][k], cen, rtol=0, atol=1e-12)
+    assert abs(r["piece_energy"][k] - vol * np.sum((cen - v[0]) ** 2)) <= 1e-8 * vol
+
+
 def test_two_sites_split_the_cube(oracle_mod):
     dom = vdgen.kuhn_cube_grid(1)
     x1, x2 = 0.23, 0.61
