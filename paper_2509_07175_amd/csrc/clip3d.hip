@@ -145,7 +145,7 @@ __device__ int compact_planes(WaveLds &S, int npl, int nc) {
 // leaving R_p and form the fan of the new face.
 // Returns 0 (nothing outside: unchanged), 1 empty, 2 capacity, 3 degenerate,
 // 4 cut (nc updated).
-__device__ int clip_poly(WaveLds &S, int P, int pt, int &nc) {
+__device__ int clip_poly(WaveLds &S, int P, int pt, int &nc, int ps = -1, int kcert = -1) {
   const int l = vd_lane();
   const double nx = S.pn[P][0], ny = S.pn[P][1], nz = S.pn[P][2], c = S.pn[P][3];
   int pl[2] = {0, 0}, nb[2] = {0, 0}, cs[2] = {0, 0};
@@ -274,7 +274,9 @@ __device__ int clip_poly(WaveLds &S, int P, int pt, int &nc) {
             const int ns = nsurv + t;
             S.cpl[ns] = pack3(u, w, P);
             S.cnb[ns] = pack3(nbn[h][e], S.byFirst[w], S.bySecond[u]);
-            S.cst[ns] = 0;
+            // the corner on the search edge (pt, ps) is the point the search's
+            // last query tested, with the same flags: already known inside
+            S.cst[ns] = (ps >= 0 && l + 64 * h == pt && p8(nb[h], e) == ps) ? (3 | ((kcert + 1) << 8)) : 0;
             t++;
           }
     }
@@ -325,6 +327,8 @@ __device__ int carve(WaveLds &S, const GridView &G, const CarveParams C, const S
   const int grp = l >> 4;
   int mode = PICK;
   int pt = -1, j = -1, ef0 = -2, ef1 = -2, lam = 2, nstep = 0;
+  int ps_edge = -1;   // inside end of the search edge when it is an edge of P
+  bool qon = false;   // the search point lies strictly inside its edge
   int tslot = -1, nbatch = 0;
   double A0 = 0, A1 = 0, A2 = 0, g0 = 0, g1 = 0, g2 = 0, u0 = 0, u1 = 0, u2 = 0, L = 0;
   double n0 = 0, n1 = 0, n2 = 0, nc3 = 0;
@@ -336,6 +340,7 @@ __device__ int carve(WaveLds &S, const GridView &G, const CarveParams C, const S
     const double e0 = g0 - A0, e1 = g1 - A1, e2 = g2 - A2;
     const double den = n0 * e0 + n1 * e1 + n2 * e2;
     const double num = nc3 - (n0 * A0 + n1 * A1 + n2 * A2);
+    qon = den > 0.0 && num > 0.0 && num < den;
     double t = den > 0.0 ? num / den : 1.0;
     t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
     q0 = A0 + t * e0; q1 = A1 + t * e1; q2 = A2 + t * e2;
@@ -389,6 +394,7 @@ __device__ int carve(WaveLds &S, const GridView &G, const CarveParams C, const S
           }
         }
         if (pt < 0) pt = olo ? __ffsll((unsigned long long)olo) - 1 : 64 + __ffsll((unsigned long long)ohi) - 1;
+        ps_edge = ps;
         A0 = A1 = A2 = 0;
         if (ps >= 0) { A0 = S.cy[ps][0]; A1 = S.cy[ps][1]; A2 = S.cy[ps][2]; }
         g0 = S.cy[pt][0]; g1 = S.cy[pt][1]; g2 = S.cy[pt][2];
@@ -497,7 +503,7 @@ __device__ int carve(WaveLds &S, const GridView &G, const CarveParams C, const S
       S.plab[P] = j;
     }
     __syncthreads();
-    const int rc = clip_poly(S, P, pt, nc);
+    const int rc = clip_poly(S, P, pt, nc, ps_edge >= 0 && qon ? ps_edge : -1, k);
     st.clips++;
     if (rc == 1) return 1;
     if (rc != 4) return rc == 0 ? 3 : rc;
