@@ -94,7 +94,7 @@ def test_jittered_domain(oracle_mod):
 
 
 @pytest.mark.parametrize("mode", [1, 0])
-@pytest.mark.parametrize("straddle,improved", [(0, 1), (1, 0), (0, 0)])
+@pytest.mark.parametrize("straddle,improved", [(0, 1), (1, 0), (0, 0), (1, 1)])
 def test_search_variants_same_result(oracle_mod, straddle, improved, mode):
     """Alg. 1 vs Alg. 3 edges and the improved search change the path, not the result."""
     sites, dom = vdgen.small_case(800, 3, seed=13)
