@@ -59,6 +59,32 @@ def test_planar_l_polygon(oracle_mod):
     assert abs(gpu["mass"].sum() - 0.75) < 1e-12
 
 
+def test_tiny_triangles_far_from_their_sites(oracle_mod):
+    """The flat L-polygon mesh with its first grid line moved to 2^-30: a corner
+    square of two triangles of area eps^2/2 about 0.5 from the five sites.
+    Both pieces are emitted with their exact area; a fan with its apex at the
+    site's foot point carries ~1e-17 of rounding here, 40x the area."""
+    eps = 2.0 ** -30
+    base = vdgen.planar_l_polygon(4)
+    v = base.verts.copy()
+    v[:, :2][v[:, :2] == 0.25] = eps
+    dom = vdgen.Domain(verts=v, simplices=base.simplices, adj=base.adj, dim=2)
+    rng = np.random.default_rng(5)
+    s = np.zeros((5, 3))
+    s[:, 0] = 0.3 + 0.15 * rng.random(5)
+    s[:, 1] = 0.3 + 0.15 * rng.random(5)
+    area = float(_area(dom).sum())
+    gpu = run_gpu(s, dom, bbox=(-1.01, -1.01, -1.01, 1.01, 1.01, 1.01), surface_area=area)
+    ref = oracle_mod.compute(s, dom, brute=True)
+    # the thin strips beside the corner square end in tips of angle ~eps/0.25,
+    # so a vertex on two of their edges is fixed only to ~1e-16 * 0.5 / 3.7e-9
+    # = 1.5e-8 by either side's arithmetic; checked with ~70x room
+    assert_parity(gpu, ref, oracle_mod.site_moments(ref, s), len(s), xyz_tol=1e-6)
+    assert abs(gpu["mass"].sum() - area) <= 1e-12 * area
+    got = gpu["res"]["piece_mass"][gpu["res"]["piece_simplex"] < 2]
+    assert len(got) == 2 and np.allclose(got, eps ** 2 / 2, rtol=1e-9, atol=0)
+
+
 def test_sites_off_the_surface(oracle_mod):
     """Sites at radius 0.8..1.2 around the sphere mesh (not on it)."""
     rng = np.random.default_rng(21)
