@@ -133,6 +133,32 @@ def test_tiny_piece_far_from_its_site(oracle_mod):
     assert abs(r["piece_energy"][k] - vol * np.sum((cen - v[0]) ** 2)) <= 1e-8 * vol
 
 
+def test_tiny_triangles_far_from_their_sites(oracle_mod):
+    """2D analogue of the tiny-piece pin: the flat L-polygon mesh with its first
+    grid line moved to 2^-30 has a corner square of two right triangles of area
+    eps^2/2, about 0.5 from every site, so each is a whole piece of one site
+    with exactly that area and the centroid of its three corners."""
+    eps = 2.0 ** -30
+    base = vdgen.planar_l_polygon(4)
+    v = base.verts.copy()
+    v[:, :2][v[:, :2] == 0.25] = eps
+    dom = vdgen.Domain(verts=v, simplices=base.simplices, adj=base.adj, dim=2)
+    rng = np.random.default_rng(5)
+    s = np.zeros((5, 3))
+    s[:, 0] = 0.3 + 0.15 * rng.random(5)
+    s[:, 1] = 0.3 + 0.15 * rng.random(5)
+    r = oracle_mod.compute(s, dom, brute=True)
+    for t in (0, 1):
+        k = np.nonzero(r["piece_simplex"] == t)[0]
+        assert len(k) == 1
+        k = int(k[0])
+        assert abs(r["piece_mass"][k] - eps ** 2 / 2) <= 1e-9 * eps ** 2 / 2
+        cen = v[dom.simplices[t]].mean(axis=0)
+        assert np.allclose(r["piece_moment"][k] / r["piece_mass"][k], cen, rtol=0, atol=1e-15)
+        d = np.linalg.norm(s - cen, axis=1)
+        assert r["piece_site"][k] == int(np.argmin(d))
+
+
 def test_two_sites_split_the_cube(oracle_mod):
     dom = vdgen.kuhn_cube_grid(1)
     x1, x2 = 0.23, 0.61
