@@ -404,8 +404,9 @@ def main():
                     help="only run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on exactly one GPU (asked for {args.gpus}); "
-              "the multi-GPU design is described in DESIGN.md", file=sys.stderr)
+        print(f"bench.py: the benchmark measures exactly one GPU (asked for {args.gpus}); a multi-GPU run "
+              "would give each GPU a range of grid-ordered sites with the sites, grid and domain replicated",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
