@@ -768,7 +768,7 @@ static double box_dist(const double *lo, const double *hi, const double *p) {
 }
 
 /* ------------------------------------------------------------------ */
-/* driver                                                                */
+/* entry point                                                           */
 /* ------------------------------------------------------------------ */
 typedef struct { int32_t site, simp; int thread; int64_t idx; } pkey;
 static int cmp_pkey(const void *x, const void *y) {
