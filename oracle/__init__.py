@@ -22,19 +22,28 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "vd_oracle.c")
 _LIB = os.path.join(_HERE, "libvdoracle.so")
+_LIB_NATIVE = os.path.join(_HERE, "libvdoracle_native.so")
 _lib = None
+_lib_native = None
 
 BOUNDARY_BASE = -2**31  # domain-boundary face f carries BOUNDARY_BASE + f
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle into oracle/libvdoracle.so (gcc, -O2, OpenMP)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.run(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", _SRC,
+def build(force: bool = True, native: bool = False) -> str:
+    """Compile the oracle with gcc and OpenMP.
+
+    native=False: oracle/libvdoracle.so, -O3 for the generic x86-64 target, so
+    the same binary runs (and rounds the same way) on any host; the tests use it.
+    native=True: oracle/libvdoracle_native.so, -O3 -march=native, built on the
+    host that runs it; only the CPU-baseline timing uses it."""
+    lib = _LIB_NATIVE if native else _LIB
+    if force or not os.path.exists(lib):
+        tmp = lib + ".tmp"
+        flags = ["-O3", "-march=native"] if native else ["-O3"]
+        subprocess.run(["gcc", *flags, "-std=c11", "-fopenmp", "-fPIC", "-shared", _SRC,
                         "-o", tmp, "-lm"], check=True)
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, lib)
+    return lib
 
 
 class _Result(C.Structure):
@@ -60,12 +69,13 @@ class _Result(C.Structure):
     ]
 
 
-def _load():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB):
-            build()
-        lib = C.CDLL(_LIB)
+def _load(native: bool = False):
+    global _lib, _lib_native
+    if (_lib_native if native else _lib) is None:
+        path = _LIB_NATIVE if native else _LIB
+        if not os.path.exists(path):
+            build(native=native)
+        lib = C.CDLL(path)
         lib.vdo_compute.restype = C.c_int
         lib.vdo_compute.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
                                     C.c_void_p, C.c_int64, C.c_int, C.c_int, C.c_void_p,
@@ -75,8 +85,11 @@ def _load():
         lib.vdo_moments_backward.restype = C.c_int
         lib.vdo_moments_backward.argtypes = [C.POINTER(_Result)] + [C.c_void_p, C.c_int64] + \
             [C.c_void_p] * 7 + [C.c_int, C.c_void_p]
-        _lib = lib
-    return _lib
+        if native:
+            _lib_native = lib
+        else:
+            _lib = lib
+    return _lib_native if native else _lib
 
 
 def _arr(ptr, n, dtype):
@@ -110,12 +123,13 @@ class _Keep:
 
 
 def compute(sites, domain, brute: bool = False, only_sites=None, threads: int = 0,
-            keep_handle: bool = False):
+            keep_handle: bool = False, native: bool = False):
     """All pieces P_{a,i} (Eq. 1) of the sites in ``domain`` (a vdgen.Domain).
 
     Returns a dict of NumPy arrays, pieces sorted by (site, simplex).
+    native=True runs the -march=native build (timing only).
     """
-    lib = _load()
+    lib = _load(native)
     s = np.ascontiguousarray(sites, dtype=np.float64)
     v = np.ascontiguousarray(domain.verts, dtype=np.float64)
     t = np.ascontiguousarray(domain.simplices, dtype=np.int32)

@@ -768,6 +768,82 @@ static double box_dist(const double *lo, const double *hi, const double *p) {
 }
 
 /* ------------------------------------------------------------------ */
+/* oracle-own uniform grid over the simplices' bounding boxes: finds the  */
+/* candidate simplices of one site (sampled-site mode) without a scan of  */
+/* all m simplices                                                        */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  double lo[3], h;
+  int g[3];
+  int32_t *start; /* [ncell+1] */
+  int32_t *ids;   /* simplices overlapping each cell */
+  double rmax;    /* largest Lipschitz radius r_a */
+} osgrid;
+
+static void oscoord(const osgrid *S, const double *p, int *c) {
+  for (int k = 0; k < 3; k++) {
+    double t = floor((p[k] - S->lo[k]) / S->h);
+    c[k] = t < 0 ? 0 : (t >= S->g[k] ? S->g[k] - 1 : (int)t);
+  }
+}
+
+static int64_t oscell(const osgrid *S, int x, int y, int z) { return x + (int64_t)S->g[0] * (y + (int64_t)S->g[1] * z); }
+
+static int osgrid_build(osgrid *S, const octx *C, int64_t m, const double *ra) {
+  double lo[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, hi[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
+  S->rmax = 0;
+  for (int64_t a = 0; a < m; a++) {
+    double l[3], h[3], dm;
+    simplex_box(C, a, l, h, &dm);
+    for (int k = 0; k < 3; k++) { if (l[k] < lo[k]) lo[k] = l[k]; if (h[k] > hi[k]) hi[k] = h[k]; }
+    if (ra[a] > S->rmax) S->rmax = ra[a];
+  }
+  double ext = 0;
+  for (int k = 0; k < 3; k++) if (hi[k] - lo[k] > ext) ext = hi[k] - lo[k];
+  if (ext <= 0) ext = 1;
+  int gm = (int)ceil(cbrt((double)m / 2.0));
+  if (gm < 1) gm = 1;
+  S->h = ext / gm * (1.0 + 1e-12);
+  for (int k = 0; k < 3; k++) {
+    S->lo[k] = lo[k];
+    S->g[k] = (int)ceil((hi[k] - lo[k]) / S->h);
+    if (S->g[k] < 1) S->g[k] = 1;
+  }
+  int64_t nc = (int64_t)S->g[0] * S->g[1] * S->g[2];
+  S->start = (int32_t *)calloc(nc + 1, sizeof(int32_t));
+  if (!S->start) return 2;
+  /* two passes: count, then fill */
+  for (int pass = 0; pass < 2; pass++) {
+    int32_t *fill = NULL;
+    if (pass == 1) {
+      for (int64_t c = 0; c < nc; c++) S->start[c + 1] += S->start[c];
+      S->ids = (int32_t *)malloc(sizeof(int32_t) * (S->start[nc] > 0 ? S->start[nc] : 1));
+      fill = (int32_t *)malloc(sizeof(int32_t) * (nc + 1));
+      if (!S->ids || !fill) { free(fill); return 2; }
+      memcpy(fill, S->start, sizeof(int32_t) * (nc + 1));
+    }
+    for (int64_t a = 0; a < m; a++) {
+      double l[3], h[3], dm;
+      int c0[3], c1[3];
+      simplex_box(C, a, l, h, &dm);
+      oscoord(S, l, c0);
+      oscoord(S, h, c1);
+      for (int z = c0[2]; z <= c1[2]; z++)
+        for (int y = c0[1]; y <= c1[1]; y++)
+          for (int x = c0[0]; x <= c1[0]; x++) {
+            int64_t c = oscell(S, x, y, z);
+            if (pass == 0) S->start[c + 1]++;
+            else S->ids[fill[c]++] = (int32_t)a;
+          }
+    }
+    free(fill);
+  }
+  return 0;
+}
+
+static void osgrid_free(osgrid *S) { free(S->start); free(S->ids); }
+
+/* ------------------------------------------------------------------ */
 /* entry point                                                           */
 /* ------------------------------------------------------------------ */
 typedef struct { int32_t site, simp; int thread; int64_t idx; } pkey;
@@ -829,6 +905,15 @@ int vdo_compute(const double *sites, int64_t n, const double *verts, int64_t nv,
   }
 
   if (only_sites) {
+    /* the candidate simplices of site i are those with dist(v_i, box_a) <= r_a
+     * (the same Lipschitz filter as the full mode); they are found through a
+     * grid over the simplices' boxes, within r_max of v_i */
+    osgrid SG;
+    memset(&SG, 0, sizeof SG);
+    if (osgrid_build(&SG, &C, m, ra)) {
+      osgrid_free(&SG); free(ra); free(bufs); ogrid_free(&G);
+      return 2;
+    }
 #pragma omp parallel num_threads(nt)
     {
 #ifdef _OPENMP
@@ -839,27 +924,43 @@ int vdo_compute(const double *sites, int64_t n, const double *verts, int64_t nv,
       obuf *b = &bufs[tid];
       opoly *PA = (opoly *)malloc(sizeof(opoly)), *PB = (opoly *)malloc(sizeof(opoly));
       ogon *GA = (ogon *)malloc(sizeof(ogon)), *GB = (ogon *)malloc(sizeof(ogon));
-      if (!PA || !PB || !GA || !GB) b->err = 2;
+      int64_t *stamp = (int64_t *)malloc(sizeof(int64_t) * m); /* last query that saw each simplex */
+      if (!PA || !PB || !GA || !GB || !stamp) b->err = 2;
+      else for (int64_t a = 0; a < m; a++) stamp[a] = -1;
 #pragma omp for schedule(dynamic, 1)
       for (int64_t q = 0; q < n_only; q++) {
         int64_t i = only_sites[q];
         if (b->err || i < 0 || i >= n) { if (i < 0 || i >= n) b->err = 1; continue; }
         const double *v = &sites[3 * i];
-        for (int64_t a = 0; a < m; a++) {
-          double lo[3], hi[3], dm;
-          simplex_box(&C, a, lo, hi, &dm);
-          if (box_dist(lo, hi, v) > ra[a]) continue;
-          int which;
-          int r = carve_pair(&C, a, i, PA, PB, GA, GB, &which, &b->margin);
-          if (r == 3) { b->err = 3; break; }
-          if (r == 1) {
-            if (simplex_dim == 3) emit_poly3(b, PA, (int32_t)i, (int32_t)a, v);
-            else emit_gon(b, GA, (int32_t)i, (int32_t)a, v);
-          }
-        }
+        double qlo[3], qhi[3];
+        for (int k = 0; k < 3; k++) { qlo[k] = v[k] - SG.rmax; qhi[k] = v[k] + SG.rmax; }
+        int c0[3], c1[3];
+        oscoord(&SG, qlo, c0);
+        oscoord(&SG, qhi, c1);
+        for (int z = c0[2]; z <= c1[2] && !b->err; z++)
+          for (int y = c0[1]; y <= c1[1] && !b->err; y++)
+            for (int x = c0[0]; x <= c1[0] && !b->err; x++) {
+              int64_t ci = oscell(&SG, x, y, z);
+              for (int32_t t = SG.start[ci]; t < SG.start[ci + 1]; t++) {
+                int64_t a = SG.ids[t];
+                if (stamp[a] == q) continue;
+                stamp[a] = q;
+                double lo[3], hi[3], dm;
+                simplex_box(&C, a, lo, hi, &dm);
+                if (box_dist(lo, hi, v) > ra[a]) continue;
+                int which;
+                int r = carve_pair(&C, a, i, PA, PB, GA, GB, &which, &b->margin);
+                if (r == 3) { b->err = 3; break; }
+                if (r == 1) {
+                  if (simplex_dim == 3) emit_poly3(b, PA, (int32_t)i, (int32_t)a, v);
+                  else emit_gon(b, GA, (int32_t)i, (int32_t)a, v);
+                }
+              }
+            }
       }
-      free(PA); free(PB); free(GA); free(GB);
+      free(PA); free(PB); free(GA); free(GB); free(stamp);
     }
+    osgrid_free(&SG);
   } else {
 #pragma omp parallel num_threads(nt)
     {

@@ -62,7 +62,10 @@ typedef struct {
 /* Clipped VD (simplex_dim 3, k = 4) or restricted VD (simplex_dim 2, k = 3).
  * sites [n*3], verts [nv*3], simp [m*k], adj [m*k] (-1 = boundary).
  * only_sites: NULL -> all sites; else n_only site indices whose pieces are
- * computed (pruned mode only).  threads <= 0 -> OpenMP default. */
+ * computed (pruned mode only); their candidate simplices are found through a
+ * grid over the simplices' bounding boxes with the same Lipschitz filter as
+ * the full run, so each listed site gets exactly the pieces the full run
+ * gives it.  threads <= 0 -> OpenMP default. */
 int vdo_compute(const double *sites, int64_t n, const double *verts, int64_t nv,
                 const int32_t *simp, const int32_t *adj, int64_t m, int simplex_dim,
                 int brute, const int32_t *only_sites, int64_t n_only, int threads,

@@ -36,3 +36,23 @@ def compare_canon(a, b, xyz_tol):
         if len(a[k][2]):
             md = max(md, float(np.abs(a[k][2] - b[k][2]).max()))
     return nkey, ncomb, md
+
+
+def subset_result(r, pieces):
+    """The pieces with the given indices (ascending) of a result, in the same
+    layout (face and vertex arrays gathered, offsets rebuilt)."""
+    pieces = np.asarray(pieces, dtype=np.int64)
+    fo, vo = r["piece_face_off"], r["piece_vert_off"]
+    nf = fo[pieces + 1] - fo[pieces]
+    nv = vo[pieces + 1] - vo[pieces]
+    fidx = np.concatenate([np.arange(fo[p], fo[p + 1]) for p in pieces]) if len(pieces) else np.zeros(0, np.int64)
+    vidx = np.concatenate([np.arange(vo[p], vo[p + 1]) for p in pieces]) if len(pieces) else np.zeros(0, np.int64)
+    out = {k: r[k][pieces] for k in ("piece_site", "piece_simplex", "piece_mass", "piece_moment", "piece_energy")}
+    out["piece_face_off"] = np.concatenate([[0], np.cumsum(nf)]).astype(np.int64)
+    out["piece_vert_off"] = np.concatenate([[0], np.cumsum(nv)]).astype(np.int64)
+    out["face_label"] = r["face_label"][fidx]
+    out["vert_xyz"] = r["vert_xyz"][vidx]
+    out["vert_label"] = r["vert_label"][vidx]
+    if "face_measure" in r:
+        out["face_measure"] = r["face_measure"][fidx]
+    return out

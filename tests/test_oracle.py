@@ -13,7 +13,7 @@ from scipy.optimize import linprog
 from scipy.spatial import ConvexHull, HalfspaceIntersection
 
 import vdgen
-from canon import canon_pieces, compare_canon
+from canon import canon_pieces, compare_canon, subset_result
 
 BND = -2**31
 
@@ -499,3 +499,114 @@ def test_adjoint_central_differences(oracle_mod, surface):
             e = np.zeros((n, 3)); e[i, k] = 1.0
             fd = (_loss(oracle_mod, s + h * e, dom, gm, gc, ge) - _loss(oracle_mod, s - h * e, dom, gm, gc, ge)) / (2 * h)
             assert abs(fd - g[i, k]) <= 1e-6 * max(1.0, abs(g[i, k]))
+
+
+# --- face measures (areas of faces, lengths of edges) -------------------------
+
+def _face_sums(r, site):
+    """Sum of face_measure over the pieces of `site`, by face label."""
+    out = {}
+    for p in np.nonzero(r["piece_site"] == site)[0]:
+        for f in range(r["piece_face_off"][p], r["piece_face_off"][p + 1]):
+            lab = int(r["face_label"][f])
+            out[lab] = out.get(lab, 0.0) + float(r["face_measure"][f])
+    return out
+
+
+def test_face_measure_two_sites_cube(oracle_mod):
+    """Two sites split the unit cube at x = xm: the bisector face is the unit
+    square (area 1, whichever tetrahedra it crosses), the boundary of cell 0
+    has area 1 + 4 xm (the face x = 0 and four xm x 1 strips)."""
+    dom = vdgen.kuhn_cube_grid(1)
+    x1, x2 = 0.23, 0.61
+    s = np.array([[x1, 0.41, 0.52], [x2, 0.41, 0.52]])
+    r = oracle_mod.compute(s, dom, brute=True)
+    xm = 0.5 * (x1 + x2)
+    f0, f1 = _face_sums(r, 0), _face_sums(r, 1)
+    assert abs(f0[1] - 1.0) < 1e-14 and abs(f1[0] - 1.0) < 1e-14
+    bnd0 = sum(v for k, v in f0.items() if k <= BND + 3)
+    bnd1 = sum(v for k, v in f1.items() if k <= BND + 3)
+    assert abs(bnd0 - (1 + 4 * xm)) < 1e-14 and abs(bnd1 - (1 + 4 * (1 - xm))) < 1e-14
+
+
+def test_face_measure_single_site_is_the_tet_faces(oracle_mod):
+    """One site: every piece is a whole tetrahedron and each of its faces has
+    the area of the tetrahedron's face, |(b - a) x (c - a)| / 2."""
+    dom = vdgen.kuhn_cube_grid(2, jitter=0.1, seed=3)
+    v = np.array([[0.41, 0.37, 0.55]])
+    r = oracle_mod.compute(v, dom, brute=True)
+    assert len(r["piece_site"]) == dom.m
+    for p in range(dom.m):
+        a = int(r["piece_simplex"][p])
+        q = dom.verts[dom.simplices[a]]
+        for f in range(r["piece_face_off"][p], r["piece_face_off"][p + 1]):
+            lab = int(r["face_label"][f])
+            if lab <= BND + 3:
+                k = lab - BND
+            else:
+                k = int(np.nonzero(dom.adj[a] == -lab - 1)[0][0])
+            tri = q[[t for t in range(4) if t != k]]
+            area = 0.5 * np.linalg.norm(np.cross(tri[1] - tri[0], tri[2] - tri[0]))
+            assert abs(r["face_measure"][f] - area) <= 1e-14 * max(area, 1.0)
+
+
+def test_face_measure_bcc_truncated_octahedron(oracle_mod):
+    """BCC lattice (cube side a): an interior cell is a truncated octahedron with
+    6 square faces of area a^2/8 (towards the neighbours at distance a) and 8
+    regular hexagons of area 3 sqrt(3) a^2 / 16 (towards the neighbours at
+    distance a sqrt(3)/2), summed over the tetrahedra each face crosses.  The
+    1e-7 a jitter moves the areas by O(1e-7) relative."""
+    a = 0.2
+    shift = np.array([0.0123, 0.0271, 0.0391])
+    g = np.arange(-1, 7)
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    corner = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1) * a + shift
+    s = np.concatenate([corner, corner + a / 2])
+    s = s[np.all((s > 0) & (s < 1), axis=1)]
+    s = s + np.random.default_rng(17).uniform(-1e-7 * a, 1e-7 * a, size=s.shape)
+    dom = vdgen.kuhn_cube_grid(3)
+    r = oracle_mod.compute(s, dom, brute=False)
+    interior = np.nonzero(np.all((s > a + 1e-3) & (s < 1 - a - 1e-3), axis=1))[0]
+    assert len(interior) >= 20
+    sq, hexa = a * a / 8, 3 * np.sqrt(3) * a * a / 16
+    for i in interior:
+        fs = {k: v for k, v in _face_sums(r, int(i)).items() if k >= 0}
+        assert len(fs) == 14
+        for j, ar in fs.items():
+            d = np.linalg.norm(s[j] - s[i])
+            want = sq if d > 0.95 * a else hexa
+            assert abs(d - (a if want == sq else a * np.sqrt(3) / 2)) < 1e-5 * a
+            assert abs(ar - want) <= 2e-6 * want, (i, j, ar, want)
+
+
+def test_face_measure_2d_edge_lengths(oracle_mod):
+    """Flat square mesh, two sites in its plane at (x1, y), (x2, y): the bisector
+    edge is the segment x = xm across the square, of length 1; the boundary of
+    cell 0 has length 1 + 2 xm."""
+    dom = _planar_square(3)
+    x1, x2 = 0.27, 0.58
+    s = np.array([[x1, 0.43, 0.0], [x2, 0.43, 0.0]])
+    r = oracle_mod.compute(s, dom, brute=True)
+    xm = 0.5 * (x1 + x2)
+    f0 = _face_sums(r, 0)
+    assert abs(f0[1] - 1.0) < 1e-14
+    assert abs(sum(v for k, v in f0.items() if k <= BND + 2) - (1 + 2 * xm)) < 1e-14
+    assert abs(_face_sums(r, 1)[0] - 1.0) < 1e-14
+
+
+def test_sampled_sites_equal_the_full_run(oracle_mod):
+    """The sampled-site mode (candidate simplices from a grid over the simplex
+    boxes) returns exactly the pieces the full pruned run gives those sites, on
+    the 100,000-site, 48,000-tetrahedron workload."""
+    sites, dom = vdgen.config_c2()
+    full = oracle_mod.compute(sites, dom, threads=0)
+    rng = np.random.default_rng(11)
+    sample = np.sort(rng.choice(len(sites), size=3000, replace=False)).astype(np.int32)
+    part = oracle_mod.compute(sites, dom, only_sites=sample, threads=0)
+    sel = np.nonzero(np.isin(full["piece_site"], sample))[0]
+    a = canon_pieces(part)
+    b = canon_pieces(subset_result(full, sel))
+    assert len(a) == len(sel) == len(b)
+    assert compare_canon(a, b, 0.0) == (0, 0, 0.0)
+    assert np.array_equal(part["piece_mass"], full["piece_mass"][sel])
+    assert np.array_equal(part["piece_energy"], full["piece_energy"][sel])
