@@ -47,7 +47,8 @@ typedef enum {
   VD_ERR_OUT_OF_MEMORY = 2, /* a device allocation failed */
   VD_ERR_HIP = 3,           /* a HIP runtime call failed (message has details) */
   VD_ERR_CAPACITY = 4,      /* a per-wave LDS capacity was exceeded (see vd_options) */
-  VD_ERR_DEGENERATE = 5     /* a search did not converge (inputs not in general position) */
+  VD_ERR_DEGENERATE = 5,    /* a search did not converge (inputs not in general position) */
+  VD_ERR_NOT_READY = 6      /* the results of enqueued work are not available yet */
 } vd_status;
 
 typedef struct vd_grid_s *vd_grid;
@@ -97,12 +98,32 @@ typedef struct {
                                  cells around its site in LDS and answers a nearest-site
                                  query there when the query's ball lies inside the block
                                  (same answer as the grid query); 0: grid queries only */
+  int32_t boundary_seeds;     /* tetrahedral domains.  A cell Omega_i cap M can have parts that
+                                 are not connected to the tetrahedron holding v_i (a non-convex
+                                 M), and a site may lie outside M.  Such parts touch the boundary
+                                 of M, so, as in Alg. 5, the restricted diagram of the boundary
+                                 surface is computed first and every boundary triangle a cell
+                                 meets seeds the tetrahedron behind it.  -1 (default): only when
+                                 needed -- the domain is not convex or a site lies outside it
+                                 (one extra synchronisation to find out); 0: never (a site
+                                 outside M is then VD_ERR_INVALID_ARG); 1: always.  A no_sync
+                                 clip never seeds from the boundary. */
+  int32_t monitor;            /* 1: count the clips' work (query rounds, corners classified and
+                                 created, wasted tests, fan simplices) and track the relative
+                                 margins of the corner classifications (vd_cells_info_t).
+                                 Default 0: those counters cost about 8 % of the 3D kernel's time
+                                 and read -1. */
 } vd_options;
 
 void vd_options_default(vd_options *opt);
 
 const char *vd_last_error(void);
 const char *vd_status_string(vd_status s);
+
+/* Waits for all work enqueued on `stream` and reports an asynchronous device
+ * error (a fault or a failed launch) as VD_ERR_HIP.  Errors of enqueued clips
+ * (capacity, degeneracy, arena overflow) are reported by vd_cells_info. */
+vd_status vd_sync(void *stream);
 
 /* ---------------------------------------------------------------------
  * vd_build_grid -- uniform grid over the sites for nearest-site queries
@@ -130,18 +151,39 @@ void vd_grid_free(vd_grid g);
  * device: copies verts/simplices/adjacency and, for tetrahedra, builds the
  * point-location grid that finds the simplex containing each site (the seed of
  * the per-site propagation over negative face flags, Alg. 5).
- *   verts [nv*3], simplices [m*(dim+1)], adjacency [m*(dim+1)] (-1 = boundary):
- *   device pointers, caller-owned, copied during the call.
+ *   verts [nv*3], simplices [m*(dim+1)]: device pointers, caller-owned,
+ *   copied during the call.
+ *   adjacency [m*(dim+1)] (-1 = boundary), device, or NULL: then it is
+ *   computed on the device by matching the vertex sets of the simplices'
+ *   faces (a face shared by more than two simplices is an error).
  *   simplex_dim 3: tetrahedra, positively oriented, local face f opposite
  *   vertex f.  simplex_dim 2: triangles in R^3, local edge f opposite vertex f.
+ * Tetrahedral domains are also tested for convexity (vd_domain_info): M is
+ * convex iff every boundary vertex lies inside the plane of every boundary face.
  * Synchronises `stream` once (validation result).
- * Errors: VD_ERR_INVALID_ARG (indices out of range, non-positive tet volume),
- * VD_ERR_OUT_OF_MEMORY, VD_ERR_HIP.
+ * Errors: VD_ERR_INVALID_ARG (indices out of range, non-positive tet volume,
+ * non-manifold faces), VD_ERR_OUT_OF_MEMORY, VD_ERR_HIP.
  * --------------------------------------------------------------------- */
 vd_status vd_domain_create(const double *verts, int64_t nv, const int32_t *simplices,
                            const int32_t *adjacency, int64_t m, int32_t simplex_dim,
                            void *stream, vd_domain *out);
 void vd_domain_free(vd_domain d);
+
+typedef struct {
+  int64_t n_simplices, n_verts;
+  int32_t simplex_dim, n_diagrams;
+  double measure;     /* total volume (tetrahedra) or area (triangles) */
+  int32_t convex;     /* tetrahedra: 1 if every diagram's domain is convex, else 0;
+                         triangles: -1 */
+} vd_domain_info_t;
+
+/* Host struct describing a staged domain (no device work). */
+vd_status vd_domain_info(vd_domain d, vd_domain_info_t *info_host);
+
+/* Adjacency of a staged domain as used by the kernels: [m*(dim+1)] int32 into
+ * `adjacency_out` (device, caller-owned), global simplex indices for batches.
+ * Enqueued on `stream`. */
+vd_status vd_domain_adjacency(vd_domain d, int32_t *adjacency_out, void *stream);
 
 /* ---------------------------------------------------------------------
  * Batches of independent diagrams (each with its own sites and its own
@@ -186,6 +228,11 @@ vd_status vd_domain_create_batch(const double *verts, const int32_t *simplices,
  * 3D (tetrahedra): one wavefront per site; the site's tetrahedra are visited
  * through negative face flags starting from the tetrahedron that contains the
  * site (Alg. 5, propagation part), and each piece is carved by Alg. 1/Alg. 3.
+ * When the domain is not convex or a site lies outside it (see
+ * vd_options.boundary_seeds), the restricted diagram of the domain's boundary
+ * surface is computed first and every boundary triangle a cell meets seeds the
+ * tetrahedron behind it (Alg. 5), so cells that meet M in several parts, and
+ * sites outside M, get all their pieces; a site whose cell misses M gets none.
  * Surface (triangles): one wavefront per triangle; the triangle's sites are
  * found by propagation over positive edge flags from the site nearest to the
  * triangle's centroid (Alg. 4), each piece carved by Alg. 3.
@@ -194,7 +241,8 @@ vd_status vd_domain_create_batch(const double *verts, const int32_t *simplices,
  *   out     *out == NULL -> a new handle; else reused.
  * Synchronises `stream` once to read the output sizes (and re-runs with
  * larger arenas if an output arena overflowed).
- * Errors: VD_ERR_INVALID_ARG (3D: a site outside every tetrahedron),
+ * Errors: VD_ERR_INVALID_ARG (3D: a site outside every tetrahedron while the
+ * clip does not seed from the boundary: boundary_seeds = 0, or no_sync),
  * VD_ERR_CAPACITY, VD_ERR_DEGENERATE, VD_ERR_OUT_OF_MEMORY, VD_ERR_HIP.
  * --------------------------------------------------------------------- */
 vd_status vd_clip_cells(vd_grid g, vd_domain d, const vd_options *opt, void *stream,
@@ -215,13 +263,35 @@ typedef struct {
                              surfaces), measured with hipEvents on the caller's stream
                              when time_kernels = 1 (else -1) */
   double split_ms;        /* 0 when timed (no second kernel), else -1 */
+  int64_t overflow_records; /* records dropped because an output arena was full
+                               (only a no_sync clip can leave them: the status is
+                               then VD_ERR_CAPACITY) */
+  /* the next six are counted with vd_options.monitor = 1 and read -1 otherwise */
+  int64_t low_margin;     /* corner classifications against a clipping plane whose
+                             relative margin |n.y - c| / (|n0 y0|+|n1 y1|+|n2 y2|+|c|)
+                             was below 1e-12 (near-degenerate decisions) */
+  double min_margin;      /* the smallest such relative margin (1 if none below 1e-3) */
+  int64_t query_rounds;   /* nearest-site query rounds: a batch of up to four corner
+                             tests or lambda steps is one round */
+  int64_t corners_classified; /* corner-plane classifications made by the clips */
+  int64_t corners_created;    /* corners created by the clips (one 3x3 solve each) */
+  int64_t tests_wasted;   /* tested corners that a clip removed besides the one
+                             whose test led to it */
+  int64_t fan_simplices;  /* simplices of the moment fans (3D: tetrahedra, three per
+                             piece corner; surfaces: triangles, one per vertex) */
+  int64_t sites_outside;  /* 3D: sites outside every tetrahedron (-1 if not counted:
+                             a no_sync clip, or boundary_seeds = 0) */
+  int32_t boundary_seeded; /* 3D: 1 if the clip seeded cells from the boundary surface */
+  int32_t reserved_;
 } vd_cells_info_t;
 
 /* Host struct of sizes and counters (synchronises `stream` of the last call). */
 vd_status vd_cells_info(vd_cells c, vd_cells_info_t *info_host);
 
 /* Device pointers into library memory, valid until the next vd_clip_cells on
- * the same handle or vd_cells_free.  Sites and simplices use the caller's
+ * the same handle or vd_cells_free.  After a no_sync clip whose work has not
+ * finished yet this returns VD_ERR_NOT_READY (call vd_cells_info, which waits,
+ * or retry); after a failed clip it returns that clip's status.  Sites and simplices use the caller's
  * indices.  Pieces of site i are piece_id[cell_piece_off[i] .. cell_piece_off[i+1]),
  * per piece p (an index into the piece arrays):
  *   piece_site[p], piece_simplex[p], piece_mass[p], piece_moment[3p..] (first
@@ -281,6 +351,7 @@ vd_status vd_cell_moments(vd_cells c, double *mass, double *centroid, double *en
  * --------------------------------------------------------------------- */
 vd_status vd_cell_moments_backward(vd_cells c, const double *g_mass, const double *g_centroid,
                                    const double *g_energy, double *g_sites, void *stream);
+
 
 #ifdef __cplusplus
 }

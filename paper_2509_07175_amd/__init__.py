@@ -19,7 +19,7 @@ import os
 import numpy as np
 
 __all__ = ["load", "Options", "Grid", "Domain", "Cells", "build_grid", "clip_cells", "lloyd",
-           "VoronoiMoments", "VDError", "BOUNDARY_BASE"]
+           "VoronoiMoments", "VDError", "BOUNDARY_BASE", "sync"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libvd.so")
@@ -39,7 +39,8 @@ class Options(C.Structure):
     _fields_ = [("sites_per_cell", C.c_double), ("improved_search", C.c_int32),
                 ("use_straddle_edges", C.c_int32), ("max_search_iters", C.c_int32),
                 ("emit_polytopes", C.c_int32), ("want_grad", C.c_int32), ("time_kernels", C.c_int32),
-                ("carve_mode", C.c_int32), ("no_sync", C.c_int32), ("site_cache", C.c_int32)]
+                ("carve_mode", C.c_int32), ("no_sync", C.c_int32), ("site_cache", C.c_int32),
+                ("boundary_seeds", C.c_int32), ("monitor", C.c_int32)]
 
     @classmethod
     def default(cls, **kw) -> "Options":
@@ -58,7 +59,15 @@ class _Info(C.Structure):
                 ("clips", C.c_int64), ("candidates", C.c_int64), ("grid_queries", C.c_int64),
                 ("first_bad_site", C.c_int32),
                 ("failed_stages", C.c_int32), ("status", C.c_int32), ("carve_ms", C.c_double),
-                ("split_ms", C.c_double)]
+                ("split_ms", C.c_double), ("overflow_records", C.c_int64), ("low_margin", C.c_int64),
+                ("min_margin", C.c_double), ("query_rounds", C.c_int64), ("corners_classified", C.c_int64),
+                ("corners_created", C.c_int64), ("tests_wasted", C.c_int64), ("fan_simplices", C.c_int64),
+                ("sites_outside", C.c_int64), ("boundary_seeded", C.c_int32), ("reserved_", C.c_int32)]
+
+
+class _DomainInfo(C.Structure):
+    _fields_ = [("n_simplices", C.c_int64), ("n_verts", C.c_int64), ("simplex_dim", C.c_int32),
+                ("n_diagrams", C.c_int32), ("measure", C.c_double), ("convex", C.c_int32)]
 
 
 class _Batch(C.Structure):
@@ -121,6 +130,9 @@ def load():
         "vd_cells_view": (C.c_int, [vp, C.POINTER(_View)]),
         "vd_cell_moments": (C.c_int, [vp, vp, vp, vp, vp]),
         "vd_cell_moments_backward": (C.c_int, [vp, vp, vp, vp, vp, vp]),
+        "vd_sync": (C.c_int, [vp]),
+        "vd_domain_info": (C.c_int, [vp, C.POINTER(_DomainInfo)]),
+        "vd_domain_adjacency": (C.c_int, [vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -133,7 +145,13 @@ def load():
 def exported_symbols():
     return ["vd_options_default", "vd_last_error", "vd_status_string", "vd_build_grid", "vd_grid_free",
             "vd_build_grid_batch", "vd_domain_create_batch", "vd_domain_create", "vd_domain_free", "vd_clip_cells", "vd_cells_free", "vd_cells_info",
-            "vd_cells_view", "vd_cell_moments", "vd_cell_moments_backward"]
+            "vd_cells_view", "vd_cell_moments", "vd_cell_moments_backward", "vd_sync", "vd_domain_info",
+            "vd_domain_adjacency"]
+
+
+def sync(stream=None):
+    """vd_sync: waits for the stream's work and reports an asynchronous device error."""
+    _check(load().vd_sync(_stream_ptr(stream)))
 
 
 def _check(status: int):
@@ -241,6 +259,7 @@ class Domain:
     """vd_domain_create handle: a simplex domain staged on the device."""
 
     def __init__(self, verts, simplices, adjacency, dim: int, stream=None):
+        """adjacency None: computed by the library (face matching on the device)."""
         import torch
         self.h = C.c_void_p()
         self.dim = int(dim)
@@ -248,11 +267,24 @@ class Domain:
         self.simplices = simplices
         self.m = simplices.shape[0]
         k = self.dim + 1
-        if simplices.dim() != 2 or simplices.shape[1] != k or adjacency.shape != simplices.shape:
+        if simplices.dim() != 2 or simplices.shape[1] != k or (adjacency is not None and adjacency.shape != simplices.shape):
             raise ValueError("simplices/adjacency must be (m, dim+1)")
         _check(load().vd_domain_create(_dptr(verts, torch.float64, 3), verts.shape[0],
-                                       _dptr(simplices, torch.int32), _dptr(adjacency, torch.int32),
+                                       _dptr(simplices, torch.int32),
+                                       None if adjacency is None else _dptr(adjacency, torch.int32),
                                        simplices.shape[0], self.dim, _stream_ptr(stream), C.byref(self.h)))
+
+    def info(self) -> dict:
+        i = _DomainInfo()
+        _check(load().vd_domain_info(self.h, C.byref(i)))
+        return {k: getattr(i, k) for k, _ in _DomainInfo._fields_}
+
+    def adjacency(self, stream=None):
+        """The adjacency the kernels use, (m, dim+1) int32 on the device."""
+        import torch
+        out = torch.empty((self.m, self.dim + 1), dtype=torch.int32, device="cuda")
+        _check(load().vd_domain_adjacency(self.h, _dptr(out, torch.int32), _stream_ptr(stream)))
+        return out
 
     @classmethod
     def batch(cls, verts, simplices, adjacency, vert_off, simp_off, dim: int, stream=None):
@@ -268,8 +300,8 @@ class Domain:
         self.simp_off = list(simp_off)
         b = _batch(vert_off=vert_off, simp_off=simp_off)
         _check(load().vd_domain_create_batch(_dptr(verts, torch.float64, 3), _dptr(simplices, torch.int32),
-                                             _dptr(adjacency, torch.int32), C.byref(b), self.dim,
-                                             _stream_ptr(stream), C.byref(self.h)))
+                                             None if adjacency is None else _dptr(adjacency, torch.int32),
+                                             C.byref(b), self.dim, _stream_ptr(stream), C.byref(self.h)))
         return self
 
     @classmethod
@@ -288,11 +320,13 @@ class Domain:
         return cls.batch(t(verts, torch.float64), t(simp, torch.int32), t(adj, torch.int32), vo, so, doms[0].dim)
 
     @classmethod
-    def from_vdgen(cls, dom):
+    def from_vdgen(cls, dom, adjacency: bool = True):
+        """adjacency=False leaves the adjacency to the library."""
         import torch
         return cls(torch.as_tensor(dom.verts, dtype=torch.float64, device="cuda").contiguous(),
                    torch.as_tensor(dom.simplices, dtype=torch.int32, device="cuda").contiguous(),
-                   torch.as_tensor(dom.adj, dtype=torch.int32, device="cuda").contiguous(), dom.dim)
+                   torch.as_tensor(dom.adj, dtype=torch.int32, device="cuda").contiguous() if adjacency else None,
+                   dom.dim)
 
     def __del__(self):
         if _lib is not None and self.h:

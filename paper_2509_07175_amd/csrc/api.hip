@@ -21,6 +21,12 @@ void vd_launch_domain_offsets(vd_domain d, int *flags, hipStream_t st);
 void vd_launch_domain_validate(vd_domain d, int *flags, double *measure, hipStream_t st);
 void vd_launch_vert_bbox(vd_domain d, double *out, hipStream_t st);
 void vd_launch_fill_int(int *p, long long n, int v, hipStream_t st);
+void vd_launch_adjacency(vd_domain d, int *count, int *start, int *fill, int *items, int *scan_tmp, int *flags,
+                         hipStream_t st);
+void vd_launch_convexity(vd_domain d, int *on_bnd, int *pos, int *list, int *scan_tmp, const double *bbox,
+                         int *convex, hipStream_t st);
+void vd_launch_boundary_scan(vd_domain d, int *flag, int *pos, int *scan_tmp, hipStream_t st);
+void vd_launch_boundary_extract(vd_domain d, const int *pos, int *tri, int *btet, long long *boff, hipStream_t st);
 
 namespace {
 
@@ -68,7 +74,9 @@ hipError_t ensure_fixed(T *&p, int64_t n) {
 
 __global__ void reset_counters(unsigned long long *cnt) {
   const int i = threadIdx.x;
-  if (i < CNT_N) cnt[i] = (i == CNT_BAD_SITE) ? 0x7fffffffull : 0ull;
+  if (i < CNT_N)
+    cnt[i] = (i == CNT_BAD_SITE) ? 0x7fffffffull
+                                 : (i == CNT_MINMARGIN ? (unsigned long long)__double_as_longlong(1.0) : 0ull);
 }
 
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
@@ -87,8 +95,17 @@ const char *vd_status_string(vd_status s) {
     case VD_ERR_HIP: return "VD_ERR_HIP";
     case VD_ERR_CAPACITY: return "VD_ERR_CAPACITY";
     case VD_ERR_DEGENERATE: return "VD_ERR_DEGENERATE";
+    case VD_ERR_NOT_READY: return "VD_ERR_NOT_READY";
   }
   return "VD_ERR_UNKNOWN";
+}
+
+vd_status vd_sync(void *stream) {
+  const hipError_t e = hipStreamSynchronize(as_stream(stream));
+  if (e != hipSuccess) return fail(VD_ERR_HIP, "vd_sync: %s", hipGetErrorString(e));
+  const hipError_t e2 = hipGetLastError();
+  if (e2 != hipSuccess) return fail(VD_ERR_HIP, "vd_sync: %s", hipGetErrorString(e2));
+  return VD_OK;
 }
 
 void vd_options_default(vd_options *opt) {
@@ -103,6 +120,8 @@ void vd_options_default(vd_options *opt) {
   opt->carve_mode = 1;
   opt->site_cache = 1;
   opt->no_sync = 0;
+  opt->boundary_seeds = -1;
+  opt->monitor = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -298,13 +317,26 @@ void vd_grid_free(vd_grid G) {
 
 namespace {
 
+// device temporaries of one call, freed when it returns (on every path)
+struct TmpBuffers {
+  std::vector<void *> p;
+  ~TmpBuffers() { for (void *q : p) hipFree(q); }
+  template <typename T>
+  hipError_t get(T *&out, int64_t n) {
+    out = nullptr;
+    const hipError_t e = hipMalloc((void **)&out, sizeof(T) * (size_t)std::max<int64_t>(n, 1));
+    if (e == hipSuccess) p.push_back(out);
+    return e;
+  }
+};
+
 vd_status domain_create_impl(const double *verts, const int32_t *simplices, const int32_t *adjacency, int nb,
                              const int64_t *vert_off_host, const int64_t *simp_off_host, int32_t simplex_dim,
                              void *stream, vd_domain *out, const char *who) {
   if (!out) return fail(VD_ERR_INVALID_ARG, "%s: out is NULL", who);
   if (nb < 1) return fail(VD_ERR_INVALID_ARG, "%s: no diagrams", who);
   const int64_t nv = vert_off_host[nb], m = simp_off_host[nb];
-  if (!verts || !simplices || !adjacency || nv < 1 || m < 1)
+  if (!verts || !simplices || nv < 1 || m < 1)
     return fail(VD_ERR_INVALID_ARG, "%s: NULL array or empty domain", who);
   if (simplex_dim != 2 && simplex_dim != 3) return fail(VD_ERR_INVALID_ARG, "%s: simplex_dim must be 2 or 3", who);
   if (m > INT_MAX / 8 || nv > INT_MAX / 4) return fail(VD_ERR_INVALID_ARG, "%s: domain too large", who);
@@ -337,28 +369,56 @@ vd_status domain_create_impl(const double *verts, const int32_t *simplices, cons
   HIP_TRY(hipMemcpy(D->d_vert_off, D->vert_off.data(), sizeof(long long) * (nb + 1), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpyAsync(D->verts, verts, sizeof(double) * 3 * nv, hipMemcpyDeviceToDevice, st));
   HIP_TRY(hipMemcpyAsync(D->simp, simplices, sizeof(int) * k * m, hipMemcpyDeviceToDevice, st));
-  HIP_TRY(hipMemcpyAsync(D->adj, adjacency, sizeof(int) * k * m, hipMemcpyDeviceToDevice, st));
-  int *flags = nullptr;
+  if (adjacency) HIP_TRY(hipMemcpyAsync(D->adj, adjacency, sizeof(int) * k * m, hipMemcpyDeviceToDevice, st));
+  else vd_launch_fill_int(D->adj, k * m, -1, st);
+  // temporaries of the staging (freed below, on every path)
+  TmpBuffers tmp;
+  int *flags = nullptr, *convex = nullptr;
   double *measure = nullptr, *bbox = nullptr;
-  HIP_TRY(hipMalloc((void **)&flags, sizeof(int) * 2));
-  HIP_TRY(hipMalloc((void **)&measure, sizeof(double) * m));
-  HIP_TRY(hipMalloc((void **)&bbox, sizeof(double) * 6 * nb));
-  vd_launch_fill_int(flags, 2, 0, st);
+  HIP_TRY(tmp.get(flags, 3));
+  HIP_TRY(tmp.get(measure, m));
+  HIP_TRY(tmp.get(bbox, 6 * nb));
+  HIP_TRY(tmp.get(convex, nb));
+  vd_launch_fill_int(flags, 3, 0, st);
+  vd_launch_fill_int(convex, nb, 1, st);
   vd_launch_domain_offsets(D, flags, st);
+  if (!adjacency) {
+    // Sec. 3.2 flags need the simplex adjacency: computed here by face matching
+    int *cnt = nullptr, *start = nullptr, *fill = nullptr, *items = nullptr, *stmp = nullptr;
+    HIP_TRY(tmp.get(cnt, nv));
+    HIP_TRY(tmp.get(start, nv + 1));
+    HIP_TRY(tmp.get(fill, nv));
+    HIP_TRY(tmp.get(items, k * m));
+    HIP_TRY(tmp.get(stmp, nv / 1024 + 2));
+    vd_launch_adjacency(D, cnt, start, fill, items, stmp, flags + 2, st);
+  }
   vd_launch_domain_validate(D, flags, measure, st);
   vd_launch_vert_bbox(D, bbox, st);
-  int hflags[2] = {0, 0};
+  if (simplex_dim == 3) {
+    int *on_bnd = nullptr, *pos = nullptr, *list = nullptr, *stmp = nullptr;
+    HIP_TRY(tmp.get(on_bnd, nv));
+    HIP_TRY(tmp.get(pos, nv + 1));
+    HIP_TRY(tmp.get(list, nv));
+    HIP_TRY(tmp.get(stmp, nv / 1024 + 2));
+    vd_launch_convexity(D, on_bnd, pos, list, stmp, bbox, convex, st);
+  }
+  int hflags[3] = {0, 0, 0};
   std::vector<double> hbox(6 * (size_t)nb);
   std::vector<double> hmeas((size_t)m);
+  std::vector<int> hconv((size_t)nb, 1);
   HIP_TRY(hipMemcpyAsync(hflags, flags, sizeof hflags, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(hbox.data(), bbox, sizeof(double) * 6 * nb, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(hmeas.data(), measure, sizeof(double) * m, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(hconv.data(), convex, sizeof(int) * nb, hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  hipFree(flags); hipFree(measure); hipFree(bbox);
   if (hflags[0]) return bail(fail(VD_ERR_INVALID_ARG, "%s: vertex or adjacency index out of range", who));
+  if (hflags[2])
+    return bail(fail(VD_ERR_INVALID_ARG, "%s: a face is shared by more than two simplices (non-manifold mesh)", who));
   if (hflags[1])
     return bail(fail(VD_ERR_INVALID_ARG, simplex_dim == 3 ? "%s: a tetrahedron has non-positive volume"
                                                           : "%s: a degenerate triangle", who));
+  D->convex = hconv;
+  D->all_convex = simplex_dim == 3 && std::all_of(hconv.begin(), hconv.end(), [](int c) { return c != 0; });
   double tot = 0;
   for (double v : hmeas) tot += v;
   D->area = tot;
@@ -412,6 +472,34 @@ vd_status domain_create_impl(const double *verts, const int32_t *simplices, cons
     HIP_TRY(hipMalloc((void **)&D->d_views, sizeof(DomainView) * nb));
     HIP_TRY(hipMemcpy(D->d_views, v.data(), sizeof(DomainView) * nb, hipMemcpyHostToDevice));
   }
+  if (simplex_dim == 3) {
+    // the boundary surface of M as a triangle domain (Alg. 5 seeds the cells
+    // that reach M away from their site's tetrahedron through it)
+    int *flag = nullptr, *pos = nullptr, *stmp = nullptr, *tri = nullptr, *adjm1 = nullptr;
+    long long *boff_d = nullptr;
+    HIP_TRY(tmp.get(flag, 4 * m));
+    HIP_TRY(tmp.get(pos, 4 * m + 1));
+    HIP_TRY(tmp.get(stmp, 4 * m / 1024 + 2));
+    vd_launch_boundary_scan(D, flag, pos, stmp, st);
+    int nbt = 0;
+    HIP_TRY(hipMemcpyAsync(&nbt, pos + 4 * m, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (nbt < 4) return bail(fail(VD_ERR_INVALID_ARG, "%s: the domain has no boundary surface", who));
+    HIP_TRY(tmp.get(tri, 3 * (int64_t)nbt));
+    HIP_TRY(tmp.get(adjm1, 3 * (int64_t)nbt));
+    HIP_TRY(tmp.get(boff_d, nb + 1));
+    hipFree(D->btet);
+    D->btet = nullptr;
+    HIP_TRY(hipMalloc((void **)&D->btet, sizeof(int) * nbt));
+    vd_launch_fill_int(adjm1, 3 * (int64_t)nbt, -1, st);
+    vd_launch_boundary_extract(D, pos, tri, D->btet, boff_d, st);
+    std::vector<int64_t> boff((size_t)nb + 1);
+    HIP_TRY(hipMemcpyAsync(boff.data(), boff_d, sizeof(long long) * (nb + 1), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const vd_status r = domain_create_impl(D->verts, tri, adjm1, nb, D->vert_off.data(), boff.data(), 2, stream,
+                                           &D->bnd, who);
+    if (r != VD_OK) return bail(r);
+  }
   HIP_TRY(hipStreamSynchronize(st));
   *out = D;
   return VD_OK;
@@ -435,8 +523,28 @@ vd_status vd_domain_create_batch(const double *verts, const int32_t *simplices, 
                             stream, out, "vd_domain_create_batch");
 }
 
+vd_status vd_domain_info(vd_domain D, vd_domain_info_t *info) {
+  if (!D || !info) return fail(VD_ERR_INVALID_ARG, "vd_domain_info: NULL");
+  info->n_simplices = D->m;
+  info->n_verts = D->nv;
+  info->simplex_dim = D->dim;
+  info->n_diagrams = D->nb;
+  info->measure = D->area;
+  info->convex = D->dim == 3 ? (D->all_convex ? 1 : 0) : -1;
+  return VD_OK;
+}
+
+vd_status vd_domain_adjacency(vd_domain D, int32_t *adjacency_out, void *stream) {
+  if (!D || !adjacency_out) return fail(VD_ERR_INVALID_ARG, "vd_domain_adjacency: NULL");
+  HIP_TRY(hipMemcpyAsync(adjacency_out, D->adj, sizeof(int) * (D->dim + 1) * D->m, hipMemcpyDeviceToDevice,
+                         as_stream(stream)));
+  return VD_OK;
+}
+
 void vd_domain_free(vd_domain D) {
   if (!D) return;
+  vd_domain_free(D->bnd);
+  hipFree(D->btet);
   hipFree(D->verts); hipFree(D->simp); hipFree(D->adj); hipFree(D->lgeom); hipFree(D->lstart);
   hipFree(D->litems); hipFree(D->lcount); hipFree(D->lfill); hipFree(D->scan_tmp);
   hipFree(D->d_simp_off); hipFree(D->d_vert_off); hipFree(D->d_loc_off); hipFree(D->d_lg); hipFree(D->d_views);
@@ -535,7 +643,9 @@ vd_status check_counts(vd_cells c, bool overflow_is_error) {
   int bad = (int)(hc[CNT_BAD_SITE] & 0xffffffffull);
   c->first_bad = bad == 0x7fffffff ? -1 : bad;
   if (hc[CNT_ERR_LOC])
-    return (vd_status)(c->status = fail(VD_ERR_INVALID_ARG, "vd_clip_cells: %llu site(s) outside every tetrahedron (first: %d)",
+    return (vd_status)(c->status = fail(VD_ERR_INVALID_ARG,
+                            "vd_clip_cells: %llu site(s) outside every tetrahedron and no boundary seeds "
+                            "(first: %d; boundary_seeds = 0 or a no_sync clip)",
                             (unsigned long long)hc[CNT_ERR_LOC], c->first_bad));
   if (hc[CNT_ERR_CAP])
     return (vd_status)(c->status = fail(VD_ERR_CAPACITY,
@@ -546,7 +656,7 @@ vd_status check_counts(vd_cells c, bool overflow_is_error) {
                             "vd_clip_cells: %llu site(s) hit a non-converging search (first: %d, stages 0x%llx)",
                             (unsigned long long)hc[CNT_ERR_DEG], c->first_bad, (unsigned long long)hc[CNT_STAGES]));
   if (overflow_is_error &&
-      ((int64_t)hc[CNT_PIECES] > d.cap_piece || (int64_t)hc[CNT_NBRS] > d.cap_nbr ||
+      (hc[CNT_OVERFLOW] || (int64_t)hc[CNT_PIECES] > d.cap_piece || (int64_t)hc[CNT_NBRS] > d.cap_nbr ||
        (d.face_label && (int64_t)hc[CNT_FACES] > d.cap_face) || (d.vert_xyz && (int64_t)hc[CNT_VERTS] > d.cap_vert) ||
        (d.fint && (int64_t)hc[CNT_FINT] > d.cap_fint)))
     return (vd_status)(c->status = fail(VD_ERR_CAPACITY, "vd_clip_cells: an output arena overflowed in a no-sync clip "
@@ -617,6 +727,7 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
     d.max_iters = opt.max_search_iters;
     d.mode = (dom->dim == 3 && opt.carve_mode == 1) ? 1 : 0;
     d.cache = opt.site_cache ? 1 : 0;
+    d.monitor = opt.monitor ? 1 : 0;
     // persistent 3D kernel: each wave reserves output chunks of about 1/8 of an
     // arena's share per wave, so unused chunk tails stay within 1/8 of it
     const int64_t items = dom->dim == 3 ? n : dom->m;  // sites, or triangles
@@ -648,8 +759,48 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
       c->d_shadow = d;
       HIP_TRY(hipMemcpyAsync(c->d_dev, &c->d_shadow, sizeof(CellsDev), hipMemcpyHostToDevice, st));
     }
-    if (dom->dim == 3) vd_launch_locate_sites(G, D, d.seed, d.cnt, st);
-    else vd_launch_fill_int(d.pcount, n, 0, st);
+    if (dom->dim == 3 && attempt == 0) {
+      // seeds: the tetrahedron holding each site, and (Alg. 5) the boundary
+      // triangles each cell meets when the domain is not convex or a site
+      // lies outside it
+      HIP_TRY(ensure_fixed(c->outside, 2));
+      vd_launch_fill_int(c->outside, 1, 0, st);
+      vd_launch_fill_int(c->outside + 1, 1, INT_MAX, st);
+      vd_launch_locate_sites(G, D, d.seed, c->outside, st);
+      bool use_b = false;
+      c->sites_outside = -1;
+      if (!opt.no_sync && opt.boundary_seeds != 0) {
+        use_b = opt.boundary_seeds == 1 || !dom->all_convex;
+        int ho[2] = {0, INT_MAX};
+        HIP_TRY(hipMemcpyAsync(ho, c->outside, sizeof ho, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        c->sites_outside = ho[0];
+        use_b = use_b || ho[0] > 0;
+      }
+      if (use_b) {
+        if (!dom->bnd) return bail(fail(VD_ERR_INVALID_ARG, "vd_clip_cells: the domain has no boundary surface"));
+        vd_options bopt;
+        vd_options_default(&bopt);
+        bopt.emit_polytopes = 0;
+        bopt.max_search_iters = opt.max_search_iters;
+        bopt.site_cache = opt.site_cache;
+        const vd_status r = vd_clip_cells(g, dom->bnd, &bopt, stream, &c->bcells);
+        if (r != VD_OK) return bail(r);
+        d.bseed_off = c->bcells->piece_off;
+        d.bseed_pid = c->bcells->piece_id;
+        d.bseed_tri = c->bcells->d.piece_simplex;
+        d.btet = dom->btet;
+      } else {
+        d.bseed_off = nullptr;
+        d.bseed_pid = d.bseed_tri = d.btet = nullptr;
+      }
+      c->used_bseeds = use_b;
+      if (std::memcmp(&c->d_shadow, &d, sizeof(CellsDev)) != 0) {
+        c->d_shadow = d;
+        HIP_TRY(hipMemcpyAsync(c->d_dev, &c->d_shadow, sizeof(CellsDev), hipMemcpyHostToDevice, st));
+      }
+    }
+    if (dom->dim == 2) vd_launch_fill_int(d.pcount, n, 0, st);
     if (opt.time_kernels) HIP_TRY(hipEventRecord(c->ev0, st));
     if (dom->dim == 3) vd_launch_sites3d(G, D, c->d_dev, wg, st);
     else vd_launch_surface(G, D, c->d_dev, wg, st);
@@ -723,6 +874,8 @@ void vd_cells_free(vd_cells c) {
   if (c->ev1) hipEventDestroy(c->ev1);
   if (c->ev2) hipEventDestroy(c->ev2);
   hipFree(c->d_dev); hipFree(d.queue); hipFree(d.tq_spill); hipFree(d.saved);
+  hipFree(c->outside);
+  vd_cells_free(c->bcells);
   if (c->host_cnt) hipHostFree(c->host_cnt);
   hipFree(d.fint_lab); hipFree(d.piece_fint_start); hipFree(d.piece_nfint); hipFree(c->wbuf);
   delete c;
@@ -735,6 +888,7 @@ vd_status vd_cells_info(vd_cells c, vd_cells_info_t *info) {
     // the caller synchronises): its counters reach host_cnt in stream order
     HIP_TRY(hipStreamSynchronize(c->last_stream));
     check_counts(c, true);
+    c->pending = false;
   }
   const unsigned long long *hc = c->host_cnt;
   info->n_sites = c->n;
@@ -756,11 +910,37 @@ vd_status vd_cells_info(vd_cells c, vd_cells_info_t *info) {
   info->status = c->status;
   info->carve_ms = c->carve_ms;
   info->split_ms = c->split_ms;
+  info->overflow_records = (int64_t)hc[CNT_OVERFLOW];
+  const bool mon = c->opt.monitor != 0;
+  info->low_margin = mon ? (int64_t)hc[CNT_LOWMARGIN] : -1;
+  {
+    const unsigned long long b = hc[CNT_MINMARGIN];
+    double mm;
+    std::memcpy(&mm, &b, sizeof mm);
+    info->min_margin = mon ? mm : -1.0;
+  }
+  info->query_rounds = mon ? (int64_t)hc[CNT_ROUNDS] : -1;
+  info->corners_classified = mon ? (int64_t)hc[CNT_CLASSIFIED] : -1;
+  info->corners_created = mon ? (int64_t)hc[CNT_NEWCORNERS] : -1;
+  info->tests_wasted = mon ? (int64_t)hc[CNT_WASTED] : -1;
+  info->fan_simplices = mon ? (int64_t)hc[CNT_FANTETS] : -1;
+  info->sites_outside = c->sites_outside;
+  info->boundary_seeded = c->used_bseeds ? 1 : 0;
+  info->reserved_ = 0;
   return VD_OK;
 }
 
 vd_status vd_cells_view(vd_cells c, vd_cells_view_t *v) {
   if (!c || !v) return fail(VD_ERR_INVALID_ARG, "vd_cells_view: NULL");
+  if (c->pending) {
+    // the sizes of a no-sync clip are known once its counters have arrived
+    const hipError_t q = hipStreamQuery(c->last_stream);
+    if (q == hipErrorNotReady) return fail(VD_ERR_NOT_READY, "vd_cells_view: the no-sync clip has not finished");
+    if (q != hipSuccess) return fail(VD_ERR_HIP, "vd_cells_view: %s", hipGetErrorString(q));
+    check_counts(c, true);
+    c->pending = false;
+  }
+  if (c->status != VD_OK) return fail((vd_status)c->status, "vd_cells_view: the clip failed (%s)", vd_status_string((vd_status)c->status));
   const CellsDev &d = c->d;
   v->n_sites = c->n;
   v->n_piece_slots = std::min<int64_t>((int64_t)c->host_cnt[CNT_PIECES], d.cap_piece);

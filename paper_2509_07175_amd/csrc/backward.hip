@@ -12,7 +12,8 @@
 // (Reynolds transport), the energy integrands of the two cells agree on the
 // face, and the interior of cell i contributes -2 int (x - v_i) gE_i.
 // One thread per site reads its own faces (pieces in CSR order) and the
-// weights of its neighbours; nothing is scattered.
+// weights of its neighbours; nothing is scattered.  After a no-sync clip that
+// dropped records the gradient is NaN (the clip's status is VD_ERR_CAPACITY).
 #include "vd_internal.h"
 
 namespace {
@@ -50,9 +51,16 @@ __global__ void __launch_bounds__(kB) adjoint_gather(long long n, const int *__r
                                                      const long long *__restrict__ poff, const int *__restrict__ pid,
                                                      const long long *__restrict__ fstart, const int *__restrict__ nfint,
                                                      const double *__restrict__ fint, const int *__restrict__ flab,
+                                                     const unsigned long long *__restrict__ cnt,
                                                      double *__restrict__ out) {
   const long long i = (long long)blockIdx.x * kB + threadIdx.x;
   if (i >= n) return;
+  if (cnt[CNT_OVERFLOW]) {
+    // a no-sync clip dropped records (face moments among them): no gradient
+    const double nan = __longlong_as_double(0x7ff8000000000000ll);
+    out[3 * i + 0] = out[3 * i + 1] = out[3 * i + 2] = nan;
+    return;
+  }
   const int p = rank[i];
   const double v0 = sx[p], v1 = sy[p], v2 = sz[p];
   const double m = mass[i];
@@ -99,5 +107,5 @@ void vd_launch_backward(const vd_cells_s *c, const GridView &G, const double *gm
                      G.sz, (const double *)d.mass, (const double *)d.mom, (const double *)work,
                      (const long long *)c->piece_off, (const int *)c->piece_id,
                      (const long long *)d.piece_fint_start, (const int *)d.piece_nfint, (const double *)d.fint,
-                     (const int *)d.fint_lab, gs);
+                     (const int *)d.fint_lab, (const unsigned long long *)d.cnt, gs);
 }

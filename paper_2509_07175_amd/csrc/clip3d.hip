@@ -48,6 +48,20 @@ namespace {
 constexpr int kMaxIters = 4096;  // queries + clips of one polytope
 constexpr int kBoxBase = VD_BND_BASE + 16;  // flags of the bounding-box planes (never emitted)
 
+// The carved cell kept in LDS for the piece phase, over the site cache's
+// arrays: the cache is not read after the carve unless a piece falls back to
+// a carve of its own, which then switches the cache off and queries the grid.
+// Cells with more planes or corners go to the wave's global save area.
+constexpr int kLF = 32;  // planes
+constexpr int kLC = 64;  // corners
+struct LdsCell {
+  double pn[kLF][4];
+  double cy[kLC][3];
+  int plab[kLF];
+  int cpl[kLC], cnb[kLC];
+};
+static_assert(sizeof(LdsCell) <= offsetof(SiteCache, step), "the LDS cell overlays only the cache's arrays");
+
 struct __align__(16) WaveLds {
   double pn[VD_P_MAX][4];    // plane: outward normal (relative coords), offset
   double cy[VD_C_MAX][3];    // corner coordinates relative to v_i
@@ -60,11 +74,18 @@ struct __align__(16) WaveLds {
   int nbl[VD_NB_MAX];        // neighbours found so far (sorted positions)
   int pfirst[VD_P_MAX];      // lowest corner slot on each plane (face walks)
   WaveArena ar;              // output chunks, queue position, statistics
-  SiteCache K;               // sites around v_i for the nearest-site queries
+  union {
+    SiteCache K;             // sites around v_i for the nearest-site queries (carve)
+    LdsCell LC;              // the carved cell (piece phase)
+  };
   // per-site sums and neighbour masks (uniform; kept here rather than in
   // registers that would be live across the whole carve)
   double acc[5];             // volume, first moment (relative to v_i), energy
   unsigned long long cellpos, nbmask;
+};
+
+struct Stats {
+  long long queries = 0, cands = 0, clips = 0, grid = 0;  // grid: queries not answered by the site cache
 };
 
 __device__ __forceinline__ int p8(int packed, int e) { return (packed >> (8 * e)) & 0xff; }
@@ -72,9 +93,6 @@ __device__ __forceinline__ int pack3(int a, int b, int c) { return a | (b << 8) 
 __device__ __forceinline__ uint64_t low_mask(int k) { return k >= 64 ? ~0ull : ((1ull << k) - 1ull); }
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-struct Stats {
-  long long queries = 0, cands = 0, clips = 0, grid = 0;  // grid: queries not answered by the site cache
-};
 
 struct SiteCtx {
   double vx, vy, vz, delta;
@@ -145,7 +163,7 @@ __device__ int compact_planes(WaveLds &S, int npl, int nc) {
 // leaving R_p and form the fan of the new face.
 // Returns 0 (nothing outside: unchanged), 1 empty, 2 capacity, 3 degenerate,
 // 4 cut (nc updated).
-__device__ int clip_poly(WaveLds &S, int P, int pt, int &nc, int ps = -1, int kcert = -1) {
+__device__ int clip_poly(WaveLds &S, bool mon, int P, int pt, int &nc, int ps = -1, int kcert = -1) {
   const int l = vd_lane();
   const double nx = S.pn[P][0], ny = S.pn[P][1], nz = S.pn[P][2], c = S.pn[P][3];
   int pl[2] = {0, 0}, nb[2] = {0, 0}, cs[2] = {0, 0};
@@ -161,6 +179,11 @@ __device__ int clip_poly(WaveLds &S, int P, int pt, int &nc, int ps = -1, int kc
       sd[h] = nx * y[h][0] + ny * y[h][1] + nz * y[h][2] - c;
     }
     o[h] = v[h] && sd[h] > 0.0;
+  }
+  if (mon) {
+    margin_track(S.ar, v[0], sd[0], fabs(nx * y[0][0]) + fabs(ny * y[0][1]) + fabs(nz * y[0][2]) + fabs(c), v[1],
+                 sd[1], fabs(nx * y[1][0]) + fabs(ny * y[1][1]) + fabs(nz * y[1][2]) + fabs(c));
+    count_add(S.ar.classified, nc);
   }
   const uint64_t olo = __ballot(o[0]), ohi = __ballot(o[1]);
   if (!(olo | ohi)) return pt < 0 ? 0 : 3;
@@ -188,6 +211,12 @@ __device__ int clip_poly(WaveLds &S, int P, int pt, int &nc, int ps = -1, int kc
     Rhi |= b;
   }
   const int nR = __popcll(Rlo) + __popcll(Rhi);
+  if (mon && pt >= 0) {
+    // tests spent on corners this clip removes, besides the one that led to it
+    const uint64_t tlo = __ballot(v[0] && (cs[0] & 2)), thi = __ballot(v[1] && (cs[1] & 2));
+    const int w = __popcll(tlo & Rlo) + __popcll(thi & Rhi) - (bit128(tlo, thi, pt) ? 1 : 0);
+    count_add(S.ar.wasted, w);
+  }
   if (nR >= nc) return 1;
   bool r[2];
   int em[2] = {0, 0};
@@ -294,6 +323,7 @@ __device__ int clip_poly(WaveLds &S, int P, int pt, int &nc, int ps = -1, int kc
   }
   __syncthreads();
   nc = nsurv + nnew;
+  if (mon) count_add(S.ar.newc, nnew);
   // three planes without a common point (e.g. all containing one direction)
   // give a non-finite corner: report the cut as degenerate
   if (__ballot(nf)) return 3;
@@ -318,6 +348,7 @@ __device__ __forceinline__ void state_masks(const WaveLds &S, int nc, uint64_t &
 // Returns 0 (done, non-empty), 1 (empty), 2 capacity, 3 degenerate.
 struct CarveParams {
   int improved, straddle, max_iters;
+  bool monitor;  // count work and track predicate margins (vd_options.monitor)
 };
 
 __device__ int carve(WaveLds &S, const GridView &G, const CarveParams C, const SiteCtx &X, int &npl, int &nc,
@@ -449,6 +480,7 @@ __device__ int carve(WaveLds &S, const GridView &G, const CarveParams C, const S
       e0 = S.plab[p8(tpl, 0)]; e1 = S.plab[p8(tpl, 1)]; e2 = S.plab[p8(tpl, 2)];
     }
     bool on_grid;
+    if (C.monitor) count_add(S.ar.rounds, 1);
     const int kq = nn_cached(S.K, G, gs, qx, qy, qz, dx * dx + dy * dy + dz * dz, X.si, e0 < 0 ? -1 : e0,
                              e1 < 0 ? -1 : e1, e2 < 0 ? -1 : e2, st.cands, on_grid);
     if (mode == TEST) {
@@ -503,7 +535,7 @@ __device__ int carve(WaveLds &S, const GridView &G, const CarveParams C, const S
       S.plab[P] = j;
     }
     __syncthreads();
-    const int rc = clip_poly(S, P, pt, nc, ps_edge >= 0 && qon ? ps_edge : -1, k);
+    const int rc = clip_poly(S, C.monitor, P, pt, nc, ps_edge >= 0 && qon ? ps_edge : -1, k);
     st.clips++;
     if (rc == 1) return 1;
     if (rc != 4) return rc == 0 ? 3 : rc;
@@ -616,6 +648,51 @@ __device__ void restore_cell(WaveLds &S, const CellsDev &C, int npl, int nc, con
   __syncthreads();
 }
 
+// the cell in LDS (npl <= kLF planes, nc <= kLC corners) over the cache
+__device__ void save_cell_lds(WaveLds &S, int npl, int nc) {
+  const int l = vd_lane();
+  __syncthreads();
+  double p4[4] = {0, 0, 0, 0};
+  int lab = 0;
+  if (l < npl) {
+    for (int k = 0; k < 4; k++) p4[k] = S.pn[l][k];
+    lab = S.plab[l];
+  }
+  int cp = 0, cn = 0;
+  double y0 = 0, y1 = 0, y2 = 0;
+  if (l < nc) { cp = S.cpl[l]; cn = S.cnb[l]; y0 = S.cy[l][0]; y1 = S.cy[l][1]; y2 = S.cy[l][2]; }
+  __syncthreads();  // the cache is read no more
+  if (l < npl) {
+    for (int k = 0; k < 4; k++) S.LC.pn[l][k] = p4[k];
+    S.LC.plab[l] = lab;
+  }
+  if (l < nc) { S.LC.cpl[l] = cp; S.LC.cnb[l] = cn; S.LC.cy[l][0] = y0; S.LC.cy[l][1] = y1; S.LC.cy[l][2] = y2; }
+  __syncthreads();
+}
+
+// start a piece from the LDS cell: the cell plus the four planes of T_a in
+// slots npl .. npl+3 (not yet cut)
+__device__ void restore_cell_lds(WaveLds &S, int npl, int nc, const DomainView &D, const SiteCtx &X, int a) {
+  const int l = vd_lane();
+  if (l < npl) {
+    for (int k = 0; k < 4; k++) S.pn[l][k] = S.LC.pn[l][k];
+    S.plab[l] = S.LC.plab[l];
+  } else if (l < npl + 4) {
+    double pl[4];
+    int lab;
+    tet_plane(D, X, a, l - npl, pl, lab);
+    for (int k = 0; k < 4; k++) S.pn[l][k] = pl[k];
+    S.plab[l] = lab;
+  }
+  if (l < nc) {
+    S.cpl[l] = S.LC.cpl[l];
+    S.cnb[l] = S.LC.cnb[l];
+    S.cst[l] = 3;
+    S.cy[l][0] = S.LC.cy[l][0]; S.cy[l][1] = S.LC.cy[l][1]; S.cy[l][2] = S.LC.cy[l][2];
+  }
+  __syncthreads();
+}
+
 // P <- box [lo, hi] (planes x-,x+,y-,y+,z-,z+; corner (bx,by,bz) = 4bx+2by+bz)
 __device__ void init_box(WaveLds &S, const SiteCtx &X, const double *lo, const double *hi) {
   const int l = vd_lane();
@@ -674,7 +751,12 @@ __device__ void face_moments(WaveLds &S, int nc, int npl, uint64_t fmask, const 
   const uint64_t pos = __ballot(mine);
   const int npos = __popcll(pos);
   const long long base = arena_take(S.ar, C, AR_FINT, npos);
-  if (l == 0 && pidx < C.cap_piece) { GL(C.piece_fint_start)[pidx] = base; GL(C.piece_nfint)[pidx] = npos; }
+  const bool fits = base + npos <= C.cap_fint;
+  if (l == 0 && pidx < C.cap_piece) {
+    GL(C.piece_fint_start)[pidx] = base;
+    GL(C.piece_nfint)[pidx] = fits ? npos : 0;
+    if (!fits) S.ar.dropped++;
+  }
   if (!mine) return;
   const int x = l;
   const double n0 = S.pn[x][0], n1 = S.pn[x][1], n2 = S.pn[x][2], cc = S.pn[x][3];
@@ -744,6 +826,27 @@ __device__ __forceinline__ void spill_put(const CellsDev &C, int i, int b) {
   if (vd_lane() == 0) GL(C.tq_spill)[(long long)blockIdx.x * VD_Q_SPILL + i - VD_Q_MAX] = b;
 }
 
+// Appends simplex b to the site's breadth-first queue unless it is there
+// already.  Returns false when the queue is full.
+__device__ __forceinline__ bool tq_push(WaveLds &S, const CellsDev &C, int &nt, int b) {
+  const int l = vd_lane();
+  bool have = false;
+  const int nl = nt < VD_Q_MAX ? nt : VD_Q_MAX;
+  for (int e = l; e < nl; e += 64) have = have || (S.tq[e] == b);
+  if (nt > VD_Q_MAX) have = have || spill_has(C, b, nt);
+  if (__ballot(have)) return true;
+  if (nt >= VD_Q_MAX + VD_Q_SPILL) return false;
+  __syncthreads();
+  if (nt < VD_Q_MAX) {
+    if (l == 0) S.tq[nt] = b;
+  } else {
+    spill_put(C, nt, b);  // large cells: the queue continues in global memory
+  }
+  nt++;
+  __syncthreads();
+  return true;
+}
+
 // ---------------------------------------------------------------------------
 // One site: its pieces, per-site sums and neighbour list.  The tetrahedra of
 // the cell are visited breadth-first through negative face flags from the
@@ -764,12 +867,12 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
   X.si = si;
   const int orig = GL(G.perm)[si];
   const int seed = GL(C.seed)[si];
-  const CarveParams P = {C.improved, C.straddle, C.max_iters};
+  const CarveParams P = {C.improved, C.straddle, C.max_iters, C.monitor != 0};
   Stats st;
-  int err = 0;  // 2 capacity, 3 degenerate
+  int err = 0;  // 2 capacity, 3 degenerate, 4 outside M without boundary seeds
   int where = 0;  // failing stage (VD_STAGE_*)
   int nt = 0, head = 0, nnb = 0, npieces = 0, npl0 = 0, nc0 = 0;
-  bool cell_job = C.mode == 1, saved = false;
+  bool cell_job = C.mode == 1, saved = false, saved_lds = false;
   // pieces cut from the saved cell: their bisector faces are cell planes, so
   // the neighbours found are a mask over the cell's plane slots (cellpos: the
   // slots whose flag is a site), turned into a list once per site
@@ -790,6 +893,19 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
     nt = 1;
   }
   __syncthreads();
+  if (C.bseed_off) {
+    // Alg. 5: every boundary triangle the cell meets seeds the tetrahedron
+    // behind it, which reaches the parts of Omega_i cap M that are not
+    // connected to the site's own tetrahedron (or all of them, for a site
+    // outside M)
+    const long long q0 = GL(C.bseed_off)[orig], q1 = GL(C.bseed_off)[orig + 1];
+    for (long long q = q0; q < q1; q++) {
+      const int t = GL(C.btet)[GL(C.bseed_tri)[GL(C.bseed_pid)[q]]];
+      if (!tq_push(S, C, nt, t)) { err = 2; where = VD_STAGE_SIMPLICES; break; }
+    }
+  } else if (!nt) {
+    err = 4;  // outside every tetrahedron, and no boundary seeds to find its cell
+  }
   if (!nt) cell_job = false;
   for (;;) {
     int a = -1, npl = 4, nc = 4;
@@ -803,19 +919,21 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
       a = head < VD_Q_MAX ? S.tq[head] : spill_get(C, head);
       head++;
       if (saved) {
-        restore_cell(S, C, npl0, nc0, D, X, a);
+        if (saved_lds) restore_cell_lds(S, npl0, nc0, D, X, a);
+        else restore_cell(S, C, npl0, nc0, D, X, a);
         npl = npl0 + 4;
         nc = nc0;
         need_carve = false;
 #pragma unroll 1
         for (int f = 0; f < 4; f++) {
-          const int rc = clip_poly(S, npl0 + f, -1, nc);
+          const int rc = clip_poly(S, P.monitor, npl0 + f, -1, nc);
           if (rc == 4) st.clips++;
           else if (rc == 1) { empty = true; break; }
           else if (rc == 2) { err = rc; where = VD_STAGE_PIECE_CUT; break; }
           else if (rc == 3) { need_carve = true; break; }  // degenerate cut: carve this piece from T_a
         }
         if (need_carve && !err) {
+          if (saved_lds && l == 0) S.K.cnt = -1;  // the cell sits over the cache: query the grid
           init_tet(S, D, X, a, 0);
           npl = 4;
           nc = 4;
@@ -832,7 +950,9 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
         if (rc == 2) continue;                           // too large: carve per simplex
         npl = compact_planes(S, npl, nc);
         if (npl <= VD_F_MAX && npl + 4 <= VD_P_MAX && nc <= VD_CB_MAX) {
-          save_cell(S, C, npl, nc);
+          saved_lds = npl <= kLF && nc <= kLC;
+          if (saved_lds) save_cell_lds(S, npl, nc);
+          else save_cell(S, C, npl, nc);
           npl0 = npl;
           nc0 = nc;
           saved = true;
@@ -891,6 +1011,7 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
     fmask = wave_or64(fmask);
     if (!(pv > 0.0)) continue;
     if (l == 0) { S.acc[0] += pv; S.acc[1] += pmx; S.acc[2] += pmy; S.acc[3] += pmz; S.acc[4] += pe; }
+    if (P.monitor) count_add(S.ar.fantets, 3 * nc);
     // ---- emit the piece ----
     const int nface = __popcll(fmask);
     const long long pidx = arena_take(S.ar, C, AR_PIECE, 1);
@@ -900,6 +1021,10 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
       vo = arena_take(S.ar, C, AR_VERT, nc);
     }
     if (C.want_grad) face_moments(S, nc, npl, fmask, C, G, pidx);
+    // a record that does not fit its arena is dropped and counted; the per-site
+    // counts below only count what was written, so the CSR built from them
+    // stays inside the arenas (the clip then reports VD_ERR_CAPACITY)
+    const bool fits_fv = C.emit && fo + nface <= C.cap_face && vo + nc <= C.cap_vert;
     if (pidx < C.cap_piece) {
       if (l == 0) {
         GL(C.piece_site)[pidx] = orig;
@@ -911,12 +1036,14 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
         GL(C.piece_mom)[3 * pidx + 1] = pmy + pv * X.vy;
         GL(C.piece_mom)[3 * pidx + 2] = pmz + pv * X.vz;
         GL(C.piece_energy)[pidx] = pe;
-        GL(C.piece_fstart)[pidx] = C.emit ? fo : -1;
-        GL(C.piece_vstart)[pidx] = C.emit ? vo : -1;
+        GL(C.piece_fstart)[pidx] = fits_fv ? fo : -1;
+        GL(C.piece_vstart)[pidx] = fits_fv ? vo : -1;
         S.ar.pieces++;
-        if (C.emit) { S.ar.faces += nface; S.ar.verts += nc; }
+        if (fits_fv) { S.ar.faces += nface; S.ar.verts += nc; }
+        if (C.emit && !fits_fv) S.ar.dropped++;
       }
-      if (C.emit && fo + nface <= C.cap_face && vo + nc <= C.cap_vert) {
+      npieces++;
+      if (fits_fv) {
         // caller-index flag of plane l, read once; corners fetch theirs from the plane's lane
         const int lab = l < npl && ((fmask >> l) & 1ull) ? convert_label(G, S.plab[l]) : 0;
         if (l < npl && ((fmask >> l) & 1ull)) GL(C.face_label)[fo + __popcll(fmask & low_mask(l))] = lab;
@@ -935,8 +1062,9 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
           }
         }
       }
+    } else if (l == 0) {
+      S.ar.dropped++;
     }
-    npieces++;
     // ---- propagate: neighbours (positive flags), tetrahedra (negative flags) ----
     // A piece cut from the saved cell adds its cell planes to the mask; only
     // the four planes of T_a can lead to other tetrahedra.
@@ -956,22 +1084,7 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
           __syncthreads();
         }
       } else if (lab > VD_BND_BASE + 3) {
-        const int b = -lab - 1;
-        bool have = false;
-        const int nl = nt < VD_Q_MAX ? nt : VD_Q_MAX;
-        for (int e = l; e < nl; e += 64) have = have || (S.tq[e] == b);
-        if (nt > VD_Q_MAX) have = have || spill_has(C, b, nt);
-        if (!__ballot(have)) {
-          if (nt >= VD_Q_MAX + VD_Q_SPILL) { err = 2; where = VD_STAGE_SIMPLICES; break; }
-          __syncthreads();
-          if (nt < VD_Q_MAX) {
-            if (l == 0) S.tq[nt] = b;
-          } else {
-            spill_put(C, nt, b);  // large cells: the queue continues in global memory
-          }
-          nt++;
-          __syncthreads();
-        }
+        if (!tq_push(S, C, nt, -lab - 1)) { err = 2; where = VD_STAGE_SIMPLICES; break; }
       }
     }
     __syncthreads();
@@ -999,18 +1112,20 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
     GL(C.mom)[3 * (long long)orig + 1] = S.acc[2] + Mv * X.vy;
     GL(C.mom)[3 * (long long)orig + 2] = S.acc[3] + Mv * X.vz;
     GL(C.energy)[orig] = S.acc[4];
+    const bool nfit = ns0 + nnb <= C.cap_nbr;
     GL(C.pcount)[orig] = npieces;
-    GL(C.ncount)[orig] = nnb;
+    GL(C.ncount)[orig] = nfit ? nnb : 0;
     GL(C.nstart)[orig] = ns0;
-    S.ar.nbrs += nnb;
+    if (nfit) S.ar.nbrs += nnb;
+    else S.ar.dropped++;
     S.ar.queries += st.queries;
     S.ar.cands += st.cands;
     S.ar.clips += st.clips;
     S.ar.gridq += st.grid;
     if (err) {
-      atomicAdd(&C.cnt[err == 2 ? CNT_ERR_CAP : CNT_ERR_DEG], 1ull);
+      atomicAdd(&C.cnt[err == 2 ? CNT_ERR_CAP : (err == 4 ? CNT_ERR_LOC : CNT_ERR_DEG)], 1ull);
       atomicMin((int *)&C.cnt[CNT_BAD_SITE], orig);
-      atomicOr((unsigned long long *)&C.cnt[CNT_STAGES], 1ull << where);
+      if (where) atomicOr((unsigned long long *)&C.cnt[CNT_STAGES], 1ull << where);
     }
   }
   __syncthreads();

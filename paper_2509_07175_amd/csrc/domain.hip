@@ -149,9 +149,10 @@ __global__ void __launch_bounds__(kB) loc_fill(LocArgs L, const int *__restrict_
 
 // Seed tetrahedron of each site (by sorted position): lowest index among the
 // tetrahedra of its location cell whose barycentric coordinates are all
-// >= -1e-12 (relative).
+// >= -1e-12 (relative); -1 for a site outside M (counted in outside[0]; the
+// lowest such caller index in outside[1], which starts at INT_MAX).
 __global__ void __launch_bounds__(kB) locate_sites(GridView G, DomainView Dall, int *__restrict__ seed,
-                                                   unsigned long long *__restrict__ cnt) {
+                                                   int *__restrict__ outside) {
   const long long p = (long long)blockIdx.x * kB + threadIdx.x;
   if (p >= G.n) return;
   const DomainView D = domain_of(Dall, G.nb > 1 ? diagram_of(G.site_off, G.nb, p) : 0);
@@ -189,9 +190,168 @@ __global__ void __launch_bounds__(kB) locate_sites(GridView G, DomainView Dall, 
   }
   seed[p] = best;
   if (best < 0) {
-    atomicAdd(&cnt[CNT_ERR_LOC], 1ull);
-    atomicMin((int *)&cnt[CNT_BAD_SITE], G.perm[p]);
+    // outside every tetrahedron: outside[0] counts them, outside[1] the lowest caller index
+    atomicAdd(&outside[0], 1);
+    atomicMin(&outside[1], G.perm[p]);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Adjacency from the simplices (Sec. 3.2: a face shared by T_a and T_b is
+// flagged -(b+1) in T_a).  Face f of simplex a (the facet opposite vertex f) is
+// bucketed by its smallest vertex index (counting sort: histogram, scan,
+// scatter); a face then looks for the face with the same vertex set in its own
+// bucket.  Buckets hold the faces around one vertex, so the pairwise search is
+// short.  A face matched by more than one other face (a non-manifold mesh)
+// sets flags[0].
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void face_verts(const int *__restrict__ simp, int k, long long a, int f, int *w) {
+  int c = 0;
+  for (int u = 0; u < k; u++)
+    if (u != f) w[c++] = simp[a * k + u];
+  // sort the k-1 (2 or 3) vertex ids
+  for (int i = 0; i < k - 1; i++)
+    for (int j = i + 1; j < k - 1; j++)
+      if (w[j] < w[i]) { const int t = w[i]; w[i] = w[j]; w[j] = t; }
+}
+
+__global__ void __launch_bounds__(kB) adj_count(const int *__restrict__ simp, long long m, int k, int *__restrict__ count) {
+  const long long x = (long long)blockIdx.x * kB + threadIdx.x;
+  if (x >= m * k) return;
+  int w[3] = {0, 0, 0};
+  face_verts(simp, k, x / k, (int)(x % k), w);
+  atomicAdd(&count[w[0]], 1);
+}
+
+__global__ void __launch_bounds__(kB) adj_scatter(const int *__restrict__ simp, long long m, int k,
+                                                  const int *__restrict__ start, int *__restrict__ fill,
+                                                  int *__restrict__ items) {
+  const long long x = (long long)blockIdx.x * kB + threadIdx.x;
+  if (x >= m * k) return;
+  int w[3] = {0, 0, 0};
+  face_verts(simp, k, x / k, (int)(x % k), w);
+  items[start[w[0]] + atomicAdd(&fill[w[0]], 1)] = (int)x;
+}
+
+__global__ void __launch_bounds__(kB) adj_match(const int *__restrict__ simp, long long m, int k,
+                                                const int *__restrict__ start, const int *__restrict__ items,
+                                                int *__restrict__ adj, int *__restrict__ flags) {
+  const long long x = (long long)blockIdx.x * kB + threadIdx.x;
+  if (x >= m * k) return;
+  const long long a = x / k;
+  int w[3] = {0, 0, 0};
+  face_verts(simp, k, a, (int)(x % k), w);
+  int other = -1, matches = 0;
+  for (int t = start[w[0]]; t < start[w[0] + 1]; t++) {
+    const int y = items[t];
+    if (y == (int)x) continue;
+    int z[3] = {0, 0, 0};
+    face_verts(simp, k, y / k, y % k, z);
+    if (z[0] == w[0] && z[1] == w[1] && (k == 3 || z[2] == w[2])) {
+      matches++;
+      other = y / k;
+    }
+  }
+  if (matches > 1 || other == (int)a) atomicOr(&flags[0], 1);
+  adj[x] = matches == 1 ? other : -1;
+}
+
+// ---------------------------------------------------------------------------
+// Convexity of each tetrahedral domain.  M is convex iff every vertex of its
+// boundary lies on the inner side of the plane of every boundary face: then M
+// is contained in the intersection K of those half-spaces, and a segment from
+// the interior of M to a point of K outside M would have to leave M through a
+// boundary face and so leave K too.  The extreme points of M are boundary
+// vertices, so testing those is enough.  One thread per boundary face tests
+// its diagram's boundary vertices (relative tolerance 1e-10 of the diagram's
+// extent); a violation clears convex[b].
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kB) bnd_mark(const int *__restrict__ simp, const int *__restrict__ adj, long long m,
+                                               int *__restrict__ on_bnd) {
+  const long long x = (long long)blockIdx.x * kB + threadIdx.x;
+  if (x >= m * 4) return;
+  if (adj[x] >= 0) return;
+  const long long a = x / 4;
+  const int f = (int)(x % 4);
+  for (int u = 0; u < 4; u++)
+    if (u != f) on_bnd[simp[a * 4 + u]] = 1;
+}
+
+__global__ void __launch_bounds__(kB) bnd_collect(const int *__restrict__ on_bnd, const int *__restrict__ pos,
+                                                  long long nv, int *__restrict__ list) {
+  const long long v = (long long)blockIdx.x * kB + threadIdx.x;
+  if (v < nv && on_bnd[v]) list[pos[v]] = (int)v;
+}
+
+__global__ void __launch_bounds__(kB) convex_check(DomainView D, const int *__restrict__ pos,
+                                                   const int *__restrict__ list, const long long *__restrict__ vert_off,
+                                                   const double *__restrict__ bbox, int *__restrict__ convex) {
+  const long long x = (long long)blockIdx.x * kB + threadIdx.x;
+  if (x >= (long long)D.m * 4) return;
+  if (D.adj[x] >= 0) return;
+  const long long a = x / 4;
+  const int f = (int)(x % 4);
+  const int b = D.nb > 1 ? diagram_of(D.simp_off, D.nb, a) : 0;
+  if (!convex[b]) return;
+  // face f opposite vertex f, oriented outward for a positively oriented tet
+  const unsigned loops = (1u | 2u << 2 | 3u << 4) | (0u | 3u << 2 | 2u << 4) << 6 |
+                         (0u | 1u << 2 | 3u << 4) << 12 | (0u | 2u << 2 | 1u << 4) << 18;
+  const unsigned lf = loops >> (6 * f);
+  const double *pA = &D.verts[3 * (long long)D.simp[a * 4 + (lf & 3)]];
+  const double *pB = &D.verts[3 * (long long)D.simp[a * 4 + ((lf >> 2) & 3)]];
+  const double *pC = &D.verts[3 * (long long)D.simp[a * 4 + ((lf >> 4) & 3)]];
+  const double ab[3] = {pB[0] - pA[0], pB[1] - pA[1], pB[2] - pA[2]};
+  const double ac[3] = {pC[0] - pA[0], pC[1] - pA[1], pC[2] - pA[2]};
+  const double n[3] = {ab[1] * ac[2] - ab[2] * ac[1], ab[2] * ac[0] - ab[0] * ac[2], ab[0] * ac[1] - ab[1] * ac[0]};
+  const double *bx = &bbox[6 * b];
+  const double ext = fmax(fmax(bx[3] - bx[0], bx[4] - bx[1]), bx[5] - bx[2]);
+  const double tol = 1e-10 * ext * sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+  for (int t = pos[vert_off[b]]; t < pos[vert_off[b + 1]]; t++) {
+    const double *p = &D.verts[3 * (long long)list[t]];
+    const double s = n[0] * (p[0] - pA[0]) + n[1] * (p[1] - pA[1]) + n[2] * (p[2] - pA[2]);
+    if (s > tol) { convex[b] = 0; return; }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Boundary surface of a tetrahedral domain: every face without a neighbour
+// becomes a triangle, oriented outward (the loop of face f of a positively
+// oriented tetrahedron), with diagram-local vertex indices; btet[t] is the
+// (global) tetrahedron it bounds.  pos[] is the exclusive scan of the
+// boundary-face flags, so triangles keep tetrahedron order (and diagrams stay
+// contiguous).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kB) bnd_flags(const int *__restrict__ adj, long long nf, int *__restrict__ flag) {
+  const long long x = (long long)blockIdx.x * kB + threadIdx.x;
+  if (x < nf) flag[x] = adj[x] < 0 ? 1 : 0;
+}
+
+__global__ void __launch_bounds__(kB) bnd_extract(const int *__restrict__ simp, const int *__restrict__ adj,
+                                                  long long m, int nb, const long long *__restrict__ simp_off,
+                                                  const long long *__restrict__ vert_off,
+                                                  const int *__restrict__ pos, int *__restrict__ tri,
+                                                  int *__restrict__ btet) {
+  const long long x = (long long)blockIdx.x * kB + threadIdx.x;
+  if (x >= m * 4 || adj[x] >= 0) return;
+  const long long a = x / 4;
+  const int f = (int)(x % 4);
+  const int b = nb > 1 ? diagram_of(simp_off, nb, a) : 0;
+  const int vo = (int)vert_off[b];
+  const unsigned loops = (1u | 2u << 2 | 3u << 4) | (0u | 3u << 2 | 2u << 4) << 6 |
+                         (0u | 1u << 2 | 3u << 4) << 12 | (0u | 2u << 2 | 1u << 4) << 18;
+  const unsigned lf = loops >> (6 * f);
+  const int t = pos[x];
+  tri[3 * (long long)t + 0] = simp[a * 4 + (lf & 3)] - vo;
+  tri[3 * (long long)t + 1] = simp[a * 4 + ((lf >> 2) & 3)] - vo;
+  tri[3 * (long long)t + 2] = simp[a * 4 + ((lf >> 4) & 3)] - vo;
+  btet[t] = (int)a;
+}
+
+// out[b] = pos[4 simp_off[b]]: boundary triangles before diagram b
+__global__ void bnd_offsets(const int *__restrict__ pos, const long long *__restrict__ simp_off, int nb,
+                            long long *__restrict__ out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b <= nb) out[b] = pos[4 * simp_off[b]];
 }
 
 }  // namespace
@@ -232,11 +392,56 @@ void vd_launch_vert_bbox(vd_domain d, double *out, hipStream_t st) {
                      (const long long *)d->d_vert_off, out);
 }
 
-void vd_launch_locate_sites(const GridView &G, const DomainView &D, int *seed, unsigned long long *cnt,
-                            hipStream_t st) {
-  hipLaunchKernelGGL(locate_sites, dim3(blocks(G.n)), dim3(kB), 0, st, G, D, seed, cnt);
+void vd_launch_locate_sites(const GridView &G, const DomainView &D, int *seed, int *outside, hipStream_t st) {
+  hipLaunchKernelGGL(locate_sites, dim3(blocks(G.n)), dim3(kB), 0, st, G, D, seed, outside);
 }
 
 void vd_launch_fill_int(int *p, long long n, int v, hipStream_t st) {
   hipLaunchKernelGGL(fill_int, dim3(blocks(n)), dim3(kB), 0, st, p, n, v);
+}
+
+// adjacency of every simplex face from the (global) vertex indices; flags[0]
+// is set for a non-manifold face.  Temporary buffers are the caller's.
+void vd_launch_adjacency(vd_domain d, int *count, int *start, int *fill, int *items, int *scan_tmp, int *flags,
+                         hipStream_t st) {
+  const long long nf = d->m * (d->dim + 1);
+  const int k = d->dim + 1;
+  hipLaunchKernelGGL(fill_int, dim3(blocks(d->nv)), dim3(kB), 0, st, count, d->nv, 0);
+  hipLaunchKernelGGL(fill_int, dim3(blocks(d->nv)), dim3(kB), 0, st, fill, d->nv, 0);
+  hipLaunchKernelGGL(adj_count, dim3(blocks(nf)), dim3(kB), 0, st, (const int *)d->simp, (long long)d->m, k, count);
+  vdscan::exclusive_scan<int, int>(count, d->nv, start, scan_tmp, st);
+  hipLaunchKernelGGL(adj_scatter, dim3(blocks(nf)), dim3(kB), 0, st, (const int *)d->simp, (long long)d->m, k,
+                     (const int *)start, fill, items);
+  hipLaunchKernelGGL(adj_match, dim3(blocks(nf)), dim3(kB), 0, st, (const int *)d->simp, (long long)d->m, k,
+                     (const int *)start, (const int *)items, d->adj, flags);
+}
+
+// per-diagram convexity of a tetrahedral domain (convex[b] = 1 on entry)
+void vd_launch_convexity(vd_domain d, int *on_bnd, int *pos, int *list, int *scan_tmp, const double *bbox,
+                         int *convex, hipStream_t st) {
+  hipLaunchKernelGGL(fill_int, dim3(blocks(d->nv)), dim3(kB), 0, st, on_bnd, d->nv, 0);
+  hipLaunchKernelGGL(bnd_mark, dim3(blocks(d->m * 4)), dim3(kB), 0, st, (const int *)d->simp, (const int *)d->adj,
+                     (long long)d->m, on_bnd);
+  vdscan::exclusive_scan<int, int>(on_bnd, d->nv, pos, scan_tmp, st);
+  hipLaunchKernelGGL(bnd_collect, dim3(blocks(d->nv)), dim3(kB), 0, st, (const int *)on_bnd, (const int *)pos,
+                     (long long)d->nv, list);
+  hipLaunchKernelGGL(convex_check, dim3(blocks(d->m * 4)), dim3(kB), 0, st, d->view(), (const int *)pos,
+                     (const int *)list, (const long long *)d->d_vert_off, bbox, convex);
+}
+
+// boundary faces of a tetrahedral domain: flags / scan into pos[4m+1], then
+// the outward triangles (diagram-local vertex indices), their tetrahedra and
+// the per-diagram triangle offsets boff[nb+1]
+void vd_launch_boundary_scan(vd_domain d, int *flag, int *pos, int *scan_tmp, hipStream_t st) {
+  const long long nf = d->m * 4;
+  hipLaunchKernelGGL(bnd_flags, dim3(blocks(nf)), dim3(kB), 0, st, (const int *)d->adj, nf, flag);
+  vdscan::exclusive_scan<int, int>(flag, nf, pos, scan_tmp, st);
+}
+
+void vd_launch_boundary_extract(vd_domain d, const int *pos, int *tri, int *btet, long long *boff, hipStream_t st) {
+  hipLaunchKernelGGL(bnd_extract, dim3(blocks(d->m * 4)), dim3(kB), 0, st, (const int *)d->simp,
+                     (const int *)d->adj, (long long)d->m, d->nb, (const long long *)d->d_simp_off,
+                     (const long long *)d->d_vert_off, pos, tri, btet);
+  hipLaunchKernelGGL(bnd_offsets, dim3((d->nb + 1 + 255) / 256), dim3(256), 0, st, pos,
+                     (const long long *)d->d_simp_off, d->nb, boff);
 }

@@ -113,7 +113,7 @@ __device__ int compact_s(TriLds &S, int npl, int nv) {
 // Clip the polygon by plane slot P, removing the run of consecutive outside
 // vertices that contains vertex pt (pt < 0: the farthest outside vertex).
 // Returns 0 unchanged, 1 empty, 2 capacity, 3 degenerate, 4 cut.
-__device__ int clip_s(TriLds &S, int P, int pt, int &nv) {
+__device__ int clip_s(TriLds &S, bool mon, int P, int pt, int &nv) {
   const int l = vd_lane();
   const double nx = S.pn[P][0], ny = S.pn[P][1], nz = S.pn[P][2], c = S.pn[P][3];
   double y0 = 0, y1 = 0, y2 = 0, sd = -1.0;
@@ -123,6 +123,10 @@ __device__ int clip_s(TriLds &S, int P, int pt, int &nv) {
     y0 = S.vy[l][0]; y1 = S.vy[l][1]; y2 = S.vy[l][2];
     e = S.ve[l]; st = S.vst[l];
     sd = nx * y0 + ny * y1 + nz * y2 - c;
+  }
+  if (mon) {
+    margin_track(S.ar, v, sd, fabs(nx * y0) + fabs(ny * y1) + fabs(nz * y2) + fabs(c), false, 0.0, 1.0);
+    count_add(S.ar.classified, nv);
   }
   const uint64_t O = __ballot(v && sd > 0.0);
   if (!O) return pt < 0 ? 0 : 3;
@@ -163,11 +167,13 @@ __device__ int clip_s(TriLds &S, int P, int pt, int &nv) {
   }
   __syncthreads();
   nv = keep + 2;
+  if (mon) count_add(S.ar.newc, 2);
   return 4;
 }
 
 struct SParams {
   int improved, straddle, max_iters;
+  bool monitor;  // count work and track predicate margins
 };
 
 // Carve the polygon until every vertex is certified inside Omega_i (TEST /
@@ -254,6 +260,7 @@ __device__ int carve_s(TriLds &S, const GridView &G, const SParams C, int si, do
     const int gs = mode == TEST ? 16 : 64;
     const double qx = vx + q0, qy = vy + q1, qz = vz + q2;
     const double dx = qx - vx, dy = qy - vy, dz = qz - vz;
+    if (C.monitor) count_add(S.ar.rounds, 1);
     const int kq = nn_query(G, gs, qx, qy, qz, dx * dx + dy * dy + dz * dz, si, ss.cands);
     if (mode == TEST) {
       ss.queries += nbatch;
@@ -303,7 +310,7 @@ __device__ int carve_s(TriLds &S, const GridView &G, const SParams C, int si, do
       S.plab[P] = j;
     }
     __syncthreads();
-    const int rc = clip_s(S, P, pt, nv);
+    const int rc = clip_s(S, C.monitor, P, pt, nv);
     ss.clips++;
     if (rc == 1) return 1;
     if (rc != 4) return rc == 0 ? 3 : rc;
@@ -316,7 +323,7 @@ __device__ __forceinline__ int conv(const GridView &G, int lab) { return lab >= 
 
 __device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, const CellsDev &C, int a) {
   const int l = vd_lane();
-  const SParams P = {C.improved, C.straddle, C.max_iters};
+  const SParams P = {C.improved, C.straddle, C.max_iters, C.monitor != 0};
   SStats ss;
   int err = 0;
   // seed: nearest site of the centroid (Alg. 4)
@@ -366,12 +373,18 @@ __device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, c
                         s0 * s0 + s1 * s1 + s2 * s2);
     }
     pa = wave_sum(pa); pmx = wave_sum(pmx); pmy = wave_sum(pmy); pmz = wave_sum(pmz); pe = wave_sum(pe);
+    if (C.monitor) count_add(S.ar.fantets, nv);
     if (!(pa > 0.0)) continue;
     const int orig = GL(G.perm)[si];
     const long long pidx = arena_take(S.ar, C, AR_PIECE, 1);
     const long long fo = arena_take(S.ar, C, AR_FACE, nv);
     const long long vo = arena_take(S.ar, C, AR_VERT, nv);
-    if (l == 0) __hip_atomic_fetch_add(GL(C.pcount) + orig, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // only records that fit are counted: the per-site CSR built from the
+    // counts then stays inside the arenas (the clip reports the overflow)
+    const bool fits_fv = fo + nv <= C.cap_face && vo + nv <= C.cap_vert;
+    if (l == 0 && pidx < C.cap_piece && fits_fv)
+      __hip_atomic_fetch_add(GL(C.pcount) + orig, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (l == 0 && !(pidx < C.cap_piece && fits_fv)) S.ar.dropped++;
     if (C.want_grad) {
       // segment moments of the bisector edges: a point of the edge moves in
       // the plane of T_a with speed (x - v_i).dv / (d s), s = |n - (n.N)N|
@@ -381,7 +394,12 @@ __device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, c
       const uint64_t pos = __ballot(lab >= 0);
       const int npos = __popcll(pos);
       const long long base = arena_take(S.ar, C, AR_FINT, npos);
-      if (l == 0 && pidx < C.cap_piece) { GL(C.piece_fint_start)[pidx] = base; GL(C.piece_nfint)[pidx] = npos; }
+      const bool ffits = base + npos <= C.cap_fint;
+      if (l == 0 && pidx < C.cap_piece) {
+        GL(C.piece_fint_start)[pidx] = base;
+        GL(C.piece_nfint)[pidx] = ffits ? npos : 0;
+        if (!ffits) S.ar.dropped++;
+      }
       const long long r = base + __popcll(pos & lowm(l));
       if (lab >= 0 && r < C.cap_fint) {
         const int t2 = (l + 1) % nv;
@@ -415,7 +433,8 @@ __device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, c
     }
     if (pidx < C.cap_piece) {
       if (l == 0) {
-        GL(C.piece_site)[pidx] = orig;
+        // a piece whose edges did not fit is written as an unused slot
+        GL(C.piece_site)[pidx] = fits_fv ? orig : -1;
         GL(C.piece_simplex)[pidx] = a;
         GL(C.piece_nface)[pidx] = nv;
         GL(C.piece_nvert)[pidx] = nv;
@@ -426,11 +445,13 @@ __device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, c
         GL(C.piece_energy)[pidx] = pe;
         GL(C.piece_fstart)[pidx] = fo;
         GL(C.piece_vstart)[pidx] = vo;
-        S.ar.pieces++;
-        S.ar.faces += nv;
-        S.ar.verts += nv;
+        if (fits_fv) {
+          S.ar.pieces++;
+          S.ar.faces += nv;
+          S.ar.verts += nv;
+        }
       }
-      if (fo + nv <= C.cap_face && vo + nv <= C.cap_vert && l < nv) {
+      if (fits_fv && l < nv) {
         const int prv = (l + nv - 1) % nv;
         GL(C.face_label)[fo + l] = conv(G, S.plab[S.ve[l]]);
         GL(C.vert_xyz)[3 * (vo + l) + 0] = S.vy[l][0] + vx;

@@ -21,6 +21,11 @@ struct WaveArena {
   long long cur[AR_N], end[AR_N];
   unsigned long long queries, cands, clips, gridq;
   unsigned long long pieces, faces, verts, nbrs;  // records written (real counts)
+  unsigned long long dropped;                     // records that did not fit their arena
+  // work counters of the clips (lane 0 updates them in LDS, so they cost no
+  // registers across the carve)
+  unsigned long long rounds, classified, newc, wasted, fantets, lowmargin;
+  double minmargin;                               // smallest relative classification margin
   int qi;                                         // queues tried so far
 };
 
@@ -29,6 +34,9 @@ __device__ __forceinline__ void arena_init(WaveArena &A) {
     for (int r = 0; r < AR_N; r++) A.cur[r] = A.end[r] = 0;
     A.queries = A.cands = A.clips = A.gridq = 0;
     A.pieces = A.faces = A.verts = A.nbrs = 0;
+    A.dropped = 0;
+    A.rounds = A.classified = A.newc = A.wasted = A.fantets = A.lowmargin = 0;
+    A.minmargin = 1.0;
     A.qi = 0;
   }
 }
@@ -83,5 +91,40 @@ __device__ __forceinline__ void arena_close(WaveArena &A, const CellsDev &C) {
     atomicAdd(&C.cnt[CNT_REAL_FACES], A.faces);
     atomicAdd(&C.cnt[CNT_REAL_VERTS], A.verts);
     atomicAdd(&C.cnt[CNT_REAL_NBRS], A.nbrs);
+    if (A.dropped) atomicAdd(&C.cnt[CNT_OVERFLOW], A.dropped);
+    atomicAdd(&C.cnt[CNT_ROUNDS], A.rounds);
+    atomicAdd(&C.cnt[CNT_CLASSIFIED], A.classified);
+    atomicAdd(&C.cnt[CNT_NEWCORNERS], A.newc);
+    atomicAdd(&C.cnt[CNT_WASTED], A.wasted);
+    atomicAdd(&C.cnt[CNT_FANTETS], A.fantets);
+    if (A.lowmargin) atomicAdd(&C.cnt[CNT_LOWMARGIN], A.lowmargin);
+    atomicMin(&C.cnt[CNT_MINMARGIN], (unsigned long long)__double_as_longlong(A.minmargin));
+  }
+}
+
+// Adds v to a work counter of the wave's LDS totals: an LDS atomic from lane 0
+// whose result is unused, so nothing waits for it and no register stays live.
+__device__ __forceinline__ void count_add(unsigned long long &ctr, unsigned long long v) {
+  if (vd_lane() == 0) __hip_atomic_fetch_add(&ctr, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Relative margin of the classification of corners y against the plane
+// n.y = c: |n.y - c| / (|n0 y0| + |n1 y1| + |n2 y2| + |c|), the signed distance
+// over the magnitude its rounding error scales with.  Each lane brings up to two
+// corners (valid flag, signed distance, scale).  Lane 0 keeps the wave's minimum
+// and the count of margins below 1e-12 (near-degenerate decisions); the
+// division is only taken when some corner is within 1e-3 of its plane.
+__device__ __forceinline__ void margin_track(WaveArena &A, bool v0, double sd0, double sc0, bool v1, double sd1,
+                                             double sc1) {
+  const bool n0 = v0 && fabs(sd0) < 1e-3 * sc0, n1 = v1 && fabs(sd1) < 1e-3 * sc1;
+  if (__ballot(n0 || n1)) {
+    const int nlow = __popcll(__ballot(v0 && fabs(sd0) < 1e-12 * sc0)) + __popcll(__ballot(v1 && fabs(sd1) < 1e-12 * sc1));
+    double r = n0 ? fabs(sd0) / sc0 : 1.0;
+    if (n1) r = fmin(r, fabs(sd1) / sc1);
+    r = wave_min(r);
+    if (vd_lane() == 0) {
+      A.lowmargin += nlow;
+      if (r < A.minmargin) A.minmargin = r;
+    }
   }
 }

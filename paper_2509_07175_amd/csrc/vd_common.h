@@ -146,6 +146,15 @@ __device__ __forceinline__ double wave_sum(double v) {
   return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
 
+// minimum over the wave, the same value in every lane
+__device__ __forceinline__ double wave_min(double v) {
+  v = fmin(v, perm_d<VD_DPP_QUAD_XOR1>(v));
+  v = fmin(v, perm_d<VD_DPP_QUAD_XOR2>(v));
+  v = fmin(v, perm_d<VD_DPP_ROW_HALF_MIRROR>(v));
+  v = fmin(v, perm_d<VD_DPP_ROW_MIRROR>(v));
+  return fmin(fmin(readlane_d(v, 0), readlane_d(v, 16)), fmin(readlane_d(v, 32), readlane_d(v, 48)));
+}
+
 __device__ __forceinline__ int wave_isum(int v) {
   v += perm_i<VD_DPP_QUAD_XOR1>(v);
   v += perm_i<VD_DPP_QUAD_XOR2>(v);

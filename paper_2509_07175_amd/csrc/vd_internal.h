@@ -33,8 +33,18 @@ enum {
   CNT_PIECES = AR_PIECE, CNT_FACES = AR_FACE, CNT_VERTS = AR_VERT, CNT_NBRS = AR_NBR, CNT_FINT = AR_FINT,
   CNT_QUERIES = AR_N, CNT_CLIPS, CNT_CANDS, CNT_ERR_CAP, CNT_ERR_DEG, CNT_ERR_LOC, CNT_BAD_SITE,
   CNT_REAL_PIECES, CNT_REAL_FACES, CNT_REAL_VERTS, CNT_REAL_NBRS, CNT_STAGES, CNT_GRIDQ,
+  CNT_OVERFLOW,    // records dropped because an arena was full (pieces, per-piece faces / vertices /
+                   // face moments, per-site neighbour lists)
+  CNT_LOWMARGIN,   // corner classifications whose relative margin was below 1e-12
+  CNT_MINMARGIN,   // bits of the smallest relative margin seen (a non-negative double)
+  CNT_ROUNDS,      // nearest-site query rounds (a batch of up to four tests is one round)
+  CNT_CLASSIFIED,  // corners classified against a clipping plane
+  CNT_NEWCORNERS,  // corners created by clips (one 3x3 solve each)
+  CNT_WASTED,      // tested corners that a clip removed besides the one that triggered it
+  CNT_FANTETS,     // fan tetrahedra integrated for piece moments
   CNT_N
 };
+static_assert(CNT_N <= 64, "reset_counters clears the counters with one wave");
 
 // persistent kernels: one work queue per XCD (8 heads, one per 128-byte line)
 #define VD_QUEUES 8
@@ -105,6 +115,14 @@ struct vd_domain_s {
   int *lstart = nullptr, *litems = nullptr, *lcount = nullptr, *lfill = nullptr, *scan_tmp = nullptr;
   int64_t nitems = 0, ncell = 0;
   double area = 0.0;  // surface area (triangles) or volume (tets), all diagrams
+  std::vector<int> convex;  // host [nb]: 1 if the tetrahedral domain of diagram b is convex
+  bool all_convex = false;  // every diagram's tetrahedral domain is convex
+  // tetrahedra: the boundary surface of M as a triangle domain (outward
+  // triangles, edges all flagged as boundary) and the tetrahedron owning each
+  // of its triangles; its restricted diagram seeds the cells that reach M
+  // from outside the tetrahedron of their site (Alg. 5)
+  vd_domain_s *bnd = nullptr;
+  int *btet = nullptr;
   // batch of nb domains (nb = 1: plain)
   int nb = 1;
   std::vector<int64_t> vert_off, simp_off, loc_off;  // host [nb + 1]
@@ -152,6 +170,7 @@ struct CellsDev {
   int max_iters;
   int mode;        // 0 per-simplex carve, 1 cell-first
   int cache;       // LDS copy of the sites around each site for its queries
+  int monitor;     // count work and track predicate margins
   unsigned long long *cnt;  // CNT_N counters
   // per site (caller index)
   double *mass, *mom, *energy;
@@ -171,7 +190,12 @@ struct CellsDev {
   // divided by the in-plane sine for surface edges), and the neighbour k
   double *fint; int *fint_lab; long long cap_fint;
   long long *piece_fint_start; int *piece_nfint;
-  int *seed;  // 3D: tetrahedron containing each site (sorted position order)
+  int *seed;  // 3D: tetrahedron containing each site (sorted position order), -1 outside M
+  // 3D, boundary seeds (Alg. 5): pieces of each site (caller index) on the
+  // boundary surface -- CSR offsets, piece ids, their triangles -- and the
+  // tetrahedron behind each boundary triangle; all NULL when not used
+  const long long *bseed_off;
+  const int *bseed_pid, *bseed_tri, *btet;
   long long chunk[AR_N];  // slots a wave reserves at a time in each arena
   int *queue;             // [VD_QUEUES * VD_QSTRIDE] work-queue heads
   int *tq_spill;          // [workgroups * VD_Q_SPILL] overflow of the per-site simplex queue
@@ -204,14 +228,17 @@ struct vd_cells_s {
   CellsDev d_shadow{};        // host copy last sent to d_dev
   double *wbuf = nullptr;     // adjoint weights [5n]
   int64_t cap_w = 0;
+  int *outside = nullptr;     // [2] sites outside every tetrahedron: count, lowest caller index
+  int64_t sites_outside = -1;  // sites outside every tetrahedron (-1: not counted)
+  vd_cells_s *bcells = nullptr;  // restricted diagram of the domain's boundary (boundary seeds)
+  bool used_bseeds = false;      // the last clip seeded from the boundary
 };
 
 // launchers (defined in the .hip files)
 void vd_launch_grid_build(vd_grid g, const double *sites, const double *user_box, hipStream_t st);
 void vd_launch_grid_delta(vd_grid g, hipStream_t st);
 void vd_launch_domain_locator(vd_domain d, hipStream_t st);
-void vd_launch_locate_sites(const GridView &G, const DomainView &D, int *seed, unsigned long long *cnt,
-                            hipStream_t st);
+void vd_launch_locate_sites(const GridView &G, const DomainView &D, int *seed, int *outside, hipStream_t st);
 // workgroups of the persistent 3D site kernel (resident waves of the device)
 int vd_sites3d_workgroups(long long n);
 void vd_launch_queue_init(int *queue, long long n, hipStream_t st);

@@ -34,15 +34,27 @@ def run_gpu(sites, dom, bbox=(0, 0, 0, 1, 1, 1), surface_area=0.0, **opts):
     return out
 
 
-def sampled_result(view, sample):
+def ranges(starts, counts):
+    """Concatenation of arange(s, s + c) over (starts, counts), vectorised."""
+    starts = np.asarray(starts, dtype=np.int64)
+    counts = np.asarray(counts, dtype=np.int64)
+    tot = int(counts.sum())
+    if tot == 0:
+        return np.zeros(0, np.int64)
+    first = np.repeat(np.cumsum(counts) - counts, counts)
+    return np.repeat(starts, counts) + (np.arange(tot, dtype=np.int64) - first)
+
+
+def sampled_result(view, sample, off=None):
     """The pieces of the sites in `sample` (caller indices), gathered on the
     device, in the oracle's layout (sorted by site, then simplex): for
     workloads whose full polytope output is too large to copy to the host."""
     import torch
-    off = view["cell_piece_off"].cpu().numpy()
-    pid_all = view["piece_id"]
-    ids = np.concatenate([pid_all[off[i]:off[i + 1]].cpu().numpy() for i in sample]).astype(np.int64)
-    dev = pid_all.device
+    off = view["cell_piece_off"].cpu().numpy() if off is None else off
+    sample = np.asarray(sample, dtype=np.int64)
+    dev = view["piece_id"].device
+    pos = ranges(off[sample], off[sample + 1] - off[sample])
+    ids = view["piece_id"][torch.as_tensor(pos, device=dev)].cpu().numpy().astype(np.int64)
     idt = torch.as_tensor(ids, device=dev)
 
     def take(name):
@@ -55,9 +67,8 @@ def sampled_result(view, sample):
     nvert = view["piece_nvert"][idt].cpu().numpy().astype(np.int64)
     fst = view["piece_face_start"][idt].cpu().numpy()
     vst = view["piece_vert_start"][idt].cpu().numpy()
-    fidx = np.concatenate([np.arange(a, a + c) for a, c in zip(fst, nface)]) if len(ids) else np.zeros(0, np.int64)
-    vidx = np.concatenate([np.arange(a, a + c) for a, c in zip(vst, nvert)]) if len(ids) else np.zeros(0, np.int64)
-    ft, vt = torch.as_tensor(fidx, device=dev), torch.as_tensor(vidx, device=dev)
+    ft = torch.as_tensor(ranges(fst, nface), device=dev)
+    vt = torch.as_tensor(ranges(vst, nvert), device=dev)
     return {
         "piece_site": site, "piece_simplex": simp,
         "piece_mass": view["piece_mass"][idt].cpu().numpy(),
@@ -69,6 +80,60 @@ def sampled_result(view, sample):
         "vert_xyz": view["vert_xyz"][vt].cpu().numpy(),
         "vert_label": view["vert_label"][vt].cpu().numpy(),
     }
+
+
+def shift_labels(lab, site_lo, simp_lo):
+    """Batch (global) face / vertex flags of one diagram -> its local flags:
+    sites minus site_lo, -(b+1) flags with b minus simp_lo, boundary flags and
+    the triangle filler INT32_MAX unchanged."""
+    lab = np.asarray(lab).astype(np.int64)
+    out = lab.copy()
+    pos = (lab >= 0) & (lab != 2**31 - 1)
+    out[pos] = lab[pos] - site_lo
+    neg = (lab < 0) & (lab > -2**31 + 16)
+    out[neg] = -((-lab[neg] - 1) - simp_lo) - 1
+    return out
+
+
+def assert_sampled_parity(res_gpu, mass, cent, en, nbr_off, nbr, ref, mom, sample, xyz_tol=1e-10, rel=1e-9,
+                          site_lo=0):
+    """Sampled sites of a full-size run against the oracle: piece sets, face
+    labels and vertex label triples bit-exact, vertices within xyz_tol,
+    masses / centroids / energies within rel, neighbour lists equal.  The GPU
+    arrays are indexed site_lo + i for oracle site i (batches)."""
+    sample = np.asarray(sample, dtype=np.int64)
+    sset = set(sample.tolist())
+    a = canon_pieces(res_gpu)
+    b = {k: v for k, v in canon_pieces(ref).items() if k[0] in sset}
+    missing = sorted(set(b) - set(a))[:5]
+    extra = sorted(set(a) - set(b))[:5]
+    assert not missing and not extra, f"piece sets differ: missing {missing} extra {extra}"
+    md = 0.0
+    for k in b:
+        assert a[k][0] == b[k][0] and a[k][1] == b[k][1], f"combinatorics differ at {k}"
+        if len(b[k][2]):
+            md = max(md, float(np.abs(a[k][2] - b[k][2]).max()))
+    assert md <= xyz_tol, f"vertex coordinates differ by {md}"
+    g = site_lo + sample
+    m_r, c_r, e_r = mom["mass"][sample], mom["centroid"][sample], mom["energy"][sample]
+    nz = m_r > 0
+    assert np.all(np.abs(mass[g] - m_r) <= rel * m_r), "mass"
+    cerr = np.linalg.norm(cent[g] - c_r, axis=1) / np.linalg.norm(c_r, axis=1)
+    assert np.all(cerr[nz] <= rel), f"centroid max rel err {cerr[nz].max()}"
+    assert np.all(np.abs(en[g] - e_r)[nz] <= rel * e_r[nz]), "energy"
+    for i in sample:
+        got = nbr[nbr_off[site_lo + i]:nbr_off[site_lo + i + 1]] - site_lo
+        assert list(got) == list(mom["neighbors"][i]), f"neighbours of site {i} differ"
+    return md
+
+
+def assert_neighbour_symmetry(nbr_off, nbr):
+    """j is a neighbour of i iff i is a neighbour of j, over all sites."""
+    n = len(nbr_off) - 1
+    owner = np.repeat(np.arange(n, dtype=np.int64), np.diff(nbr_off))
+    fwd = owner * n + nbr.astype(np.int64)
+    bwd = nbr.astype(np.int64) * n + owner
+    assert np.array_equal(np.sort(fwd), np.sort(bwd)), "neighbour relation is not symmetric"
 
 
 def assert_csr(gpu, n):

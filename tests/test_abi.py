@@ -33,6 +33,9 @@ def test_host_only_entry_points():
     o = vd.Options.default()
     assert o.sites_per_cell == 2.0 and o.improved_search == 0 and o.use_straddle_edges == 0
     assert lib.vd_status_string(4) == b"VD_ERR_CAPACITY"
+    assert lib.vd_status_string(6) == b"VD_ERR_NOT_READY"
+    assert lib.vd_domain_info(None, None) == 1
+    assert lib.vd_domain_adjacency(None, None, None) == 1
     # argument checks happen before any device work
     h = C.c_void_p()
     assert lib.vd_build_grid(None, 10, None, 0.0, 0.0, None, C.byref(h)) == 1
@@ -58,3 +61,30 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=300)
     assert r.returncode == 2
     assert "exactly one GPU" in r.stderr
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The binding's ctypes structs have the sizes and field offsets that a C
+    compiler gives the structs of include/vd.h."""
+    import shutil
+    import subprocess
+    import paper_2509_07175_amd as vd
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    structs = {"vd_options": vd.Options, "vd_cells_info_t": vd._Info, "vd_cells_view_t": vd._View,
+               "vd_domain_info_t": vd._DomainInfo, "vd_batch": vd._Batch}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "vd.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname}.{fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("  return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines())
+    for cname, py in structs.items():
+        assert int(out[cname]) == C.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert int(out[f"{cname}.{fname}"]) == getattr(py, fname).offset, f"{cname}.{fname}"

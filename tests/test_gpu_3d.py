@@ -10,7 +10,8 @@ import pytest
 
 import vdgen
 from canon import canon_pieces
-from gpu_util import assert_parity, gpu_neighbors, log, run_gpu, sampled_result
+from gpu_util import (assert_neighbour_symmetry, assert_parity, assert_sampled_parity, gpu_neighbors, log, run_gpu,
+                      sampled_result)
 
 pytestmark = pytest.mark.gpu
 
@@ -109,30 +110,40 @@ def test_clustered_small(oracle_mod, mode):
     _check_case(oracle_mod, s, dom, brute=False, carve_mode=mode)
 
 
-def test_c2_full_size_sampled(oracle_mod):
-    """C2 at its full size: 100,000 sites in 48,000 tetrahedra.  Sampled sites
-    are compared piece by piece with the oracle; partition and symmetry are
-    checked for all sites."""
+@pytest.mark.parametrize("mode", [1, 0])
+def test_c2_full_size_sampled(oracle_mod, mode):
+    """C2 at its full size: 100,000 sites in 48,000 tetrahedra, both carve
+    modes.  5,000 sampled sites are compared piece by piece with the oracle;
+    per-tetrahedron partition and neighbour symmetry are checked for all
+    sites."""
+    import torch
+    import paper_2509_07175_amd as vd
     sites, dom = vdgen.config_c2()
-    gpu = run_gpu(sites, dom)
-    log(f"C2 info {gpu['info']}")
     n = len(sites)
-    assert abs(gpu["mass"].sum() - 1.0) < 1e-11
-    rng = np.random.default_rng(2024)
-    sample = np.sort(rng.choice(n, size=120, replace=False))
-    ref = oracle_mod.compute(sites, dom, only_sites=sample)
-    mom = oracle_mod.site_moments(ref, sites)
-    assert_parity(gpu, ref, mom, n, sites_subset=sample)
-    # per-tet partition
-    res = gpu["res"]
+    s = torch.as_tensor(sites, dtype=torch.float64, device="cuda")
+    d = vd.Domain.from_vdgen(dom)
+    g = vd.build_grid(s, bbox=(0.0, 0.0, 0.0, 1.0, 1.0, 1.0))
+    c = vd.clip_cells(g, d, vd.Options.default(carve_mode=mode))
+    m, ce, e = c.moments()
+    torch.cuda.synchronize()
+    log(f"C2 mode {mode} info {c.info()}")
+    mass, cent, en = m.cpu().numpy(), ce.cpu().numpy(), e.cpu().numpy()
+    assert abs(mass.sum() - 1.0) < 1e-11
+    view = c.view()
+    psite = view["piece_site"].cpu().numpy()
+    used = psite >= 0
     q = dom.verts[dom.simplices]
     tv = np.einsum("ij,ij->i", np.cross(q[:, 1] - q[:, 0], q[:, 2] - q[:, 0]), q[:, 3] - q[:, 0]) / 6
-    per = np.bincount(res["piece_simplex"], weights=res["piece_mass"], minlength=dom.m)
+    per = np.bincount(view["piece_simplex"].cpu().numpy()[used], weights=view["piece_mass"].cpu().numpy()[used],
+                      minlength=dom.m)
     assert np.allclose(per, tv, rtol=1e-10, atol=0)
-    nb = gpu_neighbors(gpu, n)
-    for i in rng.choice(n, size=2000, replace=False):
-        for j in nb[i]:
-            assert i in set(nb[j].tolist())
+    nbo, nb = view["nbr_off"].cpu().numpy(), view["nbr"].cpu().numpy()
+    assert_neighbour_symmetry(nbo, nb)
+    rng = np.random.default_rng(2024)
+    sample = np.sort(rng.choice(n, size=5000, replace=False))
+    ref = oracle_mod.compute(sites, dom, only_sites=sample)
+    mom = oracle_mod.site_moments(ref, sites)
+    assert_sampled_parity(sampled_result(view, sample), mass, cent, en, nbo, nb, ref, mom, sample)
 
 
 @pytest.mark.parametrize("mode", [1, 0])
@@ -189,11 +200,13 @@ def test_near_degenerate_lattice(oracle_mod, mode):
 def test_c3_full_size_sampled(oracle_mod):
     """The headline workload in the benchmark's launch configuration: 1,000,000
     clustered sites in 750,000 tetrahedra, grid at 0.25 sites per cell, default
-    options.  All sites: total and per-tetrahedron volume, CSR consistency.
-    Sampled sites (random, the smallest cells of the cluster cores, the
-    largest cells of the background): pieces, face labels and vertex label
-    triples bit-exact, vertices, masses, centroids and energies against the
-    oracle."""
+    options.  All sites: total and per-tetrahedron volume, CSR consistency,
+    neighbour symmetry.  About 12,000 sampled sites, stratified by cell size
+    (cluster cores: the smallest cells; cluster edges: the middle of the
+    distribution; background: the largest cells; plus a uniform draw), and
+    every site with a piece below 1e-15 of its tetrahedron's volume: pieces,
+    face labels and vertex label triples bit-exact, vertices, masses,
+    centroids, energies and neighbour lists against the oracle."""
     import torch
     import paper_2509_07175_amd as vd
     sites, dom = vdgen.config_c3()
@@ -220,31 +233,23 @@ def test_c3_full_size_sampled(oracle_mod):
     assert np.allclose(per, tv, rtol=1e-10, atol=0)
     off = view["cell_piece_off"].cpu().numpy()
     assert off[0] == 0 and off[-1] == used.sum() and np.all(np.diff(off) >= 1)
+    nbo, nb = view["nbr_off"].cpu().numpy(), view["nbr"].cpu().numpy()
+    assert_neighbour_symmetry(nbo, nb)
     rng = np.random.default_rng(3003)
     order = np.argsort(mass)
-    # site 908627: a vertex of its cell lies 1.4e-8 inside tetrahedron 718229,
-    # a piece of volume 1.8e-23 about 0.015 from the site
-    sample = np.unique(np.concatenate([rng.choice(n, size=24, replace=False), order[:12], order[-12:], [908627]]))
+    tiny = np.unique(psite[used][pmass < 1e-15 * tv[psimp]])
+    log(f"C3: {len(tiny)} sites with a piece below 1e-15 of its tetrahedron")
+    sample = np.unique(np.concatenate([
+        order[:3000],                                  # cluster cores
+        order[n // 2 - 1500:n // 2 + 1500],            # cluster edges
+        order[-3000:],                                 # background
+        rng.choice(n, size=3000, replace=False),       # uniform
+        tiny, [908627]]).astype(np.int64))
+    log(f"C3: comparing {len(sample)} sites with the oracle")
     ref = oracle_mod.compute(sites, dom, only_sites=sample)
     mom = oracle_mod.site_moments(ref, sites)
-    a = canon_pieces(sampled_result(view, sample))
-    b = {k: v for k, v in canon_pieces(ref).items() if k[0] in set(sample.tolist())}
-    assert set(a) == set(b), "piece sets differ"
-    md = 0.0
-    for k in b:
-        assert a[k][0] == b[k][0] and a[k][1] == b[k][1], f"combinatorics differ at {k}"
-        if len(b[k][2]):
-            md = max(md, float(np.abs(a[k][2] - b[k][2]).max()))
-    assert md <= 1e-10, f"vertex coordinates differ by {md}"
-    for i in sample:
-        assert abs(mass[i] - mom["mass"][i]) <= 1e-9 * mom["mass"][i]
-        assert np.linalg.norm(cent[i] - mom["centroid"][i]) <= 1e-9 * np.linalg.norm(mom["centroid"][i])
-        assert abs(en[i] - mom["energy"][i]) <= 1e-9 * mom["energy"][i]
-    nbo, nb = view["nbr_off"].cpu().numpy(), view["nbr"].cpu().numpy()
-    for i in sample:
-        assert list(nb[nbo[i]:nbo[i + 1]]) == list(mom["neighbors"][i]), f"neighbours of site {i} differ"
-        for j in nb[nbo[i]:nbo[i + 1]]:
-            assert i in set(nb[nbo[j]:nbo[j + 1]].tolist()), f"neighbour symmetry {i} {j}"
+    md = assert_sampled_parity(sampled_result(view, sample, off), mass, cent, en, nbo, nb, ref, mom, sample)
+    log(f"C3: {len(sample)} sites, {len(ref['piece_site'])} pieces identical; max vertex difference {md:.2e}")
 
 
 def test_c3_pieces_do_not_depend_on_the_schedule():

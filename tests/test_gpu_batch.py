@@ -195,23 +195,44 @@ def test_graph_replays_match_eager():
 
 
 def test_batched_workload_full_size(oracle_mod):
-    """256 diagrams, 1,000 - 64,000 sites each, jittered 8^3 - 24^3 cube grids."""
+    """256 diagrams, 1,000 - 64,000 sites each, jittered 8^3 - 24^3 cube grids,
+    in one launch.  Every diagram: its volume, and 20 sampled sites against the
+    oracle (pieces, face labels and vertex label triples bit-exact after the
+    shift to diagram-local indices; vertices, masses, centroids, energies and
+    neighbour lists).  Neighbour symmetry over all sites."""
+    import torch
+    import paper_2509_07175_amd as vd
+    from gpu_util import assert_neighbour_symmetry, assert_sampled_parity, sampled_result, shift_labels
     items = vdgen.config_c4()
-    B = _run_batch(items)
-    so = B["site_off"]
-    log(f"batch: {len(items)} diagrams, {so[-1]} sites, info {B['info']}")
-    for b in range(len(items)):
-        vol = B["mass"][so[b]:so[b + 1]].sum()
-        assert abs(vol - 1.0) < 1e-10, f"diagram {b}: volume {vol}"
+    so = np.concatenate([[0], np.cumsum([len(s) for s, _ in items])])
+    sites = torch.as_tensor(np.concatenate([s for s, _ in items]), dtype=torch.float64, device="cuda")
+    dom = vd.Domain.batch_from_vdgen([d for _, d in items])
+    g = vd.build_grid_batch(sites, so, bboxes=[(0, 0, 0, 1, 1, 1)] * len(items))
+    c = vd.clip_cells(g, dom, vd.Options.default())
+    m, ce, e = c.moments()
+    torch.cuda.synchronize()
+    info = c.info()
+    log(f"batch: {len(items)} diagrams, {so[-1]} sites, info {info}")
+    assert info["status"] == 0
+    mass, cent, en = m.cpu().numpy(), ce.cpu().numpy(), e.cpu().numpy()
+    view = c.view()
+    off = view["cell_piece_off"].cpu().numpy()
+    nbo, nb = view["nbr_off"].cpu().numpy(), view["nbr"].cpu().numpy()
+    assert_neighbour_symmetry(nbo, nb)
     rng = np.random.default_rng(2026)
-    for b in rng.choice(len(items), size=3, replace=False):
-        s, d = items[b]
-        sample = np.sort(rng.choice(len(s), size=40, replace=False))
+    npieces = 0
+    for b, (s, d) in enumerate(items):
+        lo = so[b]
+        vol = mass[lo:so[b + 1]].sum()
+        assert abs(vol - 1.0) < 1e-10, f"diagram {b}: volume {vol}"
+        sample = np.sort(rng.choice(len(s), size=20, replace=False))
         ref = oracle_mod.compute(s, d, only_sites=sample)
         mom = oracle_mod.site_moments(ref, s)
-        lo = so[b]
-        for i in sample:
-            assert abs(B["mass"][lo + i] - mom["mass"][i]) <= 1e-9 * mom["mass"][i]
-            assert np.linalg.norm(B["centroid"][lo + i] - mom["centroid"][i]) <= 1e-9 * np.linalg.norm(mom["centroid"][i])
-            nb = B["nbr"][B["nbr_off"][lo + i]:B["nbr_off"][lo + i + 1]] - lo
-            assert list(nb) == list(mom["neighbors"][i])
+        got = sampled_result(view, lo + sample, off)
+        got["piece_site"] = got["piece_site"] - lo
+        got["piece_simplex"] = got["piece_simplex"] - dom.simp_off[b]
+        got["face_label"] = shift_labels(got["face_label"], lo, dom.simp_off[b])
+        got["vert_label"] = shift_labels(got["vert_label"], lo, dom.simp_off[b])
+        assert_sampled_parity(got, mass, cent, en, nbo, nb, ref, mom, sample, site_lo=lo)
+        npieces += len(ref["piece_site"])
+    log(f"batch: {20 * len(items)} sites, {npieces} pieces identical")

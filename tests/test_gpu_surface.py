@@ -8,7 +8,8 @@ import numpy as np
 import pytest
 
 import vdgen
-from gpu_util import assert_parity, gpu_neighbors, log, run_gpu
+from gpu_util import (assert_neighbour_symmetry, assert_parity, assert_sampled_parity, gpu_neighbors, log, run_gpu,
+                      sampled_result)
 
 pytestmark = pytest.mark.gpu
 
@@ -94,22 +95,32 @@ def test_sites_off_the_surface(oracle_mod):
 
 def test_c5_full_size_sampled(oracle_mod):
     """C5 at its full size: 200,000 sites on S^2, level-6 icosphere (81,920
-    triangles).  Sampled sites against the oracle; partition for all."""
+    triangles).  5,000 sampled sites against the oracle piece by piece;
+    per-triangle partition and neighbour symmetry for all sites."""
+    import torch
+    import paper_2509_07175_amd as vd
     s, dom = vdgen.config_c5()
     area = float(_area(dom).sum())
-    gpu = run_gpu(s, dom, bbox=(-1.01, -1.01, -1.01, 1.01, 1.01, 1.01), surface_area=area)
-    log(f"C5 info {gpu['info']}")
     n = len(s)
-    assert abs(gpu["mass"].sum() - area) <= 1e-11 * area
+    st = torch.as_tensor(s, dtype=torch.float64, device="cuda")
+    d = vd.Domain.from_vdgen(dom)
+    g = vd.build_grid(st, bbox=(-1.01, -1.01, -1.01, 1.01, 1.01, 1.01), surface_area=area)
+    c = vd.clip_cells(g, d, vd.Options.default())
+    m, ce, e = c.moments()
+    torch.cuda.synchronize()
+    log(f"C5 info {c.info()}")
+    mass, cent, en = m.cpu().numpy(), ce.cpu().numpy(), e.cpu().numpy()
+    assert abs(mass.sum() - area) <= 1e-11 * area
+    view = c.view()
+    psite = view["piece_site"].cpu().numpy()
+    used = psite >= 0
+    per = np.bincount(view["piece_simplex"].cpu().numpy()[used], weights=view["piece_mass"].cpu().numpy()[used],
+                      minlength=dom.m)
+    assert np.allclose(per, _area(dom), rtol=1e-10, atol=0)
+    nbo, nb = view["nbr_off"].cpu().numpy(), view["nbr"].cpu().numpy()
+    assert_neighbour_symmetry(nbo, nb)
     rng = np.random.default_rng(2025)
-    sample = np.sort(rng.choice(n, size=100, replace=False))
+    sample = np.sort(rng.choice(n, size=5000, replace=False))
     ref = oracle_mod.compute(s, dom, only_sites=sample)
     mom = oracle_mod.site_moments(ref, s)
-    assert_parity(gpu, ref, mom, n, sites_subset=sample)
-    res = gpu["res"]
-    per = np.bincount(res["piece_simplex"], weights=res["piece_mass"], minlength=dom.m)
-    assert np.allclose(per, _area(dom), rtol=1e-10, atol=0)
-    nb = gpu_neighbors(gpu, n)
-    for i in rng.choice(n, size=2000, replace=False):
-        for j in nb[i]:
-            assert i in set(nb[j].tolist())
+    assert_sampled_parity(sampled_result(view, sample), mass, cent, en, nbo, nb, ref, mom, sample)

@@ -29,7 +29,7 @@ __all__ = [
     "Domain", "kuhn_cube_grid", "icosphere", "adjacency",
     "uniform_cube_sites", "gaussian_mixture_sites", "sphere_sites",
     "config_c1", "config_c2", "config_c3", "config_c4", "config_c5",
-    "lattice_sites", "small_case",
+    "lattice_sites", "small_case", "kuhn_cube_subset", "l_block", "cube_with_cavity", "l_block_sites",
 ]
 
 
@@ -121,6 +121,52 @@ def kuhn_cube_grid(k: int, jitter: float = 0.0, seed: int | None = None) -> Doma
         raise ValueError("inverted tetrahedron; jitter too large")
     tets = tets.astype(np.int32)
     return Domain(verts=verts, simplices=tets, adj=adjacency(tets), dim=3)
+
+
+def kuhn_cube_subset(k: int, keep) -> Domain:
+    """The cubes (ix, iy, iz) of a k^3 Kuhn grid of the unit cube for which
+    ``keep(ix, iy, iz)`` holds, each cut into the same 6 tetrahedra as in
+    ``kuhn_cube_grid`` (so the mesh stays conforming), unused vertices dropped."""
+    full = kuhn_cube_grid(k)
+    # kuhn_cube_grid lists the 6 tets of cube (ix, iy, iz) at rows 6c .. 6c+5,
+    # c = the cube's index with ix varying slowest
+    order = [(ix, iy, iz) for ix in range(k) for iy in range(k) for iz in range(k)]
+    rows = [6 * c + t for c, (ix, iy, iz) in enumerate(order) if keep(ix, iy, iz) for t in range(6)]
+    sub = full.simplices[np.array(rows, dtype=np.int64)]
+    used = np.unique(sub)
+    remap = -np.ones(len(full.verts), dtype=np.int64)
+    remap[used] = np.arange(len(used))
+    sub = remap[sub].astype(np.int32)
+    verts = full.verts[used]
+    assert np.all(_tet_volumes(verts, sub) > 0)
+    return Domain(verts=verts, simplices=sub, adj=adjacency(sub), dim=3)
+
+
+def l_block(k: int) -> Domain:
+    """Non-convex L-shaped prism: the unit cube without the quarter
+    x > 1/2, y > 1/2 (all z), as a Kuhn grid of k^3 cubes (k even)."""
+    assert k % 2 == 0
+    return kuhn_cube_subset(k, lambda ix, iy, iz: not (ix >= k // 2 and iy >= k // 2))
+
+
+def cube_with_cavity(k: int) -> Domain:
+    """Unit cube with a closed cubic cavity: the cubes of the middle third
+    (k divisible by 3) are removed, leaving an inner boundary surface."""
+    assert k % 3 == 0
+    lo, hi = k // 3, 2 * k // 3
+    return kuhn_cube_subset(k, lambda ix, iy, iz: not (lo <= ix < hi and lo <= iy < hi and lo <= iz < hi))
+
+
+def l_block_sites(n: int, seed: int) -> np.ndarray:
+    """n uniform sites in the L-shaped prism (rejection), off the grid planes."""
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < n:
+        p = rng.uniform(1e-6, 1 - 1e-6, size=3)
+        if p[0] > 0.5 and p[1] > 0.5:
+            continue
+        out.append(p)
+    return _jitter_inside(rng, np.array(out), 1e-7)
 
 
 def icosphere(level: int) -> Domain:
