@@ -352,6 +352,21 @@ vd_status vd_cell_moments(vd_cells c, double *mass, double *centroid, double *en
 vd_status vd_cell_moments_backward(vd_cells c, const double *g_mass, const double *g_centroid,
                                    const double *g_energy, double *g_sites, void *stream);
 
+/* ---------------------------------------------------------------------
+ * vd_cell_moments_backward_noalloc -- vd_cell_moments_backward for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Same arguments, same
+ * kernels and the same result; the per-site weight table the adjoint needs
+ * (40 bytes per site) lives in a fixed device array of VD_NOALLOC_MAX_SITES
+ * sites that each GPU holds until the process ends, instead of the handle's
+ * lazily allocated buffer.  Call it with the device of the handle current.
+ * Calls that overlap on one GPU share that array and race: serialise them.
+ * Errors: as vd_cell_moments_backward, plus VD_ERR_CAPACITY when the handle
+ * has more than VD_NOALLOC_MAX_SITES sites.
+ * --------------------------------------------------------------------- */
+#define VD_NOALLOC_MAX_SITES (1 << 20)
+vd_status vd_cell_moments_backward_noalloc(vd_cells c, const double *g_mass, const double *g_centroid,
+                                           const double *g_energy, double *g_sites, void *stream);
 
 #ifdef __cplusplus
 }

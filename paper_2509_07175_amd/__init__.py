@@ -131,6 +131,7 @@ def load():
         "vd_cell_moments": (C.c_int, [vp, vp, vp, vp, vp]),
         "vd_cell_moments_backward": (C.c_int, [vp, vp, vp, vp, vp, vp]),
         "vd_sync": (C.c_int, [vp]),
+        "vd_cell_moments_backward_noalloc": (C.c_int, [vp, vp, vp, vp, vp, vp]),
         "vd_domain_info": (C.c_int, [vp, C.POINTER(_DomainInfo)]),
         "vd_domain_adjacency": (C.c_int, [vp, vp, vp]),
     }
@@ -146,7 +147,7 @@ def exported_symbols():
     return ["vd_options_default", "vd_last_error", "vd_status_string", "vd_build_grid", "vd_grid_free",
             "vd_build_grid_batch", "vd_domain_create_batch", "vd_domain_create", "vd_domain_free", "vd_clip_cells", "vd_cells_free", "vd_cells_info",
             "vd_cells_view", "vd_cell_moments", "vd_cell_moments_backward", "vd_sync", "vd_domain_info",
-            "vd_domain_adjacency"]
+            "vd_domain_adjacency", "vd_cell_moments_backward_noalloc"]
 
 
 def sync(stream=None):
@@ -376,6 +377,20 @@ class Cells:
 
         _check(load().vd_cell_moments_backward(self.h, p(g_mass), p(g_centroid, 3), p(g_energy),
                                                _dptr(out, torch.float64, 3), _stream_ptr(stream)))
+        return out
+
+    def backward_noalloc(self, g_mass=None, g_centroid=None, g_energy=None, out=None, stream=None):
+        """vd_cell_moments_backward_noalloc: the adjoint without any allocation in
+        the library (its weight table sits in a fixed device array)."""
+        import torch
+        n = self.n
+        out = out if out is not None else torch.empty((n, 3), dtype=torch.float64, device="cuda")
+
+        def p(t, last=None):
+            return None if t is None else _dptr(t, torch.float64, last)
+
+        _check(load().vd_cell_moments_backward_noalloc(self.h, p(g_mass), p(g_centroid, 3), p(g_energy),
+                                                       _dptr(out, torch.float64, 3), _stream_ptr(stream)))
         return out
 
     def view(self) -> dict:

@@ -990,3 +990,54 @@ vd_status vd_cell_moments_backward(vd_cells c, const double *g_mass, const doubl
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free adjoint.  The adjoint's only scratch memory is the table of
+// per-site weights (a_i, b_i, gE_i: 5 doubles per site), written by the first
+// kernel and read by the second.  Here it lives in a fixed device array of
+// VD_NOALLOC_MAX_SITES entries, one per GPU for the life of the process.  In
+// host code the array's name is not a device address, so its address on each
+// device is looked up once (hipGetSymbolAddress, that device current) and
+// only that address is handed to the kernels.  The weights are fully
+// rewritten by every call, so nothing needs clearing; calls that overlap on
+// one GPU share the array and race.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[5 * (int64_t)VD_NOALLOC_MAX_SITES];
+
+namespace {
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[64] = {};  // per device: the address of `scratch`
+}  // namespace
+
+extern "C" {
+
+vd_status vd_cell_moments_backward_noalloc(vd_cells c, const double *g_mass, const double *g_centroid,
+                                           const double *g_energy, double *g_sites, void *stream) {
+  if (!c || !g_sites) return fail(VD_ERR_INVALID_ARG, "vd_cell_moments_backward_noalloc: NULL argument");
+  if (!c->opt.want_grad)
+    return fail(VD_ERR_INVALID_ARG, "vd_cell_moments_backward_noalloc: clip ran without want_grad");
+  if (c->status != VD_OK) return fail(VD_ERR_INVALID_ARG, "vd_cell_moments_backward_noalloc: the clip failed");
+  if (c->n > VD_NOALLOC_MAX_SITES)
+    return fail(VD_ERR_CAPACITY, "vd_cell_moments_backward_noalloc: %lld sites exceed the fixed scratch of %d sites",
+                (long long)c->n, (int)VD_NOALLOC_MAX_SITES);
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(VD_ERR_INVALID_ARG, "vd_cell_moments_backward_noalloc: device %d", dev);
+  double *ptr = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+      void *p = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !p)
+        return fail(VD_ERR_HIP, "vd_cell_moments_backward_noalloc: hipGetSymbolAddress: %s", hipGetErrorString(e));
+      g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    ptr = g_scratch_ptr[dev];
+  }
+  vd_launch_backward(c, c->grid->view(), g_mass, g_centroid, g_energy, g_sites, ptr, as_stream(stream));
+  HIP_TRY(hipGetLastError());
+  return VD_OK;
+}
+
+}  // extern "C"
