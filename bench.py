@@ -345,6 +345,36 @@ def bench_surface(steps, warmup, log):
             "forward_plus_adjoint_vs_forward": f_ms / fb_ms, "cvt_gradient_rel_err": err}
 
 
+def bench_cvt(log, iterations=10):
+    """CVT on the 100,000-site workload with a quadratic density (Eq. 3):
+    L-BFGS on the library's moments and adjoint, and Lloyd (sites <- weighted
+    centroids) from the same start; energies per iteration and time."""
+    import torch
+    import paper_2509_07175_amd as vd
+    import vdgen
+    sites, dom = vdgen.config_c2()
+    d = vd.Domain.from_vdgen(dom)
+    rho = [1.0, 0.5, -0.3, 0.2, 0.4, 0.1, -0.2, 0.3, 0.05, 0.6]
+    opt = vd.Options.default(density=rho)
+    s = torch.as_tensor(sites, dtype=torch.float64, device="cuda").contiguous()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, e_lbfgs = vd.cvt_lbfgs(s, d, iterations, options=opt, bbox=(0, 0, 0, 1, 1, 1))
+    torch.cuda.synchronize()
+    t_lbfgs = time.perf_counter() - t0
+    ls = s.clone()
+    t0 = time.perf_counter()
+    _, e_lloyd = vd.lloyd(ls, d, iterations, options=opt, bbox=(0, 0, 0, 1, 1, 1), energy=True)
+    torch.cuda.synchronize()
+    t_lloyd = time.perf_counter() - t0
+    mono = all(b <= a * (1 + 1e-12) for a, b in zip(e_lbfgs, e_lbfgs[1:]))
+    log(f"cvt: L-BFGS energy {e_lbfgs[0]:.6e} -> {e_lbfgs[-1]:.6e} in {t_lbfgs:.2f} s (monotone {mono}); "
+        f"Lloyd -> {e_lloyd[-1]:.6e} in {t_lloyd:.2f} s")
+    return {"workload": "100,000 uniform sites, 48,000 tetrahedra, density rho(x) quadratic " + str(rho),
+            "iterations": iterations, "lbfgs_energies": e_lbfgs, "lbfgs_monotone": mono, "lbfgs_s": t_lbfgs,
+            "lloyd_energies": e_lloyd, "lloyd_s": t_lloyd}
+
+
 def measured_peaks(log):
     """Measured ceilings on this GPU: FP64 FMA rate (a HIP probe of eight
     independent v_fma_f64 chains per lane) and device-to-device copy rate
@@ -612,6 +642,8 @@ def main():
         out["backward_surface"] = bench_surface(max(1, min(args.steps, 5)), 1, log)
     if not args.no_batched:
         out["batched"] = bench_batched(max(1, min(args.steps, 5)), 1, log)
+    if not args.no_small:
+        out["cvt_density"] = bench_cvt(log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sites, dom)
         if args.workload == "c3":

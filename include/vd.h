@@ -113,6 +113,15 @@ typedef struct {
                                  margins of the corner classifications (vd_cells_info_t).
                                  Default 0: those counters cost about 8 % of the 3D kernel's time
                                  and read -1. */
+  int32_t use_density;        /* 1: every moment is weighted by the density rho of Eq. 3 given in
+                                 density[] (mass = integral of rho, centroid = integral of rho x
+                                 over it, energy = integral of rho |x - v_i|^2; the per-piece
+                                 records too), integrated exactly by degree-5 simplex rules on
+                                 the moment fans; the adjoint then carries rho as well.  Pieces
+                                 still exist by positive volume (area).  Default 0: rho = 1. */
+  double density[10];         /* rho(x) = d0 + d1 x + d2 y + d3 z + d4 x^2 + d5 x y + d6 x z
+                                 + d7 y^2 + d8 y z + d9 z^2 (absolute coordinates); it should be
+                                 positive on M */
 } vd_options;
 
 void vd_options_default(vd_options *opt);

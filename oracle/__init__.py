@@ -85,6 +85,12 @@ def _load(native: bool = False):
         lib.vdo_moments_backward.restype = C.c_int
         lib.vdo_moments_backward.argtypes = [C.POINTER(_Result)] + [C.c_void_p, C.c_int64] + \
             [C.c_void_p] * 7 + [C.c_int, C.c_void_p]
+        lib.vdo_moments_backward_rho.restype = C.c_int
+        lib.vdo_moments_backward_rho.argtypes = [C.POINTER(_Result)] + [C.c_void_p, C.c_int64] + \
+            [C.c_void_p] * 7 + [C.c_int, C.c_void_p, C.c_void_p]
+        lib.vdo_density_moments.restype = C.c_int
+        lib.vdo_density_moments.argtypes = [C.POINTER(_Result), C.c_void_p, C.c_void_p, C.c_int,
+                                            C.c_void_p, C.c_void_p, C.c_void_p]
         if native:
             _lib_native = lib
         else:
@@ -211,10 +217,35 @@ def _nsum(x) -> float:
     return s + c
 
 
+def density_result(result: dict, sites, coef, dim: int) -> dict:
+    """A copy of ``result`` (computed with ``keep_handle=True``) whose per-piece
+    mass, first moment and energy are weighted by the quadratic density
+    rho(x) = c0 + c1 x + c2 y + c3 z + c4 x^2 + c5 xy + c6 xz + c7 y^2 + c8 yz
+    + c9 z^2 (Eq. 3), integrated exactly on each piece's fan of simplices."""
+    lib = _load()
+    h = result.get("_handle")
+    if h is None:
+        raise ValueError("compute(..., keep_handle=True) is required")
+    s = np.ascontiguousarray(sites, dtype=np.float64)
+    c = np.ascontiguousarray(coef, dtype=np.float64)
+    if c.shape != (10,):
+        raise ValueError("10 density coefficients")
+    npc = len(result["piece_site"])
+    m, mo, e = np.zeros(npc), np.zeros((npc, 3)), np.zeros(npc)
+    st = lib.vdo_density_moments(C.byref(h), s.ctypes.data, c.ctypes.data, int(dim), m.ctypes.data,
+                                 mo.ctypes.data, e.ctypes.data)
+    if st != 0:
+        raise RuntimeError(f"oracle density moments failed with status {st}")
+    out = {k: v for k, v in result.items() if k != "_handle"}
+    out["piece_mass"], out["piece_moment"], out["piece_energy"] = m, mo, e
+    return out
+
+
 def moments_backward(result: dict, sites, domain, mass, centroid, g_mass=None, g_centroid=None,
-                     g_energy=None):
+                     g_energy=None, rho=None):
     """Adjoint of sum_k g_m m_k + g_c.c_k + g_E E_k w.r.t. the sites (result must
-    cover all sites and be computed with ``keep_handle=True``)."""
+    cover all sites and be computed with ``keep_handle=True``); with ``rho`` (10
+    coefficients) the moments are the density-weighted ones."""
     lib = _load()
     h = result.get("_handle")
     if h is None:
@@ -236,9 +267,10 @@ def moments_backward(result: dict, sites, domain, mass, centroid, g_mass=None, g
     v = np.ascontiguousarray(domain.verts, dtype=np.float64)
     t = np.ascontiguousarray(domain.simplices, dtype=np.int32)
     out = np.zeros((n, 3))
-    st = lib.vdo_moments_backward(C.byref(h), s.ctypes.data, n, m_.ctypes.data, c_.ctypes.data,
-                                  gm_p, gc_p, ge_p, v.ctypes.data, t.ctypes.data, int(domain.dim),
-                                  out.ctypes.data)
+    rc = None if rho is None else np.ascontiguousarray(rho, dtype=np.float64)
+    st = lib.vdo_moments_backward_rho(C.byref(h), s.ctypes.data, n, m_.ctypes.data, c_.ctypes.data,
+                                      gm_p, gc_p, ge_p, v.ctypes.data, t.ctypes.data, int(domain.dim),
+                                      None if rc is None else rc.ctypes.data, out.ctypes.data)
     if st != 0:
         raise RuntimeError(f"oracle adjoint failed with status {st}")
     return out

@@ -1142,11 +1142,140 @@ static void tri_integrals(const double y[3][3], double A, double *I1, double I2[
   }
 }
 
+/* ------------------------------------------------------------------ */
+/* density-weighted moments (Eq. 3 with a quadratic density)            */
+/* ------------------------------------------------------------------ */
+/* rho(x) = c0 + c1 x + c2 y + c3 z + c4 x^2 + c5 xy + c6 xz + c7 y^2 + c8 yz + c9 z^2 */
+static double rho_at(const double *c, const double *x) {
+  return c[0] + c[1] * x[0] + c[2] * x[1] + c[3] * x[2] + c[4] * x[0] * x[0] + c[5] * x[0] * x[1] +
+         c[6] * x[0] * x[2] + c[7] * x[1] * x[1] + c[8] * x[1] * x[2] + c[9] * x[2] * x[2];
+}
+
+/* Gauss-Legendre, 4 points on [0, 1] (exact to degree 7 in each variable) */
+static const double GL4_T[4] = {0.5 - 0.5 * 0.8611363115940526, 0.5 - 0.5 * 0.3399810435848563,
+                                0.5 + 0.5 * 0.3399810435848563, 0.5 + 0.5 * 0.8611363115940526};
+static const double GL4_W[4] = {0.5 * 0.3478548451374538, 0.5 * 0.6521451548625461,
+                                0.5 * 0.6521451548625461, 0.5 * 0.3478548451374538};
+
+/* Integral over the triangle (P0, P1, P2) of f, by the conical product
+ * (Duffy) rule: lambda1 = u, lambda2 = (1 - u) v, dA = 2 |A| (1 - u) du dv,
+ * 4 x 4 Gauss points -- exact for polynomials of degree <= 6.  `area` is the
+ * (signed) area; f(x, ctx, acc) adds weight * integrand to acc[0..nacc). */
+typedef void (*vdo_integrand)(const double *x, double w, const void *ctx, double *acc);
+static void tri_conical(const double *P0, const double *P1, const double *P2, double area, vdo_integrand f,
+                        const void *ctx, double *acc) {
+  for (int a = 0; a < 4; a++)
+    for (int b = 0; b < 4; b++) {
+      double u = GL4_T[a], v = GL4_T[b];
+      double l1 = u, l2 = (1 - u) * v, l0 = 1 - l1 - l2;
+      double x[3];
+      for (int d = 0; d < 3; d++) x[d] = l0 * P0[d] + l1 * P1[d] + l2 * P2[d];
+      f(x, 2.0 * area * (1 - u) * GL4_W[a] * GL4_W[b], ctx, acc);
+    }
+}
+
+/* Integral over the tetrahedron (P0..P3) of f: lambda1 = u, lambda2 = (1-u) v,
+ * lambda3 = (1-u)(1-v) w, dV = 6 V (1-u)^2 (1-v) du dv dw, 4^3 Gauss points
+ * -- exact for polynomials of degree <= 5. */
+static void tet_conical(const double *P0, const double *P1, const double *P2, const double *P3, double vol,
+                        vdo_integrand f, const void *ctx, double *acc) {
+  for (int a = 0; a < 4; a++)
+    for (int b = 0; b < 4; b++)
+      for (int c = 0; c < 4; c++) {
+        double u = GL4_T[a], v = GL4_T[b], w = GL4_T[c];
+        double l1 = u, l2 = (1 - u) * v, l3 = (1 - u) * (1 - v) * w, l0 = 1 - l1 - l2 - l3;
+        double x[3];
+        for (int d = 0; d < 3; d++) x[d] = l0 * P0[d] + l1 * P1[d] + l2 * P2[d] + l3 * P3[d];
+        f(x, 6.0 * vol * (1 - u) * (1 - u) * (1 - v) * GL4_W[a] * GL4_W[b] * GL4_W[c], ctx, acc);
+      }
+}
+
+typedef struct {
+  const double *c;  /* density coefficients */
+  const double *v;  /* the site */
+} rho_ctx;
+
+/* acc += w rho(x) {1, x (3), |x - v|^2} */
+static void rho_moments_integrand(const double *x, double w, const void *ctx, double *acc) {
+  const rho_ctx *k = (const rho_ctx *)ctx;
+  double wr = w * rho_at(k->c, x);
+  double y[3];
+  sub3(x, k->v, y);
+  acc[0] += wr;
+  acc[1] += wr * x[0]; acc[2] += wr * x[1]; acc[3] += wr * x[2];
+  acc[4] += wr * dot3(y, y);
+}
+
+int vdo_density_moments(const vdo_result *r, const double *sites, const double *coef, int simplex_dim,
+                        double *mass, double *moment, double *energy) {
+  if (!r || !sites || !coef || !mass || !moment || !energy) return 1;
+  for (int64_t p = 0; p < r->n_pieces; p++) {
+    const double *v = &sites[3 * (int64_t)r->piece_site[p]];
+    rho_ctx k = {coef, v};
+    double acc[5] = {0, 0, 0, 0, 0};
+    int64_t vb = r->piece_vert_off[p];
+    const double *apex = &r->vert_xyz[3 * vb];
+    for (int64_t f = r->piece_face_off[p]; f < r->piece_face_off[p + 1]; f++) {
+      int64_t e0 = r->face_vert_off[f], e1 = r->face_vert_off[f + 1];
+      if (simplex_dim == 3) {
+        /* fan of tetrahedra (apex, face loop fan): positive volumes for
+         * counter-clockwise loops seen from outside */
+        const double *q0 = &r->vert_xyz[3 * (vb + r->face_vert[e0])];
+        for (int64_t e = e0 + 1; e + 1 < e1; e++) {
+          const double *q1 = &r->vert_xyz[3 * (vb + r->face_vert[e])];
+          const double *q2 = &r->vert_xyz[3 * (vb + r->face_vert[e + 1])];
+          double a[3], b[3], c[3], cr[3];
+          sub3(q0, apex, a); sub3(q1, apex, b); sub3(q2, apex, c);
+          cross3(b, c, cr);
+          double vol = dot3(a, cr) / 6.0;
+          if (vol != 0.0) tet_conical(apex, q0, q1, q2, vol, rho_moments_integrand, &k, acc);
+        }
+      } else {
+        /* a polygon: its edges are the faces; fan of triangles (apex, edge) */
+        const double *q0 = &r->vert_xyz[3 * (vb + r->face_vert[e0])];
+        const double *q1 = &r->vert_xyz[3 * (vb + r->face_vert[e0 + 1])];
+        double a[3], b[3], cr[3];
+        sub3(q0, apex, a); sub3(q1, apex, b);
+        cross3(a, b, cr);
+        double ar = 0.5 * sqrt(dot3(cr, cr));
+        if (ar > 0.0) tri_conical(apex, q0, q1, ar, rho_moments_integrand, &k, acc);
+      }
+    }
+    mass[p] = acc[0];
+    moment[3 * p] = acc[1]; moment[3 * p + 1] = acc[2]; moment[3 * p + 2] = acc[3];
+    energy[p] = acc[4];
+  }
+  return 0;
+}
+
+/* integrand of the adjoint's face term with a density:
+ * acc += w rho(x) (a0 + b.y + g |y|^2) y, y = x - v */
+typedef struct {
+  const double *c, *v, *b;
+  double a0, g;
+} face_ctx;
+static void rho_face_integrand(const double *x, double w, const void *ctx, double *acc) {
+  const face_ctx *k = (const face_ctx *)ctx;
+  double y[3];
+  sub3(x, k->v, y);
+  double f = w * rho_at(k->c, x) * (k->a0 + dot3(k->b, y) + k->g * dot3(y, y));
+  for (int d = 0; d < 3; d++) acc[d] += f * y[d];
+}
+
 int vdo_moments_backward(const vdo_result *r, const double *sites, int64_t n,
                          const double *mass, const double *cent,
                          const double *g_m, const double *g_c, const double *g_E,
                          const double *verts, const int32_t *simp, int simplex_dim,
                          double *g_sites) {
+  return vdo_moments_backward_rho(r, sites, n, mass, cent, g_m, g_c, g_E, verts, simp, simplex_dim, NULL,
+                                  g_sites);
+}
+
+int vdo_moments_backward_rho(const vdo_result *r, const double *sites, int64_t n,
+                             const double *mass, const double *cent,
+                             const double *g_m, const double *g_c, const double *g_E,
+                             const double *verts, const int32_t *simp, int simplex_dim,
+                             const double *rho, double *g_sites) {
   if (!r || !sites || !mass || !cent || !g_sites) return 1;
   double *al = (double *)calloc(n, sizeof(double));
   double *be = (double *)calloc(3 * n, sizeof(double));
@@ -1208,6 +1337,17 @@ int vdo_moments_backward(const vdo_result *r, const double *sites, int64_t n,
           /* oriented area: the loop is counter-clockwise around the outward
            * normal of cell i, which points towards v_k */
           double A = 0.5 * dot3(cr, nk) / dik;
+          if (rho) {
+            /* with a density the integrand rho (a0 + b.y + g|y|^2) y has
+             * degree 5: the conical product rule on the triangle */
+            double P[3][3], acc[3] = {0, 0, 0};
+            for (int t = 0; t < 3; t++)
+              for (int d = 0; d < 3; d++) P[t][d] = vi[d] + y[t][d];
+            face_ctx fc = {rho, vi, bdiff, a0, gdiff};
+            tri_conical(P[0], P[1], P[2], A, rho_face_integrand, &fc, acc);
+            for (int q = 0; q < 3; q++) contrib[q] += acc[q] / dik;
+            continue;
+          }
           double I1[3], I2[3][3], I3[3];
           tri_integrals(y, A, I1, I2, I3);
           for (int q = 0; q < 3; q++) {
@@ -1231,12 +1371,24 @@ int vdo_moments_backward(const vdo_result *r, const double *sites, int64_t n,
         double dl[3];
         sub3(yB, yA, dl);
         double len = sqrt(dot3(dl, dl));
-        const double *pts[3] = {yA, yM, yB};
-        const double w[3] = {1.0 / 6.0, 4.0 / 6.0, 1.0 / 6.0};
-        for (int t = 0; t < 3; t++) {
-          const double *y = pts[t];
-          double f = a0 + dot3(bdiff, y) + gdiff * dot3(y, y);
-          for (int q = 0; q < 3; q++) contrib[q] += w[t] * len * f * y[q] / (dik * sfac);
+        if (rho) {
+          /* with a density the integrand has degree 5: Boole's rule (five
+           * equally spaced points, weights 7, 32, 12, 32, 7 over 90) */
+          const double bw[5] = {7.0 / 90.0, 32.0 / 90.0, 12.0 / 90.0, 32.0 / 90.0, 7.0 / 90.0};
+          for (int t = 0; t < 5; t++) {
+            double y[3], x[3];
+            for (int d = 0; d < 3; d++) { y[d] = yA[d] + 0.25 * t * dl[d]; x[d] = vi[d] + y[d]; }
+            double f = rho_at(rho, x) * (a0 + dot3(bdiff, y) + gdiff * dot3(y, y));
+            for (int q = 0; q < 3; q++) contrib[q] += bw[t] * len * f * y[q] / (dik * sfac);
+          }
+        } else {
+          const double *pts[3] = {yA, yM, yB};
+          const double w[3] = {1.0 / 6.0, 4.0 / 6.0, 1.0 / 6.0};
+          for (int t = 0; t < 3; t++) {
+            const double *y = pts[t];
+            double f = a0 + dot3(bdiff, y) + gdiff * dot3(y, y);
+            for (int q = 0; q < 3; q++) contrib[q] += w[t] * len * f * y[q] / (dik * sfac);
+          }
         }
       }
       for (int q = 0; q < 3; q++) g_sites[3 * i + q] += contrib[q];

@@ -83,6 +83,24 @@ int vdo_moments_backward(const vdo_result *r, const double *sites, int64_t n,
                          const double *verts, const int32_t *simp, int simplex_dim,
                          double *g_sites);
 
+/* As vdo_moments_backward, for moments weighted by the quadratic density
+ * rho (10 coefficients, see vdo_density_moments; NULL = density 1): mass and
+ * cent are then the weighted ones and every face integrand carries rho. */
+int vdo_moments_backward_rho(const vdo_result *r, const double *sites, int64_t n,
+                             const double *mass, const double *cent,
+                             const double *g_m, const double *g_c, const double *g_E,
+                             const double *verts, const int32_t *simp, int simplex_dim,
+                             const double *rho, double *g_sites);
+
+/* Density-weighted moments of every piece of a result (Sec. 7.4, Eq. 3 with
+ * rho(x) = c0 + c1 x + c2 y + c3 z + c4 x^2 + c5 xy + c6 xz + c7 y^2 + c8 yz
+ * + c9 z^2): mass = int rho, moment = int rho x (absolute coordinates),
+ * energy = int rho |x - v_i|^2 over each piece, on the fan of simplices from
+ * the piece's first vertex with conical (Duffy) product Gauss rules, exact
+ * for these polynomial degrees.  Arrays [n_pieces], [3 n_pieces], [n_pieces]. */
+int vdo_density_moments(const vdo_result *r, const double *sites, const double *coef, int simplex_dim,
+                        double *mass, double *moment, double *energy);
+
 #ifdef __cplusplus
 }
 #endif

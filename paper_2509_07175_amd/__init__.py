@@ -18,7 +18,7 @@ import os
 
 import numpy as np
 
-__all__ = ["load", "Options", "Grid", "Domain", "Cells", "build_grid", "clip_cells", "lloyd",
+__all__ = ["load", "Options", "Grid", "Domain", "Cells", "build_grid", "clip_cells", "lloyd", "cvt_lbfgs",
            "VoronoiMoments", "VDError", "BOUNDARY_BASE", "sync"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -40,7 +40,8 @@ class Options(C.Structure):
                 ("use_straddle_edges", C.c_int32), ("max_search_iters", C.c_int32),
                 ("emit_polytopes", C.c_int32), ("want_grad", C.c_int32), ("time_kernels", C.c_int32),
                 ("carve_mode", C.c_int32), ("no_sync", C.c_int32), ("site_cache", C.c_int32),
-                ("boundary_seeds", C.c_int32), ("monitor", C.c_int32)]
+                ("boundary_seeds", C.c_int32), ("monitor", C.c_int32), ("use_density", C.c_int32),
+                ("density", C.c_double * 10)]
 
     @classmethod
     def default(cls, **kw) -> "Options":
@@ -49,6 +50,13 @@ class Options(C.Structure):
         for k, v in kw.items():
             if not hasattr(o, k):
                 raise TypeError(f"unknown option {k}")
+            if k == "density":
+                v = list(v)
+                if len(v) != 10:
+                    raise ValueError("density takes 10 coefficients (quadratic in x, y, z)")
+                o.density = (C.c_double * 10)(*[float(x) for x in v])
+                o.use_density = 1
+                continue
             setattr(o, k, v)
         return o
 
@@ -465,6 +473,61 @@ def lloyd(sites, domain: Domain, iterations: int, options: Options | None = None
         if energy:
             energies.append(float(en.sum().item()))
     return (sites, energies) if energy else sites
+
+
+def cvt_lbfgs(sites, domain: Domain, iterations: int, options: Options | None = None, bbox=None,
+              sites_per_cell: float = 0.0, surface_area: float = 0.0, history: int = 10, stream=None):
+    """Minimises the CVT energy of Eq. 3 (with the density of ``options``, if
+    any) over the sites by L-BFGS with a strong-Wolfe line search.  Every
+    evaluation is a grid build, a clip and the moments through the library,
+    and the gradient is the library's adjoint of the energy (2 m_i (v_i - c_i)
+    for each site); torch.optim.LBFGS only keeps the optimiser's state.
+    The energy's Hessian is close to 2 m_i per site (the Lloyd step is the
+    Newton step), so the optimiser runs on z = sqrt(2 M / n) v, M the total
+    (weighted) mass of the first diagram: there the Hessian is close to the
+    identity and the first steps are well scaled.
+    Returns the final sites (a new tensor) and the energy before each
+    iteration and at the end (non-increasing: the line search enforces
+    sufficient decrease)."""
+    import torch
+    if sites.dtype != torch.float64 or not sites.is_cuda or sites.dim() != 2 or sites.shape[1] != 3:
+        raise ValueError("sites must be an (n, 3) float64 CUDA tensor")
+    n = sites.shape[0]
+    opt = Options.default() if options is None else Options.from_buffer_copy(options)
+    opt.want_grad = 1
+    grid, cells = Grid(), Cells()
+    mass = torch.empty(n, dtype=torch.float64, device=sites.device)
+    cent = torch.empty((n, 3), dtype=torch.float64, device=sites.device)
+    en = torch.empty(n, dtype=torch.float64, device=sites.device)
+    ones = torch.ones(n, dtype=torch.float64, device=sites.device)
+    gout = torch.empty((n, 3), dtype=torch.float64, device=sites.device)
+    v = sites.detach().clone().contiguous()
+
+    def evaluate():
+        build_grid(v, bbox=bbox, sites_per_cell=sites_per_cell, surface_area=surface_area, grid=grid, stream=stream)
+        clip_cells(grid, domain, opt, cells=cells, stream=stream)
+        cells.moments(mass, cent, en, stream=stream)
+        cells.backward(None, None, ones, out=gout, stream=stream)
+        return en.sum()
+
+    evaluate()
+    sigma = float((2.0 * mass.sum() / n).sqrt().item())
+    z = (v * sigma).requires_grad_(False)
+    lbfgs = torch.optim.LBFGS([z], lr=1.0, max_iter=1, history_size=int(history), line_search_fn="strong_wolfe",
+                              tolerance_grad=0.0, tolerance_change=0.0)
+    energies = []
+
+    def closure():
+        v.copy_(z.detach() / sigma)
+        e = evaluate()
+        z.grad = gout / sigma
+        return e
+
+    for _ in range(int(iterations)):
+        energies.append(float(lbfgs.step(closure).item()))
+    v.copy_(z.detach() / sigma)
+    energies.append(float(evaluate().item()))
+    return v, energies
 
 
 def pieces_as_result(view: dict) -> dict:

@@ -122,6 +122,8 @@ void vd_options_default(vd_options *opt) {
   opt->no_sync = 0;
   opt->boundary_seeds = -1;
   opt->monitor = 0;
+  opt->use_density = 0;
+  for (int k = 0; k < 10; k++) opt->density[k] = k == 0 ? 1.0 : 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -728,6 +730,8 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
     d.mode = (dom->dim == 3 && opt.carve_mode == 1) ? 1 : 0;
     d.cache = opt.site_cache ? 1 : 0;
     d.monitor = opt.monitor ? 1 : 0;
+    d.density = opt.use_density ? 1 : 0;
+    for (int k = 0; k < 10; k++) d.dens[k] = opt.use_density ? opt.density[k] : (k == 0 ? 1.0 : 0.0);
     // persistent 3D kernel: each wave reserves output chunks of about 1/8 of an
     // arena's share per wave, so unused chunk tails stay within 1/8 of it
     const int64_t items = dom->dim == 3 ? n : dom->m;  // sites, or triangles
@@ -802,8 +806,8 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
     }
     if (dom->dim == 2) vd_launch_fill_int(d.pcount, n, 0, st);
     if (opt.time_kernels) HIP_TRY(hipEventRecord(c->ev0, st));
-    if (dom->dim == 3) vd_launch_sites3d(G, D, c->d_dev, wg, st);
-    else vd_launch_surface(G, D, c->d_dev, wg, st);
+    if (dom->dim == 3) vd_launch_sites3d(G, D, c->d_dev, wg, opt.monitor != 0, opt.use_density != 0, st);
+    else vd_launch_surface(G, D, c->d_dev, wg, opt.use_density != 0, st);
     if (opt.time_kernels) HIP_TRY(hipEventRecord(c->ev1, st));
     HIP_TRY(hipGetLastError());
     if (opt.no_sync) {

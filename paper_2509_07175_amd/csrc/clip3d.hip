@@ -163,7 +163,8 @@ __device__ int compact_planes(WaveLds &S, int npl, int nc) {
 // leaving R_p and form the fan of the new face.
 // Returns 0 (nothing outside: unchanged), 1 empty, 2 capacity, 3 degenerate,
 // 4 cut (nc updated).
-__device__ int clip_poly(WaveLds &S, bool mon, int P, int pt, int &nc, int ps = -1, int kcert = -1) {
+template <bool MON>
+__device__ int clip_poly(WaveLds &S, int P, int pt, int &nc, int ps = -1, int kcert = -1) {
   const int l = vd_lane();
   const double nx = S.pn[P][0], ny = S.pn[P][1], nz = S.pn[P][2], c = S.pn[P][3];
   int pl[2] = {0, 0}, nb[2] = {0, 0}, cs[2] = {0, 0};
@@ -180,7 +181,7 @@ __device__ int clip_poly(WaveLds &S, bool mon, int P, int pt, int &nc, int ps = 
     }
     o[h] = v[h] && sd[h] > 0.0;
   }
-  if (mon) {
+  if (MON) {
     margin_track(S.ar, v[0], sd[0], fabs(nx * y[0][0]) + fabs(ny * y[0][1]) + fabs(nz * y[0][2]) + fabs(c), v[1],
                  sd[1], fabs(nx * y[1][0]) + fabs(ny * y[1][1]) + fabs(nz * y[1][2]) + fabs(c));
     count_add(S.ar.classified, nc);
@@ -211,7 +212,7 @@ __device__ int clip_poly(WaveLds &S, bool mon, int P, int pt, int &nc, int ps = 
     Rhi |= b;
   }
   const int nR = __popcll(Rlo) + __popcll(Rhi);
-  if (mon && pt >= 0) {
+  if (MON && pt >= 0) {
     // tests spent on corners this clip removes, besides the one that led to it
     const uint64_t tlo = __ballot(v[0] && (cs[0] & 2)), thi = __ballot(v[1] && (cs[1] & 2));
     const int w = __popcll(tlo & Rlo) + __popcll(thi & Rhi) - (bit128(tlo, thi, pt) ? 1 : 0);
@@ -323,7 +324,7 @@ __device__ int clip_poly(WaveLds &S, bool mon, int P, int pt, int &nc, int ps = 
   }
   __syncthreads();
   nc = nsurv + nnew;
-  if (mon) count_add(S.ar.newc, nnew);
+  if (MON) count_add(S.ar.newc, nnew);
   // three planes without a common point (e.g. all containing one direction)
   // give a non-finite corner: report the cut as degenerate
   if (__ballot(nf)) return 3;
@@ -348,9 +349,9 @@ __device__ __forceinline__ void state_masks(const WaveLds &S, int nc, uint64_t &
 // Returns 0 (done, non-empty), 1 (empty), 2 capacity, 3 degenerate.
 struct CarveParams {
   int improved, straddle, max_iters;
-  bool monitor;  // count work and track predicate margins (vd_options.monitor)
 };
 
+template <bool MON>
 __device__ int carve(WaveLds &S, const GridView &G, const CarveParams C, const SiteCtx &X, int &npl, int &nc,
                      Stats &st) {
   enum { PICK = 0, TEST, LAMBDA, SEARCH };
@@ -480,7 +481,7 @@ __device__ int carve(WaveLds &S, const GridView &G, const CarveParams C, const S
       e0 = S.plab[p8(tpl, 0)]; e1 = S.plab[p8(tpl, 1)]; e2 = S.plab[p8(tpl, 2)];
     }
     bool on_grid;
-    if (C.monitor) count_add(S.ar.rounds, 1);
+    if (MON) count_add(S.ar.rounds, 1);
     const int kq = nn_cached(S.K, G, gs, qx, qy, qz, dx * dx + dy * dy + dz * dz, X.si, e0 < 0 ? -1 : e0,
                              e1 < 0 ? -1 : e1, e2 < 0 ? -1 : e2, st.cands, on_grid);
     if (mode == TEST) {
@@ -535,7 +536,7 @@ __device__ int carve(WaveLds &S, const GridView &G, const CarveParams C, const S
       S.plab[P] = j;
     }
     __syncthreads();
-    const int rc = clip_poly(S, C.monitor, P, pt, nc, ps_edge >= 0 && qon ? ps_edge : -1, k);
+    const int rc = clip_poly<MON>(S, P, pt, nc, ps_edge >= 0 && qon ? ps_edge : -1, k);
     st.clips++;
     if (rc == 1) return 1;
     if (rc != 4) return rc == 0 ? 3 : rc;
@@ -733,9 +734,11 @@ __device__ __forceinline__ int convert_label(const GridView &G, int lab) { retur
 // lowest corner (a fixed order, so the sums are reproducible) and integrates
 // the fan of triangles (foot of the plane, corner, next corner): linear and
 // quadratic terms in closed form, the cubic term with the degree-3 rule of
-// Strang and Fix (centroid -27/48, points (3/5,1/5,1/5) 25/48).
+// Strang and Fix (centroid -27/48, points (3/5,1/5,1/5) 25/48); with a density
+// every integrand carries it and one degree-5 rule takes all twelve.
+template <bool DENS>
 __device__ void face_moments(WaveLds &S, int nc, int npl, uint64_t fmask, const CellsDev &C, const GridView &G,
-                             long long pidx) {
+                             const SiteCtx &X, long long pidx) {
   const int l = vd_lane();
   __syncthreads();
   if (l < npl) S.pfirst[l] = 0x7fffffff;
@@ -776,6 +779,14 @@ __device__ void face_moments(WaveLds &S, int nc, int npl, uint64_t fmask, const 
     const double b0 = S.cy[nx][0], b1 = S.cy[nx][1], b2 = S.cy[nx][2];
     const double u0 = a0 - r0, u1 = a1 - r1, u2 = a2 - r2, w0 = b0 - r0, w1 = b1 - r1, w2 = b2 - r2;
     const double A = 0.5 * ((u1 * w2 - u2 * w1) * h0 + (u2 * w0 - u0 * w2) * h1 + (u0 * w1 - u1 * w0) * h2);
+    if (DENS) {
+      // weighted by the density: one degree-5 rule for all twelve integrals
+      const double P0[3] = {r0, r1, r2}, P1[3] = {a0, a1, a2}, P2[3] = {b0, b1, b2};
+      tri_density_face(C.dens, X.vx, X.vy, X.vz, P0, P1, P2, A, I);
+      T = nx;
+      if (T == start) break;
+      continue;
+    }
     const double s0 = r0 + a0 + b0, s1 = r1 + a1 + b1, s2 = r2 + a2 + b2;
     I[0] += A * s0 / 3.0; I[1] += A * s1 / 3.0; I[2] += A * s2 / 3.0;
     const double q = A / 12.0;
@@ -859,6 +870,7 @@ __device__ __forceinline__ bool tq_push(WaveLds &S, const CellsDev &C, int &nt, 
 //     tests and the bisector search.
 // The carve has one call site: the first job of a cell-first site is the cell.
 // ---------------------------------------------------------------------------
+template <bool MON, bool DENS>
 __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, const CellsDev &C, int si) {
   const int l = vd_lane();
   SiteCtx X;
@@ -867,7 +879,7 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
   X.si = si;
   const int orig = GL(G.perm)[si];
   const int seed = GL(C.seed)[si];
-  const CarveParams P = {C.improved, C.straddle, C.max_iters, C.monitor != 0};
+  const CarveParams P = {C.improved, C.straddle, C.max_iters};
   Stats st;
   int err = 0;  // 2 capacity, 3 degenerate, 4 outside M without boundary seeds
   int where = 0;  // failing stage (VD_STAGE_*)
@@ -926,7 +938,7 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
         need_carve = false;
 #pragma unroll 1
         for (int f = 0; f < 4; f++) {
-          const int rc = clip_poly(S, P.monitor, npl0 + f, -1, nc);
+          const int rc = clip_poly<MON>(S, npl0 + f, -1, nc);
           if (rc == 4) st.clips++;
           else if (rc == 1) { empty = true; break; }
           else if (rc == 2) { err = rc; where = VD_STAGE_PIECE_CUT; break; }
@@ -943,7 +955,7 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
       }
     }
     if (need_carve) {
-      const int rc = carve(S, G, P, X, npl, nc, st);
+      const int rc = carve<MON>(S, G, P, X, npl, nc, st);
       if (cell_job) {
         cell_job = false;
         if (rc == 1 || rc == 3) { err = 3; where = VD_STAGE_CELL; continue; }  // the site lies in the box
@@ -974,6 +986,7 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
     // volume's rounding error scales with the piece and not with its distance
     // to v_i (a tip of the cell in a far tetrahedron keeps a positive volume)
     double pv = 0, pmx = 0, pmy = 0, pmz = 0, pe = 0;
+    double dm = 0, dmx = 0, dmy = 0, dmz = 0, de = 0;  // density-weighted (DENS)
     uint64_t fmask = 0;
     const double o0 = S.cy[0][0], o1 = S.cy[0][1], o2 = S.cy[0][2];
     const double oo = o0 * o0 + o1 * o1 + o2 * o2;
@@ -1005,13 +1018,22 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
         pmx += vol * s0 * 0.25; pmy += vol * s1 * 0.25; pmz += vol * s2 * 0.25;
         pe += vol * (1.0 / 20.0) *
               (oo + R0 * R0 + R1 * R1 + R2 * R2 + YY + Z0 * Z0 + Z1 * Z1 + Z2 * Z2 + s0 * s0 + s1 * s1 + s2 * s2);
+        if (DENS) {
+          const double V0[3] = {o0, o1, o2}, V1[3] = {R0, R1, R2}, V2[3] = {Y0, Y1, Y2}, V3[3] = {Z0, Z1, Z2};
+          tet_density_moments(C.dens, X.vx, X.vy, X.vz, V0, V1, V2, V3, vol, dm, dmx, dmy, dmz, de);
+        }
       }
     }
     pv = wave_sum(pv); pmx = wave_sum(pmx); pmy = wave_sum(pmy); pmz = wave_sum(pmz); pe = wave_sum(pe);
     fmask = wave_or64(fmask);
+    // a piece exists when its volume is positive; with a density its moments
+    // are the weighted ones
     if (!(pv > 0.0)) continue;
+    if (DENS) {
+      pv = wave_sum(dm); pmx = wave_sum(dmx); pmy = wave_sum(dmy); pmz = wave_sum(dmz); pe = wave_sum(de);
+    }
     if (l == 0) { S.acc[0] += pv; S.acc[1] += pmx; S.acc[2] += pmy; S.acc[3] += pmz; S.acc[4] += pe; }
-    if (P.monitor) count_add(S.ar.fantets, 3 * nc);
+    if (MON) count_add(S.ar.fantets, 3 * nc);
     // ---- emit the piece ----
     const int nface = __popcll(fmask);
     const long long pidx = arena_take(S.ar, C, AR_PIECE, 1);
@@ -1020,7 +1042,7 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
       fo = arena_take(S.ar, C, AR_FACE, nface);
       vo = arena_take(S.ar, C, AR_VERT, nc);
     }
-    if (C.want_grad) face_moments(S, nc, npl, fmask, C, G, pidx);
+    if (C.want_grad) face_moments<DENS>(S, nc, npl, fmask, C, G, X, pidx);
     // a record that does not fit its arena is dropped and counted; the per-site
     // counts below only count what was written, so the CSR built from them
     // stays inside the arenas (the clip then reports VD_ERR_CAPACITY)
@@ -1145,6 +1167,10 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
 // all are done.  Three waves per SIMD: 168 VGPRs (a few values spill around
 // the carve) and 12.7 KB of LDS per wave (the carved cell is kept in a global
 // buffer); the third wave hides more LDS and memory latency than that costs.
+// MON: the work counters and margin tracking of vd_options.monitor; DENS: the
+// density-weighted moments of vd_options.use_density.  Each is compiled in only
+// for the instances that use it, so the default instance carries neither.
+template <bool MON, bool DENS>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3))) site_kernel(GridView G, DomainView D, const CellsDev *__restrict__ Cp) {
   __shared__ WaveLds S;
   const CellsDev &C = *Cp;
@@ -1155,7 +1181,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3)))
     // the site's own diagram (a batch) or the only one; one call site keeps
     // the per-site code inlined once
     const int b = G.nb > 1 ? diagram_of(G.site_off, G.nb, si) : 0;
-    do_site(S, G.views[b], D.views[b], C, si);
+    do_site<MON, DENS>(S, G.views[b], D.views[b], C, si);
   }
   arena_close(S.ar, C);
 }
@@ -1173,7 +1199,8 @@ int resident_workgroups() {
   int &w = cache[dev];
   if (!w) {
     int per_cu = 0, ncu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, site_kernel, 64, 0) != hipSuccess || per_cu < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, site_kernel<false, false>, 64, 0) != hipSuccess ||
+        per_cu < 1)
       per_cu = 1;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1) ncu = 1;
     w = per_cu * ncu;
@@ -1192,7 +1219,10 @@ void vd_launch_queue_init(int *queue, long long n, hipStream_t st) {
   hipLaunchKernelGGL(queue_init, dim3(1), dim3(64), 0, st, queue, n);
 }
 
-void vd_launch_sites3d(const GridView &G, const DomainView &D, const CellsDev *Cdev, int workgroups,
-                       hipStream_t st) {
-  hipLaunchKernelGGL(site_kernel, dim3(workgroups), dim3(64), 0, st, G, D, Cdev);
+void vd_launch_sites3d(const GridView &G, const DomainView &D, const CellsDev *Cdev, int workgroups, bool monitor,
+                       bool density, hipStream_t st) {
+  if (monitor && density) hipLaunchKernelGGL((site_kernel<true, true>), dim3(workgroups), dim3(64), 0, st, G, D, Cdev);
+  else if (monitor) hipLaunchKernelGGL((site_kernel<true, false>), dim3(workgroups), dim3(64), 0, st, G, D, Cdev);
+  else if (density) hipLaunchKernelGGL((site_kernel<false, true>), dim3(workgroups), dim3(64), 0, st, G, D, Cdev);
+  else hipLaunchKernelGGL((site_kernel<false, false>), dim3(workgroups), dim3(64), 0, st, G, D, Cdev);
 }

@@ -321,6 +321,7 @@ __device__ int carve_s(TriLds &S, const GridView &G, const SParams C, int si, do
 
 __device__ __forceinline__ int conv(const GridView &G, int lab) { return lab >= 0 ? GL(G.perm)[lab] : lab; }
 
+template <bool DENS>
 __device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, const CellsDev &C, int a) {
   const int l = vd_lane();
   const SParams P = {C.improved, C.straddle, C.max_iters, C.monitor != 0};
@@ -358,6 +359,7 @@ __device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, c
     const double inrm = 1.0 / sqrt(N0 * N0 + N1 * N1 + N2 * N2);
     const double o0 = S.vy[0][0], o1 = S.vy[0][1], o2 = S.vy[0][2];
     double pa = 0, pmx = 0, pmy = 0, pmz = 0, pe = 0;
+    double dm = 0, dmx = 0, dmy = 0, dmz = 0, de = 0;  // density-weighted (DENS)
     if (l < nv) {
       const int t2 = (l + 1) % nv;
       const double y0 = S.vy[l][0], y1 = S.vy[l][1], y2 = S.vy[l][2];
@@ -371,10 +373,19 @@ __device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, c
       pmx = ar * s0 / 3.0; pmy = ar * s1 / 3.0; pmz = ar * s2 / 3.0;
       pe = ar / 12.0 * (o0 * o0 + o1 * o1 + o2 * o2 + y0 * y0 + y1 * y1 + y2 * y2 + z0 * z0 + z1 * z1 + z2 * z2 +
                         s0 * s0 + s1 * s1 + s2 * s2);
+      if (DENS) {
+        const double P0[3] = {o0, o1, o2}, P1[3] = {y0, y1, y2}, P2[3] = {z0, z1, z2};
+        tri_density_moments(C.dens, vx, vy, vz, P0, P1, P2, ar, dm, dmx, dmy, dmz, de);
+      }
     }
     pa = wave_sum(pa); pmx = wave_sum(pmx); pmy = wave_sum(pmy); pmz = wave_sum(pmz); pe = wave_sum(pe);
     if (C.monitor) count_add(S.ar.fantets, nv);
+    // a piece exists when its area is positive; with a density its moments are
+    // the weighted ones
     if (!(pa > 0.0)) continue;
+    if (DENS) {
+      pa = wave_sum(dm); pmx = wave_sum(dmx); pmy = wave_sum(dmy); pmz = wave_sum(dmz); pe = wave_sum(de);
+    }
     const int orig = GL(G.perm)[si];
     const long long pidx = arena_take(S.ar, C, AR_PIECE, 1);
     const long long fo = arena_take(S.ar, C, AR_FACE, nv);
@@ -415,11 +426,15 @@ __device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, c
         const double ln = sqrt((b0 - a0) * (b0 - a0) + (b1 - a1) * (b1 - a1) + (b2 - a2) * (b2 - a2));
         double I[12];
         for (int k = 0; k < 12; k++) I[k] = 0.0;
-        const double gq = 0.5 / sqrt(3.0);
-        for (int g = 0; g < 2; g++) {
-          const double xi = g == 0 ? 0.5 - gq : 0.5 + gq;
+        // Gauss-Legendre: 2 points (exact for the cubic integrand), or 3 with a
+        // density (quadratic times cubic)
+        const double gq = 0.5 / sqrt(3.0), g3 = 0.5 * sqrt(0.6);
+        const int ng = DENS ? 3 : 2;
+        for (int g = 0; g < ng; g++) {
+          const double xi = ng == 2 ? (g == 0 ? 0.5 - gq : 0.5 + gq) : (g == 0 ? 0.5 - g3 : (g == 1 ? 0.5 : 0.5 + g3));
           const double y0 = a0 + xi * (b0 - a0), y1 = a1 + xi * (b1 - a1), y2 = a2 + xi * (b2 - a2);
-          const double w = 0.5 * ln;
+          const double w = (ng == 2 ? 0.5 : (g == 1 ? 8.0 / 18.0 : 5.0 / 18.0)) * ln *
+                           (DENS ? density_at(C.dens, vx + y0, vy + y1, vz + y2) : 1.0);
           const double yy = y0 * y0 + y1 * y1 + y2 * y2;
           I[0] += w * y0; I[1] += w * y1; I[2] += w * y2;
           I[3] += w * y0 * y0; I[4] += w * y0 * y1; I[5] += w * y0 * y2;
@@ -496,6 +511,7 @@ __device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, c
 // Persistent: every workgroup (one wave) takes triangles from the queues.
 // Four waves per SIMD (128 VGPRs, a few spilled values): the polygon carve is
 // latency-bound, and the extra wave hides more of it than the spills cost.
+template <bool DENS>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) surface_kernel(GridView G, DomainView D, const CellsDev *__restrict__ Cp) {
   __shared__ TriLds S;
   const CellsDev &C = *Cp;
@@ -505,7 +521,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4)))
     if (a < 0) break;
     // the triangle's own diagram (a batch) or the only one
     const int b = D.nb > 1 ? diagram_of(D.simp_off, D.nb, a) : 0;
-    do_triangle(S, G.views[b], D.views[b], C, a);
+    do_triangle<DENS>(S, G.views[b], D.views[b], C, a);
   }
   arena_close(S.ar, C);
 }
@@ -585,7 +601,7 @@ int resident_workgroups() {
   int &w = cache[dev];
   if (!w) {
     int per_cu = 0, ncu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, surface_kernel, 64, 0) != hipSuccess || per_cu < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, surface_kernel<false>, 64, 0) != hipSuccess || per_cu < 1)
       per_cu = 1;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1) ncu = 1;
     w = per_cu * ncu;
@@ -600,9 +616,10 @@ int vd_surface_workgroups(long long m) {
   return (int)(m < w ? (m > 0 ? m : 1) : w);
 }
 
-void vd_launch_surface(const GridView &G, const DomainView &D, const CellsDev *Cdev, int workgroups,
+void vd_launch_surface(const GridView &G, const DomainView &D, const CellsDev *Cdev, int workgroups, bool density,
                        hipStream_t st) {
-  hipLaunchKernelGGL(surface_kernel, dim3((unsigned)workgroups), dim3(64), 0, st, G, D, Cdev);
+  if (density) hipLaunchKernelGGL(surface_kernel<true>, dim3((unsigned)workgroups), dim3(64), 0, st, G, D, Cdev);
+  else hipLaunchKernelGGL(surface_kernel<false>, dim3((unsigned)workgroups), dim3(64), 0, st, G, D, Cdev);
 }
 
 void vd_launch_site_reduce(long long n, const long long *poff, const int *pid, const CellsDev *Cdev,

@@ -171,6 +171,8 @@ struct CellsDev {
   int mode;        // 0 per-simplex carve, 1 cell-first
   int cache;       // LDS copy of the sites around each site for its queries
   int monitor;     // count work and track predicate margins
+  int density;     // weight the moments by the quadratic density dens[] (Eq. 3)
+  double dens[10]; // rho(x) = c0 + c1 x + c2 y + c3 z + c4 x^2 + c5 xy + c6 xz + c7 y^2 + c8 yz + c9 z^2
   unsigned long long *cnt;  // CNT_N counters
   // per site (caller index)
   double *mass, *mom, *energy;
@@ -234,6 +236,112 @@ struct vd_cells_s {
   bool used_bseeds = false;      // the last clip seeded from the boundary
 };
 
+// The density of Eq. 3 at the absolute point (x, y, z).
+__device__ __forceinline__ double density_at(const double *c, double x, double y, double z) {
+  return c[0] + x * (c[1] + c[4] * x + c[5] * y + c[6] * z) + y * (c[2] + c[7] * y + c[8] * z) + z * (c[3] + c[9] * z);
+}
+
+// Density-weighted moments of a tetrahedron with corners V0..V3 relative to
+// the site v (6 vol = det(V1 - V0, V2 - V0, V3 - V0)): mass += int rho,
+// m1 += int rho y, e += int rho |y|^2 (y = x - v).  Rule of Grundmann and
+// Moeller of degree 5 (15 points, barycentric (5,1,1,1)/8, (3,3,1,1)/8,
+// (3,1,1,1)/6, (1,1,1,1)/4 with weights 16/315, 16/315, -27/280, 2/45 of the
+// unit simplex): exact for a quadratic density, whose integrands have degree
+// at most 4.
+__device__ __forceinline__ void tet_density_moments(const double *c, double vx, double vy, double vz,
+                                                    const double *V0, const double *V1, const double *V2,
+                                                    const double *V3, double vol, double &mass, double &m0,
+                                                    double &m1, double &m2, double &e) {
+  double am = 0, a0 = 0, a1 = 0, a2 = 0, ae = 0;
+  auto add = [&](double w, double y0, double y1, double y2) {
+    const double wr = w * density_at(c, vx + y0, vy + y1, vz + y2);
+    am += wr;
+    a0 += wr * y0; a1 += wr * y1; a2 += wr * y2;
+    ae += wr * (y0 * y0 + y1 * y1 + y2 * y2);
+  };
+  const double S0 = V0[0] + V1[0] + V2[0] + V3[0], S1 = V0[1] + V1[1] + V2[1] + V3[1],
+               S2 = V0[2] + V1[2] + V2[2] + V3[2];
+  constexpr double wA = 16.0 / 315.0, wC = -27.0 / 280.0, wD = 2.0 / 45.0;
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const double *Vk = k == 0 ? V0 : (k == 1 ? V1 : (k == 2 ? V2 : V3));
+    add(wA, S0 * 0.125 + Vk[0] * 0.5, S1 * 0.125 + Vk[1] * 0.5, S2 * 0.125 + Vk[2] * 0.5);           // (5,1,1,1)/8
+    add(wC, S0 / 6.0 + Vk[0] / 3.0, S1 / 6.0 + Vk[1] / 3.0, S2 / 6.0 + Vk[2] / 3.0);                   // (3,1,1,1)/6
+  }
+#pragma unroll
+  for (int k = 1; k < 4; k++) {
+    // the pair {0, k} and its complement: (3,3,1,1)/8
+    const double *Vk = k == 1 ? V1 : (k == 2 ? V2 : V3);
+    const double P0 = V0[0] + Vk[0], P1 = V0[1] + Vk[1], P2 = V0[2] + Vk[2];
+    add(wA, S0 * 0.125 + P0 * 0.25, S1 * 0.125 + P1 * 0.25, S2 * 0.125 + P2 * 0.25);
+    add(wA, S0 * 0.375 - P0 * 0.25, S1 * 0.375 - P1 * 0.25, S2 * 0.375 - P2 * 0.25);
+  }
+  add(wD, S0 * 0.25, S1 * 0.25, S2 * 0.25);
+  const double sc = 6.0 * vol;
+  mass += sc * am; m0 += sc * a0; m1 += sc * a1; m2 += sc * a2; e += sc * ae;
+}
+
+// Density-weighted integrals over a triangle (A0, A1, A2 relative to v,
+// area `area`) of y, y y^T and |y|^2 y (the adjoint's face moments before the
+// division by |v_k - v|): rule of Grundmann and Moeller of degree 5
+// (barycentric (5,1,1)/7 and (3,3,1)/7 with weight 16807/80640, (3,1,1)/5
+// with -3125/11520, (1,1,1)/3 with 243/3840, of the unit triangle), exact
+// for a quadratic density times a cubic.
+__device__ __forceinline__ void tri_density_face(const double *c, double vx, double vy, double vz, const double *A0,
+                                                 const double *A1, const double *A2, double area, double *I) {
+  double acc[12];
+#pragma unroll
+  for (int k = 0; k < 12; k++) acc[k] = 0.0;
+  auto add = [&](double w, double y0, double y1, double y2) {
+    const double wr = w * density_at(c, vx + y0, vy + y1, vz + y2);
+    const double yy = y0 * y0 + y1 * y1 + y2 * y2;
+    acc[0] += wr * y0; acc[1] += wr * y1; acc[2] += wr * y2;
+    acc[3] += wr * y0 * y0; acc[4] += wr * y0 * y1; acc[5] += wr * y0 * y2;
+    acc[6] += wr * y1 * y1; acc[7] += wr * y1 * y2; acc[8] += wr * y2 * y2;
+    acc[9] += wr * yy * y0; acc[10] += wr * yy * y1; acc[11] += wr * yy * y2;
+  };
+  const double T0 = A0[0] + A1[0] + A2[0], T1 = A0[1] + A1[1] + A2[1], T2 = A0[2] + A1[2] + A2[2];
+  constexpr double w0 = 16807.0 / 80640.0, w1 = -3125.0 / 11520.0, w2 = 243.0 / 3840.0;
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    const double *Ak = k == 0 ? A0 : (k == 1 ? A1 : A2);
+    add(w0, (T0 + 4.0 * Ak[0]) / 7.0, (T1 + 4.0 * Ak[1]) / 7.0, (T2 + 4.0 * Ak[2]) / 7.0);        // (5,1,1)/7
+    add(w0, (3.0 * T0 - 2.0 * Ak[0]) / 7.0, (3.0 * T1 - 2.0 * Ak[1]) / 7.0, (3.0 * T2 - 2.0 * Ak[2]) / 7.0);  // (3,3,1)/7
+    add(w1, (T0 + 2.0 * Ak[0]) / 5.0, (T1 + 2.0 * Ak[1]) / 5.0, (T2 + 2.0 * Ak[2]) / 5.0);        // (3,1,1)/5
+  }
+  add(w2, T0 / 3.0, T1 / 3.0, T2 / 3.0);
+#pragma unroll
+  for (int k = 0; k < 12; k++) I[k] += 2.0 * area * acc[k];
+}
+
+// Density-weighted moments of a triangle (A0, A1, A2 relative to v, area
+// `area`): mass += int rho, m1 += int rho y, e += int rho |y|^2, with the same
+// degree-5 rule.
+__device__ __forceinline__ void tri_density_moments(const double *c, double vx, double vy, double vz,
+                                                    const double *A0, const double *A1, const double *A2,
+                                                    double area, double &mass, double &m0, double &m1, double &m2,
+                                                    double &e) {
+  double am = 0, a0 = 0, a1 = 0, a2 = 0, ae = 0;
+  auto add = [&](double w, double y0, double y1, double y2) {
+    const double wr = w * density_at(c, vx + y0, vy + y1, vz + y2);
+    am += wr;
+    a0 += wr * y0; a1 += wr * y1; a2 += wr * y2;
+    ae += wr * (y0 * y0 + y1 * y1 + y2 * y2);
+  };
+  const double T0 = A0[0] + A1[0] + A2[0], T1 = A0[1] + A1[1] + A2[1], T2 = A0[2] + A1[2] + A2[2];
+  constexpr double w0 = 16807.0 / 80640.0, w1 = -3125.0 / 11520.0, w2 = 243.0 / 3840.0;
+#pragma unroll
+  for (int k = 0; k < 3; k++) {
+    const double *Ak = k == 0 ? A0 : (k == 1 ? A1 : A2);
+    add(w0, (T0 + 4.0 * Ak[0]) / 7.0, (T1 + 4.0 * Ak[1]) / 7.0, (T2 + 4.0 * Ak[2]) / 7.0);
+    add(w0, (3.0 * T0 - 2.0 * Ak[0]) / 7.0, (3.0 * T1 - 2.0 * Ak[1]) / 7.0, (3.0 * T2 - 2.0 * Ak[2]) / 7.0);
+    add(w1, (T0 + 2.0 * Ak[0]) / 5.0, (T1 + 2.0 * Ak[1]) / 5.0, (T2 + 2.0 * Ak[2]) / 5.0);
+  }
+  add(w2, T0 / 3.0, T1 / 3.0, T2 / 3.0);
+  const double sc = 2.0 * area;
+  mass += sc * am; m0 += sc * a0; m1 += sc * a1; m2 += sc * a2; e += sc * ae;
+}
+
 // launchers (defined in the .hip files)
 void vd_launch_grid_build(vd_grid g, const double *sites, const double *user_box, hipStream_t st);
 void vd_launch_grid_delta(vd_grid g, hipStream_t st);
@@ -242,10 +350,10 @@ void vd_launch_locate_sites(const GridView &G, const DomainView &D, int *seed, i
 // workgroups of the persistent 3D site kernel (resident waves of the device)
 int vd_sites3d_workgroups(long long n);
 void vd_launch_queue_init(int *queue, long long n, hipStream_t st);
-void vd_launch_sites3d(const GridView &G, const DomainView &D, const CellsDev *Cdev, int workgroups,
-                       hipStream_t st);
+void vd_launch_sites3d(const GridView &G, const DomainView &D, const CellsDev *Cdev, int workgroups, bool monitor,
+                       bool density, hipStream_t st);
 int vd_surface_workgroups(long long m);
-void vd_launch_surface(const GridView &G, const DomainView &D, const CellsDev *Cdev, int workgroups,
+void vd_launch_surface(const GridView &G, const DomainView &D, const CellsDev *Cdev, int workgroups, bool density,
                        hipStream_t st);
 void vd_launch_site_nbrs(long long n, const long long *poff, const int *pid, const long long *noff, int *nbr,
                          const CellsDev *Cdev, hipStream_t st);
