@@ -156,6 +156,26 @@ vd_status vd_build_grid(const double *sites, int64_t n, const double *bbox_host,
 void vd_grid_free(vd_grid g);
 
 /* ---------------------------------------------------------------------
+ * vd_grid_set_weights -- turns the grid's sites into weighted sites of a
+ * power diagram (Sec. 7.3): the cell of v_i is the set of points x with
+ * |x - v_i|^2 - w_i <= |x - v_j|^2 - w_j for all j.  The sites are lifted to
+ * (v_i, sqrt(eta - w_i)) with eta = max w (the smallest admissible constant),
+ * so a nearest-site query of the lifted point is the smallest power distance,
+ * and vd_clip_cells computes the restricted Voronoi diagram of the lifted
+ * sites on the domain.  A power cell may be empty and need not contain its
+ * site.  The clips of a weighted grid use lifted grid queries (no site cache,
+ * no lambda steps), carve each 3D cell from the domain box and seed it from
+ * the boundary surface and from the tetrahedron holding the mean of its
+ * corners; they take no want_grad, use_density or no_sync.
+ *   weights [n] device, caller's site order, copied; NULL clears them.
+ * Must follow every vd_build_grid of the handle (a rebuild clears them).
+ * Synchronises `stream` once (validation).
+ * Errors: VD_ERR_INVALID_ARG (NULL grid, a weight that is not finite),
+ * VD_ERR_OUT_OF_MEMORY, VD_ERR_HIP.
+ * --------------------------------------------------------------------- */
+vd_status vd_grid_set_weights(vd_grid g, const double *weights, void *stream);
+
+/* ---------------------------------------------------------------------
  * vd_domain_create -- stages a simplex domain M = {T_a} (Sec. 3.1) on the
  * device: copies verts/simplices/adjacency and, for tetrahedra, builds the
  * point-location grid that finds the simplex containing each site (the seed of

@@ -80,6 +80,10 @@ def _load(native: bool = False):
         lib.vdo_compute.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
                                     C.c_void_p, C.c_int64, C.c_int, C.c_int, C.c_void_p,
                                     C.c_int64, C.c_int, C.POINTER(_Result)]
+        lib.vdo_compute_power.restype = C.c_int
+        lib.vdo_compute_power.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
+                                          C.c_void_p, C.c_int64, C.c_int, C.c_int, C.c_void_p,
+                                          C.c_int64, C.c_int, C.POINTER(_Result)]
         lib.vdo_free_result.restype = None
         lib.vdo_free_result.argtypes = [C.POINTER(_Result)]
         lib.vdo_moments_backward.restype = C.c_int
@@ -129,11 +133,12 @@ class _Keep:
 
 
 def compute(sites, domain, brute: bool = False, only_sites=None, threads: int = 0,
-            keep_handle: bool = False, native: bool = False):
+            keep_handle: bool = False, native: bool = False, weights=None):
     """All pieces P_{a,i} (Eq. 1) of the sites in ``domain`` (a vdgen.Domain).
 
     Returns a dict of NumPy arrays, pieces sorted by (site, simplex).
-    native=True runs the -march=native build (timing only).
+    native=True runs the -march=native build (timing only).  ``weights`` (n)
+    gives the power diagram of Sec. 7.3 instead.
     """
     lib = _load(native)
     s = np.ascontiguousarray(sites, dtype=np.float64)
@@ -146,10 +151,13 @@ def compute(sites, domain, brute: bool = False, only_sites=None, threads: int = 
         only = np.ascontiguousarray(only_sites, dtype=np.int32)
         n_only = only.size
     res = _Result()
-    st = lib.vdo_compute(s.ctypes.data, s.shape[0], v.ctypes.data, v.shape[0], t.ctypes.data,
-                         a.ctypes.data, t.shape[0], int(domain.dim), int(brute),
-                         only.ctypes.data if only is not None else None, n_only, int(threads),
-                         C.byref(res))
+    w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
+    if w is not None and w.shape != (s.shape[0],):
+        raise ValueError("one weight per site")
+    st = lib.vdo_compute_power(s.ctypes.data, None if w is None else w.ctypes.data, s.shape[0], v.ctypes.data,
+                               v.shape[0], t.ctypes.data, a.ctypes.data, t.shape[0], int(domain.dim), int(brute),
+                               only.ctypes.data if only is not None else None, n_only, int(threads),
+                               C.byref(res))
     if st != 0:
         raise RuntimeError(f"oracle failed with status {st}")
     out = _to_result(res)

@@ -111,9 +111,12 @@ static void sort3slots(const opl *pl, int *p) {
       if (pl[p[j]].key < pl[p[i]].key) { int t = p[i]; p[i] = p[j]; p[j] = t; }
 }
 
-static void bisector_plane(const double *vi, const double *vj, int j, opl *h) {
+/* H_ij relative to v_i: n.y <= c with n = v_j - v_i.  Voronoi (Eq. 1):
+ * c = |n|^2 / 2.  Power diagram (Sec. 7.3) with weights w: |x - v_i|^2 - w_i
+ * <= |x - v_j|^2 - w_j gives c = (|n|^2 + w_i - w_j) / 2. */
+static void bisector_plane(const double *vi, const double *vj, int j, double wij, opl *h) {
   sub3(vj, vi, h->n);
-  h->c = 0.5 * dot3(h->n, h->n);
+  h->c = 0.5 * (dot3(h->n, h->n) + wij);
   h->key = j;
   h->label = j;
 }
@@ -650,6 +653,8 @@ typedef struct {
   int dim, k;
   int brute;
   const ogrid *G;
+  const double *w;     /* power weights (NULL: Voronoi) */
+  double wmin, wmax;
 } octx;
 
 /* Clip the piece of site i in simplex a.  Returns 0 (empty), 1 (kept in
@@ -666,7 +671,8 @@ static int carve_pair(const octx *C, int64_t a, int64_t i, opoly *bufA, opoly *b
   opl h;
 #define APPLY_J(jj)                                                               \
   do {                                                                            \
-    bisector_plane(v, &C->sites[3 * (int64_t)(jj)], (int)(jj), &h);               \
+    bisector_plane(v, &C->sites[3 * (int64_t)(jj)], (int)(jj),                    \
+                   C->w ? C->w[i] - C->w[(jj)] : 0.0, &h);                          \
     int r_;                                                                       \
     if (C->dim == 3) {                                                            \
       r_ = clip3(P, &h, Q, margin);                                               \
@@ -714,14 +720,22 @@ static int carve_pair(const octx *C, int64_t a, int64_t i, opoly *bufA, opoly *b
       if (!any) break; /* the shell lies entirely outside the grid */
       /* security radius: every unvisited site is >= s*h from v_i; if that is
        * at least twice the largest |x - v_i| over the piece, each remaining
-       * half-space contains the piece. */
+       * half-space contains the piece.  With power weights, a site at distance
+       * d >= R from v_i has |x - v_j|^2 - w_j >= (d - R)^2 - w_max for x in the
+       * piece, which is >= R^2 - w_i >= |x - v_i|^2 - w_i once
+       * d >= R + sqrt(R^2 + w_max - w_i). */
       double R2 = 0;
       if (C->dim == 3) {
         for (int x = 0; x < P->nvx; x++) { double d = dot3(P->vx[x].y, P->vx[x].y); if (d > R2) R2 = d; }
       } else {
         for (int x = 0; x < Pg->nv; x++) { double d = dot3(Pg->y[x], Pg->y[x]); if (d > R2) R2 = d; }
       }
-      if (s * G->h >= 2.0 * sqrt(R2)) break;
+      double reach = 2.0 * sqrt(R2);
+      if (C->w) {
+        double t = R2 + C->wmax - C->w[i];
+        reach = sqrt(R2) + (t > 0 ? sqrt(t) : 0.0);
+      }
+      if (s * G->h >= reach) break;
     }
   }
 #undef APPLY_J
@@ -864,6 +878,14 @@ int vdo_compute(const double *sites, int64_t n, const double *verts, int64_t nv,
                 const int32_t *simp, const int32_t *adj, int64_t m, int simplex_dim,
                 int brute, const int32_t *only_sites, int64_t n_only, int threads,
                 vdo_result *out) {
+  return vdo_compute_power(sites, NULL, n, verts, nv, simp, adj, m, simplex_dim, brute, only_sites, n_only,
+                           threads, out);
+}
+
+int vdo_compute_power(const double *sites, const double *weights, int64_t n, const double *verts, int64_t nv,
+                      const int32_t *simp, const int32_t *adj, int64_t m, int simplex_dim,
+                      int brute, const int32_t *only_sites, int64_t n_only, int threads,
+                      vdo_result *out) {
   memset(out, 0, sizeof *out);
   out->min_margin = DBL_MAX;
   if (n < 1 || m < 1 || (simplex_dim != 2 && simplex_dim != 3) || !sites || !verts || !simp || !adj)
@@ -876,7 +898,16 @@ int vdo_compute(const double *sites, int64_t n, const double *verts, int64_t nv,
   ogrid G;
   memset(&G, 0, sizeof G);
   if (ogrid_build(&G, sites, n, verts, nv)) { ogrid_free(&G); return 2; }
-  octx C = {sites, n, verts, simp, adj, simplex_dim, k, brute, &G};
+  octx C = {sites, n, verts, simp, adj, simplex_dim, k, brute, &G, weights, 0.0, 0.0};
+  if (weights) {
+    C.wmin = DBL_MAX;
+    C.wmax = -DBL_MAX;
+    for (int64_t i = 0; i < n; i++) {
+      if (!isfinite(weights[i])) { ogrid_free(&G); return 1; }
+      if (weights[i] < C.wmin) C.wmin = weights[i];
+      if (weights[i] > C.wmax) C.wmax = weights[i];
+    }
+  }
 
 #ifdef _OPENMP
   int nt = threads > 0 ? threads : omp_get_max_threads();
@@ -901,6 +932,9 @@ int vdo_compute(const double *sites, int64_t n, const double *verts, int64_t nv,
       double lo[3], hi[3], dm;
       simplex_box(&C, a, lo, hi, &dm);
       ra[a] = onn_dist(&G, sites, &verts[3 * (int64_t)simp[a * k]]) + dm;
+      /* power: some site k has |x - v_k|^2 - w_k <= r_a^2 - w_min on T_a, so
+       * an owner i of x has |x - v_i|^2 <= r_a^2 - w_min + w_max */
+      if (weights) ra[a] = sqrt(ra[a] * ra[a] - C.wmin + C.wmax);
     }
   }
 

@@ -71,6 +71,15 @@ int vdo_compute(const double *sites, int64_t n, const double *verts, int64_t nv,
                 int brute, const int32_t *only_sites, int64_t n_only, int threads,
                 vdo_result *out);
 
+/* Power diagram (Sec. 7.3): as vdo_compute with the half-spaces
+ * |x - v_i|^2 - w_i <= |x - v_j|^2 - w_j (weights [n]; NULL = Voronoi).  A
+ * site's cell may be empty, and need not contain the site.  The pruned mode
+ * uses the matching security radius and candidate bound. */
+int vdo_compute_power(const double *sites, const double *weights, int64_t n, const double *verts, int64_t nv,
+                      const int32_t *simp, const int32_t *adj, int64_t m, int simplex_dim,
+                      int brute, const int32_t *only_sites, int64_t n_only, int threads,
+                      vdo_result *out);
+
 void vdo_free_result(vdo_result *r);
 
 /* Adjoint of L = sum_k g_m[k] m_k + g_c[k].c_k + g_E[k] E_k with respect to the

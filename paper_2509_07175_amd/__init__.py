@@ -139,6 +139,7 @@ def load():
         "vd_cell_moments": (C.c_int, [vp, vp, vp, vp, vp]),
         "vd_cell_moments_backward": (C.c_int, [vp, vp, vp, vp, vp, vp]),
         "vd_sync": (C.c_int, [vp]),
+        "vd_grid_set_weights": (C.c_int, [vp, vp, vp]),
         "vd_cell_moments_backward_noalloc": (C.c_int, [vp, vp, vp, vp, vp, vp]),
         "vd_domain_info": (C.c_int, [vp, C.POINTER(_DomainInfo)]),
         "vd_domain_adjacency": (C.c_int, [vp, vp, vp]),
@@ -155,7 +156,7 @@ def exported_symbols():
     return ["vd_options_default", "vd_last_error", "vd_status_string", "vd_build_grid", "vd_grid_free",
             "vd_build_grid_batch", "vd_domain_create_batch", "vd_domain_create", "vd_domain_free", "vd_clip_cells", "vd_cells_free", "vd_cells_info",
             "vd_cells_view", "vd_cell_moments", "vd_cell_moments_backward", "vd_sync", "vd_domain_info",
-            "vd_domain_adjacency", "vd_cell_moments_backward_noalloc"]
+            "vd_domain_adjacency", "vd_cell_moments_backward_noalloc", "vd_grid_set_weights"]
 
 
 def sync(stream=None):
@@ -234,6 +235,19 @@ class Grid:
         self.sites = sites
         return self
 
+    def set_weights(self, weights, stream=None):
+        """vd_grid_set_weights: power-diagram weights of the sites (n float64 on
+        the device, caller order), or None for the Voronoi diagram."""
+        import torch
+        w = None
+        if weights is not None:
+            if weights.shape != (self.sites.shape[0],):
+                raise ValueError("one weight per site")
+            w = _dptr(weights, torch.float64)
+        _check(load().vd_grid_set_weights(self.h, w, _stream_ptr(stream)))
+        self.weights = weights
+        return self
+
     def __del__(self):
         if _lib is not None and self.h:
             _lib.vd_grid_free(self.h)
@@ -241,9 +255,14 @@ class Grid:
 
 
 def build_grid(sites, bbox=None, sites_per_cell=0.0, surface_area=0.0, grid: Grid | None = None,
-               stream=None) -> Grid:
+               stream=None, weights=None) -> Grid:
+    """vd_build_grid (and vd_grid_set_weights when ``weights`` is given: a
+    power diagram)."""
     g = grid if grid is not None else Grid()
-    return g.build(sites, bbox, sites_per_cell, surface_area, stream)
+    g.build(sites, bbox, sites_per_cell, surface_area, stream)
+    if weights is not None:
+        g.set_weights(weights, stream)
+    return g
 
 
 def build_grid_batch(sites, site_off, bboxes=None, sites_per_cell=0.0, grid: Grid | None = None,

@@ -143,6 +143,19 @@ hipError_t upload_if_changed(T *dev, const T *host, size_t count, std::vector<T>
   return hipMemcpyAsync(dev, shadow.data(), sizeof(T) * count, hipMemcpyHostToDevice, st);
 }
 
+// device temporaries of one call, freed when it returns (on every path)
+struct TmpBuffers {
+  std::vector<void *> p;
+  ~TmpBuffers() { for (void *q : p) hipFree(q); }
+  template <typename T>
+  hipError_t get(T *&out, int64_t n) {
+    out = nullptr;
+    const hipError_t e = hipMalloc((void **)&out, sizeof(T) * (size_t)std::max<int64_t>(n, 1));
+    if (e == hipSuccess) p.push_back(out);
+    return e;
+  }
+};
+
 struct GridShadow {
   std::vector<long long> site_off, cell_off;
   std::vector<int> dims;
@@ -250,6 +263,7 @@ vd_status build_grid_impl(const double *sites, int64_t n, int nb, const int64_t 
       tmp = 0; if ((e = ensure(G->bbox_part, tmp, 6 * (int64_t)std::max(nb, 256))) != hipSuccess) goto herr;
       G->cap_nb = nb;
     }
+    G->power = false;  // weights belong to one sorting of the sites
     GridShadow *sh;
     {
       std::lock_guard<std::mutex> lk(g_shadow_mu);
@@ -298,8 +312,44 @@ vd_status vd_build_grid_batch(const double *sites, const vd_batch *batch, const 
                          0.0, stream, out, "vd_build_grid_batch");
 }
 
+vd_status vd_grid_set_weights(vd_grid G, const double *weights, void *stream) {
+  if (!G) return fail(VD_ERR_INVALID_ARG, "vd_grid_set_weights: NULL grid");
+  hipStream_t st = as_stream(stream);
+  if (weights) {
+    int64_t t = G->cap_w;
+    HIP_TRY(ensure(G->sw, t, G->n));
+    t = G->cap_w;
+    HIP_TRY(ensure(G->sh, t, G->n));
+    G->cap_w = t;
+    HIP_TRY(ensure_fixed(G->eta, 1));
+    TmpBuffers tmp;
+    int *flags = nullptr;
+    HIP_TRY(tmp.get(flags, 1));
+    vd_launch_fill_int(flags, 1, 0, st);
+    vd_launch_grid_weights(G, weights, flags, st);
+    int hf = 0;
+    HIP_TRY(hipMemcpyAsync(&hf, flags, sizeof hf, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (hf) return fail(VD_ERR_INVALID_ARG, "vd_grid_set_weights: a weight is not finite");
+  }
+  G->power = weights != nullptr;
+  std::vector<GridView> v(G->nb);
+  for (int b = 0; b < G->nb; b++) v[b] = G->view_of(b);
+  std::vector<unsigned char> bytes((const unsigned char *)v.data(), (const unsigned char *)(v.data() + G->nb));
+  {
+    std::lock_guard<std::mutex> lk(g_shadow_mu);
+    GridShadow &sh = g_grid_shadow[G];
+    if (sh.views != bytes) {
+      sh.views = bytes;
+      HIP_TRY(hipMemcpyAsync(G->d_views, sh.views.data(), bytes.size(), hipMemcpyHostToDevice, st));
+    }
+  }
+  return VD_OK;
+}
+
 void vd_grid_free(vd_grid G) {
   if (!G) return;
+  hipFree(G->sw); hipFree(G->sh); hipFree(G->eta);
   hipFree(G->geom); hipFree(G->bbox_part); hipFree(G->sx); hipFree(G->sy); hipFree(G->sz);
   hipFree(G->delta); hipFree(G->perm); hipFree(G->rank); hipFree(G->cellid); hipFree(G->fill);
   hipFree(G->cstart); hipFree(G->ccount); hipFree(G->scan_tmp);
@@ -319,18 +369,7 @@ void vd_grid_free(vd_grid G) {
 
 namespace {
 
-// device temporaries of one call, freed when it returns (on every path)
-struct TmpBuffers {
-  std::vector<void *> p;
-  ~TmpBuffers() { for (void *q : p) hipFree(q); }
-  template <typename T>
-  hipError_t get(T *&out, int64_t n) {
-    out = nullptr;
-    const hipError_t e = hipMalloc((void **)&out, sizeof(T) * (size_t)std::max<int64_t>(n, 1));
-    if (e == hipSuccess) p.push_back(out);
-    return e;
-  }
-};
+
 
 vd_status domain_create_impl(const double *verts, const int32_t *simplices, const int32_t *adjacency, int nb,
                              const int64_t *vert_off_host, const int64_t *simp_off_host, int32_t simplex_dim,
@@ -685,6 +724,19 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
   vd_options_default(&opt);
   if (opt_in) opt = *opt_in;
   if (opt.max_search_iters < 1) opt.max_search_iters = 1;
+  if (g->power) {
+    // power diagram (Sec. 7.3): lifted grid queries (no site cache, no lambda
+    // steps); in 3D the cell is carved first and seeded from the boundary too,
+    // since a power cell need not contain its site
+    if (opt.want_grad || opt.use_density || opt.no_sync)
+      return fail(VD_ERR_INVALID_ARG, "vd_clip_cells: power diagrams take no want_grad, use_density or no_sync");
+    opt.improved_search = 0;
+    opt.site_cache = 0;
+    if (dom->dim == 3) {
+      opt.carve_mode = 1;
+      opt.boundary_seeds = 1;
+    }
+  }
   hipStream_t st = as_stream(stream);
   vd_cells c = *out ? *out : new vd_cells_s();
   const int64_t n = g->n;
@@ -714,7 +766,7 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
     want.vert = keep_faces ? c->d.cap_vert : 0;
     want.fint = opt.want_grad ? c->d.cap_fint : 0;
   }
-  for (int attempt = 0; attempt < 4; attempt++) {
+  for (int attempt = 0; attempt < 8; attempt++) {
     hipError_t e = alloc_cells(c, n, want);
     if (e != hipSuccess)
       return bail(fail(e == hipErrorOutOfMemory ? VD_ERR_OUT_OF_MEMORY : VD_ERR_HIP, "vd_clip_cells: %s",
@@ -731,18 +783,25 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
     d.cache = opt.site_cache ? 1 : 0;
     d.monitor = opt.monitor ? 1 : 0;
     d.density = opt.use_density ? 1 : 0;
+    d.power = g->power ? 1 : 0;
     for (int k = 0; k < 10; k++) d.dens[k] = opt.use_density ? opt.density[k] : (k == 0 ? 1.0 : 0.0);
     // persistent 3D kernel: each wave reserves output chunks of about 1/8 of an
     // arena's share per wave, so unused chunk tails stay within 1/8 of it
     const int64_t items = dom->dim == 3 ? n : dom->m;  // sites, or triangles
     const int wg = dom->dim == 3 ? vd_sites3d_workgroups(n) : vd_surface_workgroups(dom->m);
-    if (dom->dim == 3 && c->cap_spill < wg) {
+    if (dom->dim == 3 &&
+        (c->cap_spill < wg || d.q_spill < c->q_spill_want || d.nbs_cap < c->nb_spill_want)) {
       if (opt.no_sync) return bail(fail(VD_ERR_INVALID_ARG, "vd_clip_cells: no_sync on an unsized handle"));
+      const int64_t w = std::max<int64_t>(wg, c->cap_spill);
       int64_t t = 0;
-      HIP_TRY(ensure(d.tq_spill, t, (int64_t)wg * VD_Q_SPILL));
+      HIP_TRY(ensure(d.tq_spill, t, w * c->q_spill_want));
       t = 0;
-      HIP_TRY(ensure(d.saved, t, (int64_t)wg * VD_SAVE_DOUBLES));
-      c->cap_spill = wg;
+      HIP_TRY(ensure(d.nb_spill, t, w * c->nb_spill_want));
+      t = 0;
+      HIP_TRY(ensure(d.saved, t, w * VD_SAVE_DOUBLES));
+      c->cap_spill = w;
+      d.q_spill = c->q_spill_want;
+      d.nbs_cap = c->nb_spill_want;
     }
     {
       const int64_t caps[AR_N] = {d.cap_piece, d.cap_face, d.cap_vert, d.cap_nbr, d.cap_fint};
@@ -806,8 +865,8 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
     }
     if (dom->dim == 2) vd_launch_fill_int(d.pcount, n, 0, st);
     if (opt.time_kernels) HIP_TRY(hipEventRecord(c->ev0, st));
-    if (dom->dim == 3) vd_launch_sites3d(G, D, c->d_dev, wg, opt.monitor != 0, opt.use_density != 0, st);
-    else vd_launch_surface(G, D, c->d_dev, wg, opt.use_density != 0, st);
+    if (dom->dim == 3) vd_launch_sites3d(G, D, c->d_dev, wg, opt.monitor != 0, opt.use_density != 0, g->power, st);
+    else vd_launch_surface(G, D, c->d_dev, wg, opt.use_density != 0, g->power, st);
     if (opt.time_kernels) HIP_TRY(hipEventRecord(c->ev1, st));
     HIP_TRY(hipGetLastError());
     if (opt.no_sync) {
@@ -842,6 +901,26 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
     if (keep_faces && (int64_t)hc[CNT_VERTS] > d.cap_vert) { need.vert = up(hc[CNT_VERTS]); grow = true; }
     if (opt.want_grad && (int64_t)hc[CNT_FINT] > d.cap_fint) { need.fint = up(hc[CNT_FINT]); grow = true; }
     if (grow) { want = need; continue; }
+    if (dom->dim == 3 && hc[CNT_ERR_CAP] && !hc[CNT_ERR_DEG] && !hc[CNT_ERR_LOC]) {
+      // a cell that meets more tetrahedra, or has more neighbours, than the
+      // per-wave overflow buffers hold: grow them (within about 4 GB each) and
+      // run again; the LDS capacities of the polytope itself are fixed
+      const unsigned long long stg = hc[CNT_STAGES];
+      const unsigned long long growable = (1ull << VD_STAGE_SIMPLICES) | (1ull << VD_STAGE_NEIGHBOURS);
+      const int64_t wmax = std::max<int64_t>(1, (int64_t)(1ll << 30) / std::max<int64_t>(c->cap_spill, 1));
+      bool regrow = !(stg & ~growable);
+      if (regrow && (stg & (1ull << VD_STAGE_SIMPLICES))) {
+        const int64_t nw = std::min<int64_t>({(int64_t)c->q_spill_want * 4, dom->m, wmax});
+        regrow = nw > c->q_spill_want;
+        c->q_spill_want = (int)nw;
+      }
+      if (regrow && (stg & (1ull << VD_STAGE_NEIGHBOURS))) {
+        const int64_t nw = std::min<int64_t>({(int64_t)c->nb_spill_want * 4, n, wmax});
+        regrow = nw > c->nb_spill_want;
+        c->nb_spill_want = (int)nw;
+      }
+      if (regrow) continue;
+    }
     {
       const vd_status r = check_counts(c, false);
       if (r != VD_OK) {
@@ -879,6 +958,7 @@ void vd_cells_free(vd_cells c) {
   if (c->ev2) hipEventDestroy(c->ev2);
   hipFree(c->d_dev); hipFree(d.queue); hipFree(d.tq_spill); hipFree(d.saved);
   hipFree(c->outside);
+  hipFree(d.nb_spill);
   vd_cells_free(c->bcells);
   if (c->host_cnt) hipHostFree(c->host_cnt);
   hipFree(d.fint_lab); hipFree(d.piece_fint_start); hipFree(d.piece_nfint); hipFree(c->wbuf);

@@ -96,6 +96,7 @@ __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlan
 
 struct SiteCtx {
   double vx, vy, vz, delta;
+  double h, w;  // power diagram: lifted coordinate and weight of the site (else 0)
   int si;
 };
 
@@ -351,7 +352,14 @@ struct CarveParams {
   int improved, straddle, max_iters;
 };
 
-template <bool MON>
+// POW: power diagram (Sec. 7.3).  The sites are lifted to (v_j, h_j) with
+// h_j = sqrt(eta - w_j) and the cell is the restricted Voronoi cell of the
+// lifted site on the hyperplane of the domain: corners are tested as points
+// of that hyperplane (4th coordinate 0), the virtual search edge starts at the
+// lifted site (v_i, h_i), whose 4D cell always contains it, and a search point
+// on it has a 4th coordinate between h_i and 0.  The clip plane is the power
+// plane n.y <= (|n|^2 + w_i - w_j)/2 (the lifted bisector on the hyperplane).
+template <bool MON, bool POW>
 __device__ int carve(WaveLds &S, const GridView &G, const CarveParams C, const SiteCtx &X, int &npl, int &nc,
                      Stats &st) {
   enum { PICK = 0, TEST, LAMBDA, SEARCH };
@@ -365,17 +373,28 @@ __device__ int carve(WaveLds &S, const GridView &G, const CarveParams C, const S
   double A0 = 0, A1 = 0, A2 = 0, g0 = 0, g1 = 0, g2 = 0, u0 = 0, u1 = 0, u2 = 0, L = 0;
   double n0 = 0, n1 = 0, n2 = 0, nc3 = 0;
   double q0 = 0, q1 = 0, q2 = 0;  // query point relative to v_i (per group for TEST)
+  double A4 = 0, g4 = 0, q4 = 0;   // POW: 4th coordinates of the edge ends and of the query
   // crossing of [A, g] with B_ij (j = current candidate)
   auto bisector_point = [&]() {
     n0 = GL(G.sx)[j] - X.vx; n1 = GL(G.sy)[j] - X.vy; n2 = GL(G.sz)[j] - X.vz;
-    nc3 = 0.5 * (n0 * n0 + n1 * n1 + n2 * n2);
     const double e0 = g0 - A0, e1 = g1 - A1, e2 = g2 - A2;
-    const double den = n0 * e0 + n1 * e1 + n2 * e2;
-    const double num = nc3 - (n0 * A0 + n1 * A1 + n2 * A2);
+    double den, num;
+    if (POW) {
+      // 4D bisector of the lifted sites, relative to (v_i, h_i)
+      const double n4 = GL(G.sh)[j] - X.h, e4 = g4 - A4;
+      den = n0 * e0 + n1 * e1 + n2 * e2 + n4 * e4;
+      num = 0.5 * (n0 * n0 + n1 * n1 + n2 * n2 + n4 * n4) - (n0 * A0 + n1 * A1 + n2 * A2 + n4 * (A4 - X.h));
+      nc3 = 0.5 * (n0 * n0 + n1 * n1 + n2 * n2 + X.w - GL(G.sw)[j]);
+    } else {
+      nc3 = 0.5 * (n0 * n0 + n1 * n1 + n2 * n2);
+      den = n0 * e0 + n1 * e1 + n2 * e2;
+      num = nc3 - (n0 * A0 + n1 * A1 + n2 * A2);
+    }
     qon = den > 0.0 && num > 0.0 && num < den;
     double t = den > 0.0 ? num / den : 1.0;
     t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
     q0 = A0 + t * e0; q1 = A1 + t * e1; q2 = A2 + t * e2;
+    if (POW) q4 = A4 + t * (g4 - A4);
   };
   for (int it = 0; it < kMaxIters; it++) {
     if (mode == PICK) {
@@ -428,6 +447,8 @@ __device__ int carve(WaveLds &S, const GridView &G, const CarveParams C, const S
         if (pt < 0) pt = olo ? __ffsll((unsigned long long)olo) - 1 : 64 + __ffsll((unsigned long long)ohi) - 1;
         ps_edge = ps;
         A0 = A1 = A2 = 0;
+        A4 = ps >= 0 ? 0.0 : X.h;  // from a corner on the hyperplane, or from the lifted site
+        g4 = 0.0;
         if (ps >= 0) { A0 = S.cy[ps][0]; A1 = S.cy[ps][1]; A2 = S.cy[ps][2]; }
         g0 = S.cy[pt][0]; g1 = S.cy[pt][1]; g2 = S.cy[pt][2];
         j = uni((S.cst[pt] >> 8) - 1);
@@ -482,8 +503,16 @@ __device__ int carve(WaveLds &S, const GridView &G, const CarveParams C, const S
     }
     bool on_grid;
     if (MON) count_add(S.ar.rounds, 1);
-    const int kq = nn_cached(S.K, G, gs, qx, qy, qz, dx * dx + dy * dy + dz * dz, X.si, e0 < 0 ? -1 : e0,
-                             e1 < 0 ? -1 : e1, e2 < 0 ? -1 : e2, st.cands, on_grid);
+    int kq;
+    if (POW) {
+      // lifted query on the grid; corners lie on the hyperplane
+      const double qw = mode == SEARCH ? q4 : 0.0, dw = qw - X.h;
+      kq = nn_query<true>(G, gs, qx, qy, qz, dx * dx + dy * dy + dz * dz + dw * dw, X.si, st.cands, qw);
+      on_grid = true;
+    } else {
+      kq = nn_cached(S.K, G, gs, qx, qy, qz, dx * dx + dy * dy + dz * dz, X.si, e0 < 0 ? -1 : e0, e1 < 0 ? -1 : e1,
+                     e2 < 0 ? -1 : e2, st.cands, on_grid);
+    }
     if (mode == TEST) {
       st.queries += nbatch;
       st.grid += __popcll(__ballot(on_grid && (l & 15) == 0 && grp < nbatch));
@@ -521,6 +550,7 @@ __device__ int carve(WaveLds &S, const GridView &G, const CarveParams C, const S
       if (++nstep >= C.max_iters) return 3;
       j = k;
       g0 = q0; g1 = q1; g2 = q2;
+      g4 = q4;
       bisector_point();
       continue;
     }
@@ -825,16 +855,16 @@ __device__ void face_moments(WaveLds &S, int nc, int npl, uint64_t fmask, const 
 // global buffer (cells that meet more simplices than the LDS queue holds).
 // Out of line: the common case never touches them.
 __device__ __forceinline__ int spill_get(const CellsDev &C, int i) {
-  return GL(C.tq_spill)[(long long)blockIdx.x * VD_Q_SPILL + i - VD_Q_MAX];
+  return GL(C.tq_spill)[(long long)blockIdx.x * C.q_spill + i - VD_Q_MAX];
 }
 __device__ __forceinline__ bool spill_has(const CellsDev &C, int b, int nt) {
-  const int*q = C.tq_spill + (long long)blockIdx.x * VD_Q_SPILL - VD_Q_MAX;
+  const int*q = C.tq_spill + (long long)blockIdx.x * C.q_spill - VD_Q_MAX;
   bool have = false;
   for (int e = VD_Q_MAX + vd_lane(); e < nt; e += 64) have = have || (q[e] == b);
   return have;
 }
 __device__ __forceinline__ void spill_put(const CellsDev &C, int i, int b) {
-  if (vd_lane() == 0) GL(C.tq_spill)[(long long)blockIdx.x * VD_Q_SPILL + i - VD_Q_MAX] = b;
+  if (vd_lane() == 0) GL(C.tq_spill)[(long long)blockIdx.x * C.q_spill + i - VD_Q_MAX] = b;
 }
 
 // Appends simplex b to the site's breadth-first queue unless it is there
@@ -846,7 +876,7 @@ __device__ __forceinline__ bool tq_push(WaveLds &S, const CellsDev &C, int &nt, 
   for (int e = l; e < nl; e += 64) have = have || (S.tq[e] == b);
   if (nt > VD_Q_MAX) have = have || spill_has(C, b, nt);
   if (__ballot(have)) return true;
-  if (nt >= VD_Q_MAX + VD_Q_SPILL) return false;
+  if (nt >= VD_Q_MAX + C.q_spill) return false;
   __syncthreads();
   if (nt < VD_Q_MAX) {
     if (l == 0) S.tq[nt] = b;
@@ -854,6 +884,49 @@ __device__ __forceinline__ bool tq_push(WaveLds &S, const CellsDev &C, int &nt, 
     spill_put(C, nt, b);  // large cells: the queue continues in global memory
   }
   nt++;
+  __syncthreads();
+  return true;
+}
+
+// The lowest-index tetrahedron containing q (the whole wave scans the point's
+// location cell), or -1.
+__device__ int locate_wave(const DomainView &D, double qx, double qy, double qz) {
+  if (!D.lstart) return -1;
+  const double q[3] = {qx, qy, qz};
+  int cc[3];
+  for (int k = 0; k < 3; k++) cc[k] = cell_coord(q[k], GL(D.lgeom)[k], GL(D.lgeom)[6 + k], D.lg[k]);
+  const int c = cc[0] + D.lg[0] * (cc[1] + D.lg[1] * cc[2]);
+  int best = 0x7fffffff;
+  for (int t = GL(D.lstart)[c] + vd_lane(); t < GL(D.lstart)[c + 1]; t += 64) {
+    const int a = GL(D.litems)[t];
+    if (a < best && tet_contains(D, a, q)) best = a;
+  }
+  const int b = (int)wave_min((double)best);
+  return b == 0x7fffffff ? -1 : b;
+}
+
+// Neighbour e of the site's list: the first VD_NB_MAX in LDS, the rest in this
+// wave's part of a global buffer.
+__device__ __forceinline__ int nb_get(const WaveLds &S, const CellsDev &C, int e) {
+  return e < VD_NB_MAX ? S.nbl[e] : GL(C.nb_spill)[(long long)blockIdx.x * C.nbs_cap + e - VD_NB_MAX];
+}
+
+// Appends neighbour lab unless it is listed already.  Returns false when the
+// list is full (the synchronous clip then grows the buffer and runs again).
+__device__ __forceinline__ bool nb_push(WaveLds &S, const CellsDev &C, int &nnb, int lab) {
+  const int l = vd_lane();
+  bool have = false;
+  const int nl = nnb < VD_NB_MAX ? nnb : VD_NB_MAX;
+  for (int e = l; e < nl; e += 64) have = have || (S.nbl[e] == lab);
+  for (int e = VD_NB_MAX + l; e < nnb; e += 64) have = have || (nb_get(S, C, e) == lab);
+  if (__ballot(have)) return true;
+  if (nnb >= VD_NB_MAX + C.nbs_cap) return false;
+  __syncthreads();
+  if (l == 0) {
+    if (nnb < VD_NB_MAX) S.nbl[nnb] = lab;
+    else GL(C.nb_spill)[(long long)blockIdx.x * C.nbs_cap + nnb - VD_NB_MAX] = lab;
+  }
+  nnb++;
   __syncthreads();
   return true;
 }
@@ -870,12 +943,14 @@ __device__ __forceinline__ bool tq_push(WaveLds &S, const CellsDev &C, int &nt, 
 //     tests and the bisector search.
 // The carve has one call site: the first job of a cell-first site is the cell.
 // ---------------------------------------------------------------------------
-template <bool MON, bool DENS>
+template <bool MON, bool DENS, bool POW>
 __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, const CellsDev &C, int si) {
   const int l = vd_lane();
   SiteCtx X;
   X.vx = GL(G.sx)[si]; X.vy = GL(G.sy)[si]; X.vz = GL(G.sz)[si];
   X.delta = GL(G.delta)[si];
+  X.h = POW ? GL(G.sh)[si] : 0.0;
+  X.w = POW ? GL(G.sw)[si] : 0.0;
   X.si = si;
   const int orig = GL(G.perm)[si];
   const int seed = GL(C.seed)[si];
@@ -915,10 +990,10 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
       const int t = GL(C.btet)[GL(C.bseed_tri)[GL(C.bseed_pid)[q]]];
       if (!tq_push(S, C, nt, t)) { err = 2; where = VD_STAGE_SIMPLICES; break; }
     }
-  } else if (!nt) {
+  } else if (!nt && !POW) {
     err = 4;  // outside every tetrahedron, and no boundary seeds to find its cell
   }
-  if (!nt) cell_job = false;
+  if (!nt && !POW) cell_job = false;
   for (;;) {
     int a = -1, npl = 4, nc = 4;
     bool empty = false, need_carve = true;
@@ -955,9 +1030,10 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
       }
     }
     if (need_carve) {
-      const int rc = carve<MON>(S, G, P, X, npl, nc, st);
+      const int rc = carve<MON, POW>(S, G, P, X, npl, nc, st);
       if (cell_job) {
         cell_job = false;
+        if (POW && rc == 1) { head = nt; continue; }     // an empty power cell: no pieces
         if (rc == 1 || rc == 3) { err = 3; where = VD_STAGE_CELL; continue; }  // the site lies in the box
         if (rc == 2) continue;                           // too large: carve per simplex
         npl = compact_planes(S, npl, nc);
@@ -973,6 +1049,17 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
             if (l == 0) S.cellpos = cp;
           }
           cell_lab = l < npl ? S.plab[l] : 0;
+          if (POW) {
+            // a power cell need not contain its site: seed the tetrahedron
+            // holding the mean of the cell's corners (a point of the cell);
+            // parts of the cell that reach the boundary of M are seeded from
+            // the boundary surface
+            double c0 = 0, c1 = 0, c2 = 0;
+            for (int x = l; x < nc; x += 64) { c0 += S.cy[x][0]; c1 += S.cy[x][1]; c2 += S.cy[x][2]; }
+            c0 = wave_sum(c0) / nc; c1 = wave_sum(c1) / nc; c2 = wave_sum(c2) / nc;
+            const int t = locate_wave(D, X.vx + c0, X.vy + c1, X.vz + c2);
+            if (t >= 0 && !tq_push(S, C, nt, t)) { err = 2; where = VD_STAGE_SIMPLICES; }
+          }
         }
         continue;
       }
@@ -1096,15 +1183,7 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
       const int x = __ffsll((unsigned long long)m) - 1;
       const int lab = uni(S.plab[x]);
       if (lab >= 0) {
-        bool have = false;
-        for (int e = l; e < nnb; e += 64) have = have || (S.nbl[e] == lab);
-        if (!__ballot(have)) {
-          if (nnb >= VD_NB_MAX) { err = 2; where = VD_STAGE_NEIGHBOURS; break; }
-          __syncthreads();
-          if (l == 0) S.nbl[nnb] = lab;
-          nnb++;
-          __syncthreads();
-        }
+        if (!nb_push(S, C, nnb, lab)) { err = 2; where = VD_STAGE_NEIGHBOURS; break; }
       } else if (lab > VD_BND_BASE + 3) {
         if (!tq_push(S, C, nt, -lab - 1)) { err = 2; where = VD_STAGE_SIMPLICES; break; }
       }
@@ -1115,15 +1194,7 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
   __syncthreads();
   for (uint64_t m = S.nbmask; m && !err; m &= m - 1) {
     const int lab = __builtin_amdgcn_readlane(cell_lab, __ffsll((unsigned long long)m) - 1);
-    bool have = false;
-    for (int e = l; e < nnb; e += 64) have = have || (S.nbl[e] == lab);
-    if (!__ballot(have)) {
-      if (nnb >= VD_NB_MAX) { err = 2; where = VD_STAGE_NEIGHBOURS; break; }
-      __syncthreads();
-      if (l == 0) S.nbl[nnb] = lab;
-      nnb++;
-      __syncthreads();
-    }
+    if (!nb_push(S, C, nnb, lab)) { err = 2; where = VD_STAGE_NEIGHBOURS; break; }
   }
   // ---- per-site results ----
   const long long ns0 = arena_take(S.ar, C, AR_NBR, nnb);
@@ -1154,9 +1225,9 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
   if (ns0 + nnb <= C.cap_nbr) {
     // neighbours in ascending caller index: rank sort
     for (int e = l; e < nnb; e += 64) {
-      const int me = GL(G.perm)[S.nbl[e]];
+      const int me = GL(G.perm)[nb_get(S, C, e)];
       int rk = 0;
-      for (int o = 0; o < nnb; o++) rk += (GL(G.perm)[S.nbl[o]] < me) ? 1 : 0;
+      for (int o = 0; o < nnb; o++) rk += (GL(G.perm)[nb_get(S, C, o)] < me) ? 1 : 0;
       GL(C.nbr_arena)[ns0 + rk] = me;
     }
   }
@@ -1170,7 +1241,7 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
 // MON: the work counters and margin tracking of vd_options.monitor; DENS: the
 // density-weighted moments of vd_options.use_density.  Each is compiled in only
 // for the instances that use it, so the default instance carries neither.
-template <bool MON, bool DENS>
+template <bool MON, bool DENS, bool POW>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3))) site_kernel(GridView G, DomainView D, const CellsDev *__restrict__ Cp) {
   __shared__ WaveLds S;
   const CellsDev &C = *Cp;
@@ -1181,7 +1252,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3)))
     // the site's own diagram (a batch) or the only one; one call site keeps
     // the per-site code inlined once
     const int b = G.nb > 1 ? diagram_of(G.site_off, G.nb, si) : 0;
-    do_site<MON, DENS>(S, G.views[b], D.views[b], C, si);
+    do_site<MON, DENS, POW>(S, G.views[b], D.views[b], C, si);
   }
   arena_close(S.ar, C);
 }
@@ -1199,7 +1270,7 @@ int resident_workgroups() {
   int &w = cache[dev];
   if (!w) {
     int per_cu = 0, ncu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, site_kernel<false, false>, 64, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, site_kernel<false, false, false>, 64, 0) != hipSuccess ||
         per_cu < 1)
       per_cu = 1;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1) ncu = 1;
@@ -1220,9 +1291,18 @@ void vd_launch_queue_init(int *queue, long long n, hipStream_t st) {
 }
 
 void vd_launch_sites3d(const GridView &G, const DomainView &D, const CellsDev *Cdev, int workgroups, bool monitor,
-                       bool density, hipStream_t st) {
-  if (monitor && density) hipLaunchKernelGGL((site_kernel<true, true>), dim3(workgroups), dim3(64), 0, st, G, D, Cdev);
-  else if (monitor) hipLaunchKernelGGL((site_kernel<true, false>), dim3(workgroups), dim3(64), 0, st, G, D, Cdev);
-  else if (density) hipLaunchKernelGGL((site_kernel<false, true>), dim3(workgroups), dim3(64), 0, st, G, D, Cdev);
-  else hipLaunchKernelGGL((site_kernel<false, false>), dim3(workgroups), dim3(64), 0, st, G, D, Cdev);
+                       bool density, bool power, hipStream_t st) {
+  const dim3 grid(workgroups), block(64);
+  if (power) {  // power diagrams: no density
+    if (monitor) hipLaunchKernelGGL((site_kernel<true, false, true>), grid, block, 0, st, G, D, Cdev);
+    else hipLaunchKernelGGL((site_kernel<false, false, true>), grid, block, 0, st, G, D, Cdev);
+  } else if (monitor && density) {
+    hipLaunchKernelGGL((site_kernel<true, true, false>), grid, block, 0, st, G, D, Cdev);
+  } else if (monitor) {
+    hipLaunchKernelGGL((site_kernel<true, false, false>), grid, block, 0, st, G, D, Cdev);
+  } else if (density) {
+    hipLaunchKernelGGL((site_kernel<false, true, false>), grid, block, 0, st, G, D, Cdev);
+  } else {
+    hipLaunchKernelGGL((site_kernel<false, false, false>), grid, block, 0, st, G, D, Cdev);
+  }
 }

@@ -173,7 +173,48 @@ __global__ void __launch_bounds__(kB) grid_delta(GridView G, double *__restrict_
 
 inline unsigned blocks(long long n) { return (unsigned)((n + kB - 1) / kB > 0 ? (n + kB - 1) / kB : 1); }
 
+// Power weights in sorted order, and eta = max w (one block, fixed reduction
+// order); flags[0] is set for a weight that is not finite.
+__global__ void __launch_bounds__(kB) weights_gather(long long n, const int *__restrict__ perm,
+                                                     const double *__restrict__ w, double *__restrict__ sw,
+                                                     int *__restrict__ flags) {
+  const long long p = (long long)blockIdx.x * kB + threadIdx.x;
+  if (p >= n) return;
+  const double x = w[perm[p]];
+  if (!isfinite(x)) atomicOr(&flags[0], 1);
+  sw[p] = x;
+}
+
+__global__ void __launch_bounds__(kB) weights_max(long long n, const double *__restrict__ sw, double *__restrict__ eta) {
+  double m = -1e300;
+  for (long long p = threadIdx.x; p < n; p += kB) m = fmax(m, sw[p]);
+  __shared__ double red[kB];
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int d = kB / 2; d > 0; d >>= 1) {
+    if (threadIdx.x < (unsigned)d) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + d]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) eta[0] = red[0];
+}
+
+// the lifted coordinate h_i = sqrt(eta - w_i) of Sec. 7.3 (eta = max w, the
+// smallest admissible constant)
+__global__ void __launch_bounds__(kB) weights_lift(long long n, const double *__restrict__ sw,
+                                                   const double *__restrict__ eta, double *__restrict__ sh) {
+  const long long p = (long long)blockIdx.x * kB + threadIdx.x;
+  if (p < n) sh[p] = sqrt(fmax(eta[0] - sw[p], 0.0));
+}
+
 }  // namespace
+
+void vd_launch_grid_weights(vd_grid g, const double *w, int *flags, hipStream_t st) {
+  const long long n = g->n;
+  hipLaunchKernelGGL(weights_gather, dim3(blocks(n)), dim3(kB), 0, st, n, (const int *)g->perm, w, g->sw, flags);
+  hipLaunchKernelGGL(weights_max, dim3(1), dim3(kB), 0, st, n, (const double *)g->sw, g->eta);
+  hipLaunchKernelGGL(weights_lift, dim3(blocks(n)), dim3(kB), 0, st, n, (const double *)g->sw,
+                     (const double *)g->eta, g->sh);
+}
 
 void vd_launch_fill_int(int *p, long long n, int v, hipStream_t st);
 

@@ -178,6 +178,10 @@ struct SParams {
 
 // Carve the polygon until every vertex is certified inside Omega_i (TEST /
 // LAMBDA / SEARCH queries as in the 3D kernel).  Returns 0, 1 empty, 2, 3.
+// POW: power diagram, as in the 3D kernel: the lifted site (v_i, h_i) starts
+// the virtual search edges, polygon vertices lie on the hyperplane (4th
+// coordinate 0) and the clip plane is the power plane.
+template <bool POW>
 __device__ int carve_s(TriLds &S, const GridView &G, const SParams C, int si, double vx, double vy, double vz,
                        double delta, int &npl, int &nv, SStats &ss) {
   enum { PICK = 0, TEST, LAMBDA, SEARCH };
@@ -187,15 +191,26 @@ __device__ int carve_s(TriLds &S, const GridView &G, const SParams C, int si, do
   int pt = -1, j = -1, ef0 = -2, lam = 2, nstep = 0, tslot = -1, nbatch = 0;
   double A0 = 0, A1 = 0, A2 = 0, g0 = 0, g1 = 0, g2 = 0, u0 = 0, u1 = 0, u2 = 0, L = 0;
   double n0 = 0, n1 = 0, n2 = 0, nc3 = 0, q0 = 0, q1 = 0, q2 = 0;
+  const double hi_ = POW ? GL(G.sh)[si] : 0.0, wi_ = POW ? GL(G.sw)[si] : 0.0;
+  double A4 = 0, g4 = 0, q4 = 0;  // POW: 4th coordinates
   auto bisector_point = [&]() {
     n0 = GL(G.sx)[j] - vx; n1 = GL(G.sy)[j] - vy; n2 = GL(G.sz)[j] - vz;
-    nc3 = 0.5 * (n0 * n0 + n1 * n1 + n2 * n2);
     const double e0 = g0 - A0, e1 = g1 - A1, e2 = g2 - A2;
-    const double den = n0 * e0 + n1 * e1 + n2 * e2;
-    const double num = nc3 - (n0 * A0 + n1 * A1 + n2 * A2);
+    double den, num;
+    if (POW) {
+      const double n4 = GL(G.sh)[j] - hi_, e4 = g4 - A4;
+      den = n0 * e0 + n1 * e1 + n2 * e2 + n4 * e4;
+      num = 0.5 * (n0 * n0 + n1 * n1 + n2 * n2 + n4 * n4) - (n0 * A0 + n1 * A1 + n2 * A2 + n4 * (A4 - hi_));
+      nc3 = 0.5 * (n0 * n0 + n1 * n1 + n2 * n2 + wi_ - GL(G.sw)[j]);
+    } else {
+      nc3 = 0.5 * (n0 * n0 + n1 * n1 + n2 * n2);
+      den = n0 * e0 + n1 * e1 + n2 * e2;
+      num = nc3 - (n0 * A0 + n1 * A1 + n2 * A2);
+    }
     double t = den > 0.0 ? num / den : 1.0;
     t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
     q0 = A0 + t * e0; q1 = A1 + t * e1; q2 = A2 + t * e2;
+    if (POW) q4 = A4 + t * (g4 - A4);
   };
   for (int it = 0; it < kMaxIters; it++) {
     if (mode == PICK) {
@@ -234,6 +249,8 @@ __device__ int carve_s(TriLds &S, const GridView &G, const SParams C, int si, do
         }
         if (pt < 0) pt = __ffsll((unsigned long long)O) - 1;
         A0 = A1 = A2 = 0;
+        A4 = ps >= 0 ? 0.0 : hi_;
+        g4 = 0.0;
         if (ps >= 0) { A0 = S.vy[ps][0]; A1 = S.vy[ps][1]; A2 = S.vy[ps][2]; }
         g0 = S.vy[pt][0]; g1 = S.vy[pt][1]; g2 = S.vy[pt][2];
         j = uni((S.vst[pt] >> 8) - 1);
@@ -261,7 +278,13 @@ __device__ int carve_s(TriLds &S, const GridView &G, const SParams C, int si, do
     const double qx = vx + q0, qy = vy + q1, qz = vz + q2;
     const double dx = qx - vx, dy = qy - vy, dz = qz - vz;
     if (C.monitor) count_add(S.ar.rounds, 1);
-    const int kq = nn_query(G, gs, qx, qy, qz, dx * dx + dy * dy + dz * dz, si, ss.cands);
+    int kq;
+    if (POW) {
+      const double qw = mode == SEARCH ? q4 : 0.0, dw = qw - hi_;
+      kq = nn_query<true>(G, gs, qx, qy, qz, dx * dx + dy * dy + dz * dz + dw * dw, si, ss.cands, qw);
+    } else {
+      kq = nn_query(G, gs, qx, qy, qz, dx * dx + dy * dy + dz * dz, si, ss.cands);
+    }
     if (mode == TEST) {
       ss.queries += nbatch;
       bool in = false;
@@ -296,6 +319,7 @@ __device__ int carve_s(TriLds &S, const GridView &G, const SParams C, int si, do
       if (++nstep >= C.max_iters) return 3;
       j = k;
       g0 = q0; g1 = q1; g2 = q2;
+      g4 = q4;
       bisector_point();
       continue;
     }
@@ -321,7 +345,7 @@ __device__ int carve_s(TriLds &S, const GridView &G, const SParams C, int si, do
 
 __device__ __forceinline__ int conv(const GridView &G, int lab) { return lab >= 0 ? GL(G.perm)[lab] : lab; }
 
-template <bool DENS>
+template <bool DENS, bool POW>
 __device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, const CellsDev &C, int a) {
   const int l = vd_lane();
   const SParams P = {C.improved, C.straddle, C.max_iters, C.monitor != 0};
@@ -335,7 +359,7 @@ __device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, c
                  p2 = &GL(D.verts)[3 * (long long)tv[2]];
     const double cx = (p0[0] + p1[0] + p2[0]) / 3.0, cy = (p0[1] + p1[1] + p2[1]) / 3.0,
                  cz = (p0[2] + p1[2] + p2[2]) / 3.0;
-    const int k = uni(nn_query(G, 64, cx, cy, cz, 1e300, -1, ss.cands));
+    const int k = uni(nn_query<POW>(G, 64, cx, cy, cz, 1e300, -1, ss.cands, 0.0));
     ss.queries++;
     if (k >= 0) {
       if (l == 0) S.sq[0] = k;
@@ -350,7 +374,7 @@ __device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, c
     const double vx = GL(G.sx)[si], vy = GL(G.sy)[si], vz = GL(G.sz)[si], delta = GL(G.delta)[si];
     init_tri(S, D, a, vx, vy, vz);
     int npl = 4, nv = 3;
-    const int rc = carve_s(S, G, P, si, vx, vy, vz, delta, npl, nv, ss);
+    const int rc = carve_s<POW>(S, G, P, si, vx, vy, vz, delta, npl, nv, ss);
     if (rc == 1) continue;
     if (rc) { err = rc; break; }
     // ---- moments: fan from corner 0 of the piece, so that the area's rounding
@@ -511,7 +535,7 @@ __device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, c
 // Persistent: every workgroup (one wave) takes triangles from the queues.
 // Four waves per SIMD (128 VGPRs, a few spilled values): the polygon carve is
 // latency-bound, and the extra wave hides more of it than the spills cost.
-template <bool DENS>
+template <bool DENS, bool POW>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4))) surface_kernel(GridView G, DomainView D, const CellsDev *__restrict__ Cp) {
   __shared__ TriLds S;
   const CellsDev &C = *Cp;
@@ -521,7 +545,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4)))
     if (a < 0) break;
     // the triangle's own diagram (a batch) or the only one
     const int b = D.nb > 1 ? diagram_of(D.simp_off, D.nb, a) : 0;
-    do_triangle<DENS>(S, G.views[b], D.views[b], C, a);
+    do_triangle<DENS, POW>(S, G.views[b], D.views[b], C, a);
   }
   arena_close(S.ar, C);
 }
@@ -601,7 +625,7 @@ int resident_workgroups() {
   int &w = cache[dev];
   if (!w) {
     int per_cu = 0, ncu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, surface_kernel<false>, 64, 0) != hipSuccess || per_cu < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, surface_kernel<false, false>, 64, 0) != hipSuccess || per_cu < 1)
       per_cu = 1;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1) ncu = 1;
     w = per_cu * ncu;
@@ -617,9 +641,11 @@ int vd_surface_workgroups(long long m) {
 }
 
 void vd_launch_surface(const GridView &G, const DomainView &D, const CellsDev *Cdev, int workgroups, bool density,
-                       hipStream_t st) {
-  if (density) hipLaunchKernelGGL(surface_kernel<true>, dim3((unsigned)workgroups), dim3(64), 0, st, G, D, Cdev);
-  else hipLaunchKernelGGL(surface_kernel<false>, dim3((unsigned)workgroups), dim3(64), 0, st, G, D, Cdev);
+                       bool power, hipStream_t st) {
+  const dim3 grid((unsigned)workgroups), block(64);
+  if (power) hipLaunchKernelGGL((surface_kernel<false, true>), grid, block, 0, st, G, D, Cdev);
+  else if (density) hipLaunchKernelGGL((surface_kernel<true, false>), grid, block, 0, st, G, D, Cdev);
+  else hipLaunchKernelGGL((surface_kernel<false, false>), grid, block, 0, st, G, D, Cdev);
 }
 
 void vd_launch_site_reduce(long long n, const long long *poff, const int *pid, const CellsDev *Cdev,

@@ -35,6 +35,8 @@ struct GridView {
   const int *cstart;  // [g0*g1*g2 + 1]
   const int *perm;    // sorted position -> caller index
   const double *delta;  // half nearest-other-site distance, by sorted position
+  const double *sw, *sh;  // power diagram (Sec. 7.3): weight w and lifted coordinate
+                          // h = sqrt(eta - w) by sorted position; NULL for Voronoi
   int nb;                      // diagrams (1: plain)
   const GridView *views;       // [nb] per-diagram views (nb > 1)
   const long long *site_off;   // [nb + 1] sorted-position offsets (nb > 1)
@@ -231,9 +233,13 @@ __device__ __forceinline__ int cell_coord(double x, double lo, double ih, int g)
 // consecutive cells is one contiguous range of sorted sites, so the group
 // flattens all rows into one candidate list (coalesced SoA loads).
 // ---------------------------------------------------------------------------
+// POW: power diagram, the sites lifted to (v_j, h_j) and the query to (q, qw):
+// the distance is |q - v_j|^2 + (qw - h_j)^2, never below the 3D one, so the
+// boxes trimmed to the 3D ball of the best distance still hold every nearer site.
+template <bool POW = false>
 __device__ __forceinline__ void scan_box(const GridView &G, int gs, int x0, int x1, int y0, int y1, int z0,
                                          int z1, double qx, double qy, double qz, double &bd, int &bk,
-                                         long long &ncand) {
+                                         long long &ncand, double qw = 0.0) {
   const int gl = vd_lane() & (gs - 1);
   const int nx = x1 - x0 + 1, ny = y1 - y0 + 1;
   const int R = ny * (z1 - z0 + 1);
@@ -264,7 +270,11 @@ __device__ __forceinline__ void scan_box(const GridView &G, int gs, int x0, int 
       if (t < total) {
         const int p = rst + (t - rex);
         const double dx = qx - GL(G.sx)[p], dy = qy - GL(G.sy)[p], dz = qz - GL(G.sz)[p];
-        const double d = dx * dx + dy * dy + dz * dz;
+        double d = dx * dx + dy * dy + dz * dz;
+        if (POW) {
+          const double dw = qw - GL(G.sh)[p];
+          d += dw * dw;
+        }
         lexmin(bd, bk, d, p);
       }
     }
@@ -276,8 +286,9 @@ __device__ __forceinline__ void group_argmin(double &d, int &k, int gs) {
   else row_argmin(d, k);  // gs == 16: a group is a DPP row
 }
 
+template <bool POW = false>
 __device__ __forceinline__ int nn_query(const GridView &G, int gs, double qx, double qy, double qz, double r2,
-                                        int k0, long long &ncand) {
+                                        int k0, long long &ncand, double qw = 0.0) {
   const double lox = GL(G.geom)[0], loy = GL(G.geom)[1], loz = GL(G.geom)[2];
   const double ihx = GL(G.geom)[6], ihy = GL(G.geom)[7], ihz = GL(G.geom)[8];
   const int gx = G.g[0], gy = G.g[1], gz = G.g[2];
@@ -297,7 +308,7 @@ __device__ __forceinline__ int nn_query(const GridView &G, int gs, double qx, do
     const int x0 = max(cx - R, X0), x1 = min(cx + R, X1);
     const int y0 = max(cy - R, Y0), y1 = min(cy + R, Y1);
     const int z0 = max(cz - R, Z0), z1 = min(cz + R, Z1);
-    scan_box(G, gs, x0, x1, y0, y1, z0, z1, qx, qy, qz, bd, bk, ncand);
+    scan_box<POW>(G, gs, x0, x1, y0, y1, z0, z1, qx, qy, qz, bd, bk, ncand, qw);
     group_argmin(bd, bk, gs);
     const double rn = sqrt(bd);
     const bool inside = cell_coord(qx - rn, lox, ihx, gx) >= x0 && cell_coord(qx + rn, lox, ihx, gx) <= x1 &&

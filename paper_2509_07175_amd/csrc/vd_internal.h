@@ -14,7 +14,8 @@
 #define VD_P_MAX 64    // planes of one intermediate polytope
 #define VD_C_MAX 128   // corners (two slots per lane)
 #define VD_Q_MAX 256   // tetrahedra visited for one site in LDS (4 per lane) ...
-#define VD_Q_SPILL 3840  // ... and after them in a per-wave global buffer
+#define VD_Q_SPILL 3840  // ... and after them in a per-wave global buffer (initial size, grown on retry)
+#define VD_NB_SPILL 160  // neighbours past VD_NB_MAX: per-wave global buffer (initial size, grown on retry)
 #define VD_NB_MAX 96   // distinct neighbours of one site
 #define VD_F_MAX 48    // planes of a saved cell (cell-first mode)
 #define VD_CB_MAX 96   // corners of a saved cell
@@ -58,6 +59,11 @@ struct vd_grid_s {
   double *bbox_part = nullptr;  // per-block partial boxes
   double *sx = nullptr, *sy = nullptr, *sz = nullptr, *delta = nullptr;
   bool delta_valid = false;   // delta is computed by the first clip that needs it after a build
+  // power diagram (vd_grid_set_weights): weights and lifted coordinates in
+  // sorted order, eta = max w; cleared by every build
+  double *sw = nullptr, *sh = nullptr, *eta = nullptr;
+  int64_t cap_w = 0;
+  bool power = false;
   int *perm = nullptr, *rank = nullptr, *cellid = nullptr, *fill = nullptr;
   int *cstart = nullptr, *ccount = nullptr, *scan_tmp = nullptr;
   // batch of nb diagrams (nb = 1: plain)
@@ -75,6 +81,7 @@ struct vd_grid_s {
     v.g[0] = dims[3 * b]; v.g[1] = dims[3 * b + 1]; v.g[2] = dims[3 * b + 2];
     v.geom = geom + 9 * b; v.sx = sx; v.sy = sy; v.sz = sz; v.cstart = cstart + cell_off[b];
     v.perm = perm; v.delta = delta;
+    v.sw = power ? sw : nullptr; v.sh = power ? sh : nullptr;
     v.nb = 1; v.views = nullptr; v.site_off = nullptr;
     return v;
   }
@@ -172,6 +179,7 @@ struct CellsDev {
   int cache;       // LDS copy of the sites around each site for its queries
   int monitor;     // count work and track predicate margins
   int density;     // weight the moments by the quadratic density dens[] (Eq. 3)
+  int power;       // power diagram: the grid's weights (Sec. 7.3)
   double dens[10]; // rho(x) = c0 + c1 x + c2 y + c3 z + c4 x^2 + c5 xy + c6 xz + c7 y^2 + c8 yz + c9 z^2
   unsigned long long *cnt;  // CNT_N counters
   // per site (caller index)
@@ -200,7 +208,9 @@ struct CellsDev {
   const int *bseed_pid, *bseed_tri, *btet;
   long long chunk[AR_N];  // slots a wave reserves at a time in each arena
   int *queue;             // [VD_QUEUES * VD_QSTRIDE] work-queue heads
-  int *tq_spill;          // [workgroups * VD_Q_SPILL] overflow of the per-site simplex queue
+  int *tq_spill;          // [workgroups * q_spill] overflow of the per-site simplex queue
+  int *nb_spill;          // [workgroups * nbs_cap] overflow of the per-site neighbour list
+  int q_spill, nbs_cap;   // entries per workgroup of the two overflow buffers
   double *saved;          // [workgroups * VD_SAVE_DOUBLES] each wave's carved cell (cell-first mode)
 };
 
@@ -226,7 +236,8 @@ struct vd_cells_s {
   hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;  // kernel timing (time_kernels)
   double carve_ms = -1.0, split_ms = -1.0;
   CellsDev *d_dev = nullptr;  // device copy of d (read by the piece kernel)
-  int64_t cap_spill = 0;      // workgroups covered by d.tq_spill
+  int64_t cap_spill = 0;      // workgroups covered by d.tq_spill / d.nb_spill / d.saved
+  int q_spill_want = VD_Q_SPILL, nb_spill_want = VD_NB_SPILL;  // per-workgroup sizes (grow on retry)
   CellsDev d_shadow{};        // host copy last sent to d_dev
   double *wbuf = nullptr;     // adjoint weights [5n]
   int64_t cap_w = 0;
@@ -235,6 +246,23 @@ struct vd_cells_s {
   vd_cells_s *bcells = nullptr;  // restricted diagram of the domain's boundary (boundary seeds)
   bool used_bseeds = false;      // the last clip seeded from the boundary
 };
+
+// Whether tetrahedron a (positively oriented) contains q: every sub-volume with
+// q in place of one vertex is >= -1e-12 of the volume.
+__device__ __forceinline__ bool tet_contains(const DomainView &D, long long a, const double *q) {
+  const double *P[4];
+  for (int u = 0; u < 4; u++) P[u] = &D.verts[3 * (long long)D.simp[a * 4 + u]];
+  auto vol6 = [](const double *A, const double *B, const double *Cc, const double *Dd) {
+    const double e1[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+    const double e2[3] = {Cc[0] - A[0], Cc[1] - A[1], Cc[2] - A[2]};
+    const double e3[3] = {Dd[0] - A[0], Dd[1] - A[1], Dd[2] - A[2]};
+    return e1[0] * (e2[1] * e3[2] - e2[2] * e3[1]) - e1[1] * (e2[0] * e3[2] - e2[2] * e3[0]) +
+           e1[2] * (e2[0] * e3[1] - e2[1] * e3[0]);
+  };
+  const double v = vol6(P[0], P[1], P[2], P[3]);
+  return vol6(q, P[1], P[2], P[3]) >= -1e-12 * v && vol6(P[0], q, P[2], P[3]) >= -1e-12 * v &&
+         vol6(P[0], P[1], q, P[3]) >= -1e-12 * v && vol6(P[0], P[1], P[2], q) >= -1e-12 * v;
+}
 
 // The density of Eq. 3 at the absolute point (x, y, z).
 __device__ __forceinline__ double density_at(const double *c, double x, double y, double z) {
@@ -345,16 +373,17 @@ __device__ __forceinline__ void tri_density_moments(const double *c, double vx, 
 // launchers (defined in the .hip files)
 void vd_launch_grid_build(vd_grid g, const double *sites, const double *user_box, hipStream_t st);
 void vd_launch_grid_delta(vd_grid g, hipStream_t st);
+void vd_launch_grid_weights(vd_grid g, const double *w, int *flags, hipStream_t st);
 void vd_launch_domain_locator(vd_domain d, hipStream_t st);
 void vd_launch_locate_sites(const GridView &G, const DomainView &D, int *seed, int *outside, hipStream_t st);
 // workgroups of the persistent 3D site kernel (resident waves of the device)
 int vd_sites3d_workgroups(long long n);
 void vd_launch_queue_init(int *queue, long long n, hipStream_t st);
 void vd_launch_sites3d(const GridView &G, const DomainView &D, const CellsDev *Cdev, int workgroups, bool monitor,
-                       bool density, hipStream_t st);
+                       bool density, bool power, hipStream_t st);
 int vd_surface_workgroups(long long m);
 void vd_launch_surface(const GridView &G, const DomainView &D, const CellsDev *Cdev, int workgroups, bool density,
-                       hipStream_t st);
+                       bool power, hipStream_t st);
 void vd_launch_site_nbrs(long long n, const long long *poff, const int *pid, const long long *noff, int *nbr,
                          const CellsDev *Cdev, hipStream_t st);
 void vd_launch_site_reduce(long long n, const long long *poff, const int *pid, const CellsDev *Cdev,

@@ -11,12 +11,13 @@ def log(msg):
     sys.stdout.flush()
 
 
-def run_gpu(sites, dom, bbox=(0, 0, 0, 1, 1, 1), surface_area=0.0, **opts):
+def run_gpu(sites, dom, bbox=(0, 0, 0, 1, 1, 1), surface_area=0.0, weights=None, **opts):
     import torch
     import paper_2509_07175_amd as vd
     s = torch.as_tensor(np.ascontiguousarray(sites), dtype=torch.float64, device="cuda")
     d = vd.Domain.from_vdgen(dom)
-    g = vd.build_grid(s, bbox=bbox, surface_area=surface_area)
+    w = None if weights is None else torch.as_tensor(np.ascontiguousarray(weights), dtype=torch.float64, device="cuda")
+    g = vd.build_grid(s, bbox=bbox, surface_area=surface_area, weights=w)
     c = vd.clip_cells(g, d, vd.Options.default(**opts))
     m, ce, e = c.moments()
     torch.cuda.synchronize()

@@ -64,21 +64,33 @@ def test_cell_over_many_tetrahedra(oracle_mod):
     assert len(gpu["res"]["piece_site"]) == dom.m
 
 
-def test_simplex_capacity_is_reported(oracle_mod):
-    """One site in 9^3 x 6 = 4,374 tetrahedra exceeds the per-wave simplex queue
-    (256 in LDS + 3,840 in global memory): the clip reports VD_ERR_CAPACITY
-    and the stage, and the library keeps working."""
-    import torch
-    import paper_2509_07175_amd as vd
+def test_cell_over_more_tetrahedra_than_the_first_buffer(oracle_mod):
+    """One site in 9^3 x 6 = 4,374 tetrahedra: more than the per-wave simplex
+    queue first holds (256 in LDS + 3,840 in global memory).  The synchronous
+    clip grows the queue's buffer and runs again: every tetrahedron is one
+    piece, identical to the oracle's."""
     dom = vdgen.kuhn_cube_grid(9)
-    s = torch.as_tensor(np.array([[0.31, 0.47, 0.59]]), dtype=torch.float64, device="cuda")
-    g = vd.build_grid(s, bbox=(0, 0, 0, 1, 1, 1))
-    with pytest.raises(vd.VDError) as ei:
-        vd.clip_cells(g, vd.Domain.from_vdgen(dom), vd.Options.default())
-    assert ei.value.status == 4 and "stages 0x20" in str(ei.value), str(ei.value)
-    torch.cuda.synchronize()
-    sites, dom2 = vdgen.small_case(300, 3, seed=5)
-    _check_case(oracle_mod, sites, dom2, brute=False)
+    s = np.array([[0.31, 0.47, 0.59]])
+    gpu, _, _ = _check_case(oracle_mod, s, dom)
+    assert len(gpu["res"]["piece_site"]) == dom.m and abs(gpu["mass"][0] - 1.0) < 1e-12
+
+
+def test_cell_with_more_neighbours_than_lds_holds(oracle_mod):
+    """A power site with a large weight among 8,000 light ones: its cell has
+    296 neighbours, more than the 96 a wave keeps in LDS plus the 160 of the
+    first global overflow buffer; the clip grows the buffer and the neighbour
+    list (and everything else) matches the oracle."""
+    sites = vdgen.uniform_cube_sites(8000, seed=8, jitter=1e-7)
+    w = np.zeros(len(sites))
+    w[0] = 0.04
+    sites[0] = (0.5, 0.5, 0.5)
+    dom = vdgen.kuhn_cube_grid(4)
+    gpu = run_gpu(sites, dom, weights=w)
+    ref = oracle_mod.compute(sites, dom, weights=w)
+    mom = oracle_mod.site_moments(ref, sites)
+    log(f"heavy site: {len(mom['neighbors'][0])} neighbours")
+    assert len(mom["neighbors"][0]) > 96 + 160
+    assert_parity(gpu, ref, mom, len(sites))
 
 
 @pytest.mark.parametrize("mode", [1, 0])
