@@ -164,15 +164,21 @@ __device__ int compact_planes(WaveLds &S, int npl, int nc) {
 // leaving R_p and form the fan of the new face.
 // Returns 0 (nothing outside: unchanged), 1 empty, 2 capacity, 3 degenerate,
 // 4 cut (nc updated).
-template <bool MON>
-__device__ int clip_poly(WaveLds &S, int P, int pt, int &nc, int ps = -1, int kcert = -1) {
+// W: the polytope may hold more than 64 corners (two slots per lane); the
+// narrow instance (nc <= 64 on entry, the common case) keeps one slot per
+// lane and one 64-bit mask per set.
+template <bool MON, bool W>
+__device__ int clip_poly_w(WaveLds &S, int P, int pt, int &nc, int ps, int kcert) {
+  constexpr int NH = W ? 2 : 1;
+  // bit s of the 128-bit set (lo, hi); narrow: every index is below 64
+  auto bit = [](uint64_t lo, uint64_t hi, int s) { return W ? bit128(lo, hi, s) : ((lo >> s) & 1ull) != 0; };
   const int l = vd_lane();
   const double nx = S.pn[P][0], ny = S.pn[P][1], nz = S.pn[P][2], c = S.pn[P][3];
   int pl[2] = {0, 0}, nb[2] = {0, 0}, cs[2] = {0, 0};
   double y[2][3] = {{0, 0, 0}, {0, 0, 0}};
-  bool v[2], o[2];
+  bool v[2] = {false, false}, o[2] = {false, false};
   double sd[2] = {-1.0, -1.0};
-  for (int h = 0; h < 2; h++) {
+  for (int h = 0; h < NH; h++) {
     const int s = l + 64 * h;
     v[h] = s < nc;
     if (v[h]) {
@@ -187,7 +193,7 @@ __device__ int clip_poly(WaveLds &S, int P, int pt, int &nc, int ps = -1, int kc
                  sd[1], fabs(nx * y[1][0]) + fabs(ny * y[1][1]) + fabs(nz * y[1][2]) + fabs(c));
     count_add(S.ar.classified, nc);
   }
-  const uint64_t olo = __ballot(o[0]), ohi = __ballot(o[1]);
+  const uint64_t olo = __ballot(o[0]), ohi = W ? __ballot(o[1]) : 0ull;
   if (!(olo | ohi)) return pt < 0 ? 0 : 3;
   uint64_t Rlo, Rhi;
   if (pt < 0) {
@@ -196,18 +202,18 @@ __device__ int clip_poly(WaveLds &S, int P, int pt, int &nc, int ps = -1, int kc
     Rlo = olo;
     Rhi = ohi;
   } else {
-    if (!bit128(olo, ohi, pt)) return 3;
+    if (!bit(olo, ohi, pt)) return 3;
     Rlo = pt < 64 ? (1ull << pt) : 0ull;
-    Rhi = pt >= 64 ? (1ull << (pt - 64)) : 0ull;
+    Rhi = (W && pt >= 64) ? (1ull << (pt - 64)) : 0ull;
   }
   for (int it = 0; pt >= 0 && it < VD_C_MAX; it++) {
-    bool j[2];
-    for (int h = 0; h < 2; h++) {
+    bool j[2] = {false, false};
+    for (int h = 0; h < NH; h++) {
       const int s = l + 64 * h;
-      j[h] = o[h] && !bit128(Rlo, Rhi, s) &&
-             (bit128(Rlo, Rhi, p8(nb[h], 0)) || bit128(Rlo, Rhi, p8(nb[h], 1)) || bit128(Rlo, Rhi, p8(nb[h], 2)));
+      j[h] = o[h] && !bit(Rlo, Rhi, s) &&
+             (bit(Rlo, Rhi, p8(nb[h], 0)) || bit(Rlo, Rhi, p8(nb[h], 1)) || bit(Rlo, Rhi, p8(nb[h], 2)));
     }
-    const uint64_t a = __ballot(j[0]), b = __ballot(j[1]);
+    const uint64_t a = __ballot(j[0]), b = W ? __ballot(j[1]) : 0ull;
     if (!(a | b)) break;
     Rlo |= a;
     Rhi |= b;
@@ -215,19 +221,19 @@ __device__ int clip_poly(WaveLds &S, int P, int pt, int &nc, int ps = -1, int kc
   const int nR = __popcll(Rlo) + __popcll(Rhi);
   if (MON && pt >= 0) {
     // tests spent on corners this clip removes, besides the one that led to it
-    const uint64_t tlo = __ballot(v[0] && (cs[0] & 2)), thi = __ballot(v[1] && (cs[1] & 2));
-    const int w = __popcll(tlo & Rlo) + __popcll(thi & Rhi) - (bit128(tlo, thi, pt) ? 1 : 0);
+    const uint64_t tlo = __ballot(v[0] && (cs[0] & 2)), thi = W ? __ballot(v[1] && (cs[1] & 2)) : 0ull;
+    const int w = __popcll(tlo & Rlo) + __popcll(thi & Rhi) - (bit(tlo, thi, pt) ? 1 : 0);
     count_add(S.ar.wasted, w);
   }
   if (nR >= nc) return 1;
-  bool r[2];
+  bool r[2] = {false, false};
   int em[2] = {0, 0};
-  for (int h = 0; h < 2; h++) {
+  for (int h = 0; h < NH; h++) {
     const int s = l + 64 * h;
-    r[h] = v[h] && bit128(Rlo, Rhi, s);
+    r[h] = v[h] && bit(Rlo, Rhi, s);
     if (r[h])
       for (int e = 0; e < 3; e++)
-        if (!bit128(Rlo, Rhi, p8(nb[h], e))) em[h] |= 1 << e;
+        if (!bit(Rlo, Rhi, p8(nb[h], e))) em[h] |= 1 << e;
   }
   const int cnt = __popc(em[0]) + __popc(em[1]);
   const int inc = wave_incl_scan(cnt);
@@ -236,7 +242,7 @@ __device__ int clip_poly(WaveLds &S, int P, int pt, int &nc, int ps = -1, int kc
   const int nsurv = nc - nR;
   if (nnew < 3) return 3;
   if (nsurv + nnew > VD_C_MAX) return 2;
-  const uint64_t vlo = low_mask(nc < 64 ? nc : 64), vhi = low_mask(nc > 64 ? nc - 64 : 0);
+  const uint64_t vlo = low_mask(nc < 64 ? nc : 64), vhi = W ? low_mask(nc > 64 ? nc - 64 : 0) : 0ull;
   const uint64_t Slo = vlo & ~Rlo, Shi = vhi & ~Rhi;
   // every plane is "first" (resp. "second") of at most one new corner when the
   // boundary of R_p is a simple loop; the tables give the fan adjacency.  A
@@ -246,7 +252,7 @@ __device__ int clip_poly(WaveLds &S, int P, int pt, int &nc, int ps = -1, int kc
   uint64_t fm = 0, sm = 0;
   {
     int t = base;
-    for (int h = 0; h < 2; h++)
+    for (int h = 0; h < NH; h++)
       for (int e = 0; e < 3; e++)
         if (em[h] & (1 << e)) {
           const int u = p8(pl[h], e), w = p8(pl[h], (e + 1) % 3);
@@ -267,16 +273,17 @@ __device__ int clip_poly(WaveLds &S, int P, int pt, int &nc, int ps = -1, int kc
     // new slot of every surviving corner (lane l: slots l and l + 64), and of
     // the three neighbours of each corner, fetched from their owning lanes
     const int nlo = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(Slo >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)Slo, 0u));
-    const int nhi = __popcll(Slo) +
-                    (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(Shi >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)Shi, 0u));
-    int nbn[2][3];
+    const int nhi = W ? __popcll(Slo) + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(Shi >> 32),
+                                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)Shi, 0u))
+                      : 0;
+    int nbn[2][3] = {{0, 0, 0}, {0, 0, 0}};
 #pragma unroll
-    for (int h = 0; h < 2; h++)
+    for (int h = 0; h < NH; h++)
 #pragma unroll
       for (int e = 0; e < 3; e++) {
         const int m = p8(nb[h], e);
         int x = __shfl(nlo, m & 63, 64);
-        if (nc > 64) {
+        if (W && nc > 64) {
           const int y = __shfl(nhi, m & 63, 64);
           x = m < 64 ? x : y;
         }
@@ -284,13 +291,13 @@ __device__ int clip_poly(WaveLds &S, int P, int pt, int &nc, int ps = -1, int kc
       }
     int t = base;
 #pragma unroll
-    for (int h = 0; h < 2; h++) {
+    for (int h = 0; h < NH; h++) {
       if (v[h] && !r[h]) {
         const int ns = h ? nhi : nlo;
         int nbo[3];
         for (int e = 0; e < 3; e++) {
           const int m = p8(nb[h], e);
-          nbo[e] = bit128(Rlo, Rhi, m) ? S.byFirst[p8(pl[h], (e + 1) % 3)] : nbn[h][e];
+          nbo[e] = bit(Rlo, Rhi, m) ? S.byFirst[p8(pl[h], (e + 1) % 3)] : nbn[h][e];
         }
         S.cpl[ns] = pl[h];
         S.cnb[ns] = pack3(nbo[0], nbo[1], nbo[2]);
@@ -332,13 +339,23 @@ __device__ int clip_poly(WaveLds &S, int P, int pt, int &nc, int ps = -1, int kc
   return 4;
 }
 
+template <bool MON>
+__device__ __forceinline__ int clip_poly(WaveLds &S, int P, int pt, int &nc, int ps = -1, int kcert = -1) {
+  return nc <= 64 ? clip_poly_w<MON, false>(S, P, pt, nc, ps, kcert) : clip_poly_w<MON, true>(S, P, pt, nc, ps, kcert);
+}
+
 __device__ __forceinline__ void state_masks(const WaveLds &S, int nc, uint64_t &tlo, uint64_t &thi,
                                             uint64_t &ilo, uint64_t &ihi) {
   const int l = vd_lane();
   const int a = l < nc ? S.cst[l] : 0;
-  const int b = l + 64 < nc ? S.cst[l + 64] : 0;
-  tlo = __ballot(a & 2); thi = __ballot(b & 2);
-  ilo = __ballot(a & 1); ihi = __ballot(b & 1);
+  tlo = __ballot(a & 2);
+  ilo = __ballot(a & 1);
+  thi = ihi = 0ull;
+  if (nc > 64) {  // the second corner slot of each lane is in use
+    const int b = l + 64 < nc ? S.cst[l + 64] : 0;
+    thi = __ballot(b & 2);
+    ihi = __ballot(b & 1);
+  }
 }
 
 // Alg. 1 / Alg. 3 on the polytope in LDS until every corner is certified inside
