@@ -72,7 +72,10 @@ struct __align__(16) WaveLds {
   unsigned char byFirst[VD_P_MAX], bySecond[VD_P_MAX];
   int tq[VD_Q_MAX];          // tetrahedra of this site, breadth-first
   int nbl[VD_NB_MAX];        // neighbours found so far (sorted positions)
-  int pfirst[VD_P_MAX];      // lowest corner slot on each plane (face walks)
+  union {
+    int pfirst[VD_P_MAX];    // lowest corner slot on each plane (face walks, after a carve)
+    int psl[VD_P_MAX];       // site cache slot of each bisector plane's site, or -1 (during a carve)
+  };
   WaveArena ar;              // output chunks, queue position, statistics
   union {
     SiteCache K;             // sites around v_i for the nearest-site queries (carve)
@@ -131,9 +134,9 @@ __device__ int compact_planes(WaveLds &S, int npl, int nc) {
   used = wave_or64(used);
   const int newnpl = __popcll(used);
   double pv[4] = {0, 0, 0, 0};
-  int lab = 0;
+  int lab = 0, sl = -1;
   const bool mine = l < npl && ((used >> l) & 1ull);
-  if (mine) { for (int k = 0; k < 4; k++) pv[k] = S.pn[l][k]; lab = S.plab[l]; }
+  if (mine) { for (int k = 0; k < 4; k++) pv[k] = S.pn[l][k]; lab = S.plab[l]; sl = S.psl[l]; }
   int cp[2] = {0, 0};
   for (int h = 0; h < 2; h++) {
     const int s = l + 64 * h;
@@ -144,6 +147,7 @@ __device__ int compact_planes(WaveLds &S, int npl, int nc) {
     const int ni = __popcll(used & low_mask(l));
     for (int k = 0; k < 4; k++) S.pn[ni][k] = pv[k];
     S.plab[ni] = lab;
+    S.psl[ni] = sl;
   }
   for (int h = 0; h < 2; h++) {
     const int s = l + 64 * h;
@@ -387,13 +391,19 @@ __device__ int carve(WaveLds &S, const GridView &G, const CarveParams C, const S
   int ps_edge = -1;   // inside end of the search edge when it is an edge of P
   bool qon = false;   // the search point lies strictly inside its edge
   int tslot = -1, nbatch = 0;
+  int jsl = -1, efs0 = -1, efs1 = -1;  // cache slots of j and of the edge's sites (-1: none)
   double A0 = 0, A1 = 0, A2 = 0, g0 = 0, g1 = 0, g2 = 0, u0 = 0, u1 = 0, u2 = 0, L = 0;
   double n0 = 0, n1 = 0, n2 = 0, nc3 = 0;
   double q0 = 0, q1 = 0, q2 = 0;  // query point relative to v_i (per group for TEST)
   double A4 = 0, g4 = 0, q4 = 0;   // POW: 4th coordinates of the edge ends and of the query
   // crossing of [A, g] with B_ij (j = current candidate)
   auto bisector_point = [&]() {
-    n0 = GL(G.sx)[j] - X.vx; n1 = GL(G.sy)[j] - X.vy; n2 = GL(G.sz)[j] - X.vz;
+    // the site's coordinates from the LDS cache when it holds them (exact copies)
+    if (jsl >= 0) {
+      n0 = S.K.x[jsl] - X.vx; n1 = S.K.y[jsl] - X.vy; n2 = S.K.z[jsl] - X.vz;
+    } else {
+      n0 = GL(G.sx)[j] - X.vx; n1 = GL(G.sy)[j] - X.vy; n2 = GL(G.sz)[j] - X.vz;
+    }
     const double e0 = g0 - A0, e1 = g1 - A1, e2 = g2 - A2;
     double den, num;
     if (POW) {
@@ -470,8 +480,10 @@ __device__ int carve(WaveLds &S, const GridView &G, const CarveParams C, const S
         g0 = S.cy[pt][0]; g1 = S.cy[pt][1]; g2 = S.cy[pt][2];
         j = uni((S.cst[pt] >> 8) - 1);
         if (j < 0 || j == X.si) return 3;
+        jsl = POW ? -1 : cache_slot(S.K, j);
         // flags of a point on the edge p_s p_t: the two planes through the edge
         ef0 = ef1 = -2;
+        efs0 = efs1 = -1;
         if (ps >= 0) {
           const int a0 = uni(S.cpl[ps]), b0 = uni(S.cpl[pt]);
           int ne = 0;
@@ -479,11 +491,13 @@ __device__ int carve(WaveLds &S, const GridView &G, const CarveParams C, const S
             const int px = p8(a0, x);
             if (px == p8(b0, 0) || px == p8(b0, 1) || px == p8(b0, 2)) {
               const int lab = S.plab[px];
-              if (ne == 0) ef0 = lab >= 0 ? lab : -2; else ef1 = lab >= 0 ? lab : -2;
+              if (ne == 0) { ef0 = lab >= 0 ? lab : -2; efs0 = lab >= 0 ? S.psl[px] : -1; }
+              else { ef1 = lab >= 0 ? lab : -2; efs1 = lab >= 0 ? S.psl[px] : -1; }
               ne++;
             }
           }
           ef0 = uni(ef0); ef1 = uni(ef1);
+          efs0 = uni(efs0); efs1 = uni(efs1);
         }
         nstep = 0;
         const double d0 = g0 - A0, d1 = g1 - A1, d2 = g2 - A2;
@@ -514,9 +528,11 @@ __device__ int carve(WaveLds &S, const GridView &G, const CarveParams C, const S
     // sites the test treats like v_i: flags of the corner's planes (TEST), the
     // candidate and the search edge's planes (SEARCH), the edge's planes (LAMBDA)
     int e0 = ef0, e1 = ef1, e2 = mode == SEARCH ? j : -1;
+    int es0 = efs0, es1 = efs1, es2 = mode == SEARCH ? jsl : -1;
     if (mode == TEST) {
       const int tpl = S.cpl[tslot >= 0 ? tslot : 0];
       e0 = S.plab[p8(tpl, 0)]; e1 = S.plab[p8(tpl, 1)]; e2 = S.plab[p8(tpl, 2)];
+      es0 = S.psl[p8(tpl, 0)]; es1 = S.psl[p8(tpl, 1)]; es2 = S.psl[p8(tpl, 2)];
     }
     bool on_grid;
     if (MON) count_add(S.ar.rounds, 1);
@@ -528,7 +544,7 @@ __device__ int carve(WaveLds &S, const GridView &G, const CarveParams C, const S
       on_grid = true;
     } else {
       kq = nn_cached(S.K, G, gs, qx, qy, qz, dx * dx + dy * dy + dz * dz, X.si, e0 < 0 ? -1 : e0, e1 < 0 ? -1 : e1,
-                     e2 < 0 ? -1 : e2, st.cands, on_grid);
+                     e2 < 0 ? -1 : e2, e0 < 0 ? -1 : es0, e1 < 0 ? -1 : es1, e2 < 0 ? -1 : es2, st.cands, on_grid);
     }
     if (mode == TEST) {
       st.queries += nbatch;
@@ -550,6 +566,7 @@ __device__ int carve(WaveLds &S, const GridView &G, const CarveParams C, const S
       if (hit) {
         const int src = __ffsll((unsigned long long)hit) - 1;  // lowest group found outside
         j = __builtin_amdgcn_readlane(kq, src);
+        jsl = POW ? -1 : cache_slot(S.K, j);
         g0 = readlane_d(q0, src); g1 = readlane_d(q1, src); g2 = readlane_d(q2, src);
       } else {
         lam += 4;
@@ -566,6 +583,7 @@ __device__ int carve(WaveLds &S, const GridView &G, const CarveParams C, const S
     if (!(k == X.si || k == j || k == ef0 || k == ef1)) {
       if (++nstep >= C.max_iters) return 3;
       j = k;
+      jsl = POW ? -1 : cache_slot(S.K, j);
       g0 = q0; g1 = q1; g2 = q2;
       g4 = q4;
       bisector_point();
@@ -581,6 +599,7 @@ __device__ int carve(WaveLds &S, const GridView &G, const CarveParams C, const S
     if (l == 0) {
       S.pn[P][0] = n0; S.pn[P][1] = n1; S.pn[P][2] = n2; S.pn[P][3] = nc3;
       S.plab[P] = j;
+      S.psl[P] = jsl;
     }
     __syncthreads();
     const int rc = clip_poly<MON>(S, P, pt, nc, ps_edge >= 0 && qon ? ps_edge : -1, k);
@@ -625,6 +644,7 @@ __device__ void init_tet(WaveLds &S, const DomainView &D, const SiteCtx &X, int 
     tet_plane(D, X, a, l, pl, lab);
     S.pn[l][0] = pl[0]; S.pn[l][1] = pl[1]; S.pn[l][2] = pl[2]; S.pn[l][3] = pl[3];
     S.plab[l] = lab;
+    S.psl[l] = -1;
     // corner l = vertex l: planes counter-clockwise from outside
     // {1,3,2},{0,2,3},{0,3,1},{0,1,2}; neighbours {2,1,3},{3,0,2},{1,0,3},{2,0,1}
     S.cpl[l] = l == 0 ? pack3(1, 3, 2) : (l == 1 ? pack3(0, 2, 3) : (l == 2 ? pack3(0, 3, 1) : pack3(0, 1, 2)));
@@ -687,6 +707,7 @@ __device__ void restore_cell(WaveLds &S, const CellsDev &C, int npl, int nc, con
     for (int k = 0; k < 4; k++) S.pn[l][k] = pl[k];
     S.plab[l] = lab;
   }
+  if (l < npl + 4) S.psl[l] = -1;  // a restored cell is only cut, never queried
   for (int s = l; s < nc; s += 64) {
     S.cpl[s] = B.cpl[s];
     S.cnb[s] = B.cnb[s];
@@ -732,6 +753,7 @@ __device__ void restore_cell_lds(WaveLds &S, int npl, int nc, const DomainView &
     for (int k = 0; k < 4; k++) S.pn[l][k] = pl[k];
     S.plab[l] = lab;
   }
+  if (l < npl + 4) S.psl[l] = -1;  // a restored cell is only cut, never queried
   if (l < nc) {
     S.cpl[l] = S.LC.cpl[l];
     S.cnb[l] = S.LC.cnb[l];
@@ -754,6 +776,7 @@ __device__ void init_box(WaveLds &S, const SiteCtx &X, const double *lo, const d
     S.pn[l][2] = ax == 2 ? (side ? 1.0 : -1.0) : 0.0;
     S.pn[l][3] = side ? hiv - vc : vc - lov;
     S.plab[l] = kBoxBase + l;
+    S.psl[l] = -1;
   }
   if (l < 8) {
     // planes / neighbours of corner l, 4 bits per entry (12 bits per corner)

@@ -617,9 +617,35 @@ __device__ __forceinline__ double sq_dist(const GridView &G, int e, double qx, d
   return dx * dx + dy * dy + dz * dz;
 }
 
+// Squared distance from q to site e, from its cache slot `slot` when it has
+// one (the cache holds exact copies of the coordinates, so both give the same
+// value), else from the grid's arrays.
+__device__ __forceinline__ double sq_dist_at(const SiteCache &K, const GridView &G, int e, int slot, double qx,
+                                             double qy, double qz) {
+  if (slot >= 0) {
+    const double dx = qx - K.x[slot], dy = qy - K.y[slot], dz = qz - K.z[slot];
+    return dx * dx + dy * dy + dz * dz;
+  }
+  return sq_dist(G, e, qx, qy, qz);
+}
+
+// Cache slot of site k (sorted position), or -1: the whole wave compares the
+// held positions (at most VD_CACHE, two per lane).
+__device__ __forceinline__ int cache_slot(const SiteCache &K, int k) {
+  const int n = K.cnt, l = vd_lane();
+  if (n <= 0 || k < 0) return -1;
+  const bool a = l < n && K.p[l] == k;
+  const bool b = l + 64 < n && K.p[l + 64] == k;
+  const uint64_t ma = __ballot(a), mb = __ballot(b);
+  if (ma) return __ffsll((unsigned long long)ma) - 1;
+  if (mb) return 64 + __ffsll((unsigned long long)mb) - 1;
+  return -1;
+}
+
+// es0..es2: the cache slots of e0..e2 (-1: not cached, or no such site).
 __device__ __forceinline__ int nn_cached(const SiteCache &K, const GridView &G, int gs, double qx, double qy,
-                                         double qz, double r2, int k0, int e0, int e1, int e2, long long &ncand,
-                                         bool &on_grid) {
+                                         double qz, double r2, int k0, int e0, int e1, int e2, int es0, int es1,
+                                         int es2, long long &ncand, bool &on_grid) {
   const int n = K.cnt;
   on_grid = false;
   if (n >= 0) {
@@ -627,9 +653,9 @@ __device__ __forceinline__ int nn_cached(const SiteCache &K, const GridView &G, 
     const double wx = qx - K.vx, wy = qy - K.vy, wz = qz - K.vz;
     const double dq = sqrt(wx * wx + wy * wy + wz * wz);
     double wit = r2;
-    if (e0 >= 0) wit = fmin(wit, sq_dist(G, e0, qx, qy, qz));
-    if (e1 >= 0) wit = fmin(wit, sq_dist(G, e1, qx, qy, qz));
-    if (e2 >= 0) wit = fmin(wit, sq_dist(G, e2, qx, qy, qz));
+    if (e0 >= 0) wit = fmin(wit, sq_dist_at(K, G, e0, es0, qx, qy, qz));
+    if (e1 >= 0) wit = fmin(wit, sq_dist_at(K, G, e1, es1, qx, qy, qz));
+    if (e2 >= 0) wit = fmin(wit, sq_dist_at(K, G, e2, es2, qx, qy, qz));
     double bd = r2;
     int bk = k0;
     for (int base = 0; base < n; base += gs) {
