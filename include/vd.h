@@ -111,7 +111,7 @@ typedef struct {
   int32_t monitor;            /* 1: count the clips' work (query rounds, corners classified and
                                  created, wasted tests, fan simplices) and track the relative
                                  margins of the corner classifications (vd_cells_info_t).
-                                 Default 0: those counters cost about 8 % of the 3D kernel's time
+                                 Default 0: those counters cost about 6 % of the 3D kernel's time
                                  and read -1. */
   int32_t use_density;        /* 1: every moment is weighted by the density rho of Eq. 3 given in
                                  density[] (mass = integral of rho, centroid = integral of rho x
@@ -122,6 +122,16 @@ typedef struct {
   double density[10];         /* rho(x) = d0 + d1 x + d2 y + d3 z + d4 x^2 + d5 x y + d6 x z
                                  + d7 y^2 + d8 y z + d9 z^2 (absolute coordinates); it should be
                                  positive on M */
+  int32_t whole_interior;     /* tetrahedral domains, carve_mode 1, synchronous clips.  1: Alg. 5's
+                                 split of boundary and interior sites -- the restricted diagram
+                                 of the boundary surface is computed first; a cell that meets no
+                                 boundary triangle lies entirely inside M (its site, or for a
+                                 power cell a point of it, is in M) and is returned as ONE piece
+                                 with simplex -1: the whole cell, not cut by the tetrahedra (its
+                                 moments, faces, vertices and neighbours are the cell's).  Cells
+                                 that meet the boundary are cut per tetrahedron as usual.  Per-site
+                                 moments and neighbour lists equal those of the default up to
+                                 rounding.  Default 0: every piece is T_a cap Omega_i. */
 } vd_options;
 
 void vd_options_default(vd_options *opt);
@@ -262,6 +272,8 @@ vd_status vd_domain_create_batch(const double *verts, const int32_t *simplices,
  * surface is computed first and every boundary triangle a cell meets seeds the
  * tetrahedron behind it (Alg. 5), so cells that meet M in several parts, and
  * sites outside M, get all their pieces; a site whose cell misses M gets none.
+ * With vd_options.whole_interior = 1 the boundary diagram is always computed
+ * and a cell that meets no boundary triangle is one piece (simplex -1).
  * Surface (triangles): one wavefront per triangle; the triangle's sites are
  * found by propagation over positive edge flags from the site nearest to the
  * triangle's centroid (Alg. 4), each piece carved by Alg. 3.
@@ -271,7 +283,8 @@ vd_status vd_domain_create_batch(const double *verts, const int32_t *simplices,
  * Synchronises `stream` once to read the output sizes (and re-runs with
  * larger arenas if an output arena overflowed).
  * Errors: VD_ERR_INVALID_ARG (3D: a site outside every tetrahedron while the
- * clip does not seed from the boundary: boundary_seeds = 0, or no_sync),
+ * clip does not seed from the boundary: boundary_seeds = 0, or no_sync;
+ * whole_interior with a surface, carve_mode 0, boundary_seeds = 0 or no_sync),
  * VD_ERR_CAPACITY, VD_ERR_DEGENERATE, VD_ERR_OUT_OF_MEMORY, VD_ERR_HIP.
  * --------------------------------------------------------------------- */
 vd_status vd_clip_cells(vd_grid g, vd_domain d, const vd_options *opt, void *stream,

@@ -123,6 +123,7 @@ void vd_options_default(vd_options *opt) {
   opt->boundary_seeds = -1;
   opt->monitor = 0;
   opt->use_density = 0;
+  opt->whole_interior = 0;
   for (int k = 0; k < 10; k++) opt->density[k] = k == 0 ? 1.0 : 0.0;
 }
 
@@ -737,6 +738,14 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
       opt.boundary_seeds = 1;
     }
   }
+  if (opt.whole_interior) {
+    // Alg. 5's interior / boundary split needs the boundary diagram and the
+    // cell-first carve
+    if (dom->dim != 3 || opt.carve_mode != 1 || opt.boundary_seeds == 0 || opt.no_sync)
+      return fail(VD_ERR_INVALID_ARG, "vd_clip_cells: whole_interior needs a tetrahedral domain, carve_mode 1, "
+                                      "boundary seeds and a synchronous clip");
+    opt.boundary_seeds = 1;
+  }
   hipStream_t st = as_stream(stream);
   vd_cells c = *out ? *out : new vd_cells_s();
   const int64_t n = g->n;
@@ -784,6 +793,7 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
     d.monitor = opt.monitor ? 1 : 0;
     d.density = opt.use_density ? 1 : 0;
     d.power = g->power ? 1 : 0;
+    d.whole = opt.whole_interior ? 1 : 0;
     for (int k = 0; k < 10; k++) d.dens[k] = opt.use_density ? opt.density[k] : (k == 0 ? 1.0 : 0.0);
     // persistent 3D kernel: each wave reserves output chunks of about 1/8 of an
     // arena's share per wave, so unused chunk tails stay within 1/8 of it

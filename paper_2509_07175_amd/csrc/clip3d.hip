@@ -1020,12 +1020,14 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
     nt = 1;
   }
   __syncthreads();
+  long long nbseed = 0;  // boundary triangles the cell meets (when computed)
   if (C.bseed_off) {
     // Alg. 5: every boundary triangle the cell meets seeds the tetrahedron
     // behind it, which reaches the parts of Omega_i cap M that are not
     // connected to the site's own tetrahedron (or all of them, for a site
     // outside M)
     const long long q0 = GL(C.bseed_off)[orig], q1 = GL(C.bseed_off)[orig + 1];
+    nbseed = q1 - q0;
     for (long long q = q0; q < q1; q++) {
       const int t = GL(C.btet)[GL(C.bseed_tri)[GL(C.bseed_pid)[q]]];
       if (!tq_push(S, C, nt, t)) { err = 2; where = VD_STAGE_SIMPLICES; break; }
@@ -1077,31 +1079,48 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
         if (rc == 1 || rc == 3) { err = 3; where = VD_STAGE_CELL; continue; }  // the site lies in the box
         if (rc == 2) continue;                           // too large: carve per simplex
         npl = compact_planes(S, npl, nc);
-        if (npl <= VD_F_MAX && npl + 4 <= VD_P_MAX && nc <= VD_CB_MAX) {
-          saved_lds = npl <= kLF && nc <= kLC;
-          if (saved_lds) save_cell_lds(S, npl, nc);
-          else save_cell(S, C, npl, nc);
-          npl0 = npl;
-          nc0 = nc;
-          saved = true;
-          {
-            const uint64_t cp = __ballot(l < npl && S.plab[l] >= 0);
-            if (l == 0) S.cellpos = cp;
-          }
-          cell_lab = l < npl ? S.plab[l] : 0;
+        if (C.whole && nbseed == 0) {
+          // Alg. 5's interior sites: a cell that meets no boundary triangle
+          // lies inside M or outside it as a whole (it contains v_i, which is
+          // in M; a power cell is judged by the mean of its corners), and is
+          // then one piece, cut by no tetrahedron
+          bool inside = true;
           if (POW) {
-            // a power cell need not contain its site: seed the tetrahedron
-            // holding the mean of the cell's corners (a point of the cell);
-            // parts of the cell that reach the boundary of M are seeded from
-            // the boundary surface
             double c0 = 0, c1 = 0, c2 = 0;
             for (int x = l; x < nc; x += 64) { c0 += S.cy[x][0]; c1 += S.cy[x][1]; c2 += S.cy[x][2]; }
             c0 = wave_sum(c0) / nc; c1 = wave_sum(c1) / nc; c2 = wave_sum(c2) / nc;
-            const int t = locate_wave(D, X.vx + c0, X.vy + c1, X.vz + c2);
-            if (t >= 0 && !tq_push(S, C, nt, t)) { err = 2; where = VD_STAGE_SIMPLICES; }
+            inside = locate_wave(D, X.vx + c0, X.vy + c1, X.vz + c2) >= 0;
           }
+          head = nt;  // no tetrahedron to visit
+          if (!inside) continue;
+          // fall through: the moments and the emission of the piece (a = -1)
+        } else {
+          if (npl <= VD_F_MAX && npl + 4 <= VD_P_MAX && nc <= VD_CB_MAX) {
+            saved_lds = npl <= kLF && nc <= kLC;
+            if (saved_lds) save_cell_lds(S, npl, nc);
+            else save_cell(S, C, npl, nc);
+            npl0 = npl;
+            nc0 = nc;
+            saved = true;
+            {
+              const uint64_t cp = __ballot(l < npl && S.plab[l] >= 0);
+              if (l == 0) S.cellpos = cp;
+            }
+            cell_lab = l < npl ? S.plab[l] : 0;
+            if (POW) {
+              // a power cell need not contain its site: seed the tetrahedron
+              // holding the mean of the cell's corners (a point of the cell);
+              // parts of the cell that reach the boundary of M are seeded from
+              // the boundary surface
+              double c0 = 0, c1 = 0, c2 = 0;
+              for (int x = l; x < nc; x += 64) { c0 += S.cy[x][0]; c1 += S.cy[x][1]; c2 += S.cy[x][2]; }
+              c0 = wave_sum(c0) / nc; c1 = wave_sum(c1) / nc; c2 = wave_sum(c2) / nc;
+              const int t = locate_wave(D, X.vx + c0, X.vy + c1, X.vz + c2);
+              if (t >= 0 && !tq_push(S, C, nt, t)) { err = 2; where = VD_STAGE_SIMPLICES; }
+            }
+          }
+          continue;
         }
-        continue;
       }
       if (rc == 1) empty = true;
       else if (rc) { err = rc; where = VD_STAGE_PIECE_CARVE; }
@@ -1224,7 +1243,7 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
       const int lab = uni(S.plab[x]);
       if (lab >= 0) {
         if (!nb_push(S, C, nnb, lab)) { err = 2; where = VD_STAGE_NEIGHBOURS; break; }
-      } else if (lab > VD_BND_BASE + 3) {
+      } else if (a >= 0 && lab > VD_BND_BASE + 3) {  // a whole cell (a = -1) has no tetrahedron planes
         if (!tq_push(S, C, nt, -lab - 1)) { err = 2; where = VD_STAGE_SIMPLICES; break; }
       }
     }
@@ -1276,8 +1295,9 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
 
 // Persistent: every workgroup (one wave) takes sites from the queues until
 // all are done.  Three waves per SIMD: 168 VGPRs (a few values spill around
-// the carve) and 12.7 KB of LDS per wave (the carved cell is kept in a global
-// buffer); the third wave hides more LDS and memory latency than that costs.
+// the carve) and 12.8 KB of LDS per wave (the carved cell is kept over the
+// site cache when it fits, else in a global buffer); the third wave hides
+// more LDS and memory latency than that costs.
 // MON: the work counters and margin tracking of vd_options.monitor; DENS: the
 // density-weighted moments of vd_options.use_density.  Each is compiled in only
 // for the instances that use it, so the default instance carries neither.

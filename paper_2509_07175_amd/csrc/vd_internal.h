@@ -180,6 +180,7 @@ struct CellsDev {
   int monitor;     // count work and track predicate margins
   int density;     // weight the moments by the quadratic density dens[] (Eq. 3)
   int power;       // power diagram: the grid's weights (Sec. 7.3)
+  int whole;       // a cell that meets no boundary triangle is one piece (needs bseed_off)
   double dens[10]; // rho(x) = c0 + c1 x + c2 y + c3 z + c4 x^2 + c5 xy + c6 xz + c7 y^2 + c8 yz + c9 z^2
   unsigned long long *cnt;  // CNT_N counters
   // per site (caller index)
