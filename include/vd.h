@@ -62,7 +62,8 @@ enum {
   VD_STAGE_PIECE_CARVE = 3, /* carving a piece from its simplex */
   VD_STAGE_NEIGHBOURS = 4,  /* more distinct neighbours than a wave holds */
   VD_STAGE_SIMPLICES = 5,   /* more simplices in one cell than a wave holds */
-  VD_STAGE_TRIANGLE = 6     /* surface: carving the pieces of a triangle */
+  VD_STAGE_TRIANGLE = 6,    /* surface: carving the pieces of a triangle */
+  VD_STAGE_TRIANGLE_SITES = 7 /* surface: more sites in one triangle than a wave holds */
 };
 
 /* Tuning and behaviour knobs; vd_options_default() fills the defaults. */

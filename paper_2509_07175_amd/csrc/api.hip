@@ -813,6 +813,15 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
       d.q_spill = c->q_spill_want;
       d.nbs_cap = c->nb_spill_want;
     }
+    if (dom->dim == 2) {
+      // surface: a triangle's site list beyond its LDS part (none until a
+      // triangle needs it; grown on retry)
+      const int64_t need = (int64_t)wg * c->sq_spill_want;
+      if (need > 0 && (c->sq_spill_elems < need || d.sq_cap != c->sq_spill_want)) {
+        HIP_TRY(ensure(d.sq_spill, c->sq_spill_elems, need));
+      }
+      d.sq_cap = need > 0 ? c->sq_spill_want : 0;
+    }
     {
       const int64_t caps[AR_N] = {d.cap_piece, d.cap_face, d.cap_vert, d.cap_nbr, d.cap_fint};
       for (int r = 0; r < AR_N; r++)
@@ -931,6 +940,17 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
       }
       if (regrow) continue;
     }
+    if (dom->dim == 2 && hc[CNT_ERR_CAP] && !hc[CNT_ERR_DEG] &&
+        hc[CNT_STAGES] == (1ull << VD_STAGE_TRIANGLE_SITES)) {
+      // a triangle meets more cells than its wave's site list holds: grow the
+      // overflow (within about 4 GB) and run again
+      const int64_t wmax = (int64_t)(1ll << 30) / std::max<int64_t>(wg, 1);
+      const int64_t nw = std::min<int64_t>({std::max<int64_t>(4096, (int64_t)c->sq_spill_want * 4), n, wmax});
+      if (nw > c->sq_spill_want) {
+        c->sq_spill_want = (int)nw;
+        continue;
+      }
+    }
     {
       const vd_status r = check_counts(c, false);
       if (r != VD_OK) {
@@ -968,7 +988,7 @@ void vd_cells_free(vd_cells c) {
   if (c->ev2) hipEventDestroy(c->ev2);
   hipFree(c->d_dev); hipFree(d.queue); hipFree(d.tq_spill); hipFree(d.saved);
   hipFree(c->outside);
-  hipFree(d.nb_spill);
+  hipFree(d.nb_spill); hipFree(d.sq_spill);
   vd_cells_free(c->bcells);
   if (c->host_cnt) hipHostFree(c->host_cnt);
   hipFree(d.fint_lab); hipFree(d.piece_fint_start); hipFree(d.piece_nfint); hipFree(c->wbuf);

@@ -22,7 +22,7 @@ namespace {
 
 constexpr int kSP = 64;        // planes of one polygon
 constexpr int kSV = 64;        // vertices of one polygon (one per lane)
-constexpr int kSS = 128;       // sites of one triangle
+constexpr int kSS = 128;       // sites of one triangle held in LDS (more spill to global memory)
 constexpr int kMaxIters = 4096;
 
 struct __align__(16) TriLds {
@@ -31,7 +31,7 @@ struct __align__(16) TriLds {
   int plab[kSP];
   int ve[kSV];        // plane slot of the edge from vertex t to vertex t+1
   int vst[kSV];       // bit 0 inside, bit 1 tested, bits 8.. nearest site + 1
-  int sq[kSS];        // sites of this triangle (sorted positions), breadth-first
+  int sq[kSS];        // first sites of this triangle (sorted positions), breadth-first
   WaveArena ar;       // output chunks, queue position, statistics
 };
 
@@ -345,6 +345,33 @@ __device__ int carve_s(TriLds &S, const GridView &G, const SParams C, int si, do
 
 __device__ __forceinline__ int conv(const GridView &G, int lab) { return lab >= 0 ? GL(G.perm)[lab] : lab; }
 
+// The triangle's site list: entries below kSS in LDS, the rest in this wave's
+// part of the global overflow buffer (C.sq_cap entries; a clip that runs out
+// reports VD_STAGE_TRIANGLE_SITES and is re-run with a larger buffer).
+__device__ __forceinline__ int sq_get(const TriLds &S, const CellsDev &C, int e) {
+  return e < kSS ? S.sq[e] : GL(C.sq_spill)[(long long)blockIdx.x * C.sq_cap + (e - kSS)];
+}
+
+// Is site j in the list?  (The whole wave scans; the answer is wave-uniform.)
+__device__ __forceinline__ bool sq_has(const TriLds &S, const CellsDev &C, int nsq, int j) {
+  bool have = false;
+  for (int e = vd_lane(); e < nsq; e += 64) have = have || (sq_get(S, C, e) == j);
+  return __ballot(have) != 0ull;
+}
+
+// Append site j; false when the overflow buffer is full.
+__device__ __forceinline__ bool sq_push(TriLds &S, const CellsDev &C, int &nsq, int j) {
+  if (nsq >= kSS + C.sq_cap) return false;
+  __syncthreads();
+  if (vd_lane() == 0) {
+    if (nsq < kSS) S.sq[nsq] = j;
+    else GL(C.sq_spill)[(long long)blockIdx.x * C.sq_cap + (nsq - kSS)] = j;
+  }
+  nsq++;
+  __syncthreads();
+  return true;
+}
+
 template <bool DENS, bool POW>
 __device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, const CellsDev &C, int a) {
   const int l = vd_lane();
@@ -369,8 +396,10 @@ __device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, c
     }
   }
   __syncthreads();
+  int where = VD_STAGE_TRIANGLE;
   while (head < nsq && !err) {
-    const int si = S.sq[head++];
+    const int si = uni(sq_get(S, C, head));
+    head++;
     const double vx = GL(G.sx)[si], vy = GL(G.sy)[si], vz = GL(G.sz)[si], delta = GL(G.delta)[si];
     init_tri(S, D, a, vx, vy, vz);
     int npl = 4, nv = 3;
@@ -507,14 +536,10 @@ __device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, c
     for (; pos; pos &= pos - 1) {
       const int t = __ffsll((unsigned long long)pos) - 1;
       const int j = __builtin_amdgcn_readlane(lab, t);
-      bool have = false;
-      for (int e = l; e < nsq; e += 64) have = have || (S.sq[e] == j);
-      if (!__ballot(have)) {
-        if (nsq >= kSS) { err = 2; break; }
-        __syncthreads();
-        if (l == 0) S.sq[nsq] = j;
-        nsq++;
-        __syncthreads();
+      if (!sq_has(S, C, nsq, j) && !sq_push(S, C, nsq, j)) {
+        err = 2;
+        where = VD_STAGE_TRIANGLE_SITES;
+        break;
       }
     }
     __syncthreads();
@@ -526,7 +551,7 @@ __device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, c
     if (err) {
       atomicAdd(&C.cnt[err == 2 ? CNT_ERR_CAP : CNT_ERR_DEG], 1ull);
       atomicMin((int *)&C.cnt[CNT_BAD_SITE], a);
-      atomicOr((unsigned long long *)&C.cnt[CNT_STAGES], 1ull << VD_STAGE_TRIANGLE);
+      atomicOr((unsigned long long *)&C.cnt[CNT_STAGES], 1ull << where);
     }
   }
   __syncthreads();

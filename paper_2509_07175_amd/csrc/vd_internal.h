@@ -212,6 +212,8 @@ struct CellsDev {
   int *tq_spill;          // [workgroups * q_spill] overflow of the per-site simplex queue
   int *nb_spill;          // [workgroups * nbs_cap] overflow of the per-site neighbour list
   int q_spill, nbs_cap;   // entries per workgroup of the two overflow buffers
+  int *sq_spill;          // [workgroups * sq_cap] surface: overflow of a triangle's site list
+  int sq_cap;             // entries per workgroup of sq_spill (0: none yet)
   double *saved;          // [workgroups * VD_SAVE_DOUBLES] each wave's carved cell (cell-first mode)
 };
 
@@ -239,6 +241,8 @@ struct vd_cells_s {
   CellsDev *d_dev = nullptr;  // device copy of d (read by the piece kernel)
   int64_t cap_spill = 0;      // workgroups covered by d.tq_spill / d.nb_spill / d.saved
   int q_spill_want = VD_Q_SPILL, nb_spill_want = VD_NB_SPILL;  // per-workgroup sizes (grow on retry)
+  int64_t sq_spill_elems = 0;  // allocated entries of d.sq_spill
+  int sq_spill_want = 0;       // surface: per-workgroup entries of d.sq_spill (grow on retry)
   CellsDev d_shadow{};        // host copy last sent to d_dev
   double *wbuf = nullptr;     // adjoint weights [5n]
   int64_t cap_w = 0;

@@ -124,3 +124,33 @@ def test_c5_full_size_sampled(oracle_mod):
     ref = oracle_mod.compute(s, dom, only_sites=sample)
     mom = oracle_mod.site_moments(ref, s)
     assert_sampled_parity(sampled_result(view, sample), mass, cent, en, nbo, nb, ref, mom, sample)
+
+
+@pytest.mark.parametrize("k,n", [(2, 3000), (4, 6000)])
+def test_triangles_meeting_many_cells(oracle_mod, k, n):
+    """Coarse flat L meshes (6 and 24 triangles) under 3,000 and 6,000 sites:
+    a triangle meets hundreds of cells, more than a wave keeps in LDS, so its
+    site list continues in the grown global overflow buffer."""
+    dom = vdgen.planar_l_polygon(k)
+    s = vdgen.planar_l_sites(n, seed=40 + k)
+    gpu = _surface_case(oracle_mod, s, dom, brute=False)
+    per_tri = np.bincount(gpu["res"]["piece_simplex"], minlength=dom.m)
+    log(f"cells per triangle: max {per_tri.max()}, min {per_tri.min()}")
+    assert per_tri.max() > 128
+
+
+def test_boundary_diagram_of_a_coarse_cube():
+    """The unit cube as 6 tetrahedra (12 boundary triangles) under 5,000
+    sites: each boundary triangle meets a few hundred cells, so the boundary
+    diagram that seeds the clip (and Alg. 5's split) needs the grown site
+    lists; results equal the plain clip's."""
+    s, dom = vdgen.small_case(5000, 1, seed=44)
+    plain = run_gpu(s, dom)
+    seeded = run_gpu(s, dom, boundary_seeds=1)
+    whole = run_gpu(s, dom, whole_interior=1)
+    assert seeded["info"]["boundary_seeded"] == 1
+    for r in (seeded, whole):
+        assert np.all(np.abs(r["mass"] - plain["mass"]) <= 1e-12 * plain["mass"])
+        assert np.array_equal(r["nbr_off"], plain["nbr_off"]) and np.array_equal(r["nbr"], plain["nbr"])
+    assert np.array_equal(seeded["res"]["piece_site"], plain["res"]["piece_site"])
+    assert np.array_equal(seeded["res"]["piece_mass"], plain["res"]["piece_mass"])
