@@ -433,17 +433,20 @@ __device__ int carve(WaveLds &S, const GridView &G, const CarveParams C, const S
         const uint64_t vlo = low_mask(nc < 64 ? nc : 64), vhi = low_mask(nc > 64 ? nc - 64 : 0);
         const uint64_t ulo = vlo & ~tlo, uhi = vhi & ~thi;
         if (!(ulo | uhi)) return 0;
+        // newest corners first (highest slots: the corners of the latest
+        // faces, nearest to v_i): fewer of them are cut away after their test
+        // than of the older, farther ones
         tslot = -1;
         nbatch = 0;
-        uint64_t m = ulo;
-        for (int h = 0; h < 2; h++) {
+        uint64_t m = uhi;
+        for (int h = 1; h >= 0; h--) {
           while (m && nbatch < 4) {
-            const int b = __ffsll((unsigned long long)m) - 1;
+            const int b = 63 - __clzll((long long)m);
             if (nbatch == grp) tslot = b + 64 * h;
             nbatch++;
-            m &= m - 1;
+            m &= ~(1ull << b);
           }
-          m = uhi;
+          m = ulo;
         }
         const int s = tslot >= 0 ? tslot : (ulo ? __ffsll((unsigned long long)ulo) - 1
                                                 : 64 + __ffsll((unsigned long long)uhi) - 1);
