@@ -91,10 +91,11 @@ typedef struct {
                                  give the same pieces. */
   int32_t no_sync;            /* 1: vd_clip_cells only enqueues work (no host synchronisation,
                                  no allocation), so it can be captured into a HIP graph.
-                                 Needs a tetrahedral domain and a handle sized by an earlier
-                                 synchronous clip of the same sites and options; errors and
-                                 arena overflow are reported by vd_cells_info, which then
-                                 synchronises the stream.  Default 0. */
+                                 Needs a handle sized by an earlier synchronous clip of the
+                                 same sites and options (tetrahedra or triangles); errors and
+                                 arena overflow (records that did not fit the sized arenas,
+                                 surface neighbour lists included) are reported by
+                                 vd_cells_info, which then synchronises the stream.  Default 0. */
   int32_t site_cache;         /* 1 (default): each wave keeps the sites of a block of grid
                                  cells around its site in LDS and answers a nearest-site
                                  query there when the query's ball lies inside the block

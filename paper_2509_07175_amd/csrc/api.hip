@@ -715,7 +715,6 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
     return fail(VD_ERR_INVALID_ARG, "vd_clip_cells: the grid holds %d diagram(s), the domain %d", g->nb, dom->nb);
   if (opt_in && opt_in->no_sync) {
     vd_cells c0 = *out;
-    if (dom->dim != 3) return fail(VD_ERR_INVALID_ARG, "vd_clip_cells: no_sync needs a tetrahedral domain");
     if (!c0 || c0->n != g->n || c0->cap_n < g->n || c0->d.cap_piece <= 0 ||
         (opt_in->emit_polytopes && !c0->d.face_label) || (opt_in->want_grad && !c0->d.fint))
       return fail(VD_ERR_INVALID_ARG, "vd_clip_cells: no_sync needs a handle sized by a synchronous clip of the "
@@ -960,9 +959,10 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
     }
     if (dom->dim == 2) {
       // a site's neighbours are distinct flags of its pieces' edges: the
-      // edges written bound the neighbour lists' total
+      // edges written bound the neighbour lists' total (with room for a later
+      // no-sync clip of moved sites, which cannot grow it)
       int64_t t = c->cap_nbr_csr;
-      HIP_TRY(ensure(c->nbr, t, std::max<int64_t>((int64_t)hc[CNT_REAL_FACES], 1)));
+      HIP_TRY(ensure(c->nbr, t, up((int64_t)hc[CNT_REAL_FACES])));
       c->cap_nbr_csr = t;
     }
     vd_launch_finalize(c, st);

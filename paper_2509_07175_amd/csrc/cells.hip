@@ -105,7 +105,7 @@ void vd_launch_finalize(vd_cells c, hipStream_t st) {
   if (c->dim == 2) {
     vd_launch_site_reduce(n, c->piece_off, c->piece_id, c->d_dev, st);
     vdscan::exclusive_scan<int, long long>(d.ncount, n, c->nbr_off, c->scan_tmp, st);
-    vd_launch_site_nbrs(n, c->piece_off, c->piece_id, c->nbr_off, c->nbr, c->d_dev, st);
+    vd_launch_site_nbrs(n, c->piece_off, c->piece_id, c->nbr_off, c->nbr, c->cap_nbr_csr, c->d_dev, st);
     return;
   }
   vdscan::exclusive_scan<int, long long>(d.ncount, n, c->nbr_off, c->scan_tmp, st);

@@ -631,15 +631,22 @@ __global__ void __launch_bounds__(kB) site_reduce(long long n, const long long *
   }
 }
 
+// cap: entries of nbr.  A no-sync clip keeps the size of the synchronous clip
+// before it; lists past the end are not written and the overflow is counted
+// (the clip then reports VD_ERR_CAPACITY).
 __global__ void __launch_bounds__(kB) site_nbrs(long long n, const long long *__restrict__ poff,
                                                 const int *__restrict__ pid, const long long *__restrict__ noff,
-                                                int *__restrict__ nbr, const CellsDev *__restrict__ Cp) {
+                                                int *__restrict__ nbr, long long cap, const CellsDev *__restrict__ Cp) {
   const long long i = (long long)blockIdx.x * kB + threadIdx.x;
   if (i >= n) return;
   int nb[kNbLocal];
   int overflow = 0;
   const int cnt = site_neighbours(*Cp, poff, pid, i, nb, overflow);
   const long long o = noff[i];
+  if (o + cnt > cap) {
+    atomicAdd(&Cp->cnt[CNT_OVERFLOW], 1ull);
+    return;
+  }
   for (int k = 0; k < cnt; k++) nbr[o + k] = nb[k];
 }
 
@@ -680,7 +687,7 @@ void vd_launch_site_reduce(long long n, const long long *poff, const int *pid, c
 }
 
 void vd_launch_site_nbrs(long long n, const long long *poff, const int *pid, const long long *noff, int *nbr,
-                         const CellsDev *Cdev, hipStream_t st) {
+                         long long cap, const CellsDev *Cdev, hipStream_t st) {
   const unsigned nb = (unsigned)((n + kB - 1) / kB > 0 ? (n + kB - 1) / kB : 1);
-  hipLaunchKernelGGL(site_nbrs, dim3(nb), dim3(kB), 0, st, n, poff, pid, noff, nbr, Cdev);
+  hipLaunchKernelGGL(site_nbrs, dim3(nb), dim3(kB), 0, st, n, poff, pid, noff, nbr, cap, Cdev);
 }

@@ -390,7 +390,7 @@ int vd_surface_workgroups(long long m);
 void vd_launch_surface(const GridView &G, const DomainView &D, const CellsDev *Cdev, int workgroups, bool density,
                        bool power, hipStream_t st);
 void vd_launch_site_nbrs(long long n, const long long *poff, const int *pid, const long long *noff, int *nbr,
-                         const CellsDev *Cdev, hipStream_t st);
+                         long long cap, const CellsDev *Cdev, hipStream_t st);
 void vd_launch_site_reduce(long long n, const long long *poff, const int *pid, const CellsDev *Cdev,
                            hipStream_t st);
 void vd_launch_finalize(vd_cells c, hipStream_t st);
