@@ -230,6 +230,8 @@ def bench_batched(steps, warmup, log):
             "plain_sequential_ms": plain_ms, "plain_sequential_cells_per_s": n / (plain_ms * 1e-3),
             "batched_graph_ms": batch_ms, "batched_cells_per_s": n / (batch_ms * 1e-3),
             "speedup_vs_plain": plain_ms / batch_ms, "site_kernel_ms": kernel_ms,
+            "pieces": info["n_pieces"], "pieces_per_site": info["n_pieces"] / n,
+            "site_kernel_pieces_per_s": info["n_pieces"] / (kernel_ms * 1e-3),
             "tuned": dict(best, sites_per_cell=rho), "tuning": [[k, ms] for k, ms in table],
             "max_volume_error": max(abs(v - 1.0) for v in vols)}
 
@@ -461,6 +463,8 @@ def main():
     ap.add_argument("--no-backward", action="store_true", help="skip the adjoint throughput")
     ap.add_argument("--no-peaks", action="store_true", help="skip the measured FMA / copy peaks")
     ap.add_argument("--no-small", action="store_true", help="skip the 1k- and 100k-site cube workloads")
+    ap.add_argument("--lloyd-whole-interior", action="store_true",
+                    help="Lloyd iterations with Alg. 5's interior split (same moments, interior cells not cut)")
     ap.add_argument("--lloyd", type=int, default=0,
                     help="also time this many Lloyd iterations (sites <- centroids) on the workload")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -646,15 +650,17 @@ def main():
         del wg, wc
     if args.lloyd > 0:
         ls = torch.as_tensor(sites, dtype=torch.float64, device=dev).contiguous()
-        vd.lloyd(ls, d, 1, options=vd.Options.default(), bbox=bbox, sites_per_cell=rho)  # sizes the arenas
+        lopt = vd.Options.default(whole_interior=1 if args.lloyd_whole_interior else 0)
+        vd.lloyd(ls, d, 1, options=lopt, bbox=bbox, sites_per_cell=rho)  # sizes the arenas
         ls.copy_(torch.as_tensor(sites, dtype=torch.float64))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, energies = vd.lloyd(ls, d, args.lloyd, options=vd.Options.default(), bbox=bbox, sites_per_cell=rho,
+        _, energies = vd.lloyd(ls, d, args.lloyd, options=lopt, bbox=bbox, sites_per_cell=rho,
                                energy=True)
         torch.cuda.synchronize()
         lt = time.perf_counter() - t0
-        out["lloyd"] = {"iterations": args.lloyd, "s_per_iteration": lt / args.lloyd,
+        out["lloyd"] = {"iterations": args.lloyd, "whole_interior": bool(args.lloyd_whole_interior),
+                        "s_per_iteration": lt / args.lloyd,
                         "cells_per_s": n * args.lloyd / lt, "energy_first": energies[0], "energy_last": energies[-1]}
         log(f"lloyd: {args.lloyd} iterations, {lt / args.lloyd * 1e3:.1f} ms each, energy {energies[0]:.6g} -> "
             f"{energies[-1]:.6g}")
@@ -674,6 +680,10 @@ def main():
         out["backward_surface"] = bench_surface(max(1, min(args.steps, 5)), 1, log)
     if not args.no_batched:
         out["batched"] = bench_batched(max(1, min(args.steps, 5)), 1, log)
+        # per piece, against the plain step's site kernel: the batch's small
+        # diagrams on fine meshes have many more pieces per cell
+        out["batched"]["pieces_per_s_vs_plain_site_kernel"] = (
+            out["batched"]["site_kernel_pieces_per_s"] / (info["n_pieces"] / (dom_ms * 1e-3)))
     if not args.no_small:
         out["cvt_density"] = bench_cvt(log)
     if not args.no_cpu_baseline:

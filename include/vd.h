@@ -125,13 +125,15 @@ typedef struct {
                                  + d7 y^2 + d8 y z + d9 z^2 (absolute coordinates); it should be
                                  positive on M */
   int32_t whole_interior;     /* tetrahedral domains, carve_mode 1, synchronous clips.  1: Alg. 5's
-                                 split of boundary and interior sites -- the restricted diagram
-                                 of the boundary surface is computed first; a cell that meets no
-                                 boundary triangle lies entirely inside M (its site, or for a
-                                 power cell a point of it, is in M) and is returned as ONE piece
-                                 with simplex -1: the whole cell, not cut by the tetrahedra (its
-                                 moments, faces, vertices and neighbours are the cell's).  Cells
-                                 that meet the boundary are cut per tetrahedron as usual.  Per-site
+                                 split of boundary and interior sites -- a cell that lies entirely
+                                 inside M is returned as ONE piece with simplex -1: the whole
+                                 cell, not cut by the tetrahedra (its moments, faces, vertices and
+                                 neighbours are the cell's).  Cells that meet the boundary are cut
+                                 per tetrahedron as usual.  Interior cells are those that meet no
+                                 triangle of the restricted diagram of the boundary surface
+                                 (computed first) and have a point in M; when M is convex, holds
+                                 every site and boundary_seeds is not 1, no boundary diagram is
+                                 needed: a cell is interior when all its corners lie in M.  Per-site
                                  moments and neighbour lists equal those of the default up to
                                  rounding.  Default 0: every piece is T_a cap Omega_i. */
 } vd_options;
@@ -274,8 +276,7 @@ vd_status vd_domain_create_batch(const double *verts, const int32_t *simplices,
  * surface is computed first and every boundary triangle a cell meets seeds the
  * tetrahedron behind it (Alg. 5), so cells that meet M in several parts, and
  * sites outside M, get all their pieces; a site whose cell misses M gets none.
- * With vd_options.whole_interior = 1 the boundary diagram is always computed
- * and a cell that meets no boundary triangle is one piece (simplex -1).
+ * With vd_options.whole_interior = 1 a cell inside M is one piece (simplex -1).
  * Surface (triangles): one wavefront per triangle; the triangle's sites are
  * found by propagation over positive edge flags from the site nearest to the
  * triangle's centroid (Alg. 4), each piece carved by Alg. 3.

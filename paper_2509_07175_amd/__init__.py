@@ -473,7 +473,8 @@ def lloyd(sites, domain: Domain, iterations: int, options: Options | None = None
 
     A site must stay inside the domain, which holds for convex domains (a cell's
     centroid lies in the cell).  For a surface, centroids are not projected back
-    onto it."""
+    onto it.  On a tetrahedral domain, options with whole_interior=1 give the
+    same moments without cutting the interior cells by the tetrahedra."""
     import torch
     if sites.dtype != torch.float64 or not sites.is_cuda or sites.dim() != 2 or sites.shape[1] != 3:
         raise ValueError("sites must be an (n, 3) float64 CUDA tensor")

@@ -743,7 +743,6 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
     if (dom->dim != 3 || opt.carve_mode != 1 || opt.boundary_seeds == 0 || opt.no_sync)
       return fail(VD_ERR_INVALID_ARG, "vd_clip_cells: whole_interior needs a tetrahedral domain, carve_mode 1, "
                                       "boundary seeds and a synchronous clip");
-    opt.boundary_seeds = 1;
   }
   hipStream_t st = as_stream(stream);
   vd_cells c = *out ? *out : new vd_cells_s();
@@ -792,7 +791,6 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
     d.monitor = opt.monitor ? 1 : 0;
     d.density = opt.use_density ? 1 : 0;
     d.power = g->power ? 1 : 0;
-    d.whole = opt.whole_interior ? 1 : 0;
     for (int k = 0; k < 10; k++) d.dens[k] = opt.use_density ? opt.density[k] : (k == 0 ? 1.0 : 0.0);
     // persistent 3D kernel: each wave reserves output chunks of about 1/8 of an
     // arena's share per wave, so unused chunk tails stay within 1/8 of it
@@ -858,6 +856,17 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
         c->sites_outside = ho[0];
         use_b = use_b || ho[0] > 0;
       }
+      // the interior split: by the boundary diagram, or, for a convex M that
+      // holds every site, by the corners of each cell (no boundary diagram).
+      // The boundary diagram takes one wave per boundary triangle, so it is
+      // chosen while a triangle meets few cells (about (n / |M|)^(2/3) per
+      // unit area); on coarse boundaries the corner test is far cheaper.
+      if (opt.whole_interior && !use_b && dom->bnd && dom->area > 0 && dom->bnd->m > 0) {
+        const double per_area = std::pow((double)n / dom->area, 2.0 / 3.0);
+        const double cells_per_tri = per_area * dom->bnd->area / (double)dom->bnd->m;
+        use_b = cells_per_tri <= 32.0;
+      }
+      d.whole = !opt.whole_interior ? 0 : (use_b ? 1 : 2);
       if (use_b) {
         if (!dom->bnd) return bail(fail(VD_ERR_INVALID_ARG, "vd_clip_cells: the domain has no boundary surface"));
         vd_options bopt;
@@ -883,7 +892,7 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
     }
     if (dom->dim == 2) vd_launch_fill_int(d.pcount, n, 0, st);
     if (opt.time_kernels) HIP_TRY(hipEventRecord(c->ev0, st));
-    if (dom->dim == 3) vd_launch_sites3d(G, D, c->d_dev, wg, opt.monitor != 0, opt.use_density != 0, g->power, st);
+    if (dom->dim == 3) vd_launch_sites3d(G, D, c->d_dev, wg, opt.monitor != 0, opt.use_density != 0, g->power, d.whole == 2, st);
     else vd_launch_surface(G, D, c->d_dev, wg, opt.use_density != 0, g->power, st);
     if (opt.time_kernels) HIP_TRY(hipEventRecord(c->ev1, st));
     HIP_TRY(hipGetLastError());

@@ -948,6 +948,26 @@ __device__ int locate_wave(const DomainView &D, double qx, double qy, double qz)
   return b == 0x7fffffff ? -1 : b;
 }
 
+// Is q in M?  One lane scans q's location cell (the tolerance of tet_contains
+// counts a point on the boundary as inside).
+__device__ bool in_domain(const DomainView &D, double qx, double qy, double qz) {
+  const double q[3] = {qx, qy, qz};
+  int cc[3];
+  for (int k = 0; k < 3; k++) cc[k] = cell_coord(q[k], GL(D.lgeom)[k], GL(D.lgeom)[6 + k], D.lg[k]);
+  const int c = cc[0] + D.lg[0] * (cc[1] + D.lg[1] * cc[2]);
+  for (int t = GL(D.lstart)[c]; t < GL(D.lstart)[c + 1]; t++)
+    if (tet_contains(D, GL(D.litems)[t], q)) return true;
+  return false;
+}
+
+// Do all nc corners of the polytope in S lie in M?  (Whole wave.)
+__device__ __forceinline__ bool cell_in_domain(const WaveLds &S, const DomainView &D, const SiteCtx &X, int nc) {
+  bool out = false;
+  for (int x = vd_lane(); x < nc; x += 64)
+    out = out || !in_domain(D, X.vx + S.cy[x][0], X.vy + S.cy[x][1], X.vz + S.cy[x][2]);
+  return !__ballot(out);
+}
+
 // Neighbour e of the site's list: the first VD_NB_MAX in LDS, the rest in this
 // wave's part of a global buffer.
 __device__ __forceinline__ int nb_get(const WaveLds &S, const CellsDev &C, int e) {
@@ -986,7 +1006,7 @@ __device__ __forceinline__ bool nb_push(WaveLds &S, const CellsDev &C, int &nnb,
 //     tests and the bisector search.
 // The carve has one call site: the first job of a cell-first site is the cell.
 // ---------------------------------------------------------------------------
-template <bool MON, bool DENS, bool POW>
+template <bool MON, bool DENS, bool POW, bool CORNERS>
 __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, const CellsDev &C, int si) {
   const int l = vd_lane();
   SiteCtx X;
@@ -1082,11 +1102,12 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
         if (rc == 1 || rc == 3) { err = 3; where = VD_STAGE_CELL; continue; }  // the site lies in the box
         if (rc == 2) continue;                           // too large: carve per simplex
         npl = compact_planes(S, npl, nc);
-        if (C.whole && nbseed == 0) {
-          // Alg. 5's interior sites: a cell that meets no boundary triangle
-          // lies inside M or outside it as a whole (it contains v_i, which is
-          // in M; a power cell is judged by the mean of its corners), and is
-          // then one piece, cut by no tetrahedron
+        // Alg. 5's interior sites.  whole == 1: a cell that meets no boundary
+        // triangle lies inside M or outside it as a whole (it contains v_i,
+        // which is in M; a power cell is judged by the mean of its corners).
+        // whole == 2 (a convex M holding every site): a cell whose corners all
+        // lie in M lies in M.  Such a cell is one piece, cut by no tetrahedron.
+        if (C.whole && nbseed == 0 && (!CORNERS || cell_in_domain(S, D, X, nc))) {
           bool inside = true;
           if (POW) {
             double c0 = 0, c1 = 0, c2 = 0;
@@ -1302,9 +1323,11 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
 // site cache when it fits, else in a global buffer); the third wave hides
 // more LDS and memory latency than that costs.
 // MON: the work counters and margin tracking of vd_options.monitor; DENS: the
-// density-weighted moments of vd_options.use_density.  Each is compiled in only
-// for the instances that use it, so the default instance carries neither.
-template <bool MON, bool DENS, bool POW>
+// density-weighted moments of vd_options.use_density; POW: power diagrams;
+// CORNERS: the interior split by the cells' corners (whole_interior on a
+// convex domain).  Each is compiled in only for the instances that use it, so
+// the default instance carries none of them.
+template <bool MON, bool DENS, bool POW, bool CORNERS>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3))) site_kernel(GridView G, DomainView D, const CellsDev *__restrict__ Cp) {
   __shared__ WaveLds S;
   const CellsDev &C = *Cp;
@@ -1315,7 +1338,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3)))
     // the site's own diagram (a batch) or the only one; one call site keeps
     // the per-site code inlined once
     const int b = G.nb > 1 ? diagram_of(G.site_off, G.nb, si) : 0;
-    do_site<MON, DENS, POW>(S, G.views[b], D.views[b], C, si);
+    do_site<MON, DENS, POW, CORNERS>(S, G.views[b], D.views[b], C, si);
   }
   arena_close(S.ar, C);
 }
@@ -1333,7 +1356,7 @@ int resident_workgroups() {
   int &w = cache[dev];
   if (!w) {
     int per_cu = 0, ncu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, site_kernel<false, false, false>, 64, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, site_kernel<false, false, false, false>, 64, 0) != hipSuccess ||
         per_cu < 1)
       per_cu = 1;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1) ncu = 1;
@@ -1354,18 +1377,23 @@ void vd_launch_queue_init(int *queue, long long n, hipStream_t st) {
 }
 
 void vd_launch_sites3d(const GridView &G, const DomainView &D, const CellsDev *Cdev, int workgroups, bool monitor,
-                       bool density, bool power, hipStream_t st) {
+                       bool density, bool power, bool corners, hipStream_t st) {
   const dim3 grid(workgroups), block(64);
-  if (power) {  // power diagrams: no density
-    if (monitor) hipLaunchKernelGGL((site_kernel<true, false, true>), grid, block, 0, st, G, D, Cdev);
-    else hipLaunchKernelGGL((site_kernel<false, false, true>), grid, block, 0, st, G, D, Cdev);
+  if (power) {  // power diagrams: no density, interior split by the boundary diagram
+    if (monitor) hipLaunchKernelGGL((site_kernel<true, false, true, false>), grid, block, 0, st, G, D, Cdev);
+    else hipLaunchKernelGGL((site_kernel<false, false, true, false>), grid, block, 0, st, G, D, Cdev);
+  } else if (corners) {
+    if (monitor && density) hipLaunchKernelGGL((site_kernel<true, true, false, true>), grid, block, 0, st, G, D, Cdev);
+    else if (monitor) hipLaunchKernelGGL((site_kernel<true, false, false, true>), grid, block, 0, st, G, D, Cdev);
+    else if (density) hipLaunchKernelGGL((site_kernel<false, true, false, true>), grid, block, 0, st, G, D, Cdev);
+    else hipLaunchKernelGGL((site_kernel<false, false, false, true>), grid, block, 0, st, G, D, Cdev);
   } else if (monitor && density) {
-    hipLaunchKernelGGL((site_kernel<true, true, false>), grid, block, 0, st, G, D, Cdev);
+    hipLaunchKernelGGL((site_kernel<true, true, false, false>), grid, block, 0, st, G, D, Cdev);
   } else if (monitor) {
-    hipLaunchKernelGGL((site_kernel<true, false, false>), grid, block, 0, st, G, D, Cdev);
+    hipLaunchKernelGGL((site_kernel<true, false, false, false>), grid, block, 0, st, G, D, Cdev);
   } else if (density) {
-    hipLaunchKernelGGL((site_kernel<false, true, false>), grid, block, 0, st, G, D, Cdev);
+    hipLaunchKernelGGL((site_kernel<false, true, false, false>), grid, block, 0, st, G, D, Cdev);
   } else {
-    hipLaunchKernelGGL((site_kernel<false, false, false>), grid, block, 0, st, G, D, Cdev);
+    hipLaunchKernelGGL((site_kernel<false, false, false, false>), grid, block, 0, st, G, D, Cdev);
   }
 }

@@ -180,7 +180,8 @@ struct CellsDev {
   int monitor;     // count work and track predicate margins
   int density;     // weight the moments by the quadratic density dens[] (Eq. 3)
   int power;       // power diagram: the grid's weights (Sec. 7.3)
-  int whole;       // a cell that meets no boundary triangle is one piece (needs bseed_off)
+  int whole;       // interior cells as one piece: 1 no boundary triangle met (needs bseed_off),
+                   // 2 every corner in M (a convex M holding every site)
   double dens[10]; // rho(x) = c0 + c1 x + c2 y + c3 z + c4 x^2 + c5 xy + c6 xz + c7 y^2 + c8 yz + c9 z^2
   unsigned long long *cnt;  // CNT_N counters
   // per site (caller index)
@@ -385,7 +386,7 @@ void vd_launch_locate_sites(const GridView &G, const DomainView &D, int *seed, i
 int vd_sites3d_workgroups(long long n);
 void vd_launch_queue_init(int *queue, long long n, hipStream_t st);
 void vd_launch_sites3d(const GridView &G, const DomainView &D, const CellsDev *Cdev, int workgroups, bool monitor,
-                       bool density, bool power, hipStream_t st);
+                       bool density, bool power, bool corners, hipStream_t st);
 int vd_surface_workgroups(long long m);
 void vd_launch_surface(const GridView &G, const DomainView &D, const CellsDev *Cdev, int workgroups, bool density,
                        bool power, hipStream_t st);

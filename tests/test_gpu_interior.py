@@ -90,6 +90,8 @@ def _check_against_oracle(gpu, ref, mom, sites, n):
 
 @pytest.mark.parametrize("n,k,seed", [(900, 4, 401), (3000, 6, 402)])
 def test_whole_interior_against_the_oracle(oracle_mod, n, k, seed):
+    """Cube grids whose boundary triangles meet a few cells each: the split by
+    the boundary diagram."""
     sites, dom = vdgen.small_case(n, k, seed=seed)
     gpu = run_gpu(sites, dom, whole_interior=1)
     ref = oracle_mod.compute(sites, dom, brute=False)
@@ -98,6 +100,22 @@ def test_whole_interior_against_the_oracle(oracle_mod, n, k, seed):
     assert len(interior) > n // 4
     assert abs(gpu["mass"].sum() - 1.0) < 1e-12
     assert gpu["info"]["boundary_seeded"] == 1
+
+
+@pytest.mark.parametrize("n,seed", [(1000, 101), (2500, 409)])
+def test_whole_interior_by_corners_against_the_oracle(oracle_mod, n, seed):
+    """The unit cube as 6 tetrahedra (12 boundary triangles, each meeting
+    dozens of cells): a convex domain holding every site, split by the cells'
+    corners without a boundary diagram (n = 1,000: the shape of the 1k-site
+    cube workload)."""
+    sites, dom = vdgen.small_case(n, 1, seed=seed)
+    gpu = run_gpu(sites, dom, whole_interior=1)
+    assert gpu["info"]["boundary_seeded"] == 0
+    ref = oracle_mod.compute(sites, dom, brute=n <= 1000)
+    mom = oracle_mod.site_moments(ref, sites)
+    interior = _check_against_oracle(gpu, ref, mom, sites, n)
+    assert len(interior) > n // 4
+    assert abs(gpu["mass"].sum() - 1.0) < 1e-12
 
 
 def test_whole_interior_non_convex(oracle_mod):

@@ -147,10 +147,13 @@ def test_boundary_diagram_of_a_coarse_cube():
     s, dom = vdgen.small_case(5000, 1, seed=44)
     plain = run_gpu(s, dom)
     seeded = run_gpu(s, dom, boundary_seeds=1)
-    whole = run_gpu(s, dom, whole_interior=1)
-    assert seeded["info"]["boundary_seeded"] == 1
-    for r in (seeded, whole):
+    whole = run_gpu(s, dom, whole_interior=1)  # convex, every site inside: split by the corners
+    whole_b = run_gpu(s, dom, whole_interior=1, boundary_seeds=1)  # split by the boundary diagram
+    assert seeded["info"]["boundary_seeded"] == 1 and whole["info"]["boundary_seeded"] == 0
+    for r in (seeded, whole, whole_b):
         assert np.all(np.abs(r["mass"] - plain["mass"]) <= 1e-12 * plain["mass"])
         assert np.array_equal(r["nbr_off"], plain["nbr_off"]) and np.array_equal(r["nbr"], plain["nbr"])
     assert np.array_equal(seeded["res"]["piece_site"], plain["res"]["piece_site"])
     assert np.array_equal(seeded["res"]["piece_mass"], plain["res"]["piece_mass"])
+    ra, rb = whole["res"], whole_b["res"]
+    assert np.array_equal(ra["piece_site"], rb["piece_site"]) and np.array_equal(ra["piece_simplex"], rb["piece_simplex"])
