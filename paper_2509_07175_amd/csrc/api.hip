@@ -27,6 +27,8 @@ void vd_launch_convexity(vd_domain d, int *on_bnd, int *pos, int *list, int *sca
                          int *convex, hipStream_t st);
 void vd_launch_boundary_scan(vd_domain d, int *flag, int *pos, int *scan_tmp, hipStream_t st);
 void vd_launch_boundary_extract(vd_domain d, const int *pos, int *tri, int *btet, long long *boff, hipStream_t st);
+void vd_launch_refine_triangles(vd_domain bnd, const int *btet, int s, double *ov, int *otri, int *oadj, int *obtet,
+                                hipStream_t st);
 
 namespace {
 
@@ -587,6 +589,8 @@ void vd_domain_free(vd_domain D) {
   if (!D) return;
   vd_domain_free(D->bnd);
   hipFree(D->btet);
+  vd_domain_free(D->bnd_ref);
+  hipFree(D->btet_ref);
   hipFree(D->verts); hipFree(D->simp); hipFree(D->adj); hipFree(D->lgeom); hipFree(D->lstart);
   hipFree(D->litems); hipFree(D->lcount); hipFree(D->lfill); hipFree(D->scan_tmp);
   hipFree(D->d_simp_off); hipFree(D->d_vert_off); hipFree(D->d_loc_off); hipFree(D->d_lg); hipFree(D->d_views);
@@ -704,6 +708,49 @@ vd_status check_counts(vd_cells c, bool overflow_is_error) {
     return (vd_status)(c->status = fail(VD_ERR_CAPACITY, "vd_clip_cells: an output arena overflowed in a no-sync clip "
                                              "(run a synchronous clip on this handle to grow it)"));
   c->status = VD_OK;
+  return VD_OK;
+}
+
+// The boundary surface on which a clip of n sites computes its boundary
+// diagram, and the tetrahedron behind each of its triangles.  The diagram
+// takes one wave per triangle, so a triangle that would meet many cells
+// (about (n / |M|)^(2/3) per unit area) is split into s^2 smaller ones; the
+// split surface is kept in the domain handle for later clips.
+vd_status boundary_for_clip(vd_domain dom, int64_t n, void *stream, vd_domain &bd, const int *&btet) {
+  bd = dom->bnd;
+  btet = dom->btet;
+  if (!bd || bd->m < 1 || dom->area <= 0) return VD_OK;
+  const double cells_per_tri = std::pow((double)n / dom->area, 2.0 / 3.0) * bd->area / (double)bd->m;
+  if (!(cells_per_tri > 32.0)) return VD_OK;
+  const int s = (int)std::min(64.0, std::ceil(std::sqrt(cells_per_tri / 8.0)));
+  if (!(dom->bnd_ref && dom->bnd_ref_s == s)) {
+    const int64_t mr = bd->m * (int64_t)s * s;
+    if (mr > INT_MAX / 8) return VD_OK;  // too fine to split: keep the coarse surface
+    hipStream_t st = as_stream(stream);
+    TmpBuffers tmp;
+    double *ov = nullptr;
+    int *otri = nullptr, *oadj = nullptr;
+    HIP_TRY(tmp.get(ov, 9 * mr));
+    HIP_TRY(tmp.get(otri, 3 * mr));
+    HIP_TRY(tmp.get(oadj, 3 * mr));
+    hipFree(dom->btet_ref);
+    dom->btet_ref = nullptr;
+    dom->bnd_ref_s = 0;
+    HIP_TRY(hipMalloc((void **)&dom->btet_ref, sizeof(int) * mr));
+    vd_launch_refine_triangles(bd, dom->btet, s, ov, otri, oadj, dom->btet_ref, st);
+    HIP_TRY(hipGetLastError());
+    std::vector<int64_t> so(bd->nb + 1), vo(bd->nb + 1);
+    for (int b = 0; b <= bd->nb; b++) {
+      so[b] = bd->simp_off[b] * (int64_t)s * s;
+      vo[b] = 3 * so[b];
+    }
+    const vd_status r = domain_create_impl(ov, otri, oadj, bd->nb, vo.data(), so.data(), 2, stream, &dom->bnd_ref,
+                                           "vd_clip_cells (split boundary)");
+    if (r != VD_OK) return r;
+    dom->bnd_ref_s = s;
+  }
+  bd = dom->bnd_ref;
+  btet = dom->btet_ref;
   return VD_OK;
 }
 
@@ -869,17 +916,23 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
       d.whole = !opt.whole_interior ? 0 : (use_b ? 1 : 2);
       if (use_b) {
         if (!dom->bnd) return bail(fail(VD_ERR_INVALID_ARG, "vd_clip_cells: the domain has no boundary surface"));
+        vd_domain bd = nullptr;
+        const int *btet = nullptr;
+        {
+          const vd_status r = boundary_for_clip(dom, n, stream, bd, btet);
+          if (r != VD_OK) return bail(r);
+        }
         vd_options bopt;
         vd_options_default(&bopt);
         bopt.emit_polytopes = 0;
         bopt.max_search_iters = opt.max_search_iters;
         bopt.site_cache = opt.site_cache;
-        const vd_status r = vd_clip_cells(g, dom->bnd, &bopt, stream, &c->bcells);
+        const vd_status r = vd_clip_cells(g, bd, &bopt, stream, &c->bcells);
         if (r != VD_OK) return bail(r);
         d.bseed_off = c->bcells->piece_off;
         d.bseed_pid = c->bcells->piece_id;
         d.bseed_tri = c->bcells->d.piece_simplex;
-        d.btet = dom->btet;
+        d.btet = btet;
       } else {
         d.bseed_off = nullptr;
         d.bseed_pid = d.bseed_tri = d.btet = nullptr;

@@ -438,6 +438,50 @@ void vd_launch_boundary_scan(vd_domain d, int *flag, int *pos, int *scan_tmp, hi
   vdscan::exclusive_scan<int, int>(flag, nf, pos, scan_tmp, st);
 }
 
+// Each boundary triangle (A, B, C) split into s^2 congruent triangles of the
+// same orientation: row r (0 <= r < s) holds s - r "up" triangles
+// P(r,c) P(r,c+1) P(r+1,c) and then s - r - 1 "down" triangles
+// P(r,c+1) P(r+1,c+1) P(r+1,c), P(r,c) = A + (c/s)(B - A) + (r/s)(C - A).
+// Sub-triangle t gets its own three vertices 3t .. 3t+2, no neighbours, and
+// the tetrahedron of its triangle.  Vertex indices are diagram-local, as a
+// batched domain takes them (diagram b of the triangles starts at simp_off[b]).
+__global__ void __launch_bounds__(kB) refine_triangles(const double *__restrict__ verts, const int *__restrict__ tri,
+                                                       const int *__restrict__ btet, long long m, int nb,
+                                                       const long long *__restrict__ simp_off, int s,
+                                                       double *__restrict__ ov, int *__restrict__ otri,
+                                                       int *__restrict__ oadj, int *__restrict__ obtet) {
+  const long long t = (long long)blockIdx.x * kB + threadIdx.x;
+  const long long ss = (long long)s * s;
+  if (t >= m * ss) return;
+  const long long a = t / ss;
+  const long long t0 = nb > 1 ? simp_off[diagram_of(simp_off, nb, a)] * ss : 0;  // first sub-triangle of the diagram
+  int k = (int)(t - a * ss), r = 0;
+  while (k >= 2 * (s - r) - 1) { k -= 2 * (s - r) - 1; r++; }
+  int pr[3], pc[3];
+  if (k < s - r) {
+    pr[0] = r; pc[0] = k; pr[1] = r; pc[1] = k + 1; pr[2] = r + 1; pc[2] = k;
+  } else {
+    const int c = k - (s - r);
+    pr[0] = r; pc[0] = c + 1; pr[1] = r + 1; pc[1] = c + 1; pr[2] = r + 1; pc[2] = c;
+  }
+  const double *A = verts + 3 * (long long)tri[3 * a], *B = verts + 3 * (long long)tri[3 * a + 1],
+               *C = verts + 3 * (long long)tri[3 * a + 2];
+  for (int v = 0; v < 3; v++) {
+    const double u = (double)pc[v] / s, w = (double)pr[v] / s;
+    for (int x = 0; x < 3; x++) ov[9 * t + 3 * v + x] = A[x] + u * (B[x] - A[x]) + w * (C[x] - A[x]);
+    otri[3 * t + v] = (int)(3 * (t - t0) + v);
+    oadj[3 * t + v] = -1;
+  }
+  obtet[t] = btet[a];
+}
+
+void vd_launch_refine_triangles(vd_domain bnd, const int *btet, int s, double *ov, int *otri, int *oadj, int *obtet,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(refine_triangles, dim3(blocks(bnd->m * (long long)s * s)), dim3(kB), 0, st,
+                     (const double *)bnd->verts, (const int *)bnd->simp, btet, (long long)bnd->m, bnd->nb,
+                     (const long long *)bnd->d_simp_off, s, ov, otri, oadj, obtet);
+}
+
 void vd_launch_boundary_extract(vd_domain d, const int *pos, int *tri, int *btet, long long *boff, hipStream_t st) {
   hipLaunchKernelGGL(bnd_extract, dim3(blocks(d->m * 4)), dim3(kB), 0, st, (const int *)d->simp,
                      (const int *)d->adj, (long long)d->m, d->nb, (const long long *)d->d_simp_off,

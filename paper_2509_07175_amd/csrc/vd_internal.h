@@ -130,6 +130,12 @@ struct vd_domain_s {
   // from outside the tetrahedron of their site (Alg. 5)
   vd_domain_s *bnd = nullptr;
   int *btet = nullptr;
+  // the boundary surface with every triangle split into bnd_ref_s^2, for the
+  // boundary diagram when a triangle would meet many cells (built by a clip
+  // and kept for later clips of the same density), and its tetrahedra
+  vd_domain_s *bnd_ref = nullptr;
+  int *btet_ref = nullptr;
+  int bnd_ref_s = 0;
   // batch of nb domains (nb = 1: plain)
   int nb = 1;
   std::vector<int64_t> vert_off, simp_off, loc_off;  // host [nb + 1]
