@@ -277,6 +277,10 @@ vd_status vd_domain_create_batch(const double *verts, const int32_t *simplices,
  * tetrahedron behind it (Alg. 5), so cells that meet M in several parts, and
  * sites outside M, get all their pieces; a site whose cell misses M gets none.
  * With vd_options.whole_interior = 1 a cell inside M is one piece (simplex -1).
+ * When the boundary triangles are coarse for the number of sites, the
+ * boundary diagram runs on a copy of the surface with every triangle split,
+ * which the clip keeps in the domain handle: a domain handle must not be used
+ * by two clips at the same time.
  * Surface (triangles): one wavefront per triangle; the triangle's sites are
  * found by propagation over positive edge flags from the site nearest to the
  * triangle's centroid (Alg. 4), each piece carved by Alg. 3.
