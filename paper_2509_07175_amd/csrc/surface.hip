@@ -578,6 +578,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 4)))
 // Per-site sums over the site's pieces (CSR order: ascending simplex) and the
 // sorted, de-duplicated positive edge flags as neighbour list: site_reduce
 // writes the sums and the list length, site_nbrs the list at its CSR offset.
+// Up to kNbLocal neighbours are gathered in registers; more are counted and
+// written in place.
 constexpr int kB = 256;
 constexpr int kNbLocal = 96;
 
@@ -596,6 +598,39 @@ __device__ __forceinline__ int site_neighbours(const CellsDev &C, const long lon
       if (cnt >= kNbLocal) { overflow = 1; continue; }
       for (int x = cnt; x > k; x--) nb[x] = nb[x - 1];
       nb[k] = lab;
+      cnt++;
+    }
+  }
+  return cnt;
+}
+
+// A site with more than kNbLocal distinct neighbours: its edge flags are
+// walked in place (no list): `first` tells whether the flag of edge (q, f)
+// does not occur on an earlier edge of the site.  The count costs a square
+// of the site's edges, which only such sites pay.
+__device__ __forceinline__ int edge_label(const CellsDev &C, const int *__restrict__ pid, long long q, int f) {
+  return GL(C.face_label)[GL(C.piece_fstart)[pid[q]] + f];
+}
+__device__ bool first_occurrence(const CellsDev &C, const long long *__restrict__ poff, const int *__restrict__ pid,
+                                 long long i, long long q, int f, int lab) {
+  for (long long q2 = poff[i]; q2 <= q; q2++) {
+    const int nf = q2 < q ? GL(C.piece_nface)[pid[q2]] : f;
+    for (int f2 = 0; f2 < nf; f2++)
+      if (edge_label(C, pid, q2, f2) == lab) return false;
+  }
+  return true;
+}
+// Distinct neighbours of site i; with out != NULL they are also written there
+// (unsorted).
+__device__ int site_neighbours_wide(const CellsDev &C, const long long *__restrict__ poff, const int *__restrict__ pid,
+                                    long long i, int *out) {
+  int cnt = 0;
+  for (long long q = poff[i]; q < poff[i + 1]; q++) {
+    const int nf = GL(C.piece_nface)[pid[q]];
+    for (int f = 0; f < nf; f++) {
+      const int lab = edge_label(C, pid, q, f);
+      if (lab < 0 || !first_occurrence(C, poff, pid, i, q, f, lab)) continue;
+      if (out) out[cnt] = lab;
       cnt++;
     }
   }
@@ -623,12 +658,8 @@ __global__ void __launch_bounds__(kB) site_reduce(long long n, const long long *
   GL(C.energy)[i] = e;
   int nb[kNbLocal];
   int overflow = 0;
-  GL(C.ncount)[i] = site_neighbours(C, poff, pid, i, nb, overflow);
-  if (overflow) {
-    atomicAdd(&C.cnt[CNT_ERR_CAP], 1ull);
-    atomicMin((int *)&C.cnt[CNT_BAD_SITE], (int)i);
-    atomicOr((unsigned long long *)&C.cnt[CNT_STAGES], 1ull << VD_STAGE_NEIGHBOURS);
-  }
+  const int cnt = site_neighbours(C, poff, pid, i, nb, overflow);
+  GL(C.ncount)[i] = overflow ? site_neighbours_wide(C, poff, pid, i, nullptr) : cnt;
 }
 
 // cap: entries of nbr.  A no-sync clip keeps the size of the synchronous clip
@@ -641,13 +672,27 @@ __global__ void __launch_bounds__(kB) site_nbrs(long long n, const long long *__
   if (i >= n) return;
   int nb[kNbLocal];
   int overflow = 0;
-  const int cnt = site_neighbours(*Cp, poff, pid, i, nb, overflow);
+  const CellsDev &C = *Cp;
+  int cnt = site_neighbours(C, poff, pid, i, nb, overflow);
+  if (overflow) cnt = site_neighbours_wide(C, poff, pid, i, nullptr);
   const long long o = noff[i];
   if (o + cnt > cap) {
     atomicAdd(&Cp->cnt[CNT_OVERFLOW], 1ull);
     return;
   }
-  for (int k = 0; k < cnt; k++) nbr[o + k] = nb[k];
+  if (!overflow) {
+    for (int k = 0; k < cnt; k++) nbr[o + k] = nb[k];
+    return;
+  }
+  // a wide site: the distinct flags in place, then sorted in place
+  int *out = nbr + o;
+  site_neighbours_wide(C, poff, pid, i, out);
+  for (int k = 1; k < cnt; k++) {
+    const int v = out[k];
+    int y = k - 1;
+    while (y >= 0 && out[y] > v) { out[y + 1] = out[y]; y--; }
+    out[y + 1] = v;
+  }
 }
 
 int resident_workgroups() {

@@ -157,3 +157,22 @@ def test_boundary_diagram_of_a_coarse_cube():
     assert np.array_equal(seeded["res"]["piece_mass"], plain["res"]["piece_mass"])
     ra, rb = whole["res"], whole_b["res"]
     assert np.array_equal(ra["piece_site"], rb["piece_site"]) and np.array_equal(ra["piece_simplex"], rb["piece_simplex"])
+
+
+def test_site_with_more_than_96_neighbours(oracle_mod):
+    """A site ringed by 120 sites in the plane of a flat L mesh: its 2D cell
+    has 120 neighbours, more than the per-site list a thread keeps, so the
+    neighbour list is counted and written in place.  Everything against the
+    oracle."""
+    rng = np.random.default_rng(47)
+    c = np.array([0.25, 0.25])
+    ang = np.linspace(0, 2 * np.pi, 120, endpoint=False) + rng.uniform(-1e-3, 1e-3, 120)
+    rad = 0.1 + rng.uniform(-1e-4, 1e-4, 120)
+    ring = np.c_[c[0] + rad * np.cos(ang), c[1] + rad * np.sin(ang)]
+    bg = vdgen.planar_l_sites(400, seed=48)[:, :2]
+    bg = bg[np.linalg.norm(bg - c, axis=1) > 0.16]
+    p2 = np.vstack([[c + 1e-5], ring, bg])
+    s = np.c_[p2, np.zeros(len(p2))]
+    gpu = _surface_case(oracle_mod, s, vdgen.planar_l_polygon(16), brute=False)
+    nb = gpu_neighbors(gpu, len(s))
+    assert len(nb[0]) > 96
