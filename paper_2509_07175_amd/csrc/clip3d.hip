@@ -1306,12 +1306,20 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
   }
   __syncthreads();
   if (ns0 + nnb <= C.cap_nbr) {
-    // neighbours in ascending caller index: rank sort
-    for (int e = l; e < nnb; e += 64) {
-      const int me = GL(G.perm)[nb_get(S, C, e)];
+    // neighbours in ascending caller index: rank sort (up to 64 from the
+    // lanes' registers, more from memory)
+    if (nnb <= 64) {
+      const int me = l < nnb ? GL(G.perm)[S.nbl[l]] : 0;
       int rk = 0;
-      for (int o = 0; o < nnb; o++) rk += (GL(G.perm)[nb_get(S, C, o)] < me) ? 1 : 0;
-      GL(C.nbr_arena)[ns0 + rk] = me;
+      for (int o = 0; o < nnb; o++) rk += (__builtin_amdgcn_readlane(me, o) < me) ? 1 : 0;
+      if (l < nnb) GL(C.nbr_arena)[ns0 + rk] = me;
+    } else {
+      for (int e = l; e < nnb; e += 64) {
+        const int me = GL(G.perm)[nb_get(S, C, e)];
+        int rk = 0;
+        for (int o = 0; o < nnb; o++) rk += (GL(G.perm)[nb_get(S, C, o)] < me) ? 1 : 0;
+        GL(C.nbr_arena)[ns0 + rk] = me;
+      }
     }
   }
   __syncthreads();
