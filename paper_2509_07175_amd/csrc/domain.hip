@@ -194,6 +194,22 @@ __global__ void __launch_bounds__(kB) locate_sites(GridView G, DomainView Dall, 
     atomicAdd(&outside[0], 1);
     atomicMin(&outside[1], G.perm[p]);
   }
+  // an exact copy of this site (the same point, and for a power diagram the
+  // same weight) sits in the same grid cell: outside[2] counts the copies with
+  // a higher caller index, outside[3] holds the lowest such index
+  const GridView Gb = G.nb > 1 ? G.views[diagram_of(G.site_off, G.nb, p)] : G;
+  int gc[3];
+  for (int k = 0; k < 3; k++) gc[k] = cell_coord(q[k], Gb.geom[k], Gb.geom[6 + k], Gb.g[k]);
+  const int gcell = gc[0] + Gb.g[0] * (gc[1] + Gb.g[1] * gc[2]);
+  const int me = G.perm[p];
+  for (int t = Gb.cstart[gcell]; t < Gb.cstart[gcell + 1]; t++) {
+    if (t == p || G.sx[t] != q[0] || G.sy[t] != q[1] || G.sz[t] != q[2]) continue;
+    if (G.sh && G.sh[t] != G.sh[p]) continue;
+    if (G.perm[t] > me) {
+      atomicAdd(&outside[2], 1);
+      atomicMin(&outside[3], G.perm[t]);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -170,3 +170,33 @@ def test_no_sync_overflow_is_reported_and_bounded():
     assert torch.equal(m2, m3)
     a, b = vd.pieces_as_result(c.view()), vd.pieces_as_result(ref.view())
     assert np.array_equal(a["piece_site"], b["piece_site"]) and np.array_equal(a["piece_simplex"], b["piece_simplex"])
+
+
+def test_repeated_sites_are_rejected(oracle_mod):
+    """Eq. 1 needs distinct sites (a copy's bisector is undefined): a 3D clip
+    whose sites repeat an earlier one exactly returns VD_ERR_INVALID_ARG,
+    naming the first copy, before any cell is carved; in a batch too.  A power
+    diagram may hold two sites at one point with different weights (the
+    lighter one has an empty cell), which matches the oracle."""
+    import paper_2509_07175_amd as vd
+    sites, dom = vdgen.small_case(400, 3, seed=61)
+    rep = sites.copy()
+    rep[250] = rep[17]
+    rep[300] = rep[17]
+    with pytest.raises(vd.VDError, match="repeat an earlier site exactly \\(first: 250\\)"):
+        run_gpu(rep, dom)
+    so = np.array([0, 400, 800])
+    both = np.vstack([sites, rep])
+    d = vd.Domain.batch_from_vdgen([dom, dom])
+    g = vd.build_grid_batch(_tensor(both, __import__("torch").float64), so, bboxes=[(0, 0, 0, 1, 1, 1)] * 2)
+    with pytest.raises(vd.VDError, match="first: 650"):
+        vd.clip_cells(g, d, vd.Options.default())
+    w = np.random.default_rng(62).uniform(-1e-3, 1e-3, size=400)
+    w[250] = w[17] - 0.01
+    pw = sites.copy()
+    pw[250] = pw[17]
+    gpu = run_gpu(pw, dom, weights=w)
+    ref = oracle_mod.compute(pw, dom, brute=False, weights=w)
+    mom = oracle_mod.site_moments(ref, pw)
+    assert gpu["mass"][250] == 0.0 and mom["mass"][250] == 0.0
+    assert np.all(np.abs(gpu["mass"] - mom["mass"]) <= 1e-9 * np.maximum(mom["mass"], 1e-300))
