@@ -289,7 +289,8 @@ vd_status vd_domain_create_batch(const double *verts, const int32_t *simplices,
  *   out     *out == NULL -> a new handle; else reused.
  * Synchronises `stream` once to read the output sizes (and re-runs with
  * larger arenas if an output arena overflowed).
- * Errors: VD_ERR_INVALID_ARG (3D: a site that repeats an earlier one exactly --
+ * Errors: VD_ERR_INVALID_ARG (3D: a site with a coordinate that is not finite,
+ * or that repeats an earlier one exactly --
  * the same point, and for a power diagram the same weight -- found before any
  * cell is carved, except in a no_sync clip, which assumes distinct sites; a
  * site outside every tetrahedron while the clip does not seed from the

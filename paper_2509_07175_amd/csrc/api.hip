@@ -889,18 +889,21 @@ vd_status vd_clip_cells(vd_grid g, vd_domain dom, const vd_options *opt_in, void
       // seeds: the tetrahedron holding each site, and (Alg. 5) the boundary
       // triangles each cell meets when the domain is not convex or a site
       // lies outside it
-      HIP_TRY(ensure_fixed(c->outside, 4));
-      vd_launch_fill_int(c->outside, 1, 0, st);
-      vd_launch_fill_int(c->outside + 1, 1, INT_MAX, st);
-      vd_launch_fill_int(c->outside + 2, 1, 0, st);
-      vd_launch_fill_int(c->outside + 3, 1, INT_MAX, st);
+      HIP_TRY(ensure_fixed(c->outside, 6));
+      for (int k = 0; k < 6; k += 2) {
+        vd_launch_fill_int(c->outside + k, 1, 0, st);
+        vd_launch_fill_int(c->outside + k + 1, 1, INT_MAX, st);
+      }
       vd_launch_locate_sites(G, D, d.seed, c->outside, st);
       bool use_b = false;
       c->sites_outside = -1;
       if (!opt.no_sync) {
-        int ho[4] = {0, INT_MAX, 0, INT_MAX};
+        int ho[6] = {0, INT_MAX, 0, INT_MAX, 0, INT_MAX};
         HIP_TRY(hipMemcpyAsync(ho, c->outside, sizeof ho, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
+        if (ho[4] > 0)
+          return bail(fail(VD_ERR_INVALID_ARG, "vd_clip_cells: %d site(s) with a coordinate that is not finite "
+                                               "(first: %d)", ho[4], ho[5]));
         // Eq. 1 needs distinct sites: a copy of a site has no cell of its own
         if (ho[2] > 0)
           return bail(fail(VD_ERR_INVALID_ARG, "vd_clip_cells: %d site(s) repeat an earlier site exactly (first: %d)",

@@ -157,6 +157,14 @@ __global__ void __launch_bounds__(kB) locate_sites(GridView G, DomainView Dall, 
   if (p >= G.n) return;
   const DomainView D = domain_of(Dall, G.nb > 1 ? diagram_of(G.site_off, G.nb, p) : 0);
   const double q[3] = {G.sx[p], G.sy[p], G.sz[p]};
+  if (!(isfinite(q[0]) && isfinite(q[1]) && isfinite(q[2]))) {
+    // outside[4] counts sites with a coordinate that is not finite, outside[5]
+    // holds the lowest such caller index
+    atomicAdd(&outside[4], 1);
+    atomicMin(&outside[5], G.perm[p]);
+    seed[p] = -1;
+    return;
+  }
   int cc[3];
   for (int k = 0; k < 3; k++) cc[k] = cell_coord(q[k], D.lgeom[k], D.lgeom[6 + k], D.lg[k]);
   const int c = cc[0] + D.lg[0] * (cc[1] + D.lg[1] * cc[2]);

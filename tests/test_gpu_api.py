@@ -200,3 +200,24 @@ def test_repeated_sites_are_rejected(oracle_mod):
     mom = oracle_mod.site_moments(ref, pw)
     assert gpu["mass"][250] == 0.0 and mom["mass"][250] == 0.0
     assert np.all(np.abs(gpu["mass"] - mom["mass"]) <= 1e-9 * np.maximum(mom["mass"], 1e-300))
+
+
+def test_argument_errors():
+    """Sites that are not finite (3D, found before any carve), no sites, an
+    empty domain: VD_ERR_INVALID_ARG with a message, and the library stays
+    usable afterwards."""
+    import torch
+    import paper_2509_07175_amd as vd
+    sites, dom = vdgen.small_case(300, 3, seed=63)
+    bad = sites.copy()
+    bad[120, 1] = np.nan
+    bad[200, 2] = np.inf
+    with pytest.raises(vd.VDError, match="not finite \\(first: 120\\)"):
+        run_gpu(bad, dom)
+    with pytest.raises(vd.VDError, match="n < 1"):
+        vd.build_grid(torch.empty((0, 3), dtype=torch.float64, device="cuda"), bbox=(0, 0, 0, 1, 1, 1))
+    with pytest.raises(vd.VDError, match="empty domain"):
+        vd.Domain(torch.zeros((4, 3), dtype=torch.float64, device="cuda"),
+                  torch.empty((0, 4), dtype=torch.int32, device="cuda"), None, 3)
+    ok = run_gpu(sites, dom)
+    assert abs(ok["mass"].sum() - 1.0) < 1e-12
