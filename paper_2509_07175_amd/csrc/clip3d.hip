@@ -1007,8 +1007,15 @@ __device__ __forceinline__ bool nb_push(WaveLds &S, const CellsDev &C, int &nnb,
 // The carve has one call site: the first job of a cell-first site is the cell.
 // ---------------------------------------------------------------------------
 template <bool MON, bool DENS, bool POW, bool CORNERS>
-__device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, const CellsDev &C, int si) {
+__device__ void do_site(WaveLds &S, const GridView &G0, const DomainView &D0, const CellsDev &C, int si) {
   const int l = vd_lane();
+  // The views are re-read from memory (scalar loads) in each piece iteration
+  // rather than held in scalar registers across the whole site: the opaque
+  // pointer copies below keep the compiler from hoisting their fields.
+  const GridView *Gp = &G0;
+  const DomainView *Dp = &D0;
+  const GridView &G = G0;
+  const DomainView &D = D0;
   SiteCtx X;
   X.vx = GL(G.sx)[si]; X.vy = GL(G.sy)[si]; X.vz = GL(G.sz)[si];
   X.delta = GL(G.delta)[si];
@@ -1060,6 +1067,9 @@ __device__ void do_site(WaveLds &S, const GridView &G, const DomainView &D, cons
   }
   if (!nt && !POW) cell_job = false;
   for (;;) {
+    asm volatile("" : "+s"(Gp), "+s"(Dp));
+    const GridView &G = *Gp;
+    const DomainView &D = *Dp;
     int a = -1, npl = 4, nc = 4;
     bool empty = false, need_carve = true;
     if (cell_job) {
