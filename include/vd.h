@@ -136,6 +136,13 @@ typedef struct {
                                  needed: a cell is interior when all its corners lie in M.  Per-site
                                  moments and neighbour lists equal those of the default up to
                                  rounding.  Default 0: every piece is T_a cap Omega_i. */
+  int32_t batch_order;        /* batches of tetrahedral domains.  1 (default): the persistent
+                                 kernel's queues hand out the sites of the diagrams with the most
+                                 tetrahedra per site (the most pieces per cell) first, diagrams
+                                 dealt over the queues by longest processing time, so the last
+                                 sites to finish are cheap ones; the order is built by a
+                                 synchronous clip and kept in the handle for later (no_sync)
+                                 clips of the same layout.  0: grid order.  Same results. */
 } vd_options;
 
 void vd_options_default(vd_options *opt);

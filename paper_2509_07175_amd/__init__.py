@@ -41,7 +41,7 @@ class Options(C.Structure):
                 ("emit_polytopes", C.c_int32), ("want_grad", C.c_int32), ("time_kernels", C.c_int32),
                 ("carve_mode", C.c_int32), ("no_sync", C.c_int32), ("site_cache", C.c_int32),
                 ("boundary_seeds", C.c_int32), ("monitor", C.c_int32), ("use_density", C.c_int32),
-                ("density", C.c_double * 10), ("whole_interior", C.c_int32)]
+                ("density", C.c_double * 10), ("whole_interior", C.c_int32), ("batch_order", C.c_int32)]
 
     @classmethod
     def default(cls, **kw) -> "Options":

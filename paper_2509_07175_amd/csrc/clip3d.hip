@@ -1361,10 +1361,14 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3)))
   arena_close(S.ar, C);
 }
 
-__global__ void queue_init(int *q, long long n) {
+struct QueueStarts {
+  long long off[VD_QUEUES];
+  int given;
+};
+__global__ void queue_init(int *q, long long n, QueueStarts qs) {
   const int k = threadIdx.x;
   const long long q8 = (n + VD_QUEUES - 1) / VD_QUEUES;
-  if (k < VD_QUEUES) q[k * VD_QSTRIDE] = (int)(k * q8 < n ? k * q8 : n);
+  if (k < VD_QUEUES) q[k * VD_QSTRIDE] = (int)(qs.given ? qs.off[k] : (k * q8 < n ? k * q8 : n));
 }
 
 int resident_workgroups() {
@@ -1390,8 +1394,13 @@ int vd_sites3d_workgroups(long long n) {
   return (int)(n < w ? (n > 0 ? n : 1) : w);
 }
 
-void vd_launch_queue_init(int *queue, long long n, hipStream_t st) {
-  hipLaunchKernelGGL(queue_init, dim3(1), dim3(64), 0, st, queue, n);
+// qoff: the first position of each queue in the batch's work order, or NULL
+void vd_launch_queue_init(int *queue, long long n, const long long *qoff, hipStream_t st) {
+  QueueStarts qs{};
+  qs.given = qoff ? 1 : 0;
+  if (qoff)
+    for (int k = 0; k < VD_QUEUES; k++) qs.off[k] = qoff[k];
+  hipLaunchKernelGGL(queue_init, dim3(1), dim3(64), 0, st, queue, n, qs);
 }
 
 void vd_launch_sites3d(const GridView &G, const DomainView &D, const CellsDev *Cdev, int workgroups, bool monitor,

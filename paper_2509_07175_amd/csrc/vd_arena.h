@@ -13,7 +13,9 @@
 // items in order; workgroup b starts on queue b % 8 (the XCD it runs on when
 // workgroups are dealt round-robin over the 8 XCDs), so an XCD works through a
 // contiguous block of grid-ordered sites and keeps their neighbourhoods in its
-// L2.  A wave whose queue is exhausted moves on to the next queue.
+// L2.  A wave whose queue is exhausted moves on to the next queue.  A batch
+// can instead give each queue a list of positions (C.order), so that every
+// queue starts with its most expensive diagrams.
 #pragma once
 #include "vd_internal.h"
 
@@ -67,10 +69,11 @@ __device__ __forceinline__ int queue_next(WaveArena &A, const CellsDev &C, long 
     const int x = (int)(blockIdx.x % VD_QUEUES);
     for (; A.qi < VD_QUEUES; A.qi++) {
       const int k = (x + A.qi) % VD_QUEUES;
-      const long long end = (k + 1) * q8 < n ? (k + 1) * q8 : n;
-      if (k * q8 >= end) continue;
+      const long long beg = C.order ? C.qoff[k] : k * q8;
+      const long long end = C.order ? C.qoff[k + 1] : ((k + 1) * q8 < n ? (k + 1) * q8 : n);
+      if (beg >= end) continue;
       const int v = __hip_atomic_fetch_add(GL(C.queue) + k * VD_QSTRIDE, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (v < end) { r = v; break; }
+      if (v < end) { r = C.order ? GL(C.order)[v] : v; break; }
     }
   }
   return __builtin_amdgcn_readlane(r, 0);

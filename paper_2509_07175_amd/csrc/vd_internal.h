@@ -216,6 +216,11 @@ struct CellsDev {
   const int *bseed_pid, *bseed_tri, *btet;
   long long chunk[AR_N];  // slots a wave reserves at a time in each arena
   int *queue;             // [VD_QUEUES * VD_QSTRIDE] work-queue heads
+  // batches: the sorted positions in the order the queues hand them out
+  // (NULL: queue k owns the k-th eighth of the sites in grid order), queue k
+  // owning order[qoff[k] .. qoff[k+1])
+  const int *order;
+  long long qoff[VD_QUEUES + 1];
   int *tq_spill;          // [workgroups * q_spill] overflow of the per-site simplex queue
   int *nb_spill;          // [workgroups * nbs_cap] overflow of the per-site neighbour list
   int q_spill, nbs_cap;   // entries per workgroup of the two overflow buffers
@@ -249,6 +254,10 @@ struct vd_cells_s {
   int64_t cap_spill = 0;      // workgroups covered by d.tq_spill / d.nb_spill / d.saved
   int q_spill_want = VD_Q_SPILL, nb_spill_want = VD_NB_SPILL;  // per-workgroup sizes (grow on retry)
   int64_t sq_spill_elems = 0;  // allocated entries of d.sq_spill
+  int *order_buf = nullptr;     // d.order's storage, and the batch layout it was built for
+  int64_t order_cap = 0;
+  std::vector<int64_t> order_key;
+  std::vector<long long> order_qoff;
   int sq_spill_want = 0;       // surface: per-workgroup entries of d.sq_spill (grow on retry)
   CellsDev d_shadow{};        // host copy last sent to d_dev
   double *wbuf = nullptr;     // adjoint weights [5n]
@@ -390,7 +399,7 @@ void vd_launch_domain_locator(vd_domain d, hipStream_t st);
 void vd_launch_locate_sites(const GridView &G, const DomainView &D, int *seed, int *outside, hipStream_t st);
 // workgroups of the persistent 3D site kernel (resident waves of the device)
 int vd_sites3d_workgroups(long long n);
-void vd_launch_queue_init(int *queue, long long n, hipStream_t st);
+void vd_launch_queue_init(int *queue, long long n, const long long *qoff, hipStream_t st);
 void vd_launch_sites3d(const GridView &G, const DomainView &D, const CellsDev *Cdev, int workgroups, bool monitor,
                        bool density, bool power, bool corners, hipStream_t st);
 int vd_surface_workgroups(long long m);

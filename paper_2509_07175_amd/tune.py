@@ -4,8 +4,10 @@ The knobs are the ones that change the work of a wavefront without changing
 any result: the grid density (sites per cell, which sets the candidates per
 nearest-site query and the block of cells a wave keeps in LDS), the per-wave
 LDS site cache (on: 128 sites, 3.7 KB of LDS per wave; off: grid queries only), the
-improved search of Sec. 6.1 and the choice of straddling edges (Alg. 1) over
-virtual edges (Alg. 3).  Every candidate is run once synchronously with kernel
+improved search of Sec. 6.1, the choice of straddling edges (Alg. 1) over
+virtual edges (Alg. 3) and, for a batch, the order in which the persistent
+kernel's queues hand out the diagrams (most tetrahedra per site first, or grid
+order).  Every candidate is run once synchronously with kernel
 timing (hipEvents on the caller's stream); the fastest wins.  Results are
 identical for every candidate, so the tuner can run on the real input.
 """
@@ -31,7 +33,11 @@ def tune(sites, domain, site_off=None, bboxes=None, bbox=None, space: dict | Non
     import torch
 
     from . import Cells, Grid, Options, build_grid, build_grid_batch, clip_cells
-    space = dict(DEFAULT_SPACE if space is None else space)
+    if space is None:
+        space = dict(DEFAULT_SPACE)
+        if site_off is not None:
+            space["batch_order"] = (1, 0)
+    space = dict(space)
     keys = list(space)
     table = []
     grid, cells = Grid(), Cells()

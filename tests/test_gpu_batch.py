@@ -236,3 +236,17 @@ def test_batched_workload_full_size(oracle_mod):
         assert_sampled_parity(got, mass, cent, en, nbo, nb, ref, mom, sample, site_lo=lo)
         npieces += len(ref["piece_site"])
     log(f"batch: {20 * len(items)} sites, {npieces} pieces identical")
+
+
+def test_batch_order_gives_identical_results():
+    """The cost-sorted work order of the batch queues (most tetrahedra per site
+    first, diagrams dealt by longest processing time) against grid order: the
+    same pieces, moments and neighbour lists, bit for bit."""
+    items = _small_batch(seed=15)
+    a = _run_batch(items, batch_order=1)
+    b = _run_batch(items, batch_order=0)
+    assert np.array_equal(a["mass"], b["mass"]) and np.array_equal(a["centroid"], b["centroid"])
+    assert np.array_equal(a["energy"], b["energy"])
+    assert np.array_equal(a["nbr_off"], b["nbr_off"]) and np.array_equal(a["nbr"], b["nbr"])
+    for k in ("piece_site", "piece_simplex", "piece_mass", "face_label", "vert_xyz"):
+        assert np.array_equal(a["res"][k], b["res"][k]), k
