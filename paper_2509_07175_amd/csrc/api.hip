@@ -647,6 +647,7 @@ hipError_t alloc_cells(vd_cells c, int64_t n, const Caps &want) {
     t = 0; if ((e = ensure(d.piece_mom, t, 3 * want.piece)) != hipSuccess) return e;
     t = 0; if ((e = ensure(d.piece_energy, t, want.piece)) != hipSuccess) return e;
     t = 0; if ((e = ensure(c->piece_id, t, want.piece)) != hipSuccess) return e;
+    t = 0; if ((e = ensure(c->pid_tmp, t, want.piece)) != hipSuccess) return e;
     t = 0; if ((e = ensure(d.piece_fint_start, t, want.piece)) != hipSuccess) return e;
     t = 0; if ((e = ensure(d.piece_nfint, t, want.piece)) != hipSuccess) return e;
     d.cap_piece = want.piece;
@@ -1105,6 +1106,7 @@ void vd_cells_free(vd_cells c) {
   CellsDev &d = c->d;
   hipFree(d.cnt); hipFree(d.mass); hipFree(d.mom); hipFree(d.energy); hipFree(d.pcount); hipFree(d.ncount);
   hipFree(d.pstart); hipFree(d.nstart); hipFree(d.nbr_arena); hipFree(d.piece_site); hipFree(c->fillc);
+  hipFree(c->pid_tmp);
   hipFree(d.piece_simplex); hipFree(d.piece_nface); hipFree(d.piece_nvert); hipFree(d.piece_fstart);
   hipFree(d.piece_vstart); hipFree(d.piece_mass); hipFree(d.piece_mom); hipFree(d.piece_energy);
   hipFree(d.face_label); hipFree(d.vert_xyz); hipFree(d.vert_label); hipFree(d.fint); hipFree(d.seed);

@@ -7,6 +7,7 @@
 // the per-site mass / first moment / energy sums (accumulated in a fixed order
 // inside each wave) into mass, centroid and energy.
 #include <algorithm>
+#include <climits>
 
 #include "vd_internal.h"
 #include "vd_scan.h"
@@ -42,19 +43,71 @@ __global__ void __launch_bounds__(kB) scatter_pieces(const unsigned long long *_
   out[off[s] + atomicAdd(&fill[s], 1)] = (int)p;
 }
 
-// each site's pieces by ascending simplex index (insertion sort: a site has a
-// few dozen pieces at most)
+// Each site's pieces by ascending simplex index, from `in` (grouped by site)
+// to `out`: a piece's position is the number of the site's pieces with a
+// smaller key (a site has at most one piece per simplex; equal keys would
+// keep their order in `in`).  Sites have from one to a few hundred pieces, so
+// a 16-lane group ranks a site of up to 16 pieces by lane shuffles, four
+// sites per wave, and the whole wave takes the larger ones, 64 pieces at a
+// time against all of the site's keys.
+constexpr int kSortWaves = kB / 64;
+constexpr int kSmall = 16;
+__device__ __forceinline__ void rank_segment_wave(long long a, int k, const int *__restrict__ simplex,
+                                                  const int *__restrict__ in, int *__restrict__ out) {
+  const int l = threadIdx.x & 63;
+  for (int x0 = 0; x0 < k; x0 += 64) {
+    const int x = x0 + l;
+    int id = 0, key = INT_MAX;
+    if (x < k) {
+      id = in[a + x];
+      key = simplex[id];
+    }
+    int rk = 0;
+    for (int y0 = 0; y0 < k; y0 += 64) {
+      int ky = key;
+      if (y0 != x0) ky = y0 + l < k ? simplex[in[a + y0 + l]] : INT_MAX;
+      const int lim = k - y0 < 64 ? k - y0 : 64;
+      for (int o = 0; o < lim; o++) {
+        const int kk = __builtin_amdgcn_readlane(ky, o);
+        rk += (kk < key || (kk == key && y0 + o < x)) ? 1 : 0;
+      }
+    }
+    if (x < k) out[a + rk] = id;
+  }
+}
+
 __global__ void __launch_bounds__(kB) sort_segments(long long n, const long long *__restrict__ off,
-                                                    const int *__restrict__ simplex, int *__restrict__ ids) {
-  const long long i = (long long)blockIdx.x * kB + threadIdx.x;
-  if (i >= n) return;
-  const long long a = off[i], b = off[i + 1];
-  for (long long x = a + 1; x < b; x++) {
-    const int id = ids[x];
-    const int key = simplex[id];
-    long long y = x - 1;
-    while (y >= a && simplex[ids[y]] > key) { ids[y + 1] = ids[y]; y--; }
-    ids[y + 1] = id;
+                                                    const int *__restrict__ simplex, const int *__restrict__ in,
+                                                    int *__restrict__ out) {
+  const int l = threadIdx.x & 63, g = l / kSmall, gl = l % kSmall;
+  const long long nw = (long long)gridDim.x * kSortWaves;
+  for (long long s0 = ((long long)blockIdx.x * kSortWaves + threadIdx.x / 64) * 4; s0 < n; s0 += 4 * nw) {
+    const long long s = s0 + g;
+    long long a = 0;
+    int k = 0;
+    if (s < n) {
+      a = off[s];
+      k = (int)(off[s + 1] - a);
+    }
+    const bool small = k <= kSmall;
+    int id = 0, key = INT_MAX;
+    if (small && gl < k) {
+      id = in[a + gl];
+      key = simplex[id];
+    }
+    int rk = 0;
+#pragma unroll
+    for (int o = 0; o < kSmall; o++) {
+      const int kk = __shfl(key, (l & ~(kSmall - 1)) + o, 64);
+      rk += (kk < key || (kk == key && o < gl)) ? 1 : 0;
+    }
+    if (small && gl < k) out[a + rk] = id;
+    for (uint64_t big = __ballot(!small && gl == 0); big; big &= big - 1) {
+      const int src = __ffsll((unsigned long long)big) - 1;
+      const long long ab = ((long long)__builtin_amdgcn_readlane((int)(a >> 32), src) << 32) |
+                           (unsigned)__builtin_amdgcn_readlane((int)a, src);
+      rank_segment_wave(ab, __builtin_amdgcn_readlane(k, src), simplex, in, out);
+    }
   }
 }
 
@@ -98,9 +151,13 @@ void vd_launch_finalize(vd_cells c, hipStream_t st) {
   vd_launch_fill_int(c->fillc, n, 0, st);
   hipLaunchKernelGGL(scatter_pieces, dim3(blocks(npieces)), dim3(kB), 0, st, (const unsigned long long *)d.cnt,
                      (long long)d.cap_piece, (const int *)d.piece_site,
-                     (const long long *)c->piece_off, c->fillc, c->piece_id);
-  hipLaunchKernelGGL(sort_segments, dim3(blocks(n)), dim3(kB), 0, st, n, (const long long *)c->piece_off,
-                     (const int *)d.piece_simplex, c->piece_id);
+                     (const long long *)c->piece_off, c->fillc, c->pid_tmp);
+  {
+    const long long groups = (n + 4 * kSortWaves - 1) / (4 * kSortWaves);
+    const unsigned nblk = (unsigned)std::max<long long>(1, std::min<long long>(groups, 8192));
+    hipLaunchKernelGGL(sort_segments, dim3(nblk), dim3(kB), 0, st, n, (const long long *)c->piece_off,
+                       (const int *)d.piece_simplex, (const int *)c->pid_tmp, c->piece_id);
+  }
   // surfaces: per-site sums and neighbour lists from the pieces, in CSR order
   if (c->dim == 2) {
     vd_launch_site_reduce(n, c->piece_off, c->piece_id, c->d_dev, st);

@@ -242,6 +242,7 @@ struct vd_cells_s {
   long long *piece_off = nullptr, *nbr_off = nullptr;  // CSR [n+1]
   int *piece_id = nullptr, *nbr = nullptr;             // CSR payloads
   int *fillc = nullptr;                                // per-site scatter counters
+  int *pid_tmp = nullptr;                              // piece ids grouped by site, before the sort
   long long *scan_tmp = nullptr;
   int64_t cap_pid = 0, cap_nbr_csr = 0;
   const double *sites_sorted_x = nullptr;  // borrowed from the grid for moments
