@@ -151,6 +151,21 @@ __global__ void __launch_bounds__(kB) loc_fill(LocArgs L, const int *__restrict_
 // tetrahedra of its location cell whose barycentric coordinates are all
 // >= -1e-12 (relative); -1 for a site outside M (counted in outside[0]; the
 // lowest such caller index in outside[1], which starts at INT_MAX).
+// the tetrahedra of each location cell in ascending index order, so that a
+// scan for the lowest-index tetrahedron containing a point stops at its
+// first hit (insertion sort: a cell lists a few tetrahedra)
+__global__ void __launch_bounds__(kB) loc_sort(const int *__restrict__ start, long long ncell, int *__restrict__ items) {
+  const long long c = (long long)blockIdx.x * kB + threadIdx.x;
+  if (c >= ncell) return;
+  const int a = start[c], b = start[c + 1];
+  for (int x = a + 1; x < b; x++) {
+    const int v = items[x];
+    int y = x - 1;
+    while (y >= a && items[y] > v) { items[y + 1] = items[y]; y--; }
+    items[y + 1] = v;
+  }
+}
+
 __global__ void __launch_bounds__(kB) locate_sites(GridView G, DomainView Dall, int *__restrict__ seed,
                                                    int *__restrict__ outside) {
   const long long p = (long long)blockIdx.x * kB + threadIdx.x;
@@ -169,9 +184,9 @@ __global__ void __launch_bounds__(kB) locate_sites(GridView G, DomainView Dall, 
   for (int k = 0; k < 3; k++) cc[k] = cell_coord(q[k], D.lgeom[k], D.lgeom[6 + k], D.lg[k]);
   const int c = cc[0] + D.lg[0] * (cc[1] + D.lg[1] * cc[2]);
   int best = -1;
-  for (int t = D.lstart[c]; t < D.lstart[c + 1]; t++) {
+  // the cell's tetrahedra in ascending order: the first that holds q is the lowest
+  for (int t = D.lstart[c]; t < D.lstart[c + 1] && best < 0; t++) {
     const int a = D.litems[t];
-    if (best >= 0 && a >= best) continue;
     const double *P[4];
     for (int u = 0; u < 4; u++) P[u] = &D.verts[3 * (long long)D.simp[(long long)a * 4 + u]];
     double vol6;
@@ -399,6 +414,8 @@ void vd_launch_domain_locator(vd_domain d, hipStream_t st) {
 
 void vd_launch_domain_fill(vd_domain d, hipStream_t st) {
   hipLaunchKernelGGL(loc_fill, dim3(blocks(d->m)), dim3(kB), 0, st, loc_args(d), (const int *)d->lstart, d->lfill,
+                     d->litems);
+  hipLaunchKernelGGL(loc_sort, dim3(blocks(d->ncell)), dim3(kB), 0, st, (const int *)d->lstart, (long long)d->ncell,
                      d->litems);
 }
 
