@@ -97,9 +97,10 @@ typedef struct {
                                  surface neighbour lists included) are reported by
                                  vd_cells_info, which then synchronises the stream.  Default 0. */
   int32_t site_cache;         /* 1 (default): each wave keeps the sites of a block of grid
-                                 cells around its site in LDS and answers a nearest-site
-                                 query there when the query's ball lies inside the block
-                                 (same answer as the grid query); 0: grid queries only */
+                                 cells around its site (3D) or its triangle's centroid
+                                 (surfaces) in LDS and answers a nearest-site query there
+                                 when the query's ball lies inside the block (same answer as
+                                 the grid query); 0: grid queries only */
   int32_t boundary_seeds;     /* tetrahedral domains.  A cell Omega_i cap M can have parts that
                                  are not connected to the tetrahedron holding v_i (a non-convex
                                  M), and a site may lie outside M.  Such parts touch the boundary

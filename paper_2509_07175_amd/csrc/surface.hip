@@ -13,6 +13,9 @@
 //
 // Polygon layout in LDS: lane t owns vertex t (up to 64); vertex t lies on the
 // supporting plane and on the planes of the edges t-1 -> t and t -> t+1.
+// The nearest-site queries of a triangle's pieces go to an LDS cache of the
+// sites around its centroid (the 3D kernel's cache, with its exact witness
+// and coverage tests), and to the grid when the cache cannot decide.
 // Per-site sums (mass, centroid, energy, neighbours) are formed afterwards
 // from the pieces in a fixed order (site_reduce), so results do not depend on
 // the order in which waves finish.
@@ -33,7 +36,11 @@ struct __align__(16) TriLds {
   int vst[kSV];       // bit 0 inside, bit 1 tested, bits 8.. nearest site + 1
   int sq[kSS];        // first sites of this triangle (sorted positions), breadth-first
   WaveArena ar;       // output chunks, queue position, statistics
+  SiteCache K;        // sites around the triangle's centroid for the nearest-site queries
 };
+static_assert(offsetof(TriLds, vy) == offsetof(TriLds, pn) + sizeof(double) * kSP * 4 &&
+                  kSP * 4 + kSV * 3 >= VD_CACHE_SCRATCH,
+              "the polygon arrays double as the site cache's fill scratch");
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ uint64_t lowm(int k) { return k >= 64 ? ~0ull : ((1ull << k) - 1ull); }
@@ -283,7 +290,17 @@ __device__ int carve_s(TriLds &S, const GridView &G, const SParams C, int si, do
       const double qw = mode == SEARCH ? q4 : 0.0, dw = qw - hi_;
       kq = nn_query<true>(G, gs, qx, qy, qz, dx * dx + dy * dy + dz * dz + dw * dw, si, ss.cands, qw);
     } else {
-      kq = nn_query(G, gs, qx, qy, qz, dx * dx + dy * dy + dz * dz, si, ss.cands);
+      // sites the test treats like v_i: the flags of the vertex's two edges
+      // (TEST), the edge's flag (LAMBDA), and the candidate (SEARCH)
+      int e0 = ef0, e1 = -1, e2 = mode == SEARCH ? j : -1;
+      if (mode == TEST) {
+        const int ts = tslot >= 0 ? tslot : 0;
+        e0 = S.plab[S.ve[(ts + nv - 1) % nv]];
+        e1 = S.plab[S.ve[ts]];
+      }
+      bool on_grid;
+      kq = nn_cached(S.K, G, gs, qx, qy, qz, dx * dx + dy * dy + dz * dz, si, e0 < 0 ? -1 : e0, e1 < 0 ? -1 : e1,
+                     e2 < 0 ? -1 : e2, -1, -1, -1, ss.cands, on_grid);
     }
     if (mode == TEST) {
       ss.queries += nbatch;
@@ -386,6 +403,14 @@ __device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, c
                  p2 = &GL(D.verts)[3 * (long long)tv[2]];
     const double cx = (p0[0] + p1[0] + p2[0]) / 3.0, cy = (p0[1] + p1[1] + p2[1]) / 3.0,
                  cz = (p0[2] + p1[2] + p2[2]) / 3.0;
+    // the sites around the centroid, for the queries of every piece of T_a
+    // (the polygon arrays are free until the first piece)
+    if (!POW && C.cache) {
+      cache_fill(S.K, G, cx, cy, cz, &S.pn[0][0]);
+    } else {
+      if (l == 0) S.K.cnt = -1;
+      __syncthreads();
+    }
     const int k = uni(nn_query<POW>(G, 64, cx, cy, cz, 1e300, -1, ss.cands, 0.0));
     ss.queries++;
     if (k >= 0) {
