@@ -35,6 +35,7 @@ struct __align__(16) TriLds {
   int ve[kSV];        // plane slot of the edge from vertex t to vertex t+1
   int vst[kSV];       // bit 0 inside, bit 1 tested, bits 8.. nearest site + 1
   int sq[kSS];        // first sites of this triangle (sorted positions), breadth-first
+  int sqf[kSS];       // the site whose piece's edge flag listed each of them (-1: the seed)
   WaveArena ar;       // output chunks, queue position, statistics
   SiteCache K;        // sites around the triangle's centroid for the nearest-site queries
 };
@@ -377,11 +378,14 @@ __device__ __forceinline__ bool sq_has(const TriLds &S, const CellsDev &C, int n
 }
 
 // Append site j; false when the overflow buffer is full.
-__device__ __forceinline__ bool sq_push(TriLds &S, const CellsDev &C, int &nsq, int j) {
+__device__ __forceinline__ bool sq_push(TriLds &S, const CellsDev &C, int &nsq, int j, int from) {
   if (nsq >= kSS + C.sq_cap) return false;
   __syncthreads();
   if (vd_lane() == 0) {
-    if (nsq < kSS) S.sq[nsq] = j;
+    if (nsq < kSS) {
+      S.sq[nsq] = j;
+      S.sqf[nsq] = from;
+    }
     else GL(C.sq_spill)[(long long)blockIdx.x * C.sq_cap + (nsq - kSS)] = j;
   }
   nsq++;
@@ -414,7 +418,10 @@ __device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, c
     const int k = uni(nn_query<POW>(G, 64, cx, cy, cz, 1e300, -1, ss.cands, 0.0));
     ss.queries++;
     if (k >= 0) {
-      if (l == 0) S.sq[0] = k;
+      if (l == 0) {
+        S.sq[0] = k;
+        S.sqf[0] = -1;
+      }
       nsq = 1;
     } else {
       err = 3;
@@ -424,11 +431,37 @@ __device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, c
   int where = VD_STAGE_TRIANGLE;
   while (head < nsq && !err) {
     const int si = uni(sq_get(S, C, head));
+    const int from = head < kSS ? uni(S.sqf[head]) : -1;
     head++;
     const double vx = GL(G.sx)[si], vy = GL(G.sy)[si], vz = GL(G.sz)[si], delta = GL(G.delta)[si];
     init_tri(S, D, a, vx, vy, vz);
     int npl = 4, nv = 3;
-    const int rc = carve_s<POW>(S, G, P, si, vx, vy, vz, delta, npl, nv, ss);
+    int rc = 0;
+    if (from >= 0) {
+      // the piece of `from` has an edge on the bisector with si inside T_a,
+      // so that bisector bounds this piece too: clip by it before the carve
+      // instead of finding it by tests and a search
+      if (l == 0) {
+        const double n0 = GL(G.sx)[from] - vx, n1 = GL(G.sy)[from] - vy, n2 = GL(G.sz)[from] - vz;
+        S.pn[4][0] = n0; S.pn[4][1] = n1; S.pn[4][2] = n2;
+        S.pn[4][3] = 0.5 * (n0 * n0 + n1 * n1 + n2 * n2 + (POW ? GL(G.sw)[si] - GL(G.sw)[from] : 0.0));
+        S.plab[4] = from;
+      }
+      __syncthreads();
+      npl = 5;
+      rc = clip_s(S, C.monitor, 4, -1, nv);
+      if (rc == 4) ss.clips++;
+      if (rc == 4 || rc == 0) {
+        rc = 0;
+      } else if (rc != 1) {
+        // a degenerate cut: carve the piece from T_a alone
+        init_tri(S, D, a, vx, vy, vz);
+        npl = 4;
+        nv = 3;
+        rc = 0;
+      }
+    }
+    if (rc == 0) rc = carve_s<POW>(S, G, P, si, vx, vy, vz, delta, npl, nv, ss);
     if (rc == 1) continue;
     if (rc) { err = rc; break; }
     // ---- moments: fan from corner 0 of the piece, so that the area's rounding
@@ -561,7 +594,7 @@ __device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, c
     for (; pos; pos &= pos - 1) {
       const int t = __ffsll((unsigned long long)pos) - 1;
       const int j = __builtin_amdgcn_readlane(lab, t);
-      if (!sq_has(S, C, nsq, j) && !sq_push(S, C, nsq, j)) {
+      if (!sq_has(S, C, nsq, j) && !sq_push(S, C, nsq, j, si)) {
         err = 2;
         where = VD_STAGE_TRIANGLE_SITES;
         break;
