@@ -35,7 +35,8 @@ struct __align__(16) TriLds {
   int ve[kSV];        // plane slot of the edge from vertex t to vertex t+1
   int vst[kSV];       // bit 0 inside, bit 1 tested, bits 8.. nearest site + 1
   int sq[kSS];        // first sites of this triangle (sorted positions), breadth-first
-  int sqf[kSS];       // the site whose piece's edge flag listed each of them (-1: the seed)
+  int sqf[kSS];       // the site whose piece's edge flag listed each of them (-1: the seed) ...
+  int sqf2[kSS];      // ... and a second one that flagged it before its turn (-1: none)
   WaveArena ar;       // output chunks, queue position, statistics
   SiteCache K;        // sites around the triangle's centroid for the nearest-site queries
 };
@@ -371,10 +372,15 @@ __device__ __forceinline__ int sq_get(const TriLds &S, const CellsDev &C, int e)
 }
 
 // Is site j in the list?  (The whole wave scans; the answer is wave-uniform.)
-__device__ __forceinline__ bool sq_has(const TriLds &S, const CellsDev &C, int nsq, int j) {
-  bool have = false;
-  for (int e = vd_lane(); e < nsq; e += 64) have = have || (sq_get(S, C, e) == j);
-  return __ballot(have) != 0ull;
+// Position of site j in the list, or -1.  (The whole wave scans; the answer
+// is wave-uniform.)
+__device__ __forceinline__ int sq_find(const TriLds &S, const CellsDev &C, int nsq, int j) {
+  for (int e0 = 0; e0 < nsq; e0 += 64) {
+    const int e = e0 + vd_lane();
+    const uint64_t m = __ballot(e < nsq && sq_get(S, C, e) == j);
+    if (m) return e0 + __ffsll((unsigned long long)m) - 1;
+  }
+  return -1;
 }
 
 // Append site j; false when the overflow buffer is full.
@@ -385,6 +391,7 @@ __device__ __forceinline__ bool sq_push(TriLds &S, const CellsDev &C, int &nsq, 
     if (nsq < kSS) {
       S.sq[nsq] = j;
       S.sqf[nsq] = from;
+      S.sqf2[nsq] = -1;
     }
     else GL(C.sq_spill)[(long long)blockIdx.x * C.sq_cap + (nsq - kSS)] = j;
   }
@@ -420,7 +427,7 @@ __device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, c
     if (k >= 0) {
       if (l == 0) {
         S.sq[0] = k;
-        S.sqf[0] = -1;
+        S.sqf[0] = S.sqf2[0] = -1;
       }
       nsq = 1;
     } else {
@@ -431,25 +438,29 @@ __device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, c
   int where = VD_STAGE_TRIANGLE;
   while (head < nsq && !err) {
     const int si = uni(sq_get(S, C, head));
-    const int from = head < kSS ? uni(S.sqf[head]) : -1;
+    const int from = head < kSS ? uni(S.sqf[head]) : -1, from2 = head < kSS ? uni(S.sqf2[head]) : -1;
     head++;
     const double vx = GL(G.sx)[si], vy = GL(G.sy)[si], vz = GL(G.sz)[si], delta = GL(G.delta)[si];
     init_tri(S, D, a, vx, vy, vz);
     int npl = 4, nv = 3;
     int rc = 0;
-    if (from >= 0) {
-      // the piece of `from` has an edge on the bisector with si inside T_a,
-      // so that bisector bounds this piece too: clip by it before the carve
-      // instead of finding it by tests and a search
+    // the pieces already carved in T_a that have an edge on a bisector with si
+    // (the one that listed si, and one more that flagged it before its turn):
+    // those bisectors bound this piece too, so clip by them before the carve
+    // instead of finding them by tests and searches
+    for (int f = 0; f < 2 && rc == 0; f++) {
+      const int nb = f == 0 ? from : from2;
+      if (nb < 0) continue;
+      __syncthreads();
       if (l == 0) {
-        const double n0 = GL(G.sx)[from] - vx, n1 = GL(G.sy)[from] - vy, n2 = GL(G.sz)[from] - vz;
-        S.pn[4][0] = n0; S.pn[4][1] = n1; S.pn[4][2] = n2;
-        S.pn[4][3] = 0.5 * (n0 * n0 + n1 * n1 + n2 * n2 + (POW ? GL(G.sw)[si] - GL(G.sw)[from] : 0.0));
-        S.plab[4] = from;
+        const double n0 = GL(G.sx)[nb] - vx, n1 = GL(G.sy)[nb] - vy, n2 = GL(G.sz)[nb] - vz;
+        S.pn[npl][0] = n0; S.pn[npl][1] = n1; S.pn[npl][2] = n2;
+        S.pn[npl][3] = 0.5 * (n0 * n0 + n1 * n1 + n2 * n2 + (POW ? GL(G.sw)[si] - GL(G.sw)[nb] : 0.0));
+        S.plab[npl] = nb;
       }
       __syncthreads();
-      npl = 5;
-      rc = clip_s(S, C.monitor, 4, -1, nv);
+      rc = clip_s(S, C.monitor, npl, -1, nv);
+      npl++;
       if (rc == 4) ss.clips++;
       if (rc == 4 || rc == 0) {
         rc = 0;
@@ -459,6 +470,7 @@ __device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, c
         npl = 4;
         nv = 3;
         rc = 0;
+        break;
       }
     }
     if (rc == 0) rc = carve_s<POW>(S, G, P, si, vx, vy, vz, delta, npl, nv, ss);
@@ -594,10 +606,15 @@ __device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, c
     for (; pos; pos &= pos - 1) {
       const int t = __ffsll((unsigned long long)pos) - 1;
       const int j = __builtin_amdgcn_readlane(lab, t);
-      if (!sq_has(S, C, nsq, j) && !sq_push(S, C, nsq, j, si)) {
-        err = 2;
-        where = VD_STAGE_TRIANGLE_SITES;
-        break;
+      const int at = sq_find(S, C, nsq, j);
+      if (at < 0) {
+        if (!sq_push(S, C, nsq, j, si)) {
+          err = 2;
+          where = VD_STAGE_TRIANGLE_SITES;
+          break;
+        }
+      } else if (at >= head && at < kSS && l == 0 && S.sqf2[at] < 0 && S.sqf[at] != si) {
+        S.sqf2[at] = si;  // a second known edge of j's piece, not yet carved
       }
     }
     __syncthreads();
