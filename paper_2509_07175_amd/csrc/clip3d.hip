@@ -968,6 +968,64 @@ __device__ __forceinline__ bool cell_in_domain(const WaveLds &S, const DomainVie
   return !__ballot(out);
 }
 
+// Gabriel neighbours among the first kGabriel cache entries (distance-bucket
+// order): a site v_j whose ball on the diameter [v_i, v_j] holds no other site
+// (and lies inside the cached radius, so every site that could be in it is
+// cached) has the midpoint of v_i v_j on the face of Omega_i towards it, so
+// the bisector B_ij is a face plane of the cell and a valid clip (Alg. 1 only
+// clips by faces).  The polytope (the box) is clipped by every such bisector
+// before the carve, which then finds the other faces by its tests and
+// searches.  Returns 0, or a clip's failure (the caller then carves the box
+// without these clips).
+constexpr int kGabriel = 32;
+template <bool MON>
+__device__ int gabriel_clips(WaveLds &S, const SiteCtx &X, int &npl, int &nc, Stats &st) {
+  const int l = vd_lane();
+  const int n = S.K.cnt;
+  const int T = n < kGabriel ? n : kGabriel;
+  if (T <= 0) return 0;
+  // sites nearer to v_i than the farthest candidate lie below position E
+  const int kbT = S.K.kb[T - 1];
+  int E = n;
+  {
+    const uint64_t a = __ballot(l < n && S.K.kb[l] > kbT);
+    const uint64_t b = __ballot(l + 64 < n && S.K.kb[l + 64] > kbT);
+    if (a) E = __ffsll((unsigned long long)a) - 1;
+    else if (b) E = 64 + __ffsll((unsigned long long)b) - 1;
+  }
+  const double rc2 = S.K.rc * S.K.rc;
+  double jx = 0, jy = 0, jz = 0, dj2 = 0;
+  bool gab = false;
+  if (l < T) {
+    jx = S.K.x[l] - X.vx; jy = S.K.y[l] - X.vy; jz = S.K.z[l] - X.vz;
+    dj2 = jx * jx + jy * jy + jz * jz;
+    gab = dj2 > 0.0 && dj2 < rc2 * (1.0 - 1e-9);
+  }
+  const double mx = 0.5 * jx, my = 0.5 * jy, mz = 0.5 * jz, r2 = 0.25 * dj2 * (1.0 + 1e-9);
+  for (int k = 0; k < E; k++) {
+    const double kx = S.K.x[k] - X.vx, ky = S.K.y[k] - X.vy, kz = S.K.z[k] - X.vz;
+    const double ex = kx - mx, ey = ky - my, ez = kz - mz;
+    const bool self = kx == 0.0 && ky == 0.0 && kz == 0.0;
+    if (k != l && !self && ex * ex + ey * ey + ez * ez <= r2) gab = false;
+  }
+  for (uint64_t m = __ballot(gab); m; m &= m - 1) {
+    const int c = __ffsll((unsigned long long)m) - 1;
+    if (npl >= VD_P_MAX) return 2;
+    const int P = npl++;
+    __syncthreads();
+    if (l == c) {
+      S.pn[P][0] = jx; S.pn[P][1] = jy; S.pn[P][2] = jz; S.pn[P][3] = 0.5 * dj2;
+      S.plab[P] = S.K.p[c];
+      S.psl[P] = c;
+    }
+    __syncthreads();
+    const int rc = clip_poly<MON>(S, P, -1, nc);
+    if (rc == 4) st.clips++;
+    else if (rc != 0) return rc;
+  }
+  return 0;
+}
+
 // Neighbour e of the site's list: the first VD_NB_MAX in LDS, the rest in this
 // wave's part of a global buffer.
 __device__ __forceinline__ int nb_get(const WaveLds &S, const CellsDev &C, int e) {
@@ -1105,6 +1163,11 @@ __device__ void do_site(WaveLds &S, const GridView &G0, const DomainView &D0, co
       }
     }
     if (need_carve) {
+      if (cell_job && !POW && S.K.cnt > 0 && gabriel_clips<MON>(S, X, npl, nc, st)) {
+        init_box(S, X, D.box_lo, D.box_hi);  // a failed clip: carve the box as it is
+        npl = 6;
+        nc = 8;
+      }
       const int rc = carve<MON, POW>(S, G, P, X, npl, nc, st);
       if (cell_job) {
         cell_job = false;
