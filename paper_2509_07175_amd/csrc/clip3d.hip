@@ -977,7 +977,7 @@ __device__ __forceinline__ bool cell_in_domain(const WaveLds &S, const DomainVie
 // before the carve, which then finds the other faces by its tests and
 // searches.  Returns 0, or a clip's failure (the caller then carves the box
 // without these clips).
-constexpr int kGabriel = 32;
+constexpr int kGabriel = 24;
 template <bool MON>
 __device__ int gabriel_clips(WaveLds &S, const SiteCtx &X, int &npl, int &nc, Stats &st) {
   const int l = vd_lane();
