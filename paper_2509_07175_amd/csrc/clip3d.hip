@@ -1002,11 +1002,58 @@ __device__ int gabriel_clips(WaveLds &S, const SiteCtx &X, int &npl, int &nc, St
     gab = dj2 > 0.0 && dj2 < rc2 * (1.0 - 1e-9);
   }
   const double mx = 0.5 * jx, my = 0.5 * jy, mz = 0.5 * jz, r2 = 0.25 * dj2 * (1.0 + 1e-9);
+  const bool cand = gab;
+  int kin = -1;          // the site deepest inside the diametral ball
+  double kdepth = 1e300;
   for (int k = 0; k < E; k++) {
     const double kx = S.K.x[k] - X.vx, ky = S.K.y[k] - X.vy, kz = S.K.z[k] - X.vz;
     const double ex = kx - mx, ey = ky - my, ez = kz - mz;
     const bool self = kx == 0.0 && ky == 0.0 && kz == 0.0;
-    if (k != l && !self && ex * ex + ey * ey + ez * ez <= r2) gab = false;
+    const double e2 = ex * ex + ey * ey + ez * ez;
+    if (k != l && !self && e2 <= r2) {
+      gab = false;
+      if (e2 < kdepth) { kdepth = e2; kin = k; }
+    }
+  }
+  // A non-Gabriel v_j is still a Delaunay neighbour when the smallest sphere
+  // through v_i, v_j and the site v_k deepest in its diametral ball holds no
+  // other site: its centre (the circumcentre of the three) is then a point of
+  // the Voronoi edge of i, j, k, which lies on the face towards v_j.
+  bool tri = false;
+  double cx = 0, cy = 0, cz = 0, R2 = 0;
+  if (cand && !gab && kin >= 0) {
+    const double ax = jx, ay = jy, az = jz;
+    const double bx = S.K.x[kin] - X.vx, by = S.K.y[kin] - X.vy, bz = S.K.z[kin] - X.vz;
+    const double wx = ay * bz - az * by, wy = az * bx - ax * bz, wz = ax * by - ay * bx;
+    const double w2 = wx * wx + wy * wy + wz * wz, a2 = dj2, b2 = bx * bx + by * by + bz * bz;
+    if (w2 > 1e-12 * a2 * b2) {
+      // c = (|a|^2 (b x w) + |b|^2 (w x a)) / (2 |w|^2), w = a x b
+      const double iw = 0.5 / w2;
+      cx = (a2 * (by * wz - bz * wy) + b2 * (wy * az - wz * ay)) * iw;
+      cy = (a2 * (bz * wx - bx * wz) + b2 * (wz * ax - wx * az)) * iw;
+      cz = (a2 * (bx * wy - by * wx) + b2 * (wx * ay - wy * ax)) * iw;
+      R2 = cx * cx + cy * cy + cz * cz;
+      tri = 4.0 * R2 < rc2 * (1.0 - 1e-9) && R2 < 4.0 * a2;
+    }
+  }
+  if (__ballot(tri)) {
+    // sites within 2 R of v_i lie below the first bucket beyond (2 R)^2
+    const double lim = -wave_min(tri ? -4.0 * R2 : 0.0);
+    int E2 = n;
+    {
+      const uint64_t a = __ballot(l < n && (double)S.K.kb[l] * S.K.step > lim);
+      const uint64_t b = __ballot(l + 64 < n && (double)S.K.kb[l + 64] * S.K.step > lim);
+      if (a) E2 = __ffsll((unsigned long long)a) - 1;
+      else if (b) E2 = 64 + __ffsll((unsigned long long)b) - 1;
+    }
+    const double R2in = R2 * (1.0 + 1e-9);
+    for (int k = 0; k < E2; k++) {
+      const double kx = S.K.x[k] - X.vx, ky = S.K.y[k] - X.vy, kz = S.K.z[k] - X.vz;
+      const double ex = kx - cx, ey = ky - cy, ez = kz - cz;
+      const bool self = kx == 0.0 && ky == 0.0 && kz == 0.0;
+      if (k != l && k != kin && !self && ex * ex + ey * ey + ez * ez <= R2in) tri = false;
+    }
+    gab = gab || tri;
   }
   for (uint64_t m = __ballot(gab); m; m &= m - 1) {
     const int c = __ffsll((unsigned long long)m) - 1;
