@@ -400,6 +400,50 @@ __device__ __forceinline__ bool sq_push(TriLds &S, const CellsDev &C, int &nsq, 
   return true;
 }
 
+// Gabriel neighbours of site si among the first kGabrielS cache entries: the
+// ball on the diameter [v_si, v_j] lies inside the cached region (every site
+// that could be in it is cached) and holds no other site, so the midpoint of
+// v_si v_j lies on the face of the cell of si towards v_j, and B(si, j) is a
+// face plane, a valid clip.  Returns the mask of their cache slots (known
+// bisectors `skip0`, `skip1` left out).
+constexpr int kGabrielS = 16;
+__device__ uint64_t gabriel_mask_s(const TriLds &S, int si, double vx, double vy, double vz, int skip0, int skip1) {
+  const int l = vd_lane();
+  const int n = S.K.cnt;
+  const int T = n < kGabrielS ? n : kGabrielS;
+  if (T <= 0) return 0ull;
+  double ax = 0, ay = 0, az = 0, r2 = 0, mx = 0, my = 0, mz = 0;
+  bool gab = false;
+  double reach2 = 0.0;
+  if (l < T) {
+    const int pj = S.K.p[l];
+    ax = S.K.x[l] - vx; ay = S.K.y[l] - vy; az = S.K.z[l] - vz;
+    const double a2 = ax * ax + ay * ay + az * az;
+    mx = vx + 0.5 * ax; my = vy + 0.5 * ay; mz = vz + 0.5 * az;
+    r2 = 0.25 * a2;
+    const double dx = mx - S.K.vx, dy = my - S.K.vy, dz = mz - S.K.vz;
+    const double reach = (sqrt(dx * dx + dy * dy + dz * dz) + sqrt(r2)) * (1.0 + 1e-9);
+    gab = pj != si && pj != skip0 && pj != skip1 && a2 > 0.0 && reach < S.K.rc;
+    reach2 = gab ? reach * reach : 0.0;
+  }
+  if (!__ballot(gab)) return 0ull;
+  // sites within reach of the centre lie below the first bucket beyond it
+  const double lim = -wave_min(-reach2);
+  int E = n;
+  {
+    const uint64_t a = __ballot(l < n && (double)S.K.kb[l] * S.K.step > lim);
+    const uint64_t b = __ballot(l + 64 < n && (double)S.K.kb[l + 64] * S.K.step > lim);
+    if (a) E = __ffsll((unsigned long long)a) - 1;
+    else if (b) E = 64 + __ffsll((unsigned long long)b) - 1;
+  }
+  const double r2in = r2 * (1.0 + 1e-9);
+  for (int k = 0; k < E; k++) {
+    const double ex = S.K.x[k] - mx, ey = S.K.y[k] - my, ez = S.K.z[k] - mz;
+    if (k != l && S.K.p[k] != si && ex * ex + ey * ey + ez * ez <= r2in) gab = false;
+  }
+  return __ballot(gab);
+}
+
 template <bool DENS, bool POW>
 __device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, const CellsDev &C, int a) {
   const int l = vd_lane();
@@ -471,6 +515,34 @@ __device__ void do_triangle(TriLds &S, const GridView &G, const DomainView &D, c
         nv = 3;
         rc = 0;
         break;
+      }
+    }
+    if (!POW && rc == 0 && nv > 0) {
+      // and by the bisectors of the site's Gabriel neighbours (those that do
+      // not cross the piece leave it unchanged)
+      for (uint64_t m = gabriel_mask_s(S, si, vx, vy, vz, from, from2); m && rc == 0; m &= m - 1) {
+        const int c = __ffsll((unsigned long long)m) - 1;
+        if (npl >= kSP) break;
+        __syncthreads();
+        if (l == 0) {
+          const double n0 = S.K.x[c] - vx, n1 = S.K.y[c] - vy, n2 = S.K.z[c] - vz;
+          S.pn[npl][0] = n0; S.pn[npl][1] = n1; S.pn[npl][2] = n2;
+          S.pn[npl][3] = 0.5 * (n0 * n0 + n1 * n1 + n2 * n2);
+          S.plab[npl] = S.K.p[c];
+        }
+        __syncthreads();
+        rc = clip_s(S, C.monitor, npl, -1, nv);
+        npl++;
+        if (rc == 4) ss.clips++;
+        if (rc == 4 || rc == 0) {
+          rc = 0;
+        } else if (rc != 1) {
+          init_tri(S, D, a, vx, vy, vz);  // a degenerate cut: carve from T_a alone
+          npl = 4;
+          nv = 3;
+          rc = 0;
+          break;
+        }
       }
     }
     if (rc == 0) rc = carve_s<POW>(S, G, P, si, vx, vy, vz, delta, npl, nv, ss);
