@@ -87,8 +87,11 @@ typedef struct {
                                  carved by point-in-cell tests and the bisector search.
                                  1 (default): the cell is carved once from the padded
                                  bounding box of the domain (Sec. 5.2), then each piece is
-                                 T_a cut by the cell's certified bisector facets.  Both
-                                 give the same pieces. */
+                                 T_a cut by the cell's certified bisector facets.  With the
+                                 site cache, the box is first cut by the bisectors of the
+                                 Delaunay neighbours that the cached sites certify (an empty
+                                 sphere through v_i and the neighbour), which are faces of
+                                 the cell.  Both modes give the same pieces. */
   int32_t no_sync;            /* 1: vd_clip_cells only enqueues work (no host synchronisation,
                                  no allocation), so it can be captured into a HIP graph.
                                  Needs a handle sized by an earlier synchronous clip of the
