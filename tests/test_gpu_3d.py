@@ -266,10 +266,12 @@ def test_c3_full_size_sampled(oracle_mod):
 
 def test_c3_pieces_do_not_depend_on_the_schedule():
     """The headline workload at full size under every schedule knob (grid
-    density, search edges, improved search, per-piece carve, no site cache):
-    the knobs change the order of queries and clips, never the result, so the
-    set of (site, tetrahedron) pieces is identical and the per-site moments
-    agree to 1e-9 relative."""
+    density, search edges, improved search, per-piece carve, no site cache --
+    which also leaves out the clips by the neighbours the cached sites
+    certify): the knobs change the order of queries and clips, never the
+    result, so the set of (site, tetrahedron) pieces and every site's
+    neighbour list are identical and the per-site moments agree to 1e-9
+    relative."""
     import torch
     import paper_2509_07175_amd as vd
     sites, dom = vdgen.config_c3()
@@ -289,7 +291,8 @@ def test_c3_pieces_do_not_depend_on_the_schedule():
         ps = v["piece_site"]
         used = ps >= 0
         key = (ps[used].to(torch.int64) * dom.m + v["piece_simplex"][used].to(torch.int64)).sort().values.cpu().numpy()
-        cur = (key, m.cpu().numpy(), ce.cpu().numpy(), e.cpu().numpy())
+        cur = (key, m.cpu().numpy(), ce.cpu().numpy(), e.cpu().numpy(), v["nbr_off"].cpu().numpy(),
+               v["nbr"].cpu().numpy())
         del c, g, v
         if ref is None:
             ref = cur
@@ -299,3 +302,4 @@ def test_c3_pieces_do_not_depend_on_the_schedule():
         assert np.all(np.abs(cur[1] - ref[1]) <= 1e-9 * ref[1])
         assert np.all(np.linalg.norm(cur[2] - ref[2], axis=1) <= 1e-9 * np.linalg.norm(ref[2], axis=1))
         assert np.all(np.abs(cur[3] - ref[3]) <= 1e-9 * ref[3])
+        assert np.array_equal(cur[4], ref[4]) and np.array_equal(cur[5], ref[5]), "neighbour lists differ"
