@@ -976,11 +976,39 @@ __device__ __forceinline__ bool cell_in_domain(const WaveLds &S, const DomainVie
 // clips by faces).  The polytope (the box) is clipped by every such bisector
 // before the carve, which then finds the other faces by its tests and
 // searches.  Returns 0, or a clip's failure (the caller then carves the box
-// without these clips).
+// without these clips).  Lanes c and c + 32 hold candidate c and scan the two
+// halves of the cached sites; the halves' results are then merged through LDS.
 constexpr int kGabriel = 24;
+static_assert(kGabriel <= 32, "a candidate per lane of each half-wave");
+
+// Merges the two half-wave scans of a candidate: the deepest site (the lower
+// position on a tie, as one scan in position order would take) and whether
+// both halves found the ball empty.  The lanes swap their results through the
+// 64 rows at ex (whole wave; the rows are free while the function runs).
+__device__ __forceinline__ void merge_halves(double (*ex)[3], double &depth, int &deep, bool &empty) {
+  const int l = vd_lane();
+  const bool lo = l < 32;
+  __syncthreads();
+  ex[l][0] = depth;
+  ex[l][1] = (double)deep;
+  ex[l][2] = empty ? 1.0 : 0.0;
+  __syncthreads();
+  const double od = ex[l ^ 32][0];
+  const int ok = (int)ex[l ^ 32][1];
+  const bool oe = ex[l ^ 32][2] != 0.0;
+  __syncthreads();
+  const double dlo = lo ? depth : od, dhi = lo ? od : depth;
+  const int klo = lo ? deep : ok, khi = lo ? ok : deep;
+  depth = dhi < dlo ? dhi : dlo;
+  deep = dhi < dlo ? khi : klo;
+  empty = empty && oe;
+}
+
 template <bool MON>
 __device__ int gabriel_clips(WaveLds &S, const SiteCtx &X, int &npl, int &nc, Stats &st) {
   const int l = vd_lane();
+  const int cl = l & 31;  // this lane's candidate
+  const bool upper = l >= 32;
   const int n = S.K.cnt;
   const int T = n < kGabriel ? n : kGabriel;
   if (T <= 0) return 0;
@@ -996,8 +1024,8 @@ __device__ int gabriel_clips(WaveLds &S, const SiteCtx &X, int &npl, int &nc, St
   const double rc2 = S.K.rc * S.K.rc;
   double jx = 0, jy = 0, jz = 0, dj2 = 0;
   bool gab = false;
-  if (l < T) {
-    jx = S.K.x[l] - X.vx; jy = S.K.y[l] - X.vy; jz = S.K.z[l] - X.vz;
+  if (cl < T) {
+    jx = S.K.x[cl] - X.vx; jy = S.K.y[cl] - X.vy; jz = S.K.z[cl] - X.vz;
     dj2 = jx * jx + jy * jy + jz * jz;
     gab = dj2 > 0.0 && dj2 < rc2 * (1.0 - 1e-9);
   }
@@ -1005,16 +1033,21 @@ __device__ int gabriel_clips(WaveLds &S, const SiteCtx &X, int &npl, int &nc, St
   const bool cand = gab;
   int kin = -1;          // the site deepest inside the diametral ball
   double kdepth = 1e300;
-  for (int k = 0; k < E; k++) {
+  // corner rows 64-127 are unused until the first clip below (the box has 8)
+  double(*const ex)[3] = &S.cy[64];
+  static_assert(VD_C_MAX >= 128, "64 free corner rows for the merge");
+  const int hE = (E + 1) >> 1;
+  for (int k = upper ? hE : 0, kend = upper ? E : hE; k < kend; k++) {
     const double kx = S.K.x[k] - X.vx, ky = S.K.y[k] - X.vy, kz = S.K.z[k] - X.vz;
     const double ex = kx - mx, ey = ky - my, ez = kz - mz;
     const bool self = kx == 0.0 && ky == 0.0 && kz == 0.0;
     const double e2 = ex * ex + ey * ey + ez * ez;
-    if (k != l && !self && e2 <= r2) {
+    if (k != cl && !self && e2 <= r2) {
       gab = false;
       if (e2 < kdepth) { kdepth = e2; kin = k; }
     }
   }
+  merge_halves(ex, kdepth, kin, gab);
   // A non-Gabriel v_j is still a Delaunay neighbour when the smallest sphere
   // through v_i, v_j and the site v_k deepest in its diametral ball holds no
   // other site: its centre (the circumcentre of the three) is then a point of
@@ -1049,14 +1082,21 @@ __device__ int gabriel_clips(WaveLds &S, const SiteCtx &X, int &npl, int &nc, St
       else if (b) E2 = 64 + __ffsll((unsigned long long)b) - 1;
     }
     const double R2in = R2 * (1.0 + 1e-9);
-    for (int k = 0; k < E2; k++) {
+    const int h2 = (E2 + 1) >> 1;
+    for (int k = upper ? h2 : 0, kend = upper ? E2 : h2; k < kend; k++) {
       const double kx = S.K.x[k] - X.vx, ky = S.K.y[k] - X.vy, kz = S.K.z[k] - X.vz;
       const double ex = kx - cx, ey = ky - cy, ez = kz - cz;
       const bool self = kx == 0.0 && ky == 0.0 && kz == 0.0;
-      if (k != l && k != kin && !self && ex * ex + ey * ey + ez * ez <= R2in) tri = false;
+      if (k != cl && k != kin && !self && ex * ex + ey * ey + ez * ez <= R2in) tri = false;
+    }
+    {
+      double dd = 0.0;
+      int dk = 0;
+      merge_halves(ex, dd, dk, tri);
     }
     gab = gab || tri;
   }
+  gab = gab && !upper;  // the lower half clips
   for (uint64_t m = __ballot(gab); m; m &= m - 1) {
     const int c = __ffsll((unsigned long long)m) - 1;
     if (npl >= VD_P_MAX) return 2;
